@@ -1,0 +1,271 @@
+/*
+ * oracle.c -- plain FP64 CPU oracle for feedforward decentralized precoding
+ * (K. Li, C. Jeon, J. R. Cavallaro, C. Studer, "Feedforward Architectures for
+ * Decentralized Precoding in Massive MU-MIMO Systems", arXiv:1804.10987).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may call, link or
+ * load this file; only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark do.  It shares no code with the HIP library.
+ *
+ * Everything is textbook scalar complex<double> loops in the order the paper
+ * states the method; no blocking, no fusion, no BLAS.
+ *
+ * Convention.  The paper writes the downlink channel of one subcarrier as a
+ * U x B matrix (Sec. II-A, downlink model).  This oracle stores its Hermitian
+ * transpose H (B x U: antenna rows, user columns), so the paper's cluster
+ * column blocks become row blocks H_c (B_c x U), the paper's local Gram
+ * H_c H_c^H becomes H_c^H H_c (U x U) and the per-cluster product H_c^H z
+ * becomes H_c z.
+ *
+ * Memory layout (complex values stored as interleaved re,im doubles):
+ *   H     [n_sc][B][U]
+ *   s     [K][n_sc][U]
+ *   x     [K][n_sc][B]
+ *   beta  [n_sc]          (PD)
+ *   wgt   [n_sc][C]       (FD)
+ *   status: 0 = ok, 1 = numerical failure (x, beta / weights set to zero).
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef double complex cplx;
+
+static cplx ld(const double *p) { return p[0] + p[1] * I; }
+static void st(double *p, cplx v) { p[0] = creal(v); p[1] = cimag(v); }
+
+/* In-place Cholesky A = L L^H of an n x n Hermitian matrix (row-major,
+ * lower triangle used).  The paper inverts the regularized Gram matrix with a
+ * batched factorization (Sec. IV-B, PD-WF implementation); A is Hermitian
+ * positive definite, so Cholesky is the factorization that applies.
+ * Returns 0 on success, 1 if a pivot is not positive and finite. */
+static int cholesky(cplx *A, int n) {
+    for (int j = 0; j < n; ++j) {
+        double d = creal(A[j * n + j]);
+        for (int k = 0; k < j; ++k) {
+            cplx l = A[j * n + k];
+            d -= creal(l * conj(l));
+        }
+        if (!(d > 0.0) || !isfinite(d)) return 1;
+        d = sqrt(d);
+        A[j * n + j] = d;
+        for (int i = j + 1; i < n; ++i) {
+            cplx acc = A[i * n + j];
+            for (int k = 0; k < j; ++k) acc -= A[i * n + k] * conj(A[j * n + k]);
+            A[i * n + j] = acc / d;
+        }
+        for (int i = 0; i < j; ++i) A[i * n + j] = 0.0;
+    }
+    return 0;
+}
+
+/* Explicit inverse of a Hermitian positive-definite matrix through its
+ * Cholesky factor: solve L Y = I by forward substitution, then
+ * L^H X = Y by back substitution, one column of the identity at a time. */
+static int hpd_inverse(const cplx *A, int n, cplx *Ainv) {
+    cplx *L = malloc(sizeof(cplx) * n * n);
+    cplx *y = malloc(sizeof(cplx) * n);
+    memcpy(L, A, sizeof(cplx) * n * n);
+    int bad = cholesky(L, n);
+    for (int col = 0; col < n && !bad; ++col) {
+        for (int i = 0; i < n; ++i) {
+            cplx acc = (i == col) ? 1.0 : 0.0;
+            for (int k = 0; k < i; ++k) acc -= L[i * n + k] * y[k];
+            y[i] = acc / L[i * n + i];
+        }
+        for (int i = n - 1; i >= 0; --i) {
+            cplx acc = y[i];
+            for (int k = i + 1; k < n; ++k) acc -= conj(L[k * n + i]) * Ainv[k * n + col];
+            Ainv[i * n + col] = acc / creal(L[i * n + i]);
+        }
+    }
+    for (int i = 0; i < n * n && !bad; ++i)
+        if (!isfinite(creal(Ainv[i])) || !isfinite(cimag(Ainv[i]))) bad = 1;
+    free(L);
+    free(y);
+    return bad;
+}
+
+/* ---------------------------------------------------------------------------
+ * Partially decentralized WF / ZF precoding (Sec. III-B).
+ *
+ *   G_c = H_c^H H_c for every cluster           (local Gram, Sec. III-B)
+ *   G   = sum_c G_c                             (feedforward adder tree)
+ *   A   = G + kappa I_U                         (regularized Gram, App. B)
+ *   beta = sqrt(Es/rho^2 (tr A^-1 - kappa ||A^-1||_F^2))    (Lemma 1)
+ *   z   = A^-1 s / beta                         (whitening node)
+ *   x_c = H_c z                                 (per-cluster precoding)
+ *
+ * kappa is the WF regularizer U N0 / rho^2 of Theorem 1; ZF is kappa = 0.
+ * power = rho^2 (power budget, Sec. II-A), Es = symbol energy.
+ * G_out / Ainv_out (optional, [n_sc][U][U] complex) expose intermediates.
+ * ------------------------------------------------------------------------- */
+int oracle_pd(const double *H, const double *s, int B, int U, int n_sc, int K,
+              const int *sizes, int C, double kappa, int zf, double power,
+              double Es, int threads, double *x, double *beta, int *status,
+              double *G_out, double *Ainv_out) {
+    if (zf) kappa = 0.0;
+    int bad_args = 0;
+    {
+        int sum = 0;
+        for (int c = 0; c < C; ++c) sum += sizes[c];
+        if (sum != B) bad_args = 1;
+    }
+    if (bad_args) return -1;
+#pragma omp parallel for schedule(dynamic) num_threads(threads)
+    for (int n = 0; n < n_sc; ++n) {
+        const double *Hn = H + (size_t)n * B * U * 2;
+        cplx *G = calloc((size_t)U * U, sizeof(cplx));
+        cplx *A = malloc(sizeof(cplx) * U * U);
+        cplx *Ai = malloc(sizeof(cplx) * U * U);
+        cplx *z = malloc(sizeof(cplx) * U);
+        /* local Gram matrices, summed cluster by cluster */
+        int row0 = 0;
+        for (int c = 0; c < C; ++c) {
+            for (int u = 0; u < U; ++u)
+                for (int v = 0; v < U; ++v) {
+                    cplx g = 0.0;
+                    for (int b = row0; b < row0 + sizes[c]; ++b)
+                        g += conj(ld(Hn + ((size_t)b * U + u) * 2)) * ld(Hn + ((size_t)b * U + v) * 2);
+                    G[u * U + v] += g;
+                }
+            row0 += sizes[c];
+        }
+        for (int i = 0; i < U * U; ++i) A[i] = G[i];
+        for (int u = 0; u < U; ++u) A[u * U + u] += kappa;
+        int bad = hpd_inverse(A, U, Ai);
+        double t = 0.0;
+        if (!bad) {
+            double tr = 0.0, fro = 0.0;
+            for (int u = 0; u < U; ++u) tr += creal(Ai[u * U + u]);
+            for (int i = 0; i < U * U; ++i) fro += creal(Ai[i] * conj(Ai[i]));
+            t = tr - kappa * fro;
+            if (!(t > 0.0) || !isfinite(t)) bad = 1;
+        }
+        double b_wf = bad ? 0.0 : sqrt(Es / power * t);
+        beta[n] = b_wf;
+        if (status) status[n] = bad;
+        for (int k = 0; k < K; ++k) {
+            const double *sk = s + ((size_t)k * n_sc + n) * U * 2;
+            double *xk = x + ((size_t)k * n_sc + n) * B * 2;
+            if (bad) {
+                memset(xk, 0, sizeof(double) * 2 * B);
+                continue;
+            }
+            for (int u = 0; u < U; ++u) {
+                cplx acc = 0.0;
+                for (int v = 0; v < U; ++v) acc += Ai[u * U + v] * ld(sk + v * 2);
+                z[u] = acc / b_wf;
+            }
+            for (int b = 0; b < B; ++b) {
+                cplx acc = 0.0;
+                for (int u = 0; u < U; ++u) acc += ld(Hn + ((size_t)b * U + u) * 2) * z[u];
+                st(xk + b * 2, acc);
+            }
+        }
+        if (G_out)
+            for (int i = 0; i < U * U; ++i) st(G_out + ((size_t)n * U * U + i) * 2, G[i]);
+        if (Ainv_out)
+            for (int i = 0; i < U * U; ++i) st(Ainv_out + ((size_t)n * U * U + i) * 2, bad ? 0.0 : Ai[i]);
+        free(G);
+        free(A);
+        free(Ai);
+        free(z);
+    }
+    return 0;
+}
+
+/* ---------------------------------------------------------------------------
+ * Fully decentralized WF / ZF precoding (Sec. III-C).
+ *
+ * Every cluster gets the power rho_c^2 = rho^2 / C and the regularizer
+ * kappa_c = tau_c U N0 / rho_c^2 = tau_c C kappa (eq. regularization), and
+ * forms its own precoding matrix Q_c (B_c x U in this file's convention):
+ *
+ *   B_c <  U :  Q_c = (H_c H_c^H + kappa_c I_{B_c})^-1 H_c
+ *   B_c >= U :  Q_c = H_c (H_c^H H_c + kappa_c I_U)^-1
+ *
+ *   x_c = sqrt(rho_c^2 / (tr(Q_c^H Q_c) Es)) Q_c s
+ *
+ * The weight sqrt(rho_c^2 / (tr(Q_c^H Q_c) Es)) is returned in wgt.
+ * ------------------------------------------------------------------------- */
+int oracle_fd(const double *H, const double *s, int B, int U, int n_sc, int K,
+              const int *sizes, int C, double kappa, int zf, double tau,
+              double power, double Es, int threads, double *x, double *wgt,
+              int *status) {
+    int sum = 0;
+    for (int c = 0; c < C; ++c) sum += sizes[c];
+    if (sum != B) return -1;
+    const double rho_c2 = power / C;
+    const double kappa_c = zf ? 0.0 : tau * C * kappa;
+#pragma omp parallel for schedule(dynamic) num_threads(threads)
+    for (int n = 0; n < n_sc; ++n) {
+        const double *Hn = H + (size_t)n * B * U * 2;
+        int row0 = 0;
+        for (int c = 0; c < C; ++c) {
+            const int Bc = sizes[c];
+            const double *Hc = Hn + (size_t)row0 * U * 2;
+            const int m = (Bc < U) ? Bc : U; /* order of the local system */
+            cplx *A = malloc(sizeof(cplx) * m * m);
+            cplx *Ai = malloc(sizeof(cplx) * m * m);
+            cplx *Q = calloc((size_t)Bc * U, sizeof(cplx));
+            if (Bc >= U) {
+                for (int u = 0; u < U; ++u)
+                    for (int v = 0; v < U; ++v) {
+                        cplx g = 0.0;
+                        for (int b = 0; b < Bc; ++b)
+                            g += conj(ld(Hc + ((size_t)b * U + u) * 2)) * ld(Hc + ((size_t)b * U + v) * 2);
+                        A[u * U + v] = g + ((u == v) ? kappa_c : 0.0);
+                    }
+            } else {
+                for (int a = 0; a < Bc; ++a)
+                    for (int b = 0; b < Bc; ++b) {
+                        cplx g = 0.0;
+                        for (int u = 0; u < U; ++u)
+                            g += ld(Hc + ((size_t)a * U + u) * 2) * conj(ld(Hc + ((size_t)b * U + u) * 2));
+                        A[a * Bc + b] = g + ((a == b) ? kappa_c : 0.0);
+                    }
+            }
+            int bad = hpd_inverse(A, m, Ai);
+            if (!bad) {
+                if (Bc >= U) {
+                    for (int b = 0; b < Bc; ++b)
+                        for (int v = 0; v < U; ++v) {
+                            cplx acc = 0.0;
+                            for (int u = 0; u < U; ++u) acc += ld(Hc + ((size_t)b * U + u) * 2) * Ai[u * U + v];
+                            Q[b * U + v] = acc;
+                        }
+                } else {
+                    for (int a = 0; a < Bc; ++a)
+                        for (int v = 0; v < U; ++v) {
+                            cplx acc = 0.0;
+                            for (int b = 0; b < Bc; ++b) acc += Ai[a * Bc + b] * ld(Hc + ((size_t)b * U + v) * 2);
+                            Q[a * U + v] = acc;
+                        }
+                }
+            }
+            double t = 0.0;
+            for (int i = 0; i < Bc * U && !bad; ++i) t += creal(Q[i] * conj(Q[i]));
+            if (!bad && (!(t > 0.0) || !isfinite(t))) bad = 1;
+            double w = bad ? 0.0 : sqrt(rho_c2 / (t * Es));
+            wgt[(size_t)n * C + c] = w;
+            if (status) status[(size_t)n * C + c] = bad;
+            for (int k = 0; k < K; ++k) {
+                const double *sk = s + ((size_t)k * n_sc + n) * U * 2;
+                double *xk = x + (((size_t)k * n_sc + n) * B + row0) * 2;
+                for (int b = 0; b < Bc; ++b) {
+                    cplx acc = 0.0;
+                    if (!bad)
+                        for (int u = 0; u < U; ++u) acc += Q[b * U + u] * ld(sk + u * 2);
+                    st(xk + b * 2, w * acc);
+                }
+            }
+            free(A);
+            free(Ai);
+            free(Q);
+            row0 += Bc;
+        }
+    }
+    return 0;
+}
