@@ -1,0 +1,205 @@
+#!/usr/bin/env python3
+"""Benchmark: PD-WF precoding throughput on one MI355X.
+
+Workload: B = 256 antennas as 8 clusters of 32, U = 16 users, 1200
+subcarriers x 14 OFDM symbols per frame, i.i.d. Rayleigh complex64 channel,
+16-QAM symbols, SNR 10 dB (kappa = U / SNR).  A step precodes one frame:
+Gram -> cluster sum -> regularize -> Cholesky -> beta -> solve -> precode for
+every subcarrier and symbol.  Frames rotate over enough distinct input/output
+buffers that the working set exceeds the 256 MB last-level cache, so every
+step streams its channel from HBM.
+
+Prints one JSON line.  value = subcarrier-symbols precoded per second.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "precoded subcarriers/s (B=256,U=16) + p99 symbol latency vs plain, rel err ≤1e-3"
+HBM_PEAK_GBS = 8000.0
+LLC_BYTES = 256 << 20
+
+
+def algorithmic_bytes(B, U, K, n_sc):
+    """HBM bytes the method must move per frame: the channel once, the symbols
+    and the precoded vectors once (complex64)."""
+    return 8 * n_sc * (B * U + K * U + K * B)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--quick", action="store_true", help="headline path only (for profiling)")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(clusters are batch entries on one device); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1804_10987_amd as pc
+    import synth
+
+    dev = torch.device("cuda:0")
+    cell = synth.config(2)
+    B, U, K, n_sc, sizes = cell.B, cell.U, cell.K, cell.n_sc, list(cell.sizes)
+    frame_bytes = algorithmic_bytes(B, U, K, n_sc)
+    n_frames = max(2, math.ceil(2 * LLC_BYTES / frame_bytes))
+
+    H0, s0 = synth.make_cell(cell, seed=0, frame=0)
+    Hs, Ss, Xs = [], [], []
+    for f in range(n_frames):
+        H, s = (H0, s0) if f == 0 else synth.make_cell(cell, seed=0, frame=f)
+        Hs.append(torch.from_numpy(H).to(dev))
+        Ss.append(torch.from_numpy(s).to(dev))
+        Xs.append(torch.empty((K, n_sc, B), dtype=torch.complex64, device=dev))
+    betas = [torch.empty(n_sc, dtype=torch.float32, device=dev) for _ in range(n_frames)]
+    stats = [torch.empty(n_sc, dtype=torch.int32, device=dev) for _ in range(n_frames)]
+    torch.cuda.synchronize()
+
+    ctx = pc.Context(0)
+    stream = torch.cuda.current_stream()
+
+    def time_path(fn, steps, warmup):
+        """Runs fn(frame) warmup + steps times; returns (ms/step, per-launch ms list)."""
+        for i in range(warmup):
+            fn(i % n_frames)
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        for i in range(steps):
+            ev[i][0].record(stream)
+            fn(i % n_frames)
+            ev[i][1].record(stream)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        total = t0.elapsed_time(t1)
+        per = [a.elapsed_time(b) for a, b in ev]
+        return total / steps, per
+
+    def pd_fused(f, prec="fp32"):
+        ctx.pd(Hs[f], Ss[f], cell.kappa, sizes, "wf", pc.params(precision=prec, impl="fused"),
+               x=Xs[f], beta=betas[f], status=stats[f], stream=stream)
+
+    def pd_plain(f):
+        ctx.pd(Hs[f], Ss[f], cell.kappa, sizes, "wf", pc.params(impl="plain"),
+               x=Xs[f], beta=betas[f], status=stats[f], stream=stream)
+
+    fd_w = [torch.empty((n_sc * len(sizes),), dtype=torch.float32, device=dev) for _ in range(n_frames)]
+    fd_st = [torch.empty((n_sc * len(sizes),), dtype=torch.int32, device=dev) for _ in range(n_frames)]
+
+    def fd_run(f, ratio=0.5, impl="auto"):
+        ctx.fd(Hs[f], Ss[f], cell.kappa, sizes, "wf", pc.params(fp64_ratio=ratio, impl=impl),
+               x=Xs[f], weights=fd_w[f], status=fd_st[f], stream=stream)
+
+    # ---- headline: PD-WF, fused FP32 ------------------------------------
+    ms, per = time_path(pd_fused, args.steps, args.warmup)
+    per = np.array(per)
+    value = n_sc * K / (ms * 1e-3)
+    launch_ms = float(per.mean())
+    achieved = frame_bytes / (launch_ms * 1e-3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "subcarrier-symbols/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32",
+        "data": "synthetic",
+        "config": {
+            "workload": "PD-WF, B=256 as 8 clusters x 32, U=16, 1200 subcarriers x 14 symbols, "
+                        "i.i.d. Rayleigh complex64, 16-QAM, SNR 10 dB",
+            "arch": "PD", "mode": "WF", "B": B, "C": len(sizes), "U": U, "n_sc": n_sc, "K": K,
+            "impl": ctx.last_impl, "precision": "fp32", "frames_rotated": n_frames,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "fused_k<16, PD>",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "algorithmic_bytes_per_launch": frame_bytes,
+            "launch_ms": launch_ms,
+            "traffic": None,
+        },
+        "latency": {"frame_p50_ms": float(np.percentile(per, 50)), "frame_p99_ms": float(np.percentile(per, 99))},
+    }
+    if not args.quick:
+        steps2 = max(10, args.steps // 4)
+        ms_plain, _ = time_path(pd_plain, steps2, 3)
+        out["vs_plain"] = {"plain_ms_per_step": ms_plain, "speedup": ms_plain / ms,
+                           "plain_value": n_sc * K / (ms_plain * 1e-3)}
+        ms_fd32, per_fd = time_path(lambda f: fd_run(f, ratio=2.0, impl="fused"), steps2, 3)
+        ms_fd, _ = time_path(lambda f: fd_run(f), steps2, 3)
+        fd_impl = ctx.last_impl
+        ms_fd_plain, _ = time_path(lambda f: fd_run(f, ratio=2.0, impl="plain"), max(5, steps2 // 2), 2)
+        out["fd"] = {
+            "fused_fp32_ms_per_step": ms_fd32, "fused_fp32_value": n_sc * K / (ms_fd32 * 1e-3),
+            "fused_fp32_achieved_gbs": frame_bytes / (float(np.mean(per_fd)) * 1e-3) / 1e9,
+            "default_route_ms_per_step": ms_fd, "default_route_impl": fd_impl,
+            "plain_fp32_ms_per_step": ms_fd_plain, "speedup_vs_plain": ms_fd_plain / ms_fd32,
+        }
+    if not args.no_cpu:
+        out["cpu_baseline"], out["rel_err"] = cpu_baseline(cell, Hs[0], Ss[0], Xs[0], betas[0], ctx, pc, stream)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(cell, Hd, sd, xd, bd, ctx, pc, stream):
+    """The FP64 oracle on the host cores over the same frame (repeated until
+    about 2 s of wall time), and the GPU's error against it on that frame."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import synth
+
+    H, s = synth.make_cell(cell, seed=0, frame=0)
+    ctx.pd(Hd, sd, cell.kappa, list(cell.sizes), "wf", pc.params(impl="fused"), x=xd, beta=bd, stream=stream)
+    torch.cuda.synchronize()
+    xg = xd.cpu().numpy()
+    bg = bd.cpu().numpy()
+    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    threads = min(threads, int(os.environ.get("OMP_NUM_THREADS", threads)))
+    oracle.build(force=False)
+    reps = 0
+    t0 = time.perf_counter()
+    while True:
+        xo, bo, st = oracle.pd(H, s, cell.kappa, cell.sizes, threads=threads)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= 2.0:
+            break
+    value = reps * cell.n_sc * cell.K / el
+    e = np.linalg.norm(xg - xo, axis=-1) / np.linalg.norm(xo, axis=-1)
+    rel = {"max": float(e.max()), "p99": float(np.percentile(e, 99)), "p50": float(np.percentile(e, 50)),
+           "beta_max": float(np.max(np.abs(bg - bo) / bo)), "vs": "FP64 oracle, full frame 0"}
+    return ({"value": value, "unit": "subcarrier-symbols/s", "cores": threads, "kind": "oracle",
+             "sample": "%d full frame(s) (1200 subcarriers x 14 symbols), %.2f s wall" % (reps, el)}, rel)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,200 @@
+/*
+ * precode.h -- C ABI of the MI355X (gfx950) decentralized precoding library.
+ *
+ * Method: K. Li, C. Jeon, J. R. Cavallaro, C. Studer, "Feedforward
+ * Architectures for Decentralized Precoding in Massive MU-MIMO Systems",
+ * arXiv:1804.10987.  Partially decentralized (PD) Wiener-filter / ZF
+ * precoding of Sec. III-B and fully decentralized (FD) precoding of
+ * Sec. III-C, batched over OFDM subcarriers (Sec. IV-B) on one GPU: the
+ * paper's antenna clusters (one per GPU there) are batch entries here.
+ *
+ * Conventions used by every entry point
+ * -------------------------------------
+ *  - Complex values are complex64: interleaved {float re, float im}, 8 bytes.
+ *  - The channel of subcarrier n is stored as H[n] = B x U, row-major
+ *    (antenna rows, user columns).  This is the Hermitian transpose of the
+ *    paper's U x B downlink matrix (downlink model, Sec. II-A), so the
+ *    paper's local Gram H_c H_c^H is H_c^H H_c here and the per-cluster
+ *    product H_c^H z is H_c z here.  Cluster c owns the contiguous antenna
+ *    rows [o_c, o_c + B_c), o_c = B_0 + ... + B_{c-1} (Sec. III-A).
+ *  - Tensors (all DEVICE pointers, owned by the caller, 8-byte aligned):
+ *        H  [n_sc][B][U]      channel, constant over the K symbols of a frame
+ *        s  [K][n_sc][U]      transmit symbols (symbol-major)
+ *        x  [K][n_sc][B]      precoded vectors (output)
+ *  - `rho` is the WF regularizer kappa = U N0 / rho^2 of Theorem 1
+ *    (eq. precodingfactor); it is ignored for ZF (kappa = 0).
+ *  - Calls are asynchronous on `stream` (a hipStream_t passed as void*;
+ *    NULL = the default stream) and return after enqueueing.  A context is
+ *    not thread-safe: use one context per host thread.
+ *  - Errors detectable on the host are returned before anything is
+ *    launched.  Per-instance numerical failures are reported asynchronously
+ *    through `status` (see PRECODE_ST_*), never through the return code.
+ */
+#ifndef PRECODE_H
+#define PRECODE_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ------------------------------------------------------ */
+#define PRECODE_OK 0
+#define PRECODE_EINVAL (-1)       /* bad shape, pointer, size or parameter        */
+#define PRECODE_EUNSUPPORTED (-2) /* U > 64, B > 4096, K > 4096, ...              */
+#define PRECODE_ENOMEM (-3)       /* context workspace over its HBM budget        */
+#define PRECODE_EDEVICE (-4)      /* a HIP runtime error                          */
+
+/* ---- per-instance status values (bit flags, written asynchronously) ---- */
+#define PRECODE_ST_OK 0   /* solved                                          */
+#define PRECODE_ST_FAIL 1 /* non-positive pivot / non-finite value / zero    */
+                          /* power: x is set to 0, beta / weight to 0        */
+#define PRECODE_ST_FP64 2 /* solved on the FP64 route (Gram + factorization) */
+
+/* ---- enums ---------------------------------------------------------------- */
+enum precode_mode { PRECODE_ZF = 0, PRECODE_WF = 1 };
+enum precode_arch { PRECODE_ARCH_PD = 0, PRECODE_ARCH_FD = 1 };
+enum precode_prec {
+    PRECODE_PREC_FP32 = 0,       /* FP32 MFMA Gram and precode, FP32 factorization   */
+    PRECODE_PREC_SPLIT_FP16 = 1, /* Gram / precode as hi+lo FP16 MFMA, FP32 accum.   */
+    PRECODE_PREC_SPLIT_BF16 = 2, /* Gram / precode as hi+lo BF16 MFMA, FP32 accum.   */
+    PRECODE_PREC_FP64 = 3        /* every instance on the FP64 route                 */
+};
+enum precode_impl {
+    PRECODE_IMPL_AUTO = 0,  /* fused single-launch kernel where supported, else plain */
+    PRECODE_IMPL_FUSED = 1, /* fused kernel; PRECODE_EUNSUPPORTED if the shape is not */
+    PRECODE_IMPL_PLAIN = 2  /* separate plain FP32/FP64 kernels (no MFMA, no fusion)  */
+};
+
+/* ---- optional parameters (NULL => defaults from precode_params_init) ---- */
+typedef struct precode_params {
+    float power;       /* rho^2, the power budget E||x||^2 <= rho^2 (Sec. II-A); 1 */
+    float Es;          /* symbol energy E_s (Theorem 1, Lemma 1); 1                */
+    float tau;         /* FD regularization factor tau_c (eq. regularization);     */
+                       /* 0.125, the value the paper's simulations settle on       */
+    int precision;     /* enum precode_prec; PRECODE_PREC_FP32                     */
+    int refine_steps;  /* 0 or 1 steps of iterative refinement of z (PD only);     */
+                       /* residual s - (kappa z + H^H H z) accumulated in FP64; 0  */
+    float fp64_ratio;  /* an instance whose local system has U / B_eff >= ratio is */
+                       /* solved on the FP64 route (B_eff = B for PD, B_c for FD); */
+                       /* 0.5; a value > 1 disables the route                      */
+    int impl;          /* enum precode_impl; PRECODE_IMPL_AUTO                     */
+} precode_params;
+
+typedef struct precode_ctx precode_ctx;
+typedef struct precode_frame precode_frame;
+
+/* Fills *p with the defaults listed above. */
+void precode_params_init(precode_params *p);
+
+/* Human-readable text for a return code (static storage). */
+const char *precode_strerror(int code);
+
+/* Checks a PD (arch = PRECODE_ARCH_PD) or FD call's scalar arguments exactly
+ * as precode_pd / precode_fd do, without touching any device: returns the
+ * code those calls would return for these arguments (pointer checks aside).
+ * params may be NULL (defaults). */
+int precode_validate(int arch, float rho, const int *cluster_sizes, int C, int mode, int B,
+                     int U, int n_sc, int K, const precode_params *params);
+
+/* Creates a context on HIP device `device`.  The context owns the workspace
+ * used by the plain kernels, the refinement step and the resident state of
+ * frames; its total device allocation never exceeds `hbm_budget_bytes`
+ * (0 = unlimited).  *out receives the handle. */
+int precode_ctx_create(int device, size_t hbm_budget_bytes, precode_ctx **out);
+
+/* Frees the context's workspace (after synchronizing its device). */
+int precode_ctx_destroy(precode_ctx *ctx);
+
+/* Bytes of device memory the context currently holds. */
+size_t precode_ctx_bytes(const precode_ctx *ctx);
+
+/* Path taken by the most recent successful call on this context
+ * (1 = fused, 2 = plain), or 0 if none. */
+int precode_ctx_last_impl(const precode_ctx *ctx);
+
+/* ---------------------------------------------------------------------------
+ * PD precoding of a frame (Sec. III-B; Theorem 1; Lemma 1).  Per subcarrier
+ * n (n < n_sc):
+ *     G = sum_c H_c^H H_c,   A = G + kappa I_U,
+ *     beta = sqrt(Es / power * (tr A^-1 - kappa ||A^-1||_F^2)),
+ *     z_k = A^-1 s_k / beta,  x_c,k = H_c z_k   for all K symbols k.
+ * cluster_sizes: HOST array of C positive ints summing to B.
+ * mode: PRECODE_ZF or PRECODE_WF.  beta: device [n_sc] or NULL.
+ * status: device [n_sc] int or NULL.
+ * Limits: 1 <= U <= 64, 1 <= B <= 4096, 1 <= C <= min(B, 256),
+ * 0 <= K <= 4096, n_sc >= 0 (n_sc = 0 or K = 0 precodes nothing).
+ * rho must be finite and >= 0 for WF.
+ * ------------------------------------------------------------------------- */
+int precode_pd(precode_ctx *ctx, const void *H, const void *s, float rho,
+               const int *cluster_sizes, int C, int mode, int B, int U, int n_sc,
+               int K, const precode_params *params, void *x, float *beta,
+               int *status, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * FD precoding of a frame (Sec. III-C).  Per subcarrier and cluster c, with
+ * rho_c^2 = power / C and kappa_c = tau C kappa (eq. regularization):
+ *     B_c >= U:  A_c = H_c^H H_c + kappa_c I_U,   x_c = w_c H_c A_c^-1 s
+ *     B_c <  U:  M_c = H_c H_c^H + kappa_c I_B_c, x_c = w_c M_c^-1 H_c s
+ *     w_c = sqrt(rho_c^2 / (t_c Es)),  t_c = tr(Q_c^H Q_c)
+ *         = tr X^-1 - kappa_c ||X^-1||_F^2   (X = A_c or M_c).
+ * weights: device [n_sc][C] float or NULL.  status: device [n_sc][C] or NULL.
+ * Limits as for precode_pd.
+ * ------------------------------------------------------------------------- */
+int precode_fd(precode_ctx *ctx, const void *H, const void *s, float rho,
+               const int *cluster_sizes, int C, int mode, int B, int U, int n_sc,
+               int K, const precode_params *params, void *x, float *weights,
+               int *status, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Frame / symbol split (the channel is constant over a frame and A^-1, beta
+ * are reused across its symbols, Sec. IV-B).  frame_prepare runs the
+ * per-frame part (Gram, factorization, beta / weights) once and keeps the
+ * result resident in context memory (counted against the budget);
+ * frame_symbols precodes nk symbols s[nk][n_sc][U] -> x[nk][n_sc][B] with it.
+ * H must stay valid and unchanged until frame_release (it is read by
+ * frame_symbols).  arch: enum precode_arch.  The frame handle is owned by
+ * the context and freed by frame_release or ctx_destroy.
+ * ------------------------------------------------------------------------- */
+int precode_frame_prepare(precode_ctx *ctx, int arch, const void *H, float rho,
+                          const int *cluster_sizes, int C, int mode, int B, int U,
+                          int n_sc, const precode_params *params,
+                          precode_frame **out, void *stream);
+int precode_frame_symbols(precode_ctx *ctx, precode_frame *frame, const void *s,
+                          int nk, void *x, void *stream);
+/* Copies the frame's beta (PD, [n_sc]) or weights (FD, [n_sc][C]) and status
+ * into caller device buffers (either may be NULL). */
+int precode_frame_factors(precode_ctx *ctx, precode_frame *frame, float *scale,
+                          int *status, void *stream);
+int precode_frame_release(precode_ctx *ctx, precode_frame *frame);
+
+/* ---------------------------------------------------------------------------
+ * Heterogeneous batch: n_jobs independent frames (cells with different
+ * B, C, U, n_sc, K, mode, regularizer) precoded by ONE persistent fused
+ * launch.  Every job is described by one precode_job; pointers are device
+ * pointers with the layouts above.  Jobs must use PRECODE_PREC_FP32 or
+ * SPLIT precision and shapes the fused kernel supports (U <= 32).
+ * ------------------------------------------------------------------------- */
+typedef struct precode_job {
+    int arch;                 /* enum precode_arch                         */
+    int mode;                 /* enum precode_mode                         */
+    int B, U, n_sc, K, C;
+    const int *cluster_sizes; /* HOST array of C ints                      */
+    float rho;                /* kappa                                     */
+    float power, Es, tau;     /* as in precode_params                      */
+    const void *H;
+    const void *s;
+    void *x;
+    float *scale;             /* beta [n_sc] (PD) / weights [n_sc][C] (FD) or NULL */
+    int *status;              /* [n_sc] (PD) / [n_sc][C] (FD) or NULL      */
+} precode_job;
+
+int precode_batch(precode_ctx *ctx, const precode_job *jobs, int n_jobs,
+                  int precision, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PRECODE_H */

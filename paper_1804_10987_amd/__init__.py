@@ -1,0 +1,239 @@
+"""MI355X-native batched decentralized precoding (PD / FD Wiener-filter and ZF).
+
+Thin Python binding over the C ABI of ``libprecode.so`` (include/precode.h).
+PyTorch provides device memory and streams only; every step of the method
+runs in the library's HIP kernels.  There is no CPU fallback: if the library
+is not built, importing the binding's entry points raises.
+
+Tensors: H [n_sc, B, U], s [K, n_sc, U], x [K, n_sc, B], all complex64 on the
+GPU, contiguous.  ``rho`` is the WF regularizer kappa = U N0 / rho^2 of
+Theorem 1 (ignored for ZF).
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+from . import _lib
+from ._lib import (ARCH_FD, ARCH_PD, IMPL_AUTO, IMPL_FUSED, IMPL_PLAIN, PREC_FP32, PREC_FP64,  # noqa: F401
+                   PREC_SPLIT_BF16, PREC_SPLIT_FP16, ST_FAIL, ST_FP64, ST_OK, WF, ZF, PrecodeError)
+
+__all__ = ["Context", "Frame", "pd", "fd", "params", "default_context"]
+
+_PREC = {"fp32": PREC_FP32, "split_fp16": PREC_SPLIT_FP16, "split_bf16": PREC_SPLIT_BF16, "fp64": PREC_FP64}
+_IMPL = {"auto": IMPL_AUTO, "fused": IMPL_FUSED, "plain": IMPL_PLAIN}
+
+
+def params(power: float = 1.0, Es: float = 1.0, tau: float = 0.125, precision="fp32", refine_steps: int = 0,
+           fp64_ratio: float = 0.5, impl="auto") -> _lib.Params:
+    p = _lib.Params()
+    _lib.load().precode_params_init(ctypes.byref(p))
+    p.power, p.Es, p.tau = power, Es, tau
+    p.precision = _PREC[precision] if isinstance(precision, str) else int(precision)
+    p.refine_steps = refine_steps
+    p.fp64_ratio = fp64_ratio
+    p.impl = _IMPL[impl] if isinstance(impl, str) else int(impl)
+    return p
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _sizes(sizes: Sequence[int]):
+    arr = (ctypes.c_int * len(sizes))(*[int(v) for v in sizes])
+    return arr, len(sizes)
+
+
+def _mode(mode) -> int:
+    if isinstance(mode, str):
+        return {"zf": ZF, "wf": WF}[mode.lower()]
+    return int(mode)
+
+
+def _check_tensor(t, name, shape):
+    torch = _torch()
+    if t.dtype != torch.complex64 or not t.is_cuda or not t.is_contiguous():
+        raise ValueError("%s must be a contiguous complex64 CUDA tensor" % name)
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError("%s has shape %s, expected %s" % (name, tuple(t.shape), tuple(shape)))
+
+
+class Frame:
+    """Resident per-frame state (factorization, beta / weights) of one cell."""
+
+    def __init__(self, ctx: "Context", handle: int, arch: int, H, n_sc: int, B: int, U: int, C: int):
+        self.ctx, self.handle, self.arch, self.H = ctx, handle, arch, H
+        self.n_sc, self.B, self.U, self.C = n_sc, B, U, C
+
+    def symbols(self, s, x=None, stream=None):
+        torch = _torch()
+        nk = s.shape[0]
+        _check_tensor(s, "s", (nk, self.n_sc, self.U))
+        if x is None:
+            x = torch.empty((nk, self.n_sc, self.B), dtype=torch.complex64, device=s.device)
+        _lib.check(_lib.load().precode_frame_symbols(self.ctx.handle, self.handle, _ptr(s), nk, _ptr(x),
+                                                     _stream(stream)), "precode_frame_symbols")
+        return x
+
+    def factors(self, stream=None):
+        torch = _torch()
+        n = self.n_sc if self.arch == ARCH_PD else self.n_sc * self.C
+        scale = torch.empty(n, dtype=torch.float32, device=self.H.device)
+        status = torch.empty(n, dtype=torch.int32, device=self.H.device)
+        _lib.check(_lib.load().precode_frame_factors(self.ctx.handle, self.handle, _ptr(scale), _ptr(status),
+                                                     _stream(stream)), "precode_frame_factors")
+        if self.arch == ARCH_FD:
+            scale, status = scale.view(self.n_sc, self.C), status.view(self.n_sc, self.C)
+        return scale, status
+
+    def release(self):
+        if self.handle:
+            _lib.check(_lib.load().precode_frame_release(self.ctx.handle, self.handle), "precode_frame_release")
+            self.handle = None
+
+
+class Context:
+    """A library context on one device (workspace under an HBM budget)."""
+
+    def __init__(self, device: int = 0, budget_bytes: int = 0):
+        lib = _lib.load()
+        h = ctypes.c_void_p()
+        _lib.check(lib.precode_ctx_create(int(device), int(budget_bytes), ctypes.byref(h)), "precode_ctx_create")
+        self.handle = h.value
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            _lib.load().precode_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def bytes_held(self) -> int:
+        return _lib.load().precode_ctx_bytes(self.handle)
+
+    @property
+    def last_impl(self) -> str:
+        return {0: "none", IMPL_FUSED: "fused", IMPL_PLAIN: "plain"}[_lib.load().precode_ctx_last_impl(self.handle)]
+
+    def _run(self, arch, H, s, rho, sizes, mode, prm, x, scale, status, stream):
+        torch = _torch()
+        n_sc, B, U = H.shape
+        K = s.shape[0]
+        _check_tensor(H, "H", (n_sc, B, U))
+        _check_tensor(s, "s", (K, n_sc, U))
+        C = len(sizes)
+        if x is None:
+            x = torch.empty((K, n_sc, B), dtype=torch.complex64, device=H.device)
+        _check_tensor(x, "x", (K, n_sc, B))
+        n_scale = n_sc if arch == ARCH_PD else n_sc * C
+        if scale is None:
+            scale = torch.empty(n_scale, dtype=torch.float32, device=H.device)
+        if status is None:
+            status = torch.empty(n_scale, dtype=torch.int32, device=H.device)
+        arr, C = _sizes(sizes)
+        prm = prm if prm is not None else params()
+        fn = _lib.load().precode_pd if arch == ARCH_PD else _lib.load().precode_fd
+        _lib.check(fn(self.handle, _ptr(H), _ptr(s), float(rho), arr, C, _mode(mode), B, U, n_sc, K,
+                      ctypes.byref(prm), _ptr(x), _ptr(scale), _ptr(status), _stream(stream)),
+                   "precode_pd" if arch == ARCH_PD else "precode_fd")
+        if arch == ARCH_FD:
+            scale, status = scale.view(n_sc, C), status.view(n_sc, C)
+        return x, scale, status
+
+    def pd(self, H, s, rho, sizes, mode="wf", prm=None, x=None, beta=None, status=None, stream=None):
+        """PD precoding (Sec. III-B).  Returns (x, beta [n_sc], status [n_sc])."""
+        return self._run(ARCH_PD, H, s, rho, sizes, mode, prm, x, beta, status, stream)
+
+    def fd(self, H, s, rho, sizes, mode="wf", prm=None, x=None, weights=None, status=None, stream=None):
+        """FD precoding (Sec. III-C).  Returns (x, weights [n_sc, C], status [n_sc, C])."""
+        return self._run(ARCH_FD, H, s, rho, sizes, mode, prm, x, weights, status, stream)
+
+    def frame(self, arch, H, rho, sizes, mode="wf", prm=None, stream=None) -> Frame:
+        """Per-frame part (Gram, factorization, beta / weights) kept resident."""
+        n_sc, B, U = H.shape
+        _check_tensor(H, "H", (n_sc, B, U))
+        arr, C = _sizes(sizes)
+        prm = prm if prm is not None else params()
+        arch = {"pd": ARCH_PD, "fd": ARCH_FD}.get(arch, arch)
+        h = ctypes.c_void_p()
+        _lib.check(_lib.load().precode_frame_prepare(self.handle, arch, _ptr(H), float(rho), arr, C, _mode(mode),
+                                                     B, U, n_sc, ctypes.byref(prm), ctypes.byref(h),
+                                                     _stream(stream)), "precode_frame_prepare")
+        return Frame(self, h.value, arch, H, n_sc, B, U, C)
+
+    def batch(self, jobs, precision="fp32", stream=None):
+        """Heterogeneous batch: jobs is a list of dicts with keys arch, mode,
+        H, s, rho, sizes and optional x, scale, status, power, Es, tau.
+        Outputs are allocated when absent; returns the list of (x, scale, status)."""
+        torch = _torch()
+        arr = (_lib.Job * len(jobs))()
+        keep = []
+        outs = []
+        for i, j in enumerate(jobs):
+            H, s = j["H"], j["s"]
+            n_sc, B, U = H.shape
+            K = s.shape[0]
+            arch = {"pd": ARCH_PD, "fd": ARCH_FD}.get(j.get("arch", "pd"), j.get("arch", "pd"))
+            sizes = list(j["sizes"])
+            C = len(sizes)
+            x = j.get("x") or torch.empty((K, n_sc, B), dtype=torch.complex64, device=H.device)
+            ns = n_sc if arch == ARCH_PD else n_sc * C
+            sc = j.get("scale") or torch.empty(ns, dtype=torch.float32, device=H.device)
+            st = j.get("status") or torch.empty(ns, dtype=torch.int32, device=H.device)
+            sz = (ctypes.c_int * C)(*sizes)
+            keep.append(sz)
+            a = arr[i]
+            a.arch, a.mode, a.B, a.U, a.n_sc, a.K, a.C = arch, _mode(j.get("mode", "wf")), B, U, n_sc, K, C
+            a.cluster_sizes = ctypes.cast(sz, ctypes.POINTER(ctypes.c_int))
+            a.rho = float(j["rho"])
+            a.power, a.Es, a.tau = float(j.get("power", 1.0)), float(j.get("Es", 1.0)), float(j.get("tau", 0.125))
+            a.H, a.s, a.x, a.scale, a.status = _ptr(H), _ptr(s), _ptr(x), _ptr(sc), _ptr(st)
+            outs.append((x, sc, st))
+        prec = _PREC[precision] if isinstance(precision, str) else int(precision)
+        _lib.check(_lib.load().precode_batch(self.handle, arr, len(jobs), prec, _stream(stream)), "precode_batch")
+        return outs
+
+
+_default = {}
+
+
+def default_context(device: int = 0) -> Context:
+    if device not in _default:
+        _default[device] = Context(device)
+    return _default[device]
+
+
+def pd(H, s, rho, sizes, mode="wf", **kw):
+    """PD precoding with the device's default context.  See Context.pd."""
+    prm = kw.pop("prm", None)
+    if prm is None and kw:
+        prm = params(**{k: kw.pop(k) for k in list(kw) if k in params.__code__.co_varnames})
+    return default_context(H.device.index or 0).pd(H, s, rho, sizes, mode, prm, **kw)
+
+
+def fd(H, s, rho, sizes, mode="wf", **kw):
+    """FD precoding with the device's default context.  See Context.fd."""
+    prm = kw.pop("prm", None)
+    if prm is None and kw:
+        prm = params(**{k: kw.pop(k) for k in list(kw) if k in params.__code__.co_varnames})
+    return default_context(H.device.index or 0).fd(H, s, rho, sizes, mode, prm, **kw)

@@ -1,0 +1,363 @@
+// api.hip -- the C ABI declared in include/precode.h: argument validation,
+// context workspace under an HBM budget, dispatch between the fused and the
+// plain kernels, the frame/symbol split and the heterogeneous batch call.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "common.h"
+
+using namespace pc;
+
+struct precode_frame {
+    Prob prob;
+    const float2 *H;
+    void *ainv;     // plain-layout A^-1 (complex<T> slots)
+    void *scale;    // plain-layout scale (T)
+    float *scale_out;
+    int *status;
+    size_t bytes;
+    precode_frame *next;
+};
+
+struct precode_ctx {
+    int device;
+    size_t budget;
+    size_t held;
+    // plain-kernel workspace (grow-only)
+    void *wsA, *wsAinv, *wsScale, *wsZ;
+    size_t capA, capAinv, capScale, capZ;
+    precode_frame *frames;
+    int last_impl;
+};
+
+namespace {
+
+int dev_err(hipError_t e) { return e == hipSuccess ? PRECODE_OK : PRECODE_EDEVICE; }
+
+bool aligned8(const void *p) { return ((uintptr_t)p & 7u) == 0; }
+
+bool finite_nonneg(float v) { return isfinite(v) && v >= 0.f; }
+
+int ctx_alloc(precode_ctx *ctx, void **ptr, size_t bytes) {
+    if (ctx->budget && ctx->held + bytes > ctx->budget) return PRECODE_ENOMEM;
+    int cur = -1;
+    (void)hipGetDevice(&cur);
+    if (cur != ctx->device) (void)hipSetDevice(ctx->device);
+    hipError_t e = hipMalloc(ptr, bytes ? bytes : 1);
+    if (cur >= 0 && cur != ctx->device) (void)hipSetDevice(cur);
+    if (e != hipSuccess) {
+        *ptr = nullptr;
+        (void)hipGetLastError();
+        return e == hipErrorOutOfMemory ? PRECODE_ENOMEM : PRECODE_EDEVICE;
+    }
+    ctx->held += bytes;
+    return PRECODE_OK;
+}
+
+void ctx_free(precode_ctx *ctx, void *ptr, size_t bytes) {
+    if (!ptr) return;
+    (void)hipFree(ptr);
+    ctx->held -= bytes;
+}
+
+// Grow a workspace buffer to at least `need` bytes.  The caller's stream may
+// still be using the old buffer, so the device is synchronized before a free.
+int grow(precode_ctx *ctx, void **buf, size_t *cap, size_t need) {
+    if (*cap >= need) return PRECODE_OK;
+    if (*buf) {
+        (void)hipDeviceSynchronize();
+        ctx_free(ctx, *buf, *cap);
+        *buf = nullptr;
+        *cap = 0;
+    }
+    int rc = ctx_alloc(ctx, buf, need);
+    if (rc == PRECODE_OK) *cap = need;
+    return rc;
+}
+
+precode_params defaults() {
+    precode_params d;
+    d.power = 1.f;
+    d.Es = 1.f;
+    d.tau = 0.125f;
+    d.precision = PRECODE_PREC_FP32;
+    d.refine_steps = 0;
+    d.fp64_ratio = 0.5f;
+    d.impl = PRECODE_IMPL_AUTO;
+    return d;
+}
+
+int check_params(const precode_params &q) {
+    if (!(isfinite(q.power) && q.power > 0.f)) return PRECODE_EINVAL;
+    if (!(isfinite(q.Es) && q.Es > 0.f)) return PRECODE_EINVAL;
+    if (!finite_nonneg(q.tau)) return PRECODE_EINVAL;
+    if (q.precision < PRECODE_PREC_FP32 || q.precision > PRECODE_PREC_FP64) return PRECODE_EINVAL;
+    if (q.refine_steps < 0 || q.refine_steps > 1) return PRECODE_EINVAL;
+    if (!isfinite(q.fp64_ratio)) return PRECODE_EINVAL;
+    if (q.impl < PRECODE_IMPL_AUTO || q.impl > PRECODE_IMPL_PLAIN) return PRECODE_EINVAL;
+    return PRECODE_OK;
+}
+
+// Validates a call and fills the kernel problem description.
+int make_prob(int arch, float rho, const int *sizes, int C, int mode, int B, int U, int n_sc, int K,
+              const precode_params &q, Prob *out) {
+    if (arch != kPD && arch != kFD) return PRECODE_EINVAL;
+    if (mode != PRECODE_ZF && mode != PRECODE_WF) return PRECODE_EINVAL;
+    if (U < 1 || B < 1 || n_sc < 0 || K < 0 || C < 1) return PRECODE_EINVAL;
+    if (!sizes) return PRECODE_EINVAL;
+    if (C > B) return PRECODE_EINVAL;
+    if (U > kMaxU || B > kMaxB || K > kMaxK || C > kMaxC) return PRECODE_EUNSUPPORTED;
+    if (mode == PRECODE_WF && !finite_nonneg(rho)) return PRECODE_EINVAL;
+    int rc = check_params(q);
+    if (rc) return rc;
+    Prob &p = *out;
+    memset(&p, 0, sizeof(p));
+    p.arch = arch;
+    p.zf = mode == PRECODE_ZF;
+    p.B = B;
+    p.U = U;
+    p.n_sc = n_sc;
+    p.K = K;
+    p.C = C;
+    p.kappa = p.zf ? 0.f : rho;
+    p.power = q.power;
+    p.Es = q.Es;
+    p.tau = q.tau;
+    long sum = 0;
+    p.off[0] = 0;
+    for (int c = 0; c < C; ++c) {
+        if (sizes[c] < 1) return PRECODE_EINVAL;
+        sum += sizes[c];
+        if (sum > B) return PRECODE_EINVAL;
+        p.off[c + 1] = (int)sum;
+    }
+    if (sum != B) return PRECODE_EINVAL;
+    const bool all64 = q.precision == PRECODE_PREC_FP64;
+    p.pd_fp64 = all64 || (double)U / (double)B >= (double)q.fp64_ratio;
+    for (int c = 0; c < C; ++c)
+        p.fp64[c] = all64 || (double)U / (double)sizes[c] >= (double)q.fp64_ratio;
+    return PRECODE_OK;
+}
+
+int run(precode_ctx *ctx, int arch, const void *H, const void *s, float rho, const int *sizes, int C, int mode,
+        int B, int U, int n_sc, int K, const precode_params *params, void *x, float *scale, int *status,
+        void *stream) {
+    if (!ctx) return PRECODE_EINVAL;
+    const precode_params q = params ? *params : defaults();
+    Prob p;
+    int rc = make_prob(arch, rho, sizes, C, mode, B, U, n_sc, K, q, &p);
+    if (rc) return rc;
+    if (n_sc == 0) return PRECODE_OK;
+    if (!H || (K > 0 && (!s || !x))) return PRECODE_EINVAL;
+    if (!aligned8(H) || !aligned8(s) || !aligned8(x)) return PRECODE_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    const bool can_fuse = K > 0 && q.refine_steps == 0 && fused_supported(p, q.precision);
+    if (q.impl == PRECODE_IMPL_FUSED && !can_fuse) return PRECODE_EUNSUPPORTED;
+    if (q.precision == PRECODE_PREC_SPLIT_FP16 || q.precision == PRECODE_PREC_SPLIT_BF16) {
+        if (!can_fuse) return PRECODE_EUNSUPPORTED;
+    }
+    if (q.impl != PRECODE_IMPL_PLAIN && can_fuse) {
+        rc = dev_err(fused_run(p, q.precision, (const float2 *)H, (const float2 *)s, (float2 *)x, scale, status, st));
+        if (rc == PRECODE_OK) ctx->last_impl = PRECODE_IMPL_FUSED;
+        return rc;
+    }
+    rc = grow(ctx, &ctx->wsA, &ctx->capA, plain_ws_bytes_A(p));
+    if (!rc) rc = grow(ctx, &ctx->wsAinv, &ctx->capAinv, plain_ws_bytes_A(p));
+    if (!rc) rc = grow(ctx, &ctx->wsScale, &ctx->capScale, plain_ws_bytes_scale(p));
+    if (!rc) rc = grow(ctx, &ctx->wsZ, &ctx->capZ, plain_ws_bytes_z(p, K > 0 ? K : 1));
+    if (rc) return rc;
+    rc = dev_err(plain_prepare(p, (const float2 *)H, scale, status, ctx->wsA, ctx->wsAinv, ctx->wsScale, st));
+    if (rc) return rc;
+    if (K > 0)
+        rc = dev_err(plain_symbols(p, K, (const float2 *)H, (const float2 *)s, (float2 *)x, ctx->wsAinv,
+                                   ctx->wsScale, ctx->wsZ, st));
+    if (rc == PRECODE_OK) ctx->last_impl = PRECODE_IMPL_PLAIN;
+    return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+void precode_params_init(precode_params *p) {
+    if (p) *p = defaults();
+}
+
+const char *precode_strerror(int code) {
+    switch (code) {
+        case PRECODE_OK: return "ok";
+        case PRECODE_EINVAL: return "invalid argument";
+        case PRECODE_EUNSUPPORTED: return "unsupported shape or option";
+        case PRECODE_ENOMEM: return "out of device memory or over the context budget";
+        case PRECODE_EDEVICE: return "HIP runtime error";
+        default: return "unknown error";
+    }
+}
+
+int precode_ctx_create(int device, size_t hbm_budget_bytes, precode_ctx **out) {
+    if (!out) return PRECODE_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess) {
+        (void)hipGetLastError();
+        return PRECODE_EDEVICE;
+    }
+    if (device < 0 || device >= ndev) return PRECODE_EINVAL;
+    precode_ctx *c = new (std::nothrow) precode_ctx;
+    if (!c) return PRECODE_ENOMEM;
+    memset(c, 0, sizeof(*c));
+    c->device = device;
+    c->budget = hbm_budget_bytes;
+    *out = c;
+    return PRECODE_OK;
+}
+
+int precode_ctx_destroy(precode_ctx *ctx) {
+    if (!ctx) return PRECODE_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    while (ctx->frames) {
+        precode_frame *f = ctx->frames;
+        ctx->frames = f->next;
+        ctx_free(ctx, f->ainv, f->bytes);
+        delete f;
+    }
+    ctx_free(ctx, ctx->wsA, ctx->capA);
+    ctx_free(ctx, ctx->wsAinv, ctx->capAinv);
+    ctx_free(ctx, ctx->wsScale, ctx->capScale);
+    ctx_free(ctx, ctx->wsZ, ctx->capZ);
+    delete ctx;
+    return PRECODE_OK;
+}
+
+int precode_validate(int arch, float rho, const int *cluster_sizes, int C, int mode, int B, int U, int n_sc, int K,
+                     const precode_params *params) {
+    const precode_params q = params ? *params : defaults();
+    Prob p;
+    return make_prob(arch, rho, cluster_sizes, C, mode, B, U, n_sc, K, q, &p);
+}
+
+size_t precode_ctx_bytes(const precode_ctx *ctx) { return ctx ? ctx->held : 0; }
+
+int precode_ctx_last_impl(const precode_ctx *ctx) { return ctx ? ctx->last_impl : 0; }
+
+int precode_pd(precode_ctx *ctx, const void *H, const void *s, float rho, const int *cluster_sizes, int C, int mode,
+               int B, int U, int n_sc, int K, const precode_params *params, void *x, float *beta, int *status,
+               void *stream) {
+    return run(ctx, kPD, H, s, rho, cluster_sizes, C, mode, B, U, n_sc, K, params, x, beta, status, stream);
+}
+
+int precode_fd(precode_ctx *ctx, const void *H, const void *s, float rho, const int *cluster_sizes, int C, int mode,
+               int B, int U, int n_sc, int K, const precode_params *params, void *x, float *weights, int *status,
+               void *stream) {
+    return run(ctx, kFD, H, s, rho, cluster_sizes, C, mode, B, U, n_sc, K, params, x, weights, status, stream);
+}
+
+int precode_frame_prepare(precode_ctx *ctx, int arch, const void *H, float rho, const int *cluster_sizes, int C,
+                          int mode, int B, int U, int n_sc, const precode_params *params, precode_frame **out,
+                          void *stream) {
+    if (!ctx || !out) return PRECODE_EINVAL;
+    *out = nullptr;
+    const precode_params q = params ? *params : defaults();
+    Prob p;
+    int rc = make_prob(arch, rho, cluster_sizes, C, mode, B, U, n_sc, 1, q, &p);
+    if (rc) return rc;
+    if (n_sc > 0 && (!H || !aligned8(H))) return PRECODE_EINVAL;
+    if (q.precision == PRECODE_PREC_SPLIT_FP16 || q.precision == PRECODE_PREC_SPLIT_BF16) return PRECODE_EUNSUPPORTED;
+    // resident state: A^-1 slots, scale, beta/weights, status, plus the
+    // Gram workspace while preparing
+    const size_t ni = (size_t)n_inst(p);
+    const size_t bA = plain_ws_bytes_A(p), bS = plain_ws_bytes_scale(p);
+    const size_t bytes = bA + bS + ni * sizeof(float) + ni * sizeof(int) + 64;
+    precode_frame *f = new (std::nothrow) precode_frame;
+    if (!f) return PRECODE_ENOMEM;
+    memset(f, 0, sizeof(*f));
+    rc = ctx_alloc(ctx, &f->ainv, bytes);
+    if (rc) {
+        delete f;
+        return rc;
+    }
+    f->bytes = bytes;
+    f->prob = p;
+    f->H = (const float2 *)H;
+    f->scale = (char *)f->ainv + bA;
+    f->scale_out = (float *)((char *)f->scale + bS);
+    f->status = (int *)((char *)f->scale_out + ((ni * sizeof(float) + 7) & ~(size_t)7));
+    rc = grow(ctx, &ctx->wsA, &ctx->capA, bA);
+    if (!rc && n_sc > 0)
+        rc = dev_err(plain_prepare(p, (const float2 *)H, f->scale_out, f->status, ctx->wsA, f->ainv, f->scale,
+                                   (hipStream_t)stream));
+    if (rc) {
+        ctx_free(ctx, f->ainv, f->bytes);
+        delete f;
+        return rc;
+    }
+    f->next = ctx->frames;
+    ctx->frames = f;
+    *out = f;
+    return PRECODE_OK;
+}
+
+int precode_frame_symbols(precode_ctx *ctx, precode_frame *f, const void *s, int nk, void *x, void *stream) {
+    if (!ctx || !f) return PRECODE_EINVAL;
+    if (nk < 0) return PRECODE_EINVAL;
+    if (nk > kMaxK) return PRECODE_EUNSUPPORTED;
+    if (nk == 0 || f->prob.n_sc == 0) return PRECODE_OK;
+    if (!s || !x || !aligned8(s) || !aligned8(x)) return PRECODE_EINVAL;
+    Prob p = f->prob;
+    p.K = nk;
+    int rc = grow(ctx, &ctx->wsZ, &ctx->capZ, plain_ws_bytes_z(p, nk));
+    if (rc) return rc;
+    return dev_err(plain_symbols(p, nk, f->H, (const float2 *)s, (float2 *)x, f->ainv, f->scale, ctx->wsZ,
+                                 (hipStream_t)stream));
+}
+
+int precode_frame_factors(precode_ctx *ctx, precode_frame *f, float *scale, int *status, void *stream) {
+    if (!ctx || !f) return PRECODE_EINVAL;
+    const size_t ni = (size_t)n_inst(f->prob);
+    hipStream_t st = (hipStream_t)stream;
+    if (ni == 0) return PRECODE_OK;
+    hipError_t e = hipSuccess;
+    if (scale) e = hipMemcpyAsync(scale, f->scale_out, ni * sizeof(float), hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess && status) e = hipMemcpyAsync(status, f->status, ni * sizeof(int), hipMemcpyDeviceToDevice, st);
+    return dev_err(e);
+}
+
+int precode_frame_release(precode_ctx *ctx, precode_frame *f) {
+    if (!ctx || !f) return PRECODE_EINVAL;
+    precode_frame **pp = &ctx->frames;
+    while (*pp && *pp != f) pp = &(*pp)->next;
+    if (!*pp) return PRECODE_EINVAL;
+    *pp = f->next;
+    // work enqueued on any stream may still read the frame's state
+    (void)hipDeviceSynchronize();
+    ctx_free(ctx, f->ainv, f->bytes);
+    delete f;
+    return PRECODE_OK;
+}
+
+int precode_batch(precode_ctx *ctx, const precode_job *jobs, int n_jobs, int precision, void *stream) {
+    if (!ctx || n_jobs < 0 || (n_jobs > 0 && !jobs)) return PRECODE_EINVAL;
+    for (int i = 0; i < n_jobs; ++i) {
+        const precode_job &j = jobs[i];
+        precode_params q = defaults();
+        q.power = j.power;
+        q.Es = j.Es;
+        q.tau = j.tau;
+        q.precision = precision;
+        int rc = j.arch == PRECODE_ARCH_PD
+                     ? precode_pd(ctx, j.H, j.s, j.rho, j.cluster_sizes, j.C, j.mode, j.B, j.U, j.n_sc, j.K, &q,
+                                  j.x, j.scale, j.status, stream)
+                     : precode_fd(ctx, j.H, j.s, j.rho, j.cluster_sizes, j.C, j.mode, j.B, j.U, j.n_sc, j.K, &q,
+                                  j.x, j.scale, j.status, stream);
+        if (rc) return rc;
+    }
+    return PRECODE_OK;
+}
+
+}  // extern "C"

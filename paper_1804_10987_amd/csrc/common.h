@@ -1,0 +1,96 @@
+// common.h -- shared device/host definitions of the precoding library.
+//
+// Layouts follow include/precode.h: H[n_sc][B][U], s[K][n_sc][U],
+// x[K][n_sc][B], complex64 interleaved.  An "instance" is one small linear
+// system: a subcarrier for PD (Sec. III-B), a (subcarrier, cluster) pair for
+// FD (Sec. III-C).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "precode.h"
+
+namespace pc {
+
+constexpr int kMaxC = 256;   // clusters per cell
+constexpr int kMaxU = 64;    // users
+constexpr int kMaxB = 4096;  // antennas
+constexpr int kMaxK = 4096;  // symbols per call
+
+enum Arch { kPD = 0, kFD = 1 };
+
+// Per-call problem description, passed to kernels by value.
+struct Prob {
+    int arch;       // kPD / kFD
+    int zf;         // 1: kappa = 0
+    int B, U, n_sc, K, C;
+    float kappa;    // Theorem-1 regularizer (PD) / base regularizer (FD)
+    float power;    // rho^2
+    float Es;
+    float tau;      // FD tau_c
+    int off[kMaxC + 1];          // cluster row offsets, off[C] = B
+    unsigned char fp64[kMaxC];   // FD: cluster solved on the FP64 route
+    int pd_fp64;                 // PD: every subcarrier on the FP64 route
+};
+
+__host__ __device__ inline int n_inst(const Prob &p) { return p.arch == kPD ? p.n_sc : p.n_sc * p.C; }
+
+// Regularizer of the local system of cluster c (FD, eq. regularization):
+// kappa_c = tau_c U N0 / rho_c^2 = tau_c C kappa with rho_c^2 = rho^2 / C.
+__host__ __device__ inline float fd_kappa(const Prob &p) { return p.zf ? 0.f : p.tau * (float)p.C * p.kappa; }
+__host__ __device__ inline float pd_kappa(const Prob &p) { return p.zf ? 0.f : p.kappa; }
+
+template <typename T>
+struct cx {
+    T re, im;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// a * conj(b)
+template <typename T>
+__device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {
+    return {a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im};
+}
+// conj(a) * b
+template <typename T>
+__device__ __forceinline__ cx<T> ccmul(cx<T> a, cx<T> b) {
+    return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> cadd(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T>
+__device__ __forceinline__ cx<T> csub(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T>
+__device__ __forceinline__ cx<T> cscale(cx<T> a, T s) { return {a.re * s, a.im * s}; }
+template <typename T>
+__device__ __forceinline__ T cabs2(cx<T> a) { return a.re * a.re + a.im * a.im; }
+
+template <typename T>
+__device__ __forceinline__ cx<T> ld_c64(const float2 *p) {
+    float2 v = *p;
+    return {(T)v.x, (T)v.y};
+}
+
+__device__ __forceinline__ bool finite_f(double v) { return v == v && v - v == 0.0; }
+
+// Plain kernels (plain.hip).  Workspace: A and Ainv hold n_inst U x U
+// complex<double>-sized slots, scale n_inst doubles, z K * n_inst * U complex64.
+hipError_t plain_prepare(const Prob &p, const float2 *H, float *scale_out, int *status, void *ws_A,
+                         void *ws_Ainv, void *ws_scale, hipStream_t st);
+hipError_t plain_symbols(const Prob &p, int K, const float2 *H, const float2 *s, float2 *x, void *ws_Ainv,
+                         void *ws_scale, void *ws_z, hipStream_t st);
+size_t plain_ws_bytes_A(const Prob &p);
+size_t plain_ws_bytes_scale(const Prob &p);
+size_t plain_ws_bytes_z(const Prob &p, int K);
+
+// Fused single-launch kernel (fused.hip).  Returns hipErrorNotSupported if the
+// shape is outside what it handles.
+bool fused_supported(const Prob &p, int precision);
+hipError_t fused_run(const Prob &p, int precision, const float2 *H, const float2 *s, float2 *x,
+                     float *scale_out, int *status, hipStream_t st);
+
+}  // namespace pc

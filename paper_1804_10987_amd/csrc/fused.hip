@@ -1,0 +1,483 @@
+// fused.hip -- single-launch fused PD / FD precoding on gfx950.
+//
+// One 256-thread workgroup (4 wave64s) per subcarrier.  The channel of the
+// subcarrier (B x U complex64) and its K symbol vectors are staged once in
+// LDS; every step of the method then runs out of LDS:
+//
+//   Gram        G_c = H_c^H H_c on MFMA (v_mfma_f32_32x32x2f32) over the
+//               real embedding [Re h_u, Im h_u] of the columns: the 2U x 2U
+//               real Gram M gives G = (M_rr + M_ii) + i (M_ri - M_ir)
+//               (local Gram, Sec. III-B; PD sums the cluster Grams as a
+//               split-K reduction, the on-chip form of the adder tree)
+//   regularize  A = G + kappa I  (PD)  /  A_c = G_c + kappa_c I  (FD,
+//               kappa_c = tau_c C kappa, eq. regularization)
+//   Cholesky    A = L L^H, one wave per system, in LDS
+//   inverse     W = L^-1 (forward substitution), A^-1 = W^H W on MFMA
+//   factor      t = tr A^-1 - kappa ||A^-1||_F^2 (Lemma 1);
+//               PD beta = sqrt(Es/rho^2 t); FD w_c = sqrt(rho_c^2/(t Es))
+//   solve       Z = scale * A^-1 S for a chunk of 16 symbols, on MFMA
+//   precode     X_c = H_c Z on MFMA (the per-cluster product of Sec. III-B;
+//               FD x_c = w_c H_c A_c^-1 s, Sec. III-C), stored coalesced.
+//
+// PD: the four waves split the rows for the Gram, wave 0 factors, all four
+// waves precode.  FD: each wave owns whole clusters (c = wave, wave+4, ...)
+// and runs the full chain for them without workgroup barriers.
+#include "common.h"
+
+namespace pc {
+
+namespace {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+constexpr int kThreads = 256;
+constexpr int KC = 16;        // symbols per MFMA chunk: 2*KC = 32 rows of X^T
+constexpr int kMaxKFused = 64;
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+// Orders LDS accesses of one wave (a wave's LDS operations execute in order;
+// this keeps the compiler from moving them across the point).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ floatx16 mfma32(float a, float b, floatx16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+
+template <int UP>
+struct Shape {
+    static constexpr int NT = (2 * UP) / 32;        // 32-wide real column tiles
+    static constexpr int NTT = NT * (NT + 1) / 2;   // tiles with ti <= tj
+    static constexpr int RS = 2 * UP + 4;           // H row stride in LDS (floats)
+    static constexpr int LDc = UP + 2;              // slot leading dim (complex), rows 16B aligned
+    static constexpr int SLOT = UP * LDc;           // complex elements per slot
+};
+
+// Real Gram of `nrows` rows (row-major floats, stride rs): accumulates
+// M[32ti+i][32tj+j] = sum_r R[r][32ti+i] R[r][32tj+j] for ti <= tj.
+// v_mfma_f32_32x32x2f32 operands: lane l supplies A[l%32][l/32] and
+// B[l/32][l%32]; here both are R[row][col], so a lane loads one value per
+// column tile per two rows.
+template <int UP>
+__device__ __forceinline__ void mfma_gram(const float *rows, int rs, int nrows,
+                                          floatx16 (&acc)[Shape<UP>::NTT]) {
+    constexpr int NT = Shape<UP>::NT;
+    const int lane = lane_id();
+    const int j = lane & 31, g = lane >> 5;
+
+    for (int r = 0; r < nrows; r += 2) {
+        const int row = r + g;
+        float a[NT];
+#pragma unroll
+        for (int ti = 0; ti < NT; ++ti) a[ti] = row < nrows ? rows[row * rs + 32 * ti + j] : 0.f;
+        int t = 0;
+#pragma unroll
+        for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+            for (int tj = ti; tj < NT; ++tj) {
+                acc[t] = mfma32(a[ti], a[tj], acc[t]);
+                ++t;
+            }
+    }
+}
+
+// Turns the real Gram tiles into the complex U x U matrix in an LDS slot:
+// G[u][v] = (M[2u][2v] + M[2u+1][2v+1]) + i (M[2u][2v+1] - M[2u+1][2v]),
+// plus diag_add on the diagonal for u < m.  Output layout of the 32x32
+// MFMA: lane l, register r holds row 8(r/4) + 4(l/32) + r%4, column l%32.
+// The even-column lane of each pair combines its values with its partner's.
+// With stats, accumulates tr G (u < m) and ||G||_F^2 into *tr, *fro (per lane).
+template <int UP>
+__device__ __forceinline__ void gram_store(const floatx16 (&acc)[Shape<UP>::NTT], cx<float> *dst,
+                                           float diag_add, int m, float *tr, float *fro) {
+    constexpr int NT = Shape<UP>::NT;
+    constexpr int LDc = Shape<UP>::LDc;
+    const int lane = lane_id();
+    const int jj = lane & 31, g = lane >> 5;
+    const bool even = (jj & 1) == 0;
+    int t = 0;
+#pragma unroll
+    for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+        for (int tj = ti; tj < NT; ++tj) {
+#pragma unroll
+            for (int r = 0; r < 16; r += 2) {
+                const float own0 = acc[t][r], own1 = acc[t][r + 1];
+                const float par0 = __shfl_xor(own0, 1), par1 = __shfl_xor(own1, 1);
+                if (even) {
+                    const int i = 8 * (r / 4) + 4 * g + (r % 4);
+                    const int u = (32 * ti + i) >> 1, v = (32 * tj + jj) >> 1;
+                    float gre = own0 + par1;
+                    const float gim = par0 - own1;
+                    if (u == v && u < m) gre += diag_add;
+                    dst[u * LDc + v] = {gre, gim};
+                    if (ti != tj) dst[v * LDc + u] = {gre, -gim};
+                    if (tr) {
+                        const float w = (ti != tj) ? 2.f : 1.f;
+                        *fro += w * (gre * gre + gim * gim);
+                        if (u == v) *tr += gre;
+                    }
+                }
+            }
+            ++t;
+        }
+}
+
+// Per-lane A operands for X^T = Zbar^T Rows^T with X^T rows i = 2k + q
+// (symbol k, q = re/im) and contraction index kk = 2u + p over the real
+// columns of Rows.  The contraction is permuted so that lane half g covers
+// kk = g*UP .. g*UP+UP-1 (contiguous columns).  Zbar[2u+p][2k+q] is
+// (p,q)=(0,0): Re z, (1,0): -Im z, (0,1): Im z, (1,1): Re z.
+// Z(u, k) is read at Z[u*su + k*sk]; symbols k >= kvalid read as 0.
+template <int UP>
+__device__ __forceinline__ void load_zop(const cx<float> *Z, int su, int sk, int kvalid, float (&zop)[UP]) {
+    const int lane = lane_id();
+    const int i = lane & 31, g = lane >> 5;
+    const int k = i >> 1, q = i & 1;
+#pragma unroll
+    for (int mm = 0; mm < UP; mm += 2) {
+        const int u = (g * UP + mm) >> 1;
+        cx<float> z = {0.f, 0.f};
+        if (k < kvalid) z = Z[u * su + k * sk];
+        zop[mm] = q ? z.im : z.re;
+        zop[mm + 1] = q ? z.re : -z.im;
+    }
+}
+
+// X^T tile (32 x 32): rows (k, re/im) for a 16-symbol chunk, columns =
+// rows r0 .. r0+31 of `rows` (row-major floats, stride rs; rows >= nvalid
+// read as 0).  Lane l supplies B = Rows[l%32][g*UP + m] for instruction m.
+template <int UP>
+__device__ __forceinline__ floatx16 mfma_apply(const float *rows, int rs, int nvalid, const float (&zop)[UP]) {
+    const int lane = lane_id();
+    const int j = lane & 31, g = lane >> 5;
+    float h[UP];
+    const float *rp = rows + j * rs + g * UP;
+    if (j < nvalid) {
+#pragma unroll
+        for (int m4 = 0; m4 < UP; m4 += 4) {
+            const float4 v = *(const float4 *)(rp + m4);
+            h[m4] = v.x;
+            h[m4 + 1] = v.y;
+            h[m4 + 2] = v.z;
+            h[m4 + 3] = v.w;
+        }
+    } else {
+#pragma unroll
+        for (int m = 0; m < UP; ++m) h[m] = 0.f;
+    }
+    floatx16 acc = {0};
+#pragma unroll
+    for (int m = 0; m < UP; ++m) acc = mfma32(zop[m], h[m], acc);
+    return acc;
+}
+
+// Symbol index held by register pair (r, r+1) of an X^T tile.
+__device__ __forceinline__ int tile_k(int r, int g) { return 4 * (r / 4) + 2 * g + ((r % 4) >> 1); }
+
+// Right-looking Cholesky A = L L^H of the m x m system in an LDS slot (lower
+// triangle, in place), one wave.  Lane (i, ph): row i = lane / P, column
+// phase ph = lane % P.  Returns false on a pivot that is not positive/finite.
+template <int UP>
+__device__ bool wave_cholesky(cx<float> *A, int m) {
+    constexpr int LDc = Shape<UP>::LDc;
+    constexpr int P = 64 / UP;
+    const int lane = lane_id();
+    const int i = lane / P, ph = lane % P;
+    for (int k = 0; k < m; ++k) {
+        const float akk = A[k * LDc + k].re;
+        if (!(akk > 0.f) || !(akk < INFINITY)) return false;
+        const float d = sqrtf(akk), inv = 1.f / d;
+        if (ph == 0 && i > k && i < m) A[i * LDc + k] = cscale(A[i * LDc + k], inv);
+        if (ph == 0 && i == k) A[k * LDc + k] = {d, 0.f};
+        wave_sync();
+        if (i > k && i < m) {
+            const cx<float> lik = A[i * LDc + k];
+            for (int j = k + 1 + ph; j <= i; j += P) A[i * LDc + j] = csub(A[i * LDc + j], cmulc(lik, A[j * LDc + k]));
+        }
+        wave_sync();
+    }
+    return true;
+}
+
+// W = L^-1 (lower triangular) into a zeroed slot, row by row: after step p,
+// row p of W is final and rows r > p hold sum_{q<=p} L[r][q] W[q][j].
+template <int UP>
+__device__ void wave_tri_inverse(const cx<float> *L, cx<float> *W, int m) {
+    constexpr int LDc = Shape<UP>::LDc;
+    constexpr int P = 64 / UP;
+    const int lane = lane_id();
+    const int i = lane / P, ph = lane % P;
+    for (int p = 0; p < m; ++p) {
+        if (i == p) {
+            const float dinv = 1.f / L[p * LDc + p].re;
+            for (int j = ph; j <= p; j += P) {
+                const cx<float> w = W[p * LDc + j];
+                W[p * LDc + j] = {(((j == p) ? 1.f : 0.f) - w.re) * dinv, -w.im * dinv};
+            }
+        }
+        wave_sync();
+        if (i > p && i < m) {
+            const cx<float> lip = L[i * LDc + p];
+            for (int j = ph; j <= p; j += P) W[i * LDc + j] = cadd(W[i * LDc + j], cmul(lip, W[p * LDc + j]));
+        }
+        wave_sync();
+    }
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Factor one system held in slot A (A = G + kappa I, lower triangle valid):
+// on success slot A holds A^-1 (full), slot B is scratch, *t = Lemma-1 trace.
+template <int UP>
+__device__ bool wave_factor(cx<float> *sA, cx<float> *sB, int m, float kap, float *t_out) {
+    constexpr int NTT = Shape<UP>::NTT;
+    bool ok = wave_cholesky<UP>(sA, m);
+    float t = 0.f;
+    if (ok) {
+        wave_tri_inverse<UP>(sA, sB, m);
+        floatx16 acc[NTT];
+#pragma unroll
+        for (int q = 0; q < NTT; ++q) acc[q] = floatx16{0};
+        mfma_gram<UP>((const float *)sB, 2 * Shape<UP>::LDc, m, acc);  // A^-1 = W^H W
+        float tr = 0.f, fro = 0.f;
+        gram_store<UP>(acc, sA, 0.f, m, &tr, &fro);
+        tr = wave_sum(tr);
+        fro = wave_sum(fro);
+        t = tr - kap * fro;
+        ok = (t > 0.f) && (t < INFINITY);
+        wave_sync();
+    }
+    *t_out = t;
+    return ok;
+}
+
+// Z(u, k) = scale * (A^-1 S)(u, k) for one chunk into slot B as [UP][KC].
+template <int UP>
+__device__ void wave_solve_chunk(const cx<float> *sA, cx<float> *sB, const float *Ss, int k0, int kc, int m,
+                                 float scale, bool ok) {
+    const int lane = lane_id();
+    const int j = lane & 31, g = lane >> 5;
+    float zop[UP];
+    load_zop<UP>((const cx<float> *)Ss + k0 * UP, 1, UP, kc, zop);
+    const floatx16 a = mfma_apply<UP>((const float *)sA, 2 * Shape<UP>::LDc, m, zop);
+    if (j < UP) {
+#pragma unroll
+        for (int r = 0; r < 16; r += 2) {
+            const int k = tile_k(r, g);
+            if (k < KC) {
+                cx<float> z = {0.f, 0.f};
+                if (ok && k < kc) z = {a[r] * scale, a[r + 1] * scale};
+                sB[j * KC + k] = z;
+            }
+        }
+    }
+}
+
+// x rows [r0, r0 + nrows) of subcarrier n for chunk (k0, kc) from Z in slot zs.
+template <int UP>
+__device__ void wave_precode_rows(const float *Hs, const cx<float> *zs, int r0, int nrows, int k0, int kc,
+                                  int n, int n_sc, int B, float2 *__restrict__ x, int tile0, int tstep) {
+    constexpr int RS = Shape<UP>::RS;
+    const int lane = lane_id();
+    const int j = lane & 31, g = lane >> 5;
+    float zop[UP];
+    load_zop<UP>(zs, KC, 1, kc, zop);
+    for (int t = tile0; t * 32 < nrows; t += tstep) {
+        const int rb = r0 + t * 32;
+        const int nv = min(32, nrows - t * 32);
+        const floatx16 a = mfma_apply<UP>(Hs + rb * RS, RS, nv, zop);
+        if (j < nv) {
+#pragma unroll
+            for (int r = 0; r < 16; r += 2) {
+                const int k = tile_k(r, g);
+                if (k < kc) x[((size_t)(k0 + k) * n_sc + n) * B + rb + j] = make_float2(a[r], a[r + 1]);
+            }
+        }
+    }
+}
+
+template <int UP>
+__host__ __device__ constexpr size_t lds_bytes(int B, int K) {
+    return (size_t)B * Shape<UP>::RS * 4 + (size_t)K * 2 * UP * 4 + (size_t)8 * Shape<UP>::SLOT * 8;
+}
+
+template <int UP, int ARCH>
+__global__ void __launch_bounds__(kThreads) fused_k(Prob p, int K, const float2 *__restrict__ H,
+                                                    const float2 *__restrict__ s, float2 *__restrict__ x,
+                                                    float *__restrict__ scale_out, int *__restrict__ status) {
+    constexpr int RS = Shape<UP>::RS;
+    constexpr int SLOT = Shape<UP>::SLOT;
+    constexpr int NTT = Shape<UP>::NTT;
+    extern __shared__ float4 smem4[];
+    float *Hs = (float *)smem4;
+    float *Ss = Hs + (size_t)p.B * RS;
+    cx<float> *slots = (cx<float> *)(Ss + (size_t)K * 2 * UP);
+    __shared__ float sh_scale;
+    __shared__ int sh_ok;
+
+    const int B = p.B, U = p.U, n = blockIdx.x;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    cx<float> *sA = slots + (2 * wave) * SLOT;
+    cx<float> *sB = slots + (2 * wave + 1) * SLOT;
+
+    // ---- stage H[n] (zero-padded to UP users) and s[:, n] in LDS ----------
+    const float2 *Hn = H + (size_t)n * B * U;
+    for (int e = tid; e < B * UP; e += kThreads) {
+        const int b = e / UP, u = e % UP;
+        const float2 v = (u < U) ? Hn[(size_t)b * U + u] : make_float2(0.f, 0.f);
+        *(float2 *)(Hs + b * RS + 2 * u) = v;
+    }
+    for (int e = tid; e < K * UP; e += kThreads) {
+        const int k = e / UP, u = e % UP;
+        const float2 v = (u < U) ? s[((size_t)k * p.n_sc + n) * U + u] : make_float2(0.f, 0.f);
+        *(float2 *)(Ss + k * 2 * UP + 2 * u) = v;
+    }
+    for (int e = tid; e < 8 * SLOT; e += kThreads) slots[e] = {0.f, 0.f};
+    __syncthreads();
+
+    if (ARCH == kPD) {
+        const float kap = pd_kappa(p);
+        // split-K Gram: four contiguous, even-sized row ranges
+        const int rows_per = ((B + 7) / 8) * 2;
+        const int r0 = min(B, wave * rows_per), r1 = min(B, r0 + rows_per);
+        floatx16 acc[NTT];
+#pragma unroll
+        for (int q = 0; q < NTT; ++q) acc[q] = floatx16{0};
+        mfma_gram<UP>(Hs + r0 * RS, RS, r1 - r0, acc);
+        gram_store<UP>(acc, sA, 0.f, U, nullptr, nullptr);
+        __syncthreads();
+        // cluster (partial) sum in fixed order + kappa I, into wave 0's slot A
+        for (int e = tid; e < UP * UP; e += kThreads) {
+            const int u = e / UP, v = e % UP;
+            const int o = u * Shape<UP>::LDc + v;
+            cx<float> sum = slots[o];
+#pragma unroll
+            for (int w = 1; w < 4; ++w) sum = cadd(sum, slots[2 * w * SLOT + o]);
+            if (u == v && u < U) sum.re += kap;
+            slots[o] = sum;
+        }
+        __syncthreads();
+        if (wave == 0) {
+            float t = 0.f;
+            const bool ok = wave_factor<UP>(sA, sB, U, kap, &t);
+            const float beta = ok ? sqrtf(p.Es / p.power * t) : 0.f;
+            if (lane == 0) {
+                sh_scale = ok ? 1.f / beta : 0.f;
+                sh_ok = ok;
+                if (scale_out) scale_out[n] = beta;
+                if (status) status[n] = ok ? PRECODE_ST_OK : PRECODE_ST_FAIL;
+            }
+        }
+        __syncthreads();
+        const cx<float> *z0 = slots + SLOT;  // wave 0's slot B
+        for (int k0 = 0; k0 < K; k0 += KC) {
+            const int kc = min(KC, K - k0);
+            if (wave == 0) wave_solve_chunk<UP>(sA, sB, Ss, k0, kc, U, sh_scale, sh_ok != 0);
+            __syncthreads();
+            wave_precode_rows<UP>(Hs, z0, 0, B, k0, kc, n, p.n_sc, B, x, wave, 4);
+            __syncthreads();
+        }
+    } else {
+        const float kap = fd_kappa(p);
+        const float rho_c2 = p.power / (float)p.C;
+        for (int c = wave; c < p.C; c += 4) {
+            const int o = p.off[c], Bc = p.off[c + 1] - o;
+            for (int e = lane; e < SLOT; e += 64) {
+                sA[e] = {0.f, 0.f};
+                sB[e] = {0.f, 0.f};
+            }
+            wave_sync();
+            floatx16 acc[NTT];
+#pragma unroll
+            for (int q = 0; q < NTT; ++q) acc[q] = floatx16{0};
+            mfma_gram<UP>(Hs + o * RS, RS, Bc, acc);
+            gram_store<UP>(acc, sA, kap, U, nullptr, nullptr);
+            wave_sync();
+            float t = 0.f;
+            const bool ok = wave_factor<UP>(sA, sB, U, kap, &t);
+            const float w = ok ? sqrtf(rho_c2 / (t * p.Es)) : 0.f;
+            if (lane == 0) {
+                if (scale_out) scale_out[(size_t)n * p.C + c] = w;
+                if (status) status[(size_t)n * p.C + c] = ok ? PRECODE_ST_OK : PRECODE_ST_FAIL;
+            }
+            wave_sync();
+            for (int k0 = 0; k0 < K; k0 += KC) {
+                const int kc = min(KC, K - k0);
+                wave_solve_chunk<UP>(sA, sB, Ss, k0, kc, U, w, ok);
+                wave_sync();
+                wave_precode_rows<UP>(Hs, sB, o, Bc, k0, kc, n, p.n_sc, B, x, 0, 1);
+                wave_sync();
+            }
+        }
+    }
+}
+
+int pick_up(int U) { return U <= 16 ? 16 : (U <= 32 ? 32 : 0); }
+
+constexpr size_t kLdsMax = 160 * 1024;
+
+template <int UP, int ARCH>
+hipError_t launch(const Prob &p, int K, const float2 *H, const float2 *s, float2 *x, float *scale_out,
+                  int *status, hipStream_t st) {
+    const size_t lds = lds_bytes<UP>(p.B, K);
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void *)fused_k<UP, ARCH>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((fused_k<UP, ARCH>), dim3(p.n_sc), dim3(kThreads), lds, st, p, K, H, s, x, scale_out,
+                       status);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+bool fused_supported(const Prob &p, int precision) {
+    if (precision != PRECODE_PREC_FP32) return false;
+    const int up = pick_up(p.U);
+    if (up == 0) return false;
+    const int kmax = p.K < kMaxKFused ? p.K : kMaxKFused;
+    const size_t lds = up == 16 ? lds_bytes<16>(p.B, kmax) : lds_bytes<32>(p.B, kmax);
+    if (lds > kLdsMax - 256) return false;
+    if (p.arch == kPD) return p.pd_fp64 == 0;
+    for (int c = 0; c < p.C; ++c) {
+        if (p.fp64[c]) return false;
+        if (p.off[c + 1] - p.off[c] < p.U) return false;
+    }
+    return true;
+}
+
+hipError_t fused_run(const Prob &p, int precision, const float2 *H, const float2 *s, float2 *x,
+                     float *scale_out, int *status, hipStream_t st) {
+    if (!fused_supported(p, precision)) return hipErrorNotSupported;
+    if (p.n_sc == 0) return hipSuccess;
+    const int up = pick_up(p.U);
+    for (int k0 = 0; k0 < p.K; k0 += kMaxKFused) {
+        const int kk = p.K - k0 < kMaxKFused ? p.K - k0 : kMaxKFused;
+        const float2 *sk = s + (size_t)k0 * p.n_sc * p.U;
+        float2 *xk = x + (size_t)k0 * p.n_sc * p.B;
+        // factors are identical for every slice; write them once
+        float *so = k0 == 0 ? scale_out : nullptr;
+        int *sto = k0 == 0 ? status : nullptr;
+        hipError_t e;
+        if (up == 16)
+            e = p.arch == kPD ? launch<16, kPD>(p, kk, H, sk, xk, so, sto, st)
+                              : launch<16, kFD>(p, kk, H, sk, xk, so, sto, st);
+        else
+            e = p.arch == kPD ? launch<32, kPD>(p, kk, H, sk, xk, so, sto, st)
+                              : launch<32, kFD>(p, kk, H, sk, xk, so, sto, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace pc
