@@ -39,15 +39,18 @@ static void st(double *p, cplx v) { p[0] = creal(v); p[1] = cimag(v); }
  * lower triangle used).  The paper inverts the regularized Gram matrix with a
  * batched factorization (Sec. IV-B, PD-WF implementation); A is Hermitian
  * positive definite, so Cholesky is the factorization that applies.
- * Returns 0 on success, 1 if a pivot is not positive and finite. */
+ * Theorem 1 needs A invertible: a pivot that is not above 2^-40 times the
+ * original diagonal entry (FP64 roundoff level) marks A numerically singular.
+ * Returns 0 on success, 1 on such a pivot or a non-finite value. */
 static int cholesky(cplx *A, int n) {
     for (int j = 0; j < n; ++j) {
-        double d = creal(A[j * n + j]);
+        const double a0 = creal(A[j * n + j]);
+        double d = a0;
         for (int k = 0; k < j; ++k) {
             cplx l = A[j * n + k];
             d -= creal(l * conj(l));
         }
-        if (!(d > 0.0) || !isfinite(d)) return 1;
+        if (!(d > 0x1p-40 * a0) || !isfinite(d)) return 1;
         d = sqrt(d);
         A[j * n + j] = d;
         for (int i = j + 1; i < n; ++i) {
