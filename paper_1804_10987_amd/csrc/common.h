@@ -20,6 +20,12 @@ constexpr int kMaxK = 4096;  // symbols per call
 
 enum Arch { kPD = 0, kFD = 1 };
 
+// A Cholesky pivot that is not above this fraction of the original diagonal
+// entry marks the system numerically singular (status PRECODE_ST_FAIL):
+// about 16 units of roundoff in FP32, 2^-40 on the FP64 route.
+constexpr float kRelPivot32 = 9.5367431640625e-07f;  // 2^-20
+constexpr double kRelPivot64 = 9.094947017729282e-13;  // 2^-40
+
 // Per-call problem description, passed to kernels by value.
 struct Prob {
     int arch;       // kPD / kFD

@@ -181,16 +181,19 @@ __device__ __forceinline__ int tile_k(int r, int g) { return 4 * (r / 4) + 2 * g
 
 // Right-looking Cholesky A = L L^H of the m x m system in an LDS slot (lower
 // triangle, in place), one wave.  Lane (i, ph): row i = lane / P, column
-// phase ph = lane % P.  Returns false on a pivot that is not positive/finite.
+// phase ph = lane % P.  Returns false when a pivot is not finite or not above
+// kRelPivot32 times the original diagonal entry (numerically singular system).
 template <int UP>
 __device__ bool wave_cholesky(cx<float> *A, int m) {
     constexpr int LDc = Shape<UP>::LDc;
     constexpr int P = 64 / UP;
     const int lane = lane_id();
     const int i = lane / P, ph = lane % P;
+    const float diag0 = (i < m) ? A[i * LDc + i].re : 0.f;  // original diagonal of row i
     for (int k = 0; k < m; ++k) {
         const float akk = A[k * LDc + k].re;
-        if (!(akk > 0.f) || !(akk < INFINITY)) return false;
+        const float a0 = __shfl(diag0, k * P);
+        if (!(akk > kRelPivot32 * a0) || !(akk < INFINITY)) return false;
         const float d = sqrtf(akk), inv = 1.f / d;
         if (ph == 0 && i > k && i < m) A[i * LDc + k] = cscale(A[i * LDc + k], inv);
         if (ph == 0 && i == k) A[k * LDc + k] = {d, 0.f};
@@ -305,6 +308,62 @@ __device__ void wave_precode_rows(const float *Hs, const cx<float> *zs, int r0, 
     }
 }
 
+// Copies the B x U complex64 channel of one subcarrier into LDS rows of stride
+// RS floats and zeroes the padding users U..UP-1.  Each thread issues a batch
+// of NB loads before its LDS stores, so a whole batch is in flight at once.
+template <int UP>
+__device__ __forceinline__ void stage_channel(const float2 *__restrict__ Hn, float *Hs, int B, int U) {
+    constexpr int RS = Shape<UP>::RS;
+    constexpr int NB = 8;
+    const int tid = threadIdx.x;
+    if ((U & 1) == 0 && (((uintptr_t)Hn) & 15) == 0) {
+        const float4 *src = (const float4 *)Hn;
+        const int hu = U >> 1;  // float4 per row
+        const int nf = B * hu;
+        for (int base = 0; base < nf; base += kThreads * NB) {
+            float4 r[NB];
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                const int f = base + j * kThreads + tid;
+                r[j] = f < nf ? src[f] : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                const int f = base + j * kThreads + tid;
+                if (f < nf) {
+                    const int b = f / hu, c = f - b * hu;
+                    *(float4 *)(Hs + b * RS + 4 * c) = r[j];
+                }
+            }
+        }
+    } else {
+        const int nf = B * U;
+        for (int base = 0; base < nf; base += kThreads * NB) {
+            float2 r[NB];
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                const int f = base + j * kThreads + tid;
+                r[j] = f < nf ? Hn[f] : make_float2(0.f, 0.f);
+            }
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                const int f = base + j * kThreads + tid;
+                if (f < nf) {
+                    const int b = f / U, u = f - b * U;
+                    *(float2 *)(Hs + b * RS + 2 * u) = r[j];
+                }
+            }
+        }
+    }
+    if (U < UP) {
+        const int pad = UP - U;
+        for (int e = tid; e < B * pad; e += kThreads) {
+            const int b = e / pad, u = U + (e - b * pad);
+            *(float2 *)(Hs + b * RS + 2 * u) = make_float2(0.f, 0.f);
+        }
+    }
+}
+
 template <int UP>
 __host__ __device__ constexpr size_t lds_bytes(int B, int K) {
     return (size_t)B * Shape<UP>::RS * 4 + (size_t)K * 2 * UP * 4 + (size_t)8 * Shape<UP>::SLOT * 8;
@@ -330,12 +389,7 @@ __global__ void __launch_bounds__(kThreads) fused_k(Prob p, int K, const float2 
     cx<float> *sB = slots + (2 * wave + 1) * SLOT;
 
     // ---- stage H[n] (zero-padded to UP users) and s[:, n] in LDS ----------
-    const float2 *Hn = H + (size_t)n * B * U;
-    for (int e = tid; e < B * UP; e += kThreads) {
-        const int b = e / UP, u = e % UP;
-        const float2 v = (u < U) ? Hn[(size_t)b * U + u] : make_float2(0.f, 0.f);
-        *(float2 *)(Hs + b * RS + 2 * u) = v;
-    }
+    stage_channel<UP>(H + (size_t)n * B * U, Hs, B, U);
     for (int e = tid; e < K * UP; e += kThreads) {
         const int k = e / UP, u = e % UP;
         const float2 v = (u < U) ? s[((size_t)k * p.n_sc + n) * U + u] : make_float2(0.f, 0.f);

@@ -110,12 +110,17 @@ __global__ void __launch_bounds__(64) plain_factor_k(Prob p, cx<T> *__restrict__
     cx<T> *a = A + (size_t)inst * p.U * p.U;
     cx<T> *ai = Ainv + (size_t)inst * p.U * p.U;
     __shared__ T diag[kMaxU];
+    __shared__ T diag0[kMaxU];
     __shared__ T red[2][64];
     bool ok = true;
-    // Cholesky, right-looking
+    const T rel = is64<T>() ? (T)kRelPivot64 : (T)kRelPivot32;
+    for (int i = tid; i < m; i += 64) diag0[i] = a[i * m + i].re;
+    __syncthreads();
+    // Cholesky, right-looking; a pivot not above rel * original diagonal marks
+    // the system numerically singular
     for (int k = 0; k < m && ok; ++k) {
         const T akk = a[k * m + k].re;
-        ok = (akk > (T)0) && finite_f((double)akk);
+        ok = (akk > rel * diag0[k]) && finite_f((double)akk);
         __syncthreads();
         if (!ok) break;
         const T d = sqrt(akk);

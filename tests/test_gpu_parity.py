@@ -115,7 +115,7 @@ def test_power_and_params(torch, ctx, pc, arch):
 def test_fd_small_clusters_auto(torch, ctx, pc):
     """FD with clusters smaller than U (B_c x B_c branch) and square clusters
     (FP64 route by the default ratio 0.5)."""
-    cell = synth.Cell(B=40, sizes=(4, 12, 8, 16), U=8, n_sc=9, K=6)
+    cell = synth.Cell(B=44, sizes=(4, 12, 8, 20), U=8, n_sc=9, K=6)
     H, s = synth.make_cell(cell, seed=5)
     for mode in ("wf", "zf"):
         xg, scg, stg = _run(torch, ctx, pc, "fd", H, s, cell.kappa, cell.sizes, mode)
@@ -140,13 +140,17 @@ def test_fp64_route_square(torch, ctx, pc):
 
 
 @pytest.mark.parametrize("impl", ["fused", "plain"])
-def test_singular_zf_sets_status(torch, ctx, pc, impl):
+@pytest.mark.parametrize("defect", ["duplicate", "zero"])
+def test_singular_zf_sets_status(torch, ctx, pc, impl, defect):
+    """ZF with a duplicated (collinear) or silent user: the Gram matrix is
+    singular, the instance is flagged and its output is zero."""
     cell = synth.Cell(B=32, sizes=(16, 16), U=4, n_sc=6, K=3)
     H, s = synth.make_cell(cell, seed=9)
-    H[2, :, 3] = H[2, :, 1]  # duplicated user on subcarrier 2
+    H[2, :, 3] = H[2, :, 1] if defect == "duplicate" else 0.0
     xg, scg, stg = _run(torch, ctx, pc, "pd", H, s, 0.0, cell.sizes, "zf", impl=impl, fp64_ratio=2.0)
     assert stg[2] & 1 == 1 and scg[2] == 0.0 and not np.any(xg[:, 2])
     xo, sco, sto = _oracle("pd", H, s, 0.0, cell.sizes, "zf")
+    assert sto[2] == 1
     keep = [n for n in range(6) if n != 2]
     assert _vec_err(xg[:, keep], xo[:, keep]).max() <= TOL
 
