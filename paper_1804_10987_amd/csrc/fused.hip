@@ -179,86 +179,142 @@ __device__ __forceinline__ floatx16 mfma_apply(const float *rows, int rs, int nv
 // Symbol index held by register pair (r, r+1) of an X^T tile.
 __device__ __forceinline__ int tile_k(int r, int g) { return 4 * (r / 4) + 2 * g + ((r % 4) >> 1); }
 
-// Right-looking Cholesky A = L L^H of the m x m system in an LDS slot (lower
-// triangle, in place), one wave.  Lane (i, ph): row i = lane / P, column
-// phase ph = lane % P.  Returns false when a pivot is not finite or not above
-// kRelPivot32 times the original diagonal entry (numerically singular system).
-template <int UP>
-__device__ bool wave_cholesky(cx<float> *A, int m) {
-    constexpr int LDc = Shape<UP>::LDc;
-    constexpr int P = 64 / UP;
-    const int lane = lane_id();
-    const int i = lane / P, ph = lane % P;
-    const float diag0 = (i < m) ? A[i * LDc + i].re : 0.f;  // original diagonal of row i
-    for (int k = 0; k < m; ++k) {
-        const float akk = A[k * LDc + k].re;
-        const float a0 = __shfl(diag0, k * P);
-        if (!(akk > kRelPivot32 * a0) || !(akk < INFINITY)) return false;
-        const float d = sqrtf(akk), inv = 1.f / d;
-        if (ph == 0 && i > k && i < m) A[i * LDc + k] = cscale(A[i * LDc + k], inv);
-        if (ph == 0 && i == k) A[k * LDc + k] = {d, 0.f};
-        wave_sync();
-        if (i > k && i < m) {
-            const cx<float> lik = A[i * LDc + k];
-            for (int j = k + 1 + ph; j <= i; j += P) A[i * LDc + j] = csub(A[i * LDc + j], cmulc(lik, A[j * LDc + k]));
-        }
-        wave_sync();
-    }
-    return true;
-}
-
-// W = L^-1 (lower triangular) into a zeroed slot, row by row: after step p,
-// row p of W is final and rows r > p hold sum_{q<=p} L[r][q] W[q][j].
-template <int UP>
-__device__ void wave_tri_inverse(const cx<float> *L, cx<float> *W, int m) {
-    constexpr int LDc = Shape<UP>::LDc;
-    constexpr int P = 64 / UP;
-    const int lane = lane_id();
-    const int i = lane / P, ph = lane % P;
-    for (int p = 0; p < m; ++p) {
-        if (i == p) {
-            const float dinv = 1.f / L[p * LDc + p].re;
-            for (int j = ph; j <= p; j += P) {
-                const cx<float> w = W[p * LDc + j];
-                W[p * LDc + j] = {(((j == p) ? 1.f : 0.f) - w.re) * dinv, -w.im * dinv};
-            }
-        }
-        wave_sync();
-        if (i > p && i < m) {
-            const cx<float> lip = L[i * LDc + p];
-            for (int j = ph; j <= p; j += P) W[i * LDc + j] = cadd(W[i * LDc + j], cmul(lip, W[p * LDc + j]));
-        }
-        wave_sync();
-    }
-}
-
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     return v;
 }
 
-// Factor one system held in slot A (A = G + kappa I, lower triangle valid):
-// on success slot A holds A^-1 (full), slot B is scratch, *t = Lemma-1 trace.
-template <int UP>
-__device__ bool wave_factor(cx<float> *sA, cx<float> *sB, int m, float kap, float *t_out) {
-    constexpr int NTT = Shape<UP>::NTT;
-    bool ok = wave_cholesky<UP>(sA, m);
-    float t = 0.f;
-    if (ok) {
-        wave_tri_inverse<UP>(sA, sB, m);
-        floatx16 acc[NTT];
-#pragma unroll
-        for (int q = 0; q < NTT; ++q) acc[q] = floatx16{0};
-        mfma_gram<UP>((const float *)sB, 2 * Shape<UP>::LDc, m, acc);  // A^-1 = W^H W
-        float tr = 0.f, fro = 0.f;
-        gram_store<UP>(acc, sA, 0.f, m, &tr, &fro);
-        tr = wave_sum(tr);
-        fro = wave_sum(fro);
-        t = tr - kap * fro;
-        ok = (t > 0.f) && (t < INFINITY);
-        wave_sync();
+// Broadcast within the lanes of one matrix row of the register layout below:
+// lane (r, c) receives the value of lane (r, k).  For UP = 16 a row is a DPP
+// row of 16 lanes (row_newbcast); for UP = 32 it is a half-wave.
+template <int UP, int k>
+__device__ __forceinline__ float bcast_row(float v) {
+    if constexpr (UP == 16) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x150 + k,
+                                                                      0xf, 0xf, false));
+    } else {
+        return __shfl(v, (lane_id() & ~(UP - 1)) | k);
     }
+}
+
+template <int UP>
+__device__ __forceinline__ float bcast_row_dyn(float v, int k) {
+    if constexpr (UP == 16) {
+        switch (k) {
+            case 0: return bcast_row<16, 0>(v);
+            case 1: return bcast_row<16, 1>(v);
+            case 2: return bcast_row<16, 2>(v);
+            case 3: return bcast_row<16, 3>(v);
+            case 4: return bcast_row<16, 4>(v);
+            case 5: return bcast_row<16, 5>(v);
+            case 6: return bcast_row<16, 6>(v);
+            case 7: return bcast_row<16, 7>(v);
+            case 8: return bcast_row<16, 8>(v);
+            case 9: return bcast_row<16, 9>(v);
+            case 10: return bcast_row<16, 10>(v);
+            case 11: return bcast_row<16, 11>(v);
+            case 12: return bcast_row<16, 12>(v);
+            case 13: return bcast_row<16, 13>(v);
+            case 14: return bcast_row<16, 14>(v);
+            default: return bcast_row<16, 15>(v);
+        }
+    } else {
+        return __shfl(v, (lane_id() & ~(UP - 1)) | k);
+    }
+}
+
+__device__ __forceinline__ float readlane_f(float v, int lane) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
+}
+
+// In-register inversion of the m x m Hermitian positive-definite system held
+// in an LDS slot (full matrix), one wave, by Gauss-Jordan elimination without
+// pivoting: step k divides row k by the pivot and eliminates column k from
+// every other row, so that after m steps the slot holds A^-1.  For a Hermitian
+// positive-definite A the pivots are the squared diagonal of its Cholesky
+// factor and need no row exchanges.
+// Layout: lane (r, c) = (lane / UP, lane % UP) holds column c, rows
+// i = s*R + r (R = 64 / UP row groups, NS = UP / R slots).  Row k of the
+// matrix reaches every lane through a bpermute, column k through bcast_row,
+// the pivot through readlane.  Returns false when a pivot is not finite or not
+// above kRelPivot32 times the original diagonal entry (numerically singular).
+// On success writes A^-1 back to the slot and sets tr A^-1, ||A^-1||_F^2.
+template <int UP>
+__device__ bool wave_inverse(cx<float> *S, int m, float *tr_out, float *fro_out) {
+    constexpr int R = 64 / UP;
+    constexpr int NS = UP / R;
+    constexpr int LDc = Shape<UP>::LDc;
+    const int lane = lane_id();
+    const int r = lane / UP, c = lane % UP;
+    float re[NS], im[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const cx<float> v = S[(s * R + r) * LDc + c];
+        re[s] = v.re;
+        im[s] = v.im;
+    }
+    const float d0 = S[c * LDc + c].re;  // original diagonal entry of column c
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < UP; ++k) {
+        if (k < m) {
+            const int sk = k / R;  // slot of row k
+            const int rk = k % R;  // row group of row k
+            const float piv = readlane_f(re[sk], rk * UP + k);
+            const float a0 = readlane_f(d0, k);
+            ok = ok && (piv > kRelPivot32 * a0) && (piv < INFINITY);
+            const float inv = 1.f / piv;
+            // row k, column c (before this step's update)
+            const float akc_re = __shfl(re[sk], rk * UP + c);
+            const float akc_im = __shfl(im[sk], rk * UP + c);
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const int i = s * R + r;
+                const float aik_re = bcast_row_dyn<UP>(re[s], k);
+                const float aik_im = bcast_row_dyn<UP>(im[s], k);
+                float nre, nim;
+                if (i == k) {
+                    nre = (c == k) ? inv : re[s] * inv;
+                    nim = (c == k) ? 0.f : im[s] * inv;
+                } else if (c == k) {
+                    nre = -aik_re * inv;
+                    nim = -aik_im * inv;
+                } else {
+                    const float tre = aik_re * akc_re - aik_im * akc_im;
+                    const float tim = aik_re * akc_im + aik_im * akc_re;
+                    nre = re[s] - tre * inv;
+                    nim = im[s] - tim * inv;
+                }
+                re[s] = nre;
+                im[s] = nim;
+            }
+        }
+    }
+    float tr = 0.f, fro = 0.f;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int i = s * R + r;
+        if (i < m && c < m) {
+            fro += re[s] * re[s] + im[s] * im[s];
+            if (i == c) tr += re[s];
+        }
+        S[i * LDc + c] = {re[s], im[s]};
+    }
+    *tr_out = wave_sum(tr);
+    *fro_out = wave_sum(fro);
+    return ok;
+}
+
+// Factor one system held in slot A (A = G + kappa I, full Hermitian matrix):
+// on success slot A holds A^-1 and *t = tr A^-1 - kappa ||A^-1||_F^2 (Lemma 1).
+template <int UP>
+__device__ bool wave_factor(cx<float> *sA, int m, float kap, float *t_out) {
+    float tr = 0.f, fro = 0.f;
+    bool ok = wave_inverse<UP>(sA, m, &tr, &fro);
+    const float t = tr - kap * fro;
+    ok = ok && (t > 0.f) && (t < INFINITY);
+    wave_sync();
     *t_out = t;
     return ok;
 }
@@ -364,6 +420,48 @@ __device__ __forceinline__ void stage_channel(const float2 *__restrict__ Hn, flo
     }
 }
 
+// Register prefetch of the next subcarrier's channel: the first kPF float4
+// of each thread's share are loaded while the current subcarrier computes and
+// written to LDS afterwards (channels with an even user count only).
+constexpr int kPF = 8;
+
+__device__ __forceinline__ void prefetch_issue(float4 (&pf)[kPF], const float2 *__restrict__ Hn, int nf) {
+    const float4 *src = (const float4 *)Hn;
+#pragma unroll
+    for (int j = 0; j < kPF; ++j) {
+        const int f = j * kThreads + (int)threadIdx.x;
+        pf[j] = f < nf ? src[f] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+}
+
+template <int UP>
+__device__ __forceinline__ void prefetch_commit(const float4 (&pf)[kPF], const float2 *__restrict__ Hn, float *Hs,
+                                                int B, int U) {
+    constexpr int RS = Shape<UP>::RS;
+    const int hu = U >> 1, nf = B * hu;
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < kPF; ++j) {
+        const int f = j * kThreads + tid;
+        if (f < nf) {
+            const int b = f / hu, c = f - b * hu;
+            *(float4 *)(Hs + b * RS + 4 * c) = pf[j];
+        }
+    }
+    const float4 *src = (const float4 *)Hn;
+    for (int f = kPF * kThreads + tid; f < nf; f += kThreads) {
+        const int b = f / hu, c = f - b * hu;
+        *(float4 *)(Hs + b * RS + 4 * c) = src[f];
+    }
+    if (U < UP) {
+        const int pad = UP - U;
+        for (int e = tid; e < B * pad; e += kThreads) {
+            const int b = e / pad, u = U + (e - b * pad);
+            *(float2 *)(Hs + b * RS + 2 * u) = make_float2(0.f, 0.f);
+        }
+    }
+}
+
 template <int UP>
 __host__ __device__ constexpr size_t lds_bytes(int B, int K) {
     return (size_t)B * Shape<UP>::RS * 4 + (size_t)K * 2 * UP * 4 + (size_t)8 * Shape<UP>::SLOT * 8;
@@ -383,13 +481,22 @@ __global__ void __launch_bounds__(kThreads) fused_k(Prob p, int K, const float2 
     __shared__ float sh_scale;
     __shared__ int sh_ok;
 
-    const int B = p.B, U = p.U, n = blockIdx.x;
+    const int B = p.B, U = p.U;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     cx<float> *sA = slots + (2 * wave) * SLOT;
     cx<float> *sB = slots + (2 * wave + 1) * SLOT;
+    // persistent blocks: subcarriers n = blockIdx.x, blockIdx.x + gridDim.x, ...
+    const bool vec = (U & 1) == 0 && (((uintptr_t)H) & 15) == 0;
+    const int nf = B * (U >> 1);
+    float4 pf[kPF];
+    if (vec && (int)blockIdx.x < p.n_sc) prefetch_issue(pf, H + (size_t)blockIdx.x * B * U, nf);
 
+    for (int n = blockIdx.x; n < p.n_sc; n += gridDim.x) {
     // ---- stage H[n] (zero-padded to UP users) and s[:, n] in LDS ----------
-    stage_channel<UP>(H + (size_t)n * B * U, Hs, B, U);
+    if (vec)
+        prefetch_commit<UP>(pf, H + (size_t)n * B * U, Hs, B, U);
+    else
+        stage_channel<UP>(H + (size_t)n * B * U, Hs, B, U);
     for (int e = tid; e < K * UP; e += kThreads) {
         const int k = e / UP, u = e % UP;
         const float2 v = (u < U) ? s[((size_t)k * p.n_sc + n) * U + u] : make_float2(0.f, 0.f);
@@ -397,6 +504,8 @@ __global__ void __launch_bounds__(kThreads) fused_k(Prob p, int K, const float2 
     }
     for (int e = tid; e < 8 * SLOT; e += kThreads) slots[e] = {0.f, 0.f};
     __syncthreads();
+    // the next subcarrier's channel is in flight while this one computes
+    if (vec && n + (int)gridDim.x < p.n_sc) prefetch_issue(pf, H + (size_t)(n + gridDim.x) * B * U, nf);
 
     if (ARCH == kPD) {
         const float kap = pd_kappa(p);
@@ -422,7 +531,7 @@ __global__ void __launch_bounds__(kThreads) fused_k(Prob p, int K, const float2 
         __syncthreads();
         if (wave == 0) {
             float t = 0.f;
-            const bool ok = wave_factor<UP>(sA, sB, U, kap, &t);
+            const bool ok = wave_factor<UP>(sA, U, kap, &t);
             const float beta = ok ? sqrtf(p.Es / p.power * t) : 0.f;
             if (lane == 0) {
                 sh_scale = ok ? 1.f / beta : 0.f;
@@ -457,7 +566,7 @@ __global__ void __launch_bounds__(kThreads) fused_k(Prob p, int K, const float2 
             gram_store<UP>(acc, sA, kap, U, nullptr, nullptr);
             wave_sync();
             float t = 0.f;
-            const bool ok = wave_factor<UP>(sA, sB, U, kap, &t);
+            const bool ok = wave_factor<UP>(sA, U, kap, &t);
             const float w = ok ? sqrtf(rho_c2 / (t * p.Es)) : 0.f;
             if (lane == 0) {
                 if (scale_out) scale_out[(size_t)n * p.C + c] = w;
@@ -472,6 +581,8 @@ __global__ void __launch_bounds__(kThreads) fused_k(Prob p, int K, const float2 
                 wave_sync();
             }
         }
+    }
+    __syncthreads();  // every LDS read of this subcarrier precedes the next staging
     }
 }
 
@@ -488,7 +599,20 @@ hipError_t launch(const Prob &p, int K, const float2 *H, const float2 *s, float2
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((fused_k<UP, ARCH>), dim3(p.n_sc), dim3(kThreads), lds, st, p, K, H, s, x, scale_out,
+    // persistent grid: as many blocks as fit on the device at once
+    static int cached_lds = -1, cached_grid = 0;
+    if (cached_lds != (int)lds) {
+        int dev = 0, cus = 0, per_cu = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e == hipSuccess)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)fused_k<UP, ARCH>, kThreads, lds);
+        if (e != hipSuccess) return e;
+        cached_grid = (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
+        cached_lds = (int)lds;
+    }
+    const int grid = p.n_sc < cached_grid ? p.n_sc : cached_grid;
+    hipLaunchKernelGGL((fused_k<UP, ARCH>), dim3(grid), dim3(kThreads), lds, st, p, K, H, s, x, scale_out,
                        status);
     return hipGetLastError();
 }

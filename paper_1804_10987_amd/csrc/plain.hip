@@ -25,6 +25,11 @@ namespace {
 template <typename T>
 constexpr bool is64() { return sizeof(T) == 8; }
 
+// FP32 and FP64-route instances share the workspace, so every instance slot
+// has the size of its FP64 form: kW elements of T per complex<double> slot.
+template <typename T>
+constexpr int kW() { return (int)(sizeof(double) / sizeof(T)); }
+
 struct InstInfo {
     int n, c, row0, rows, m;  // subcarrier, cluster, first row, rows, system order
     bool big;                 // FD: B_c >= U (U x U system) ; PD: true
@@ -66,7 +71,7 @@ __global__ void __launch_bounds__(256) plain_gram_k(Prob p, const float2 *__rest
     const InstInfo q = inst_info(p, inst);
     if (q.r64 != is64<T>()) return;
     const float2 *Hn = H + (size_t)q.n * p.B * p.U;
-    cx<T> *An = A + (size_t)inst * p.U * p.U;
+    cx<T> *An = A + (size_t)inst * p.U * p.U * kW<T>();
     const int m = q.m;
     for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
         const int i = e / m, j = e % m;
@@ -107,8 +112,8 @@ __global__ void __launch_bounds__(64) plain_factor_k(Prob p, cx<T> *__restrict__
     if (q.r64 != is64<T>()) return;
     const int m = q.m;
     const int tid = threadIdx.x;
-    cx<T> *a = A + (size_t)inst * p.U * p.U;
-    cx<T> *ai = Ainv + (size_t)inst * p.U * p.U;
+    cx<T> *a = A + (size_t)inst * p.U * p.U * kW<T>();
+    cx<T> *ai = Ainv + (size_t)inst * p.U * p.U * kW<T>();
     __shared__ T diag[kMaxU];
     __shared__ T diag0[kMaxU];
     __shared__ T red[2][64];
@@ -195,7 +200,7 @@ __global__ void __launch_bounds__(64) plain_factor_k(Prob p, cx<T> *__restrict__
                 out = w;
             }
         }
-        scale_ws[inst] = sc;
+        scale_ws[inst * kW<T>()] = sc;
         if (scale_out) scale_out[inst] = (float)out;
         if (status) status[inst] = (ok ? PRECODE_ST_OK : PRECODE_ST_FAIL) | (q.r64 ? PRECODE_ST_FP64 : 0);
     }
@@ -217,8 +222,8 @@ __global__ void __launch_bounds__(256) plain_solve_k(Prob p, int K, const float2
     const int k = (int)(gid / ((size_t)p.U * ni));
     const InstInfo q = inst_info(p, (int)inst);
     if (q.r64 != is64<T>()) return;
-    const T sc = scale_ws[inst];  // 0 marks a failed instance: its output is 0
-    const cx<T> *ai = Ainv + inst * p.U * p.U;
+    const T sc = scale_ws[inst * kW<T>()];  // 0 marks a failed instance: its output is 0
+    const cx<T> *ai = Ainv + inst * p.U * p.U * kW<T>();
     const float2 *sk = s + ((size_t)k * p.n_sc + q.n) * p.U;
     if (q.big) {
         if (r >= q.m) return;
