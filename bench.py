@@ -148,6 +148,12 @@ def main():
         },
         "latency": {"frame_p50_ms": float(np.percentile(per, 50)), "frame_p99_ms": float(np.percentile(per, 99))},
     }
+    variants = {}
+    for prec in ("split_fp16", "split_bf16"):
+        ms_v, per_v = time_path(lambda f, prec=prec: pd_fused(f, prec), args.steps, args.warmup)
+        variants[prec] = {"ms_per_step": ms_v, "value": n_sc * K / (ms_v * 1e-3),
+                          "achieved_gbs": frame_bytes / (float(np.mean(per_v)) * 1e-3) / 1e9}
+    out["pd_precision_variants"] = variants
     if not args.quick:
         steps2 = max(10, args.steps // 4)
         ms_plain, _ = time_path(pd_plain, steps2, 3)

@@ -88,17 +88,26 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("impl", ["fused", "plain"])
+# (impl, precision, tolerance): FP32 paths 1e-5; split 16-bit MFMA (hi + lo,
+# three products, FP32 accumulation) FP16 1e-5, BF16 1e-3 (the reduced-precision
+# bound; its hi + lo keeps ~16 mantissa bits per operand)
+PATHS = [("fused", "fp32", 1e-5), ("plain", "fp32", 1e-5), ("fused", "split_fp16", 1e-5),
+         ("fused", "split_bf16", 1e-3)]
+
+
+@pytest.mark.parametrize("impl,prec,tol", PATHS, ids=["%s-%s" % (a, b) for a, b, _ in PATHS])
 @pytest.mark.parametrize("arch", ["pd", "fd"])
 @pytest.mark.parametrize("name,cell,mode", CASES, ids=[c[0] for c in CASES])
-def test_parity(torch, ctx, pc, name, cell, mode, arch, impl):
+def test_parity(torch, ctx, pc, name, cell, mode, arch, impl, prec, tol):
     H, s = synth.make_cell(cell, seed=11)
-    print("case", name, arch, mode, impl, flush=True)
+    print("case", name, arch, mode, impl, prec, flush=True)
     # keep every instance on the FP32 path here (the FP64 route has its own test)
-    xg, scg, stg = _run(torch, ctx, pc, arch, H, s, cell.kappa, cell.sizes, mode, impl=impl, fp64_ratio=2.0)
+    xg, scg, stg = _run(torch, ctx, pc, arch, H, s, cell.kappa, cell.sizes, mode, impl=impl, fp64_ratio=2.0,
+                        precision=prec)
     assert ctx.last_impl == impl
     xo, sco, sto = _oracle(arch, H, s, cell.kappa, cell.sizes, mode)
-    _check(xg, scg, stg, xo, sco, sto)
+    e = _check(xg, scg, stg, xo, sco, sto, tol=tol)
+    print("max rel err %.3e" % e, flush=True)
 
 
 @pytest.mark.parametrize("arch", ["pd", "fd"])
@@ -214,20 +223,22 @@ def test_batch_matches_individual(torch, ctx, pc):
         _check(x.cpu().numpy(), scg, stg, xo, sco, sto)
 
 
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("split_fp16", 1e-5), ("split_bf16", 1e-3)])
 @pytest.mark.parametrize("arch", ["pd", "fd"])
-def test_full_size_sampled(torch, ctx, pc, arch):
+def test_full_size_sampled(torch, ctx, pc, arch, prec, tol):
     """B=256 as 8 x 32, U=16, 1200 subcarriers x 14 symbols in the launch
     configuration the benchmark times; the oracle checks 40 sampled
     subcarriers."""
     cell = synth.config(2)
     H, s = synth.make_cell(cell, seed=0)
     Hd, sd = _dev(torch, H), _dev(torch, s)
-    prm = pc.params(fp64_ratio=2.0)
+    prm = pc.params(fp64_ratio=2.0, precision=prec)
     fn = ctx.pd if arch == "pd" else ctx.fd
     x, sc, st = fn(Hd, sd, cell.kappa, cell.sizes, "wf", prm)
     torch.cuda.synchronize()
     assert ctx.last_impl == "fused"
     idx = np.random.default_rng(0).choice(cell.n_sc, size=40, replace=False)
     xo, sco, sto = _oracle(arch, H[idx], s[:, idx], cell.kappa, cell.sizes, "wf")
-    _check(x.cpu().numpy()[:, idx], sc.cpu().numpy().reshape((cell.n_sc,) + sco.shape[1:])[idx],
-           st.cpu().numpy().reshape((cell.n_sc,) + sto.shape[1:])[idx], xo, sco, sto)
+    e = _check(x.cpu().numpy()[:, idx], sc.cpu().numpy().reshape((cell.n_sc,) + sco.shape[1:])[idx],
+               st.cpu().numpy().reshape((cell.n_sc,) + sto.shape[1:])[idx], xo, sco, sto, tol=tol)
+    print("max rel err %.3e" % e, flush=True)
