@@ -32,6 +32,8 @@
 // PD: the four waves split the rows for the Gram, wave 0 factors, all four
 // waves precode.  FD: each wave owns whole clusters (c = wave, wave+4, ...)
 // and runs the full chain for them without workgroup barriers.
+#include <stddef.h>
+
 #include "common.h"
 
 namespace pc {
@@ -151,34 +153,63 @@ __device__ __forceinline__ void mfma_gram(const float *rows, int rs, int nrows, 
     const int lane = lane_id();
     const int j = lane & 31, g = lane >> 5;
     if constexpr (PREC == kF32) {
-        for (int r = 0; r < nrows; r += 2) {
-            const int row = r + g;
-            float a[NT];
+        // groups of G instructions (2 rows each); the LDS reads of the next
+        // group are issued before the MFMAs of the current one
+        constexpr int G = 4;
+        float cur[G][NT], nxt[G][NT];
+        auto load = [&](float (&v)[G][NT], int r) {
 #pragma unroll
-            for (int ti = 0; ti < NT; ++ti) a[ti] = row < nrows ? rows[row * rs + 32 * ti + j] : 0.f;
-            int t = 0;
+            for (int a = 0; a < G; ++a) {
+                const int row = r + 2 * a + g;
 #pragma unroll
-            for (int ti = 0; ti < NT; ++ti)
+                for (int ti = 0; ti < NT; ++ti) v[a][ti] = row < nrows ? rows[row * rs + 32 * ti + j] : 0.f;
+            }
+        };
+        load(nxt, 0);
+#pragma unroll 1
+        for (int r = 0; r < nrows; r += 2 * G) {
 #pragma unroll
-                for (int tj = ti; tj < NT; ++tj) {
-                    acc[t] = mfma32(a[ti], a[tj], acc[t]);
-                    ++t;
-                }
+            for (int a = 0; a < G; ++a)
+#pragma unroll
+                for (int ti = 0; ti < NT; ++ti) cur[a][ti] = nxt[a][ti];
+            if (r + 2 * G < nrows) load(nxt, r + 2 * G);
+#pragma unroll
+            for (int a = 0; a < G; ++a) {
+                int t = 0;
+#pragma unroll
+                for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+                    for (int tj = ti; tj < NT; ++tj) {
+                        acc[t] = mfma32(cur[a][ti], cur[a][tj], acc[t]);
+                        ++t;
+                    }
+            }
         }
     } else {
         typedef typename Split<PREC>::V V;
-        for (int r = 0; r < nrows; r += 16) {
-            V hi[NT], lo[NT];
+        // 16 rows per step; the LDS reads of the next step are issued before
+        // the split and MFMAs of the current one
+        float cur[NT][8], nxt[NT][8];
+        auto load = [&](float (&v)[NT][8], int r) {
 #pragma unroll
-            for (int ti = 0; ti < NT; ++ti) {
-                float v[8];
+            for (int ti = 0; ti < NT; ++ti)
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
                     const int row = r + 8 * g + e;
-                    v[e] = row < nrows ? rows[row * rs + 32 * ti + j] * sc : 0.f;
+                    v[ti][e] = row < nrows ? rows[row * rs + 32 * ti + j] : 0.f;
                 }
-                Split<PREC>::split(v, hi[ti], lo[ti]);
-            }
+        };
+        load(nxt, 0);
+#pragma unroll 1
+        for (int r = 0; r < nrows; r += 16) {
+#pragma unroll
+            for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+                for (int e = 0; e < 8; ++e) cur[ti][e] = nxt[ti][e] * sc;
+            if (r + 16 < nrows) load(nxt, r + 16);
+            V hi[NT], lo[NT];
+#pragma unroll
+            for (int ti = 0; ti < NT; ++ti) Split<PREC>::split(cur[ti], hi[ti], lo[ti]);
             int t = 0;
 #pragma unroll
             for (int ti = 0; ti < NT; ++ti)
@@ -406,21 +437,27 @@ __device__ bool wave_inverse(cx<float> *S, int m, float *tr_out, float *fro_out,
             // row k, column c, before this step's update
             const float akc_re = __shfl(re[sk], rk * UP + c);
             const float akc_im = __shfl(im[sk], rk * UP + c);
+            // multiplier row: a_kc / a_kk for c != k and 1 + 1/a_kk for c = k,
+            // so that one update a_ic - a_ik * mult_c also turns column k into
+            // -a_ik / a_kk; row k itself becomes a_kc / a_kk (pivot 1/a_kk)
             const bool iscol = c == k;
+            const float mre = iscol ? 1.f + inv : akc_re * inv;
+            const float mim = iscol ? 0.f : akc_im * inv;
+            const float rowre = iscol ? inv : mre, rowim = mim;
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
-                const bool isrow = (s * R + r) == k;
                 const float aik_re = bcast_row_dyn<UP>(re[s], k);
                 const float aik_im = bcast_row_dyn<UP>(im[s], k);
-                // generic element: a_ic - a_ik a_kc / a_kk
-                const float tre = aik_re * akc_re - aik_im * akc_im;
-                const float tim = aik_re * akc_im + aik_im * akc_re;
-                const float gre = re[s] - tre * inv, gim = im[s] - tim * inv;
-                // row k: a_kc / a_kk ; column k: -a_ik / a_kk ; pivot: 1 / a_kk
-                const float rre = iscol ? inv : re[s] * inv, rim = iscol ? 0.f : im[s] * inv;
-                const float cre = -aik_re * inv, cim = -aik_im * inv;
-                re[s] = isrow ? rre : (iscol ? cre : gre);
-                im[s] = isrow ? rim : (iscol ? cim : gim);
+                const float nre = re[s] - (aik_re * mre - aik_im * mim);
+                const float nim = im[s] - (aik_re * mim + aik_im * mre);
+                if (s == sk) {
+                    const bool isrow = r == rk;
+                    re[s] = isrow ? rowre : nre;
+                    im[s] = isrow ? rowim : nim;
+                } else {
+                    re[s] = nre;
+                    im[s] = nim;
+                }
             }
         }
     }
@@ -479,250 +516,297 @@ __device__ void wave_solve_chunk(const cx<float> *sA, cx<float> *sB, const float
     }
 }
 
-// x rows [r0, r0 + nrows) of subcarrier n for chunk (k0, kc) from Z in slot zs;
-// this wave takes the 32-row tiles t = tile0, tile0 + tstep, ...
+// ---- channel tiles in registers -----------------------------------------------
+// A wave keeps the channel rows it precodes in registers, 32 rows per tile, in
+// the B-operand layout of the precode MFMA: lane (j, g) holds row row0 + j,
+// real columns g*UP .. g*UP + UP - 1 (users g*UP/2 .. g*UP/2 + UP/2 - 1).
+// For 16-bit MFMA the tile is kept split (hi + lo of the scaled values).
 template <int UP, int PREC>
-__device__ void wave_precode_rows(const float *Hs, const cx<float> *zs, int r0, int nrows, int k0, int kc, int n,
-                                  int n_sc, int B, float2 *__restrict__ x, int tile0, int tstep, float hsc,
-                                  float hunsc) {
+struct Tile {
+    float f[UP];
+    typename Split<PREC == kF32 ? kF16 : PREC>::V hi[UP / 8], lo[UP / 8];
+};
+
+// Loads rows [row0, row0 + nrows) of a subcarrier's channel Hn (B x U) into a
+// tile (rows >= nrows and users >= U read as 0); returns the lane's max |h|.
+template <int UP, int PREC>
+__device__ __forceinline__ float load_tile(const float2 *__restrict__ Hn, int U, int row0, int nrows, bool vec,
+                                           Tile<UP, PREC> &tl) {
+    const int lane = lane_id();
+    const int j = lane & 31, g = lane >> 5;
+    float mx = 0.f;
+    if (j < nrows) {
+        const float2 *rp = Hn + (size_t)(row0 + j) * U + g * (UP / 2);
+        if (vec) {  // U == UP, 16-byte aligned rows
+#pragma unroll
+            for (int m4 = 0; m4 < UP; m4 += 4) {
+                const float4 v = *(const float4 *)(rp + m4 / 2);
+                tl.f[m4] = v.x;
+                tl.f[m4 + 1] = v.y;
+                tl.f[m4 + 2] = v.z;
+                tl.f[m4 + 3] = v.w;
+            }
+        } else {
+#pragma unroll
+            for (int m2 = 0; m2 < UP / 2; ++m2) {
+                const int u = g * (UP / 2) + m2;
+                const float2 v = u < U ? rp[m2] : make_float2(0.f, 0.f);
+                tl.f[2 * m2] = v.x;
+                tl.f[2 * m2 + 1] = v.y;
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < UP; ++m) mx = fmaxf(mx, fabsf(tl.f[m]));
+    } else {
+#pragma unroll
+        for (int m = 0; m < UP; ++m) tl.f[m] = 0.f;
+    }
+    return mx;
+}
+
+// Writes a tile row-major into the wave's LDS scratch (row stride RS floats).
+template <int UP, int PREC>
+__device__ __forceinline__ void tile_to_lds(const Tile<UP, PREC> &tl, float *scr) {
     constexpr int RS = Shape<UP>::RS;
     const int lane = lane_id();
     const int j = lane & 31, g = lane >> 5;
-    ZOp<UP, PREC> z;
-    make_zop<UP, PREC>(zs, KC, 1, kc, z);
-    for (int t = tile0; t * 32 < nrows; t += tstep) {
-        const int rb = r0 + t * 32;
-        const int nv = min(32, nrows - t * 32);
-        const floatx16 a = mfma_apply<UP, PREC>(Hs + rb * RS, RS, nv, hsc, hunsc, z);
-        if (j < nv) {
+    float *rp = scr + j * RS + g * UP;
 #pragma unroll
-            for (int r = 0; r < 16; r += 2) {
-                const int k = tile_k(r, g);
-                if (k < kc) x[((size_t)(k0 + k) * n_sc + n) * B + rb + j] = make_float2(a[r], a[r + 1]);
-            }
+    for (int m4 = 0; m4 < UP; m4 += 4)
+        *(float4 *)(rp + m4) = make_float4(tl.f[m4], tl.f[m4 + 1], tl.f[m4 + 2], tl.f[m4 + 3]);
+}
+
+// For 16-bit MFMA: splits the tile (scaled by sc) into hi + lo once.
+template <int UP, int PREC>
+__device__ __forceinline__ void tile_split(Tile<UP, PREC> &tl, float sc) {
+    if constexpr (PREC != kF32) {
+#pragma unroll
+        for (int q = 0; q < UP / 8; ++q) {
+            float v[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[e] = tl.f[8 * q + e] * sc;
+            Split<PREC>::split(v, tl.hi[q], tl.lo[q]);
         }
     }
 }
 
-// ---- staging ----------------------------------------------------------------
-// Copies the B x U complex64 channel of one subcarrier into LDS rows of stride
-// RS floats; returns this thread's max |component| over what it stored.  Each
-// thread issues a batch of NB loads before its LDS stores, so a whole batch is
-// in flight at once.
-template <int UP>
-__device__ __forceinline__ float stage_channel(const float2 *__restrict__ Hn, float *Hs, int B, int U) {
-    constexpr int RS = Shape<UP>::RS;
-    constexpr int NB = 8;
-    const int tid = threadIdx.x;
-    float mx = 0.f;
-    const int nf = B * U;
-    for (int base = 0; base < nf; base += kThreads * NB) {
-        float2 r[NB];
+// X^T tile from a register channel tile: rows (k, re/im) of a 16-symbol
+// chunk, columns = the tile's 32 rows, times `post` (and the Z unscale).
+template <int UP, int PREC>
+__device__ __forceinline__ floatx16 mfma_apply_tile(const Tile<UP, PREC> &tl, float post, const ZOp<UP, PREC> &z) {
+    floatx16 acc = {0};
+    if constexpr (PREC == kF32) {
 #pragma unroll
-        for (int j = 0; j < NB; ++j) {
-            const int f = base + j * kThreads + tid;
-            r[j] = f < nf ? Hn[f] : make_float2(0.f, 0.f);
-        }
+        for (int m = 0; m < UP; ++m) acc = mfma32(z.f[m], tl.f[m], acc);
+        acc *= post;
+    } else {
 #pragma unroll
-        for (int j = 0; j < NB; ++j) {
-            const int f = base + j * kThreads + tid;
-            if (f < nf) {
-                const int b = f / U, u = f - b * U;
-                *(float2 *)(Hs + b * RS + 2 * u) = r[j];
-                mx = fmaxf(mx, fmaxf(fabsf(r[j].x), fabsf(r[j].y)));
-            }
-        }
+        for (int q = 0; q < UP / 8; ++q) acc = mfma3<PREC>(z.hi[q], z.lo[q], tl.hi[q], tl.lo[q], acc);
+        acc *= post * z.unscale;
     }
-    return mx;
+    return acc;
 }
 
-// Zeroes the padding users U..UP-1 of every staged row.
-template <int UP>
-__device__ __forceinline__ void zero_padding(float *Hs, int B, int U) {
-    constexpr int RS = Shape<UP>::RS;
-    if (U < UP) {
-        const int pad = UP - U;
-        for (int e = threadIdx.x; e < B * pad; e += kThreads) {
-            const int b = e / pad, u = U + (e - b * pad);
-            *(float2 *)(Hs + b * RS + 2 * u) = make_float2(0.f, 0.f);
+// Stores the X^T tile of rows [row0, row0 + nrows), symbols k0 .. k0 + kc - 1.
+__device__ __forceinline__ void store_x(const floatx16 &a, int row0, int nrows, int k0, int kc, int n, int n_sc,
+                                        int B, float2 *__restrict__ x) {
+    const int lane = lane_id();
+    const int j = lane & 31, g = lane >> 5;
+    if (j < nrows) {
+#pragma unroll
+        for (int r = 0; r < 16; r += 2) {
+            const int k = tile_k(r, g);
+            if (k < kc) x[((size_t)(k0 + k) * n_sc + n) * B + row0 + j] = make_float2(a[r], a[r + 1]);
         }
     }
-}
-
-// Register prefetch of the next subcarrier's channel: the first kPF float4
-// of each thread's share are loaded while the current subcarrier computes and
-// written to LDS afterwards (channels with an even user count only).
-constexpr int kPF = 8;
-
-__device__ __forceinline__ void prefetch_issue(float4 (&pf)[kPF], const float2 *__restrict__ Hn, int nf) {
-    const float4 *src = (const float4 *)Hn;
-#pragma unroll
-    for (int j = 0; j < kPF; ++j) {
-        const int f = j * kThreads + (int)threadIdx.x;
-        pf[j] = f < nf ? src[f] : make_float4(0.f, 0.f, 0.f, 0.f);
-    }
-}
-
-__device__ __forceinline__ float max4(float4 v) {
-    return fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w)));
 }
 
 template <int UP>
-__device__ __forceinline__ float prefetch_commit(const float4 (&pf)[kPF], const float2 *__restrict__ Hn, float *Hs,
-                                                 int B, int U) {
-    constexpr int RS = Shape<UP>::RS;
-    const int hu = U >> 1, nf = B * hu;
-    const int tid = threadIdx.x;
-    float mx = 0.f;
-#pragma unroll
-    for (int j = 0; j < kPF; ++j) {
-        const int f = j * kThreads + tid;
-        if (f < nf) {
-            const int b = f / hu, c = f - b * hu;
-            *(float4 *)(Hs + b * RS + 4 * c) = pf[j];
-            mx = fmaxf(mx, max4(pf[j]));
-        }
-    }
-    const float4 *src = (const float4 *)Hn;
-    for (int f = kPF * kThreads + tid; f < nf; f += kThreads) {
-        const int b = f / hu, c = f - b * hu;
-        const float4 v = src[f];
-        *(float4 *)(Hs + b * RS + 4 * c) = v;
-        mx = fmaxf(mx, max4(v));
-    }
-    return mx;
+struct Lds {
+    static constexpr int SCRF = 32 * Shape<UP>::RS > 2 * Shape<UP>::SLOT ? 32 * Shape<UP>::RS : 2 * Shape<UP>::SLOT;
+    // per wave: scratch (SCRF floats; Gram transpose, then partial / Z) and
+    // one system slot (SLOT complex)
+    static constexpr size_t per_wave = (size_t)SCRF * 4 + (size_t)Shape<UP>::SLOT * 8;
+    static __host__ __device__ constexpr size_t bytes(int K) { return (size_t)K * 2 * UP * 4 + 4 * per_wave; }
+};
+
+// Minimum waves per SIMD the register allocation targets (more channel tiles
+// per wave need more registers).
+template <int UP, int MAXT>
+constexpr int min_waves() {
+    return UP == 16 ? (MAXT <= 2 ? 4 : (MAXT <= 4 ? 2 : 1)) : (MAXT <= 2 ? 2 : 1);
 }
 
-template <int UP>
-__host__ __device__ constexpr size_t lds_bytes(int B, int K) {
-    return (size_t)B * Shape<UP>::RS * 4 + (size_t)K * 2 * UP * 4 + (size_t)8 * Shape<UP>::SLOT * 8;
-}
-
-// ---- the kernel -----------------------------------------------------------------
-template <int UP, int ARCH, int PREC>
-__global__ void __launch_bounds__(kThreads, UP == 16 ? 2 : 1) fused_k(Prob p, int K, const float2 *__restrict__ H,
-                                                    const float2 *__restrict__ s, float2 *__restrict__ x,
-                                                    float *__restrict__ scale_out, int *__restrict__ status) {
-    constexpr int RS = Shape<UP>::RS;
+// ---- the kernel ---------------------------------------------------------------
+// One workgroup per subcarrier.  Wave w owns up to MAXT channel tiles:
+//   PD: tiles t = w, w + 4, ... of 32 rows over the whole array;
+//   FD: the tiles (32 rows each) of cluster 4 * (group) + w.
+template <int UP, int ARCH, int PREC, int MAXT>
+__global__ void __launch_bounds__(kThreads, (min_waves<UP, MAXT>()))
+    fused_k(Prob p, int K, const float2 *__restrict__ H, const float2 *__restrict__ s, float2 *__restrict__ x,
+            float *__restrict__ scale_out, int *__restrict__ status) {
     constexpr int SLOT = Shape<UP>::SLOT;
     constexpr int NTT = Shape<UP>::NTT;
+    constexpr int SCRF = Lds<UP>::SCRF;
     extern __shared__ float4 smem4[];
-    float *Hs = (float *)smem4;
-    float *Ss = Hs + (size_t)p.B * RS;
-    cx<float> *slots = (cx<float> *)(Ss + (size_t)K * 2 * UP);
+    float *Ss = (float *)smem4;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    char *wbase = (char *)(Ss + (size_t)K * 2 * UP);
+    float *scr_of[4];
+#pragma unroll
+    for (int w = 0; w < 4; ++w) scr_of[w] = (float *)(wbase + w * Lds<UP>::per_wave);
+    float *scr = scr_of[wave];
+    cx<float> *sA = (cx<float> *)(scr + SCRF);
     __shared__ float sh_scale, sh_amax;
     __shared__ int sh_ok;
-    __shared__ float sh_hmax[4];
 
-    const int B = p.B, U = p.U;
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    cx<float> *sA = slots + (2 * wave) * SLOT;
-    cx<float> *sB = slots + (2 * wave + 1) * SLOT;
-    const bool vec = (U & 1) == 0 && (((uintptr_t)H) & 15) == 0;
-    const int nf = B * (U >> 1);
-    float4 pf[kPF];
-    if (vec && (int)blockIdx.x < p.n_sc) prefetch_issue(pf, H + (size_t)blockIdx.x * B * U, nf);
+    // PD: one workgroup per subcarrier; FD: one workgroup per (subcarrier,
+    // group of four clusters), one cluster per wave
+    const int CQ = ARCH == kPD ? 1 : (p.C + 3) / 4;
+    const int B = p.B, U = p.U, n = blockIdx.x / CQ, cq = blockIdx.x % CQ;
+    const float2 *Hn = H + (size_t)n * B * U;
+    const bool vec = U == UP && (((uintptr_t)H) & 15) == 0;
+    // cluster offsets read in place from the kernel-argument segment (p is the
+    // first argument); indexing the by-value copy would force it to scratch
+    const int *off = (const int *)((const char *)__builtin_amdgcn_kernarg_segment_ptr() + offsetof(Prob, off));
 
-    for (int n = blockIdx.x; n < p.n_sc; n += gridDim.x) {
-        // ---- stage H[n] (zero-padded to UP users) and s[:, n] in LDS ------
-        float mx = vec ? prefetch_commit<UP>(pf, H + (size_t)n * B * U, Hs, B, U)
-                       : stage_channel<UP>(H + (size_t)n * B * U, Hs, B, U);
-        zero_padding<UP>(Hs, B, U);
-        for (int e = tid; e < K * UP; e += kThreads) {
-            const int k = e / UP, u = e % UP;
-            const float2 v = (u < U) ? s[((size_t)k * p.n_sc + n) * U + u] : make_float2(0.f, 0.f);
-            *(float2 *)(Ss + k * 2 * UP + 2 * u) = v;
+    // symbols of this subcarrier
+    for (int e = tid; e < K * UP; e += kThreads) {
+        const int k = e / UP, u = e % UP;
+        const float2 v = (u < U) ? s[((size_t)k * p.n_sc + n) * U + u] : make_float2(0.f, 0.f);
+        *(float2 *)(Ss + k * 2 * UP + 2 * u) = v;
+    }
+    Tile<UP, PREC> tiles[MAXT];
+    int t_row0[MAXT], t_rows[MAXT];
+
+    if (ARCH == kPD) {
+        const float kap = pd_kappa(p);
+        // this wave's tiles: t = wave, wave + 4, ... of 32 rows
+        float hmax = 0.f;
+#pragma unroll
+        for (int q = 0; q < MAXT; ++q) {
+            const int tt = wave + 4 * q;
+            t_row0[q] = 32 * tt;
+            t_rows[q] = max(0, min(32, B - 32 * tt));
+            hmax = fmaxf(hmax, load_tile<UP, PREC>(Hn, U, t_row0[q], t_rows[q], vec, tiles[q]));
         }
-        for (int e = tid; e < 8 * SLOT; e += kThreads) slots[e] = {0.f, 0.f};
-        if (PREC != kF32) {
-            mx = wave_max(mx);
-            if (lane == 0) sh_hmax[wave] = mx;
+        // power-of-two operand scale of this wave's rows (16-bit MFMA)
+        const int eh = PREC == kF32 ? 0 : fp16_exp(wave_max(hmax));
+        const float hsc = ldexpf(1.f, eh), hunsc = ldexpf(1.f, -eh), gunsc = ldexpf(1.f, -2 * eh);
+        // split-K Gram over this wave's tiles (transposed through the scratch)
+        floatx16 acc[NTT];
+#pragma unroll
+        for (int q = 0; q < NTT; ++q) acc[q] = floatx16{0};
+#pragma unroll
+        for (int q = 0; q < MAXT; ++q) {
+            if (t_rows[q] > 0) {
+                tile_to_lds<UP, PREC>(tiles[q], scr);
+                wave_sync();
+                mfma_gram<UP, PREC>(scr, Shape<UP>::RS, t_rows[q], hsc, acc);
+                wave_sync();
+            }
+            tile_split<UP, PREC>(tiles[q], hsc);
+        }
+        cx<float> *part = (cx<float> *)scr;
+        for (int e = lane; e < SLOT; e += 64) part[e] = {0.f, 0.f};
+        wave_sync();
+        gram_store<UP>(acc, part, gunsc, 0.f, U);
+        __syncthreads();
+        // partial (cluster) sum in fixed order + kappa I, into wave 0's slot
+        cx<float> *A0 = (cx<float> *)(scr_of[0] + SCRF);
+        for (int e = tid; e < UP * UP; e += kThreads) {
+            const int u = e / UP, v = e % UP;
+            const int o = u * Shape<UP>::LDc + v;
+            cx<float> sum = ((cx<float> *)scr_of[0])[o];
+#pragma unroll
+            for (int w = 1; w < 4; ++w) sum = cadd(sum, ((cx<float> *)scr_of[w])[o]);
+            if (u == v && u < U) sum.re += kap;
+            A0[o] = sum;
         }
         __syncthreads();
-        // the next subcarrier's channel is in flight while this one computes
-        if (vec && n + (int)gridDim.x < p.n_sc) prefetch_issue(pf, H + (size_t)(n + gridDim.x) * B * U, nf);
-        // power-of-two operand scale of the channel for 16-bit MFMA
-        int eh = 0;
-        if (PREC != kF32) eh = fp16_exp(fmaxf(fmaxf(sh_hmax[0], sh_hmax[1]), fmaxf(sh_hmax[2], sh_hmax[3])));
-        const float hsc = ldexpf(1.f, eh), hunsc = ldexpf(1.f, -eh), gunsc = ldexpf(1.f, -2 * eh);
-
-        if (ARCH == kPD) {
-            const float kap = pd_kappa(p);
-            // split-K Gram: four contiguous row ranges (multiples of 16 rows)
-            const int rows_per = ((B + 63) / 64) * 16;
-            const int r0 = min(B, wave * rows_per), r1 = min(B, r0 + rows_per);
+        if (wave == 0) {
+            float t = 0.f, amax = 0.f;
+            const bool ok = wave_factor<UP>(A0, U, kap, &t, &amax);
+            const float beta = ok ? sqrtf(p.Es / p.power * t) : 0.f;
+            if (lane == 0) {
+                sh_scale = ok ? 1.f / beta : 0.f;
+                sh_ok = ok;
+                sh_amax = amax;
+                if (scale_out) scale_out[n] = beta;
+                if (status) status[n] = ok ? PRECODE_ST_OK : PRECODE_ST_FAIL;
+            }
+        }
+        __syncthreads();
+        cx<float> *Zw = (cx<float> *)scr_of[0];  // free after the partial sum
+        for (int k0 = 0; k0 < K; k0 += KC) {
+            const int kc = min(KC, K - k0);
+            if (wave == 0) wave_solve_chunk<UP, PREC>(A0, Zw, Ss, k0, kc, U, sh_scale, sh_amax, sh_ok != 0);
+            __syncthreads();
+            ZOp<UP, PREC> z;
+            make_zop<UP, PREC>(Zw, KC, 1, kc, z);
+#pragma unroll
+            for (int q = 0; q < MAXT; ++q)
+                if (t_rows[q] > 0) {
+                    const floatx16 a = mfma_apply_tile<UP, PREC>(tiles[q], hunsc, z);
+                    store_x(a, t_row0[q], t_rows[q], k0, kc, n, p.n_sc, B, x);
+                }
+            __syncthreads();
+        }
+    } else {
+        __syncthreads();  // symbols staged
+        const float kap = fd_kappa(p);
+        const float rho_c2 = p.power / (float)p.C;
+        const int c = 4 * cq + wave;
+        if (c < p.C) {
+            const int o0 = off[c], o1 = off[c + 1];
+            // this cluster's rows as tiles of 32
+            float hmax = 0.f;
+#pragma unroll
+            for (int q = 0; q < MAXT; ++q) {
+                t_row0[q] = o0 + 32 * q;
+                t_rows[q] = max(0, min(32, o1 - t_row0[q]));
+                hmax = fmaxf(hmax, load_tile<UP, PREC>(Hn, U, t_row0[q], t_rows[q], vec, tiles[q]));
+            }
+            const int eh = PREC == kF32 ? 0 : fp16_exp(wave_max(hmax));
+            const float hsc = ldexpf(1.f, eh), hunsc = ldexpf(1.f, -eh), gunsc = ldexpf(1.f, -2 * eh);
+            for (int e = lane; e < SLOT; e += 64) sA[e] = {0.f, 0.f};
             floatx16 acc[NTT];
 #pragma unroll
             for (int q = 0; q < NTT; ++q) acc[q] = floatx16{0};
-            mfma_gram<UP, PREC>(Hs + r0 * RS, RS, r1 - r0, hsc, acc);
-            gram_store<UP>(acc, sA, gunsc, 0.f, U);
-            __syncthreads();
-            // partial (cluster) sum in fixed order + kappa I, into wave 0's slot A
-            for (int e = tid; e < UP * UP; e += kThreads) {
-                const int u = e / UP, v = e % UP;
-                const int o = u * Shape<UP>::LDc + v;
-                cx<float> sum = slots[o];
 #pragma unroll
-                for (int w = 1; w < 4; ++w) sum = cadd(sum, slots[2 * w * SLOT + o]);
-                if (u == v && u < U) sum.re += kap;
-                slots[o] = sum;
-            }
-            __syncthreads();
-            if (wave == 0) {
-                float t = 0.f, amax = 0.f;
-                const bool ok = wave_factor<UP>(sA, U, kap, &t, &amax);
-                const float beta = ok ? sqrtf(p.Es / p.power * t) : 0.f;
-                if (lane == 0) {
-                    sh_scale = ok ? 1.f / beta : 0.f;
-                    sh_ok = ok;
-                    sh_amax = amax;
-                    if (scale_out) scale_out[n] = beta;
-                    if (status) status[n] = ok ? PRECODE_ST_OK : PRECODE_ST_FAIL;
+            for (int q = 0; q < MAXT; ++q)
+                if (t_rows[q] > 0) {
+                    tile_to_lds<UP, PREC>(tiles[q], scr);
+                    wave_sync();
+                    mfma_gram<UP, PREC>(scr, Shape<UP>::RS, t_rows[q], hsc, acc);
+                    wave_sync();
+                    tile_split<UP, PREC>(tiles[q], hsc);
                 }
+            gram_store<UP>(acc, sA, gunsc, kap, U);
+            wave_sync();
+            float t = 0.f, amax = 0.f;
+            const bool ok = wave_factor<UP>(sA, U, kap, &t, &amax);
+            const float w = ok ? sqrtf(rho_c2 / (t * p.Es)) : 0.f;
+            if (lane == 0) {
+                if (scale_out) scale_out[(size_t)n * p.C + c] = w;
+                if (status) status[(size_t)n * p.C + c] = ok ? PRECODE_ST_OK : PRECODE_ST_FAIL;
             }
-            __syncthreads();
-            const cx<float> *z0 = slots + SLOT;  // wave 0's slot B
+            cx<float> *Zw = (cx<float> *)scr;
             for (int k0 = 0; k0 < K; k0 += KC) {
                 const int kc = min(KC, K - k0);
-                if (wave == 0) wave_solve_chunk<UP, PREC>(sA, sB, Ss, k0, kc, U, sh_scale, sh_amax, sh_ok != 0);
-                __syncthreads();
-                wave_precode_rows<UP, PREC>(Hs, z0, 0, B, k0, kc, n, p.n_sc, B, x, wave, 4, hsc, hunsc);
-                __syncthreads();
-            }
-        } else {
-            const float kap = fd_kappa(p);
-            const float rho_c2 = p.power / (float)p.C;
-            for (int c = wave; c < p.C; c += 4) {
-                const int o = p.off[c], Bc = p.off[c + 1] - o;
-                for (int e = lane; e < SLOT; e += 64) {
-                    sA[e] = {0.f, 0.f};
-                    sB[e] = {0.f, 0.f};
-                }
                 wave_sync();
-                floatx16 acc[NTT];
+                wave_solve_chunk<UP, PREC>(sA, Zw, Ss, k0, kc, U, w, amax, ok);
+                wave_sync();
+                ZOp<UP, PREC> z;
+                make_zop<UP, PREC>(Zw, KC, 1, kc, z);
 #pragma unroll
-                for (int q = 0; q < NTT; ++q) acc[q] = floatx16{0};
-                mfma_gram<UP, PREC>(Hs + o * RS, RS, Bc, hsc, acc);
-                gram_store<UP>(acc, sA, gunsc, kap, U);
-                wave_sync();
-                float t = 0.f, amax = 0.f;
-                const bool ok = wave_factor<UP>(sA, U, kap, &t, &amax);
-                const float w = ok ? sqrtf(rho_c2 / (t * p.Es)) : 0.f;
-                if (lane == 0) {
-                    if (scale_out) scale_out[(size_t)n * p.C + c] = w;
-                    if (status) status[(size_t)n * p.C + c] = ok ? PRECODE_ST_OK : PRECODE_ST_FAIL;
-                }
-                wave_sync();
-                for (int k0 = 0; k0 < K; k0 += KC) {
-                    const int kc = min(KC, K - k0);
-                    wave_solve_chunk<UP, PREC>(sA, sB, Ss, k0, kc, U, w, amax, ok);
-                    wave_sync();
-                    wave_precode_rows<UP, PREC>(Hs, sB, o, Bc, k0, kc, n, p.n_sc, B, x, 0, 1, hsc, hunsc);
-                    wave_sync();
-                }
+                for (int q = 0; q < MAXT; ++q)
+                    if (t_rows[q] > 0) {
+                        const floatx16 a = mfma_apply_tile<UP, PREC>(tiles[q], hunsc, z);
+                        store_x(a, t_row0[q], t_rows[q], k0, kc, n, p.n_sc, B, x);
+                    }
             }
         }
-        __syncthreads();  // every LDS read of this subcarrier precedes the next staging
     }
 }
 
@@ -737,41 +821,64 @@ int prec_of(int precision) {
     }
 }
 
+// Channel tiles (32 rows) a wave holds in registers.
+int tiles_per_wave(const Prob &p) {
+    if (p.arch == kPD) return ((p.B + 31) / 32 + 3) / 4;
+    int worst = 0;  // FD: a wave holds one cluster at a time
+    for (int c = 0; c < p.C; ++c) {
+        const int n = (p.off[c + 1] - p.off[c] + 31) / 32;
+        worst = n > worst ? n : worst;
+    }
+    return worst;
+}
+
+int pick_maxt(const Prob &p, int up) {
+    const int t = tiles_per_wave(p);
+    const int lim = up == 16 ? 8 : 4;
+    if (t <= 1) return 1;
+    if (t <= 2) return 2;
+    if (t <= 4) return 4;
+    if (t <= 8 && lim >= 8) return 8;
+    return 0;
+}
+
 constexpr size_t kLdsMax = 160 * 1024;
 
-template <int UP, int ARCH, int PREC>
+template <int UP, int ARCH, int PREC, int MAXT>
 hipError_t launch(const Prob &p, int K, const float2 *H, const float2 *s, float2 *x, float *scale_out, int *status,
                   hipStream_t st) {
-    const void *fn = (const void *)fused_k<UP, ARCH, PREC>;
-    const size_t lds = lds_bytes<UP>(p.B, K);
+    const void *fn = (const void *)fused_k<UP, ARCH, PREC, MAXT>;
+    const size_t lds = Lds<UP>::bytes(K);
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    // persistent grid: as many workgroups as fit on the device at once
-    static int cached_lds = -1, cached_grid = 0;
-    if (cached_lds != (int)lds) {
-        int dev = 0, cus = 0, per_cu = 0;
-        hipError_t e = hipGetDevice(&dev);
-        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads, lds);
-        if (e != hipSuccess) return e;
-        cached_grid = (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
-        cached_lds = (int)lds;
-    }
-    const int grid = p.n_sc < cached_grid ? p.n_sc : cached_grid;
-    hipLaunchKernelGGL((fused_k<UP, ARCH, PREC>), dim3(grid), dim3(kThreads), lds, st, p, K, H, s, x, scale_out,
-                       status);
+    const unsigned grid = (unsigned)p.n_sc * (ARCH == kPD ? 1u : (unsigned)((p.C + 3) / 4));
+    hipLaunchKernelGGL((fused_k<UP, ARCH, PREC, MAXT>), dim3(grid), dim3(kThreads), lds, st, p, K, H, s, x,
+                       scale_out, status);
     return hipGetLastError();
 }
 
+template <int UP, int ARCH, int PREC>
+hipError_t launch_t(int maxt, const Prob &p, int K, const float2 *H, const float2 *s, float2 *x, float *so, int *sto,
+                    hipStream_t st) {
+    switch (maxt) {
+        case 1: return launch<UP, ARCH, PREC, 1>(p, K, H, s, x, so, sto, st);
+        case 2: return launch<UP, ARCH, PREC, 2>(p, K, H, s, x, so, sto, st);
+        case 4: return launch<UP, ARCH, PREC, 4>(p, K, H, s, x, so, sto, st);
+        default:
+            if constexpr (UP == 16) return launch<UP, ARCH, PREC, 8>(p, K, H, s, x, so, sto, st);
+            return hipErrorNotSupported;
+    }
+}
+
 template <int UP, int ARCH>
-hipError_t launch_prec(int prec, const Prob &p, int K, const float2 *H, const float2 *s, float2 *x, float *so,
-                       int *sto, hipStream_t st) {
+hipError_t launch_prec(int prec, int maxt, const Prob &p, int K, const float2 *H, const float2 *s, float2 *x,
+                       float *so, int *sto, hipStream_t st) {
     switch (prec) {
-        case kF32: return launch<UP, ARCH, kF32>(p, K, H, s, x, so, sto, st);
-        case kF16: return launch<UP, ARCH, kF16>(p, K, H, s, x, so, sto, st);
-        default: return launch<UP, ARCH, kBF16>(p, K, H, s, x, so, sto, st);
+        case kF32: return launch_t<UP, ARCH, kF32>(maxt, p, K, H, s, x, so, sto, st);
+        case kF16: return launch_t<UP, ARCH, kF16>(maxt, p, K, H, s, x, so, sto, st);
+        default: return launch_t<UP, ARCH, kBF16>(maxt, p, K, H, s, x, so, sto, st);
     }
 }
 
@@ -781,8 +888,9 @@ bool fused_supported(const Prob &p, int precision) {
     if (prec_of(precision) < 0) return false;
     const int up = pick_up(p.U);
     if (up == 0) return false;
+    if (pick_maxt(p, up) == 0) return false;
     const int kmax = p.K < kMaxKFused ? p.K : kMaxKFused;
-    const size_t lds = up == 16 ? lds_bytes<16>(p.B, kmax) : lds_bytes<32>(p.B, kmax);
+    const size_t lds = up == 16 ? Lds<16>::bytes(kmax) : Lds<32>::bytes(kmax);
     if (lds > kLdsMax - 256) return false;
     if (p.arch == kPD) return p.pd_fp64 == 0;
     for (int c = 0; c < p.C; ++c) {
@@ -798,6 +906,7 @@ hipError_t fused_run(const Prob &p, int precision, const float2 *H, const float2
     if (p.n_sc == 0) return hipSuccess;
     const int up = pick_up(p.U);
     const int prec = prec_of(precision);
+    const int maxt = pick_maxt(p, up);
     for (int k0 = 0; k0 < p.K; k0 += kMaxKFused) {
         const int kk = p.K - k0 < kMaxKFused ? p.K - k0 : kMaxKFused;
         const float2 *sk = s + (size_t)k0 * p.n_sc * p.U;
@@ -807,11 +916,11 @@ hipError_t fused_run(const Prob &p, int precision, const float2 *H, const float2
         int *sto = k0 == 0 ? status : nullptr;
         hipError_t e;
         if (up == 16)
-            e = p.arch == kPD ? launch_prec<16, kPD>(prec, p, kk, H, sk, xk, so, sto, st)
-                              : launch_prec<16, kFD>(prec, p, kk, H, sk, xk, so, sto, st);
+            e = p.arch == kPD ? launch_prec<16, kPD>(prec, maxt, p, kk, H, sk, xk, so, sto, st)
+                              : launch_prec<16, kFD>(prec, maxt, p, kk, H, sk, xk, so, sto, st);
         else
-            e = p.arch == kPD ? launch_prec<32, kPD>(prec, p, kk, H, sk, xk, so, sto, st)
-                              : launch_prec<32, kFD>(prec, p, kk, H, sk, xk, so, sto, st);
+            e = p.arch == kPD ? launch_prec<32, kPD>(prec, maxt, p, kk, H, sk, xk, so, sto, st)
+                              : launch_prec<32, kFD>(prec, maxt, p, kk, H, sk, xk, so, sto, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
