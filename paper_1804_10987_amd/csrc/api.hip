@@ -16,8 +16,10 @@ using namespace pc;
 struct precode_frame {
     Prob prob;
     const float2 *H;
-    void *ainv;     // plain-layout A^-1 (complex<T> slots)
-    void *scale;    // plain-layout scale (T)
+    int fused;      // state from the fused prepare pass (else from the plain kernels)
+    int precision;
+    void *ainv;     // fused: scale * A^-1 (n_inst x U x U complex64); plain: A^-1 slots (complex<T>)
+    void *scale;    // plain-layout scale (T); unused when fused
     float *scale_out;
     int *status;
     size_t bytes;
@@ -268,11 +270,15 @@ int precode_frame_prepare(precode_ctx *ctx, int arch, const void *H, float rho, 
     int rc = make_prob(arch, rho, cluster_sizes, C, mode, B, U, n_sc, 1, q, &p);
     if (rc) return rc;
     if (n_sc > 0 && (!H || !aligned8(H))) return PRECODE_EINVAL;
-    if (q.precision == PRECODE_PREC_SPLIT_FP16 || q.precision == PRECODE_PREC_SPLIT_BF16) return PRECODE_EUNSUPPORTED;
-    // resident state: A^-1 slots, scale, beta/weights, status, plus the
-    // Gram workspace while preparing
+    const bool fuse = q.impl != PRECODE_IMPL_PLAIN && q.refine_steps == 0 && fused_supported(p, q.precision);
+    if (q.impl == PRECODE_IMPL_FUSED && !fuse) return PRECODE_EUNSUPPORTED;
+    if ((q.precision == PRECODE_PREC_SPLIT_FP16 || q.precision == PRECODE_PREC_SPLIT_BF16) && !fuse)
+        return PRECODE_EUNSUPPORTED;
+    // resident state: factors (fused: scale * A^-1; plain: A^-1 slots and
+    // scale), beta / weights and status
     const size_t ni = (size_t)n_inst(p);
-    const size_t bA = plain_ws_bytes_A(p), bS = plain_ws_bytes_scale(p);
+    const size_t bA = fuse ? ni * p.U * p.U * sizeof(float2) : plain_ws_bytes_A(p);
+    const size_t bS = fuse ? 0 : plain_ws_bytes_scale(p);
     const size_t bytes = bA + bS + ni * sizeof(float) + ni * sizeof(int) + 64;
     precode_frame *f = new (std::nothrow) precode_frame;
     if (!f) return PRECODE_ENOMEM;
@@ -285,18 +291,28 @@ int precode_frame_prepare(precode_ctx *ctx, int arch, const void *H, float rho, 
     f->bytes = bytes;
     f->prob = p;
     f->H = (const float2 *)H;
+    f->fused = fuse;
+    f->precision = q.precision;
     f->scale = (char *)f->ainv + bA;
     f->scale_out = (float *)((char *)f->scale + bS);
     f->status = (int *)((char *)f->scale_out + ((ni * sizeof(float) + 7) & ~(size_t)7));
-    rc = grow(ctx, &ctx->wsA, &ctx->capA, bA);
-    if (!rc && n_sc > 0)
-        rc = dev_err(plain_prepare(p, (const float2 *)H, f->scale_out, f->status, ctx->wsA, f->ainv, f->scale,
-                                   (hipStream_t)stream));
+    if (n_sc > 0) {
+        if (fuse) {
+            rc = dev_err(fused_prepare(p, q.precision, (const float2 *)H, (float2 *)f->ainv, f->scale_out, f->status,
+                                       (hipStream_t)stream));
+        } else {
+            rc = grow(ctx, &ctx->wsA, &ctx->capA, bA);
+            if (!rc)
+                rc = dev_err(plain_prepare(p, (const float2 *)H, f->scale_out, f->status, ctx->wsA, f->ainv,
+                                           f->scale, (hipStream_t)stream));
+        }
+    }
     if (rc) {
         ctx_free(ctx, f->ainv, f->bytes);
         delete f;
         return rc;
     }
+    if (rc == PRECODE_OK) ctx->last_impl = fuse ? PRECODE_IMPL_FUSED : PRECODE_IMPL_PLAIN;
     f->next = ctx->frames;
     ctx->frames = f;
     *out = f;
@@ -311,6 +327,9 @@ int precode_frame_symbols(precode_ctx *ctx, precode_frame *f, const void *s, int
     if (!s || !x || !aligned8(s) || !aligned8(x)) return PRECODE_EINVAL;
     Prob p = f->prob;
     p.K = nk;
+    if (f->fused)
+        return dev_err(fused_symbols(p, f->precision, nk, f->H, (const float2 *)f->ainv, (const float2 *)s,
+                                     (float2 *)x, (hipStream_t)stream));
     int rc = grow(ctx, &ctx->wsZ, &ctx->capZ, plain_ws_bytes_z(p, nk));
     if (rc) return rc;
     return dev_err(plain_symbols(p, nk, f->H, (const float2 *)s, (float2 *)x, f->ainv, f->scale, ctx->wsZ,

@@ -98,5 +98,13 @@ size_t plain_ws_bytes_z(const Prob &p, int K);
 bool fused_supported(const Prob &p, int precision);
 hipError_t fused_run(const Prob &p, int precision, const float2 *H, const float2 *s, float2 *x,
                      float *scale_out, int *status, hipStream_t st);
+// Frame split of the fused kernel: prepare writes scale * A^-1 per instance
+// (n_inst x U x U complex64, scale = 1/beta for PD, w_c for FD, zero for a
+// failed instance) with beta / weights and status; symbols precodes nk symbols
+// from it.
+hipError_t fused_prepare(const Prob &p, int precision, const float2 *H, float2 *ainv, float *scale_out, int *status,
+                         hipStream_t st);
+hipError_t fused_symbols(const Prob &p, int precision, int nk, const float2 *H, const float2 *ainv, const float2 *s,
+                         float2 *x, hipStream_t st);
 
 }  // namespace pc

@@ -630,6 +630,40 @@ struct Lds {
     static __host__ __device__ constexpr size_t bytes(int K) { return (size_t)K * 2 * UP * 4 + 4 * per_wave; }
 };
 
+// Kernel modes: the whole frame, the per-frame part only (factors to
+// global memory), or the per-symbol part from stored factors.
+enum Mode { kFull = 0, kPrepare = 1, kSymbols = 2 };
+
+// scale * A^-1 (m x m, from an LDS slot) to global memory, row-major m x m;
+// scale = 0 (a failed instance) stores zeros.
+template <int UP>
+__device__ __forceinline__ void store_factor(const cx<float> *S, int m, float scale, cx<float> *__restrict__ g) {
+    constexpr int LDc = Shape<UP>::LDc;
+    for (int e = lane_id(); e < m * m; e += 64) {
+        const int i = e / m, j = e - i * m;
+        const cx<float> v = S[i * LDc + j];
+        g[e] = scale != 0.f ? cx<float>{v.re * scale, v.im * scale} : cx<float>{0.f, 0.f};
+    }
+}
+
+// Loads a stored factor into a zeroed-then-filled LDS slot; returns max |entry|.
+template <int UP>
+__device__ __forceinline__ float load_factor(const cx<float> *__restrict__ g, int m, cx<float> *S) {
+    constexpr int LDc = Shape<UP>::LDc;
+    constexpr int SLOT = Shape<UP>::SLOT;
+    for (int e = lane_id(); e < SLOT; e += 64) S[e] = {0.f, 0.f};
+    wave_sync();
+    float mx = 0.f;
+    for (int e = lane_id(); e < m * m; e += 64) {
+        const int i = e / m, j = e - i * m;
+        const cx<float> v = g[e];
+        S[i * LDc + j] = v;
+        mx = fmaxf(mx, fmaxf(fabsf(v.re), fabsf(v.im)));
+    }
+    wave_sync();
+    return wave_max(mx);
+}
+
 // Minimum waves per SIMD the register allocation targets (more channel tiles
 // per wave need more registers).
 template <int UP, int MAXT>
@@ -643,8 +677,9 @@ constexpr int min_waves() {
 //   FD: the tiles (32 rows each) of cluster 4 * (group) + w.
 template <int UP, int ARCH, int PREC, int MAXT>
 __global__ void __launch_bounds__(kThreads, (min_waves<UP, MAXT>()))
-    fused_k(Prob p, int K, const float2 *__restrict__ H, const float2 *__restrict__ s, float2 *__restrict__ x,
-            float *__restrict__ scale_out, int *__restrict__ status) {
+    fused_k(Prob p, int K, int mode, const float2 *__restrict__ H, const float2 *__restrict__ s,
+            float2 *__restrict__ x, cx<float> *__restrict__ ainv_g, float *__restrict__ scale_out,
+            int *__restrict__ status) {
     constexpr int SLOT = Shape<UP>::SLOT;
     constexpr int NTT = Shape<UP>::NTT;
     constexpr int SCRF = Lds<UP>::SCRF;
@@ -693,6 +728,21 @@ __global__ void __launch_bounds__(kThreads, (min_waves<UP, MAXT>()))
         // power-of-two operand scale of this wave's rows (16-bit MFMA)
         const int eh = PREC == kF32 ? 0 : fp16_exp(wave_max(hmax));
         const float hsc = ldexpf(1.f, eh), hunsc = ldexpf(1.f, -eh), gunsc = ldexpf(1.f, -2 * eh);
+        cx<float> *A0 = (cx<float> *)(scr_of[0] + SCRF);
+        if (mode == kSymbols) {
+            // per-frame factors from the prepare pass: scale * A^-1
+#pragma unroll
+            for (int q = 0; q < MAXT; ++q) tile_split<UP, PREC>(tiles[q], hsc);
+            if (wave == 0) {
+                const float amax = load_factor<UP>(ainv_g + (size_t)n * U * U, U, A0);
+                if (lane == 0) {
+                    sh_scale = 1.f;
+                    sh_ok = 1;
+                    sh_amax = amax;
+                }
+            }
+            __syncthreads();
+        } else {
         // split-K Gram over this wave's tiles (transposed through the scratch)
         floatx16 acc[NTT];
 #pragma unroll
@@ -713,7 +763,6 @@ __global__ void __launch_bounds__(kThreads, (min_waves<UP, MAXT>()))
         gram_store<UP>(acc, part, gunsc, 0.f, U);
         __syncthreads();
         // partial (cluster) sum in fixed order + kappa I, into wave 0's slot
-        cx<float> *A0 = (cx<float> *)(scr_of[0] + SCRF);
         for (int e = tid; e < UP * UP; e += kThreads) {
             const int u = e / UP, v = e % UP;
             const int o = u * Shape<UP>::LDc + v;
@@ -735,10 +784,12 @@ __global__ void __launch_bounds__(kThreads, (min_waves<UP, MAXT>()))
                 if (scale_out) scale_out[n] = beta;
                 if (status) status[n] = ok ? PRECODE_ST_OK : PRECODE_ST_FAIL;
             }
+            if (mode == kPrepare) store_factor<UP>(A0, U, ok ? 1.f / beta : 0.f, ainv_g + (size_t)n * U * U);
         }
         __syncthreads();
+        }
         cx<float> *Zw = (cx<float> *)scr_of[0];  // free after the partial sum
-        for (int k0 = 0; k0 < K; k0 += KC) {
+        for (int k0 = 0; mode != kPrepare && k0 < K; k0 += KC) {
             const int kc = min(KC, K - k0);
             if (wave == 0) wave_solve_chunk<UP, PREC>(A0, Zw, Ss, k0, kc, U, sh_scale, sh_amax, sh_ok != 0);
             __syncthreads();
@@ -769,30 +820,40 @@ __global__ void __launch_bounds__(kThreads, (min_waves<UP, MAXT>()))
             }
             const int eh = PREC == kF32 ? 0 : fp16_exp(wave_max(hmax));
             const float hsc = ldexpf(1.f, eh), hunsc = ldexpf(1.f, -eh), gunsc = ldexpf(1.f, -2 * eh);
-            for (int e = lane; e < SLOT; e += 64) sA[e] = {0.f, 0.f};
-            floatx16 acc[NTT];
+            cx<float> *fac = ainv_g + ((size_t)n * p.C + c) * U * U;
+            float w = 1.f, amax = 0.f;
+            bool ok = true;
+            if (mode == kSymbols) {
 #pragma unroll
-            for (int q = 0; q < NTT; ++q) acc[q] = floatx16{0};
+                for (int q = 0; q < MAXT; ++q) tile_split<UP, PREC>(tiles[q], hsc);
+                amax = load_factor<UP>(fac, U, sA);
+            } else {
+                for (int e = lane; e < SLOT; e += 64) sA[e] = {0.f, 0.f};
+                floatx16 acc[NTT];
 #pragma unroll
-            for (int q = 0; q < MAXT; ++q)
-                if (t_rows[q] > 0) {
-                    tile_to_lds<UP, PREC>(tiles[q], scr);
-                    wave_sync();
-                    mfma_gram<UP, PREC>(scr, Shape<UP>::RS, t_rows[q], hsc, acc);
-                    wave_sync();
-                    tile_split<UP, PREC>(tiles[q], hsc);
+                for (int q = 0; q < NTT; ++q) acc[q] = floatx16{0};
+#pragma unroll
+                for (int q = 0; q < MAXT; ++q)
+                    if (t_rows[q] > 0) {
+                        tile_to_lds<UP, PREC>(tiles[q], scr);
+                        wave_sync();
+                        mfma_gram<UP, PREC>(scr, Shape<UP>::RS, t_rows[q], hsc, acc);
+                        wave_sync();
+                        tile_split<UP, PREC>(tiles[q], hsc);
+                    }
+                gram_store<UP>(acc, sA, gunsc, kap, U);
+                wave_sync();
+                float t = 0.f;
+                ok = wave_factor<UP>(sA, U, kap, &t, &amax);
+                w = ok ? sqrtf(rho_c2 / (t * p.Es)) : 0.f;
+                if (lane == 0) {
+                    if (scale_out) scale_out[(size_t)n * p.C + c] = w;
+                    if (status) status[(size_t)n * p.C + c] = ok ? PRECODE_ST_OK : PRECODE_ST_FAIL;
                 }
-            gram_store<UP>(acc, sA, gunsc, kap, U);
-            wave_sync();
-            float t = 0.f, amax = 0.f;
-            const bool ok = wave_factor<UP>(sA, U, kap, &t, &amax);
-            const float w = ok ? sqrtf(rho_c2 / (t * p.Es)) : 0.f;
-            if (lane == 0) {
-                if (scale_out) scale_out[(size_t)n * p.C + c] = w;
-                if (status) status[(size_t)n * p.C + c] = ok ? PRECODE_ST_OK : PRECODE_ST_FAIL;
+                if (mode == kPrepare) store_factor<UP>(sA, U, w, fac);
             }
             cx<float> *Zw = (cx<float> *)scr;
-            for (int k0 = 0; k0 < K; k0 += KC) {
+            for (int k0 = 0; mode != kPrepare && k0 < K; k0 += KC) {
                 const int kc = min(KC, K - k0);
                 wave_sync();
                 wave_solve_chunk<UP, PREC>(sA, Zw, Ss, k0, kc, U, w, amax, ok);
@@ -844,9 +905,18 @@ int pick_maxt(const Prob &p, int up) {
 
 constexpr size_t kLdsMax = 160 * 1024;
 
+struct Call {
+    int K, mode;
+    const float2 *H, *s;
+    float2 *x;
+    cx<float> *ainv;
+    float *scale_out;
+    int *status;
+};
+
 template <int UP, int ARCH, int PREC, int MAXT>
-hipError_t launch(const Prob &p, int K, const float2 *H, const float2 *s, float2 *x, float *scale_out, int *status,
-                  hipStream_t st) {
+hipError_t launch(const Prob &p, const Call &a, hipStream_t st) {
+    const int K = a.K;
     const void *fn = (const void *)fused_k<UP, ARCH, PREC, MAXT>;
     const size_t lds = Lds<UP>::bytes(K);
     if (lds > 64 * 1024) {
@@ -854,32 +924,59 @@ hipError_t launch(const Prob &p, int K, const float2 *H, const float2 *s, float2
         if (e != hipSuccess) return e;
     }
     const unsigned grid = (unsigned)p.n_sc * (ARCH == kPD ? 1u : (unsigned)((p.C + 3) / 4));
-    hipLaunchKernelGGL((fused_k<UP, ARCH, PREC, MAXT>), dim3(grid), dim3(kThreads), lds, st, p, K, H, s, x,
-                       scale_out, status);
+    hipLaunchKernelGGL((fused_k<UP, ARCH, PREC, MAXT>), dim3(grid), dim3(kThreads), lds, st, p, K, a.mode, a.H,
+                       a.s, a.x, a.ainv, a.scale_out, a.status);
     return hipGetLastError();
 }
 
 template <int UP, int ARCH, int PREC>
-hipError_t launch_t(int maxt, const Prob &p, int K, const float2 *H, const float2 *s, float2 *x, float *so, int *sto,
-                    hipStream_t st) {
+hipError_t launch_t(int maxt, const Prob &p, const Call &a, hipStream_t st) {
     switch (maxt) {
-        case 1: return launch<UP, ARCH, PREC, 1>(p, K, H, s, x, so, sto, st);
-        case 2: return launch<UP, ARCH, PREC, 2>(p, K, H, s, x, so, sto, st);
-        case 4: return launch<UP, ARCH, PREC, 4>(p, K, H, s, x, so, sto, st);
+        case 1: return launch<UP, ARCH, PREC, 1>(p, a, st);
+        case 2: return launch<UP, ARCH, PREC, 2>(p, a, st);
+        case 4: return launch<UP, ARCH, PREC, 4>(p, a, st);
         default:
-            if constexpr (UP == 16) return launch<UP, ARCH, PREC, 8>(p, K, H, s, x, so, sto, st);
+            if constexpr (UP == 16) return launch<UP, ARCH, PREC, 8>(p, a, st);
             return hipErrorNotSupported;
     }
 }
 
 template <int UP, int ARCH>
-hipError_t launch_prec(int prec, int maxt, const Prob &p, int K, const float2 *H, const float2 *s, float2 *x,
-                       float *so, int *sto, hipStream_t st) {
+hipError_t launch_prec(int prec, int maxt, const Prob &p, const Call &a, hipStream_t st) {
     switch (prec) {
-        case kF32: return launch_t<UP, ARCH, kF32>(maxt, p, K, H, s, x, so, sto, st);
-        case kF16: return launch_t<UP, ARCH, kF16>(maxt, p, K, H, s, x, so, sto, st);
-        default: return launch_t<UP, ARCH, kBF16>(maxt, p, K, H, s, x, so, sto, st);
+        case kF32: return launch_t<UP, ARCH, kF32>(maxt, p, a, st);
+        case kF16: return launch_t<UP, ARCH, kF16>(maxt, p, a, st);
+        default: return launch_t<UP, ARCH, kBF16>(maxt, p, a, st);
     }
+}
+
+// Launches one mode over symbol slices of at most kMaxKFused.
+hipError_t run_mode(const Prob &p, int precision, int mode, int K, const float2 *H, const float2 *s, float2 *x,
+                    cx<float> *ainv, float *scale_out, int *status, hipStream_t st) {
+    const int up = pick_up(p.U);
+    const int prec = prec_of(precision);
+    const int maxt = pick_maxt(p, up);
+    for (int k0 = 0; k0 < K || (k0 == 0 && mode == kPrepare); k0 += kMaxKFused) {
+        const int kk = mode == kPrepare ? 0 : (K - k0 < kMaxKFused ? K - k0 : kMaxKFused);
+        Call a;
+        a.K = kk;
+        a.mode = mode;
+        a.H = H;
+        a.s = s ? s + (size_t)k0 * p.n_sc * p.U : nullptr;
+        a.x = x ? x + (size_t)k0 * p.n_sc * p.B : nullptr;
+        a.ainv = ainv;
+        // factors are identical for every slice; write them once
+        a.scale_out = k0 == 0 ? scale_out : nullptr;
+        a.status = k0 == 0 ? status : nullptr;
+        hipError_t e;
+        if (up == 16)
+            e = p.arch == kPD ? launch_prec<16, kPD>(prec, maxt, p, a, st) : launch_prec<16, kFD>(prec, maxt, p, a, st);
+        else
+            e = p.arch == kPD ? launch_prec<32, kPD>(prec, maxt, p, a, st) : launch_prec<32, kFD>(prec, maxt, p, a, st);
+        if (e != hipSuccess) return e;
+        if (mode == kPrepare) break;
+    }
+    return hipSuccess;
 }
 
 }  // namespace
@@ -889,8 +986,7 @@ bool fused_supported(const Prob &p, int precision) {
     const int up = pick_up(p.U);
     if (up == 0) return false;
     if (pick_maxt(p, up) == 0) return false;
-    const int kmax = p.K < kMaxKFused ? p.K : kMaxKFused;
-    const size_t lds = up == 16 ? Lds<16>::bytes(kmax) : Lds<32>::bytes(kmax);
+    const size_t lds = up == 16 ? Lds<16>::bytes(kMaxKFused) : Lds<32>::bytes(kMaxKFused);
     if (lds > kLdsMax - 256) return false;
     if (p.arch == kPD) return p.pd_fp64 == 0;
     for (int c = 0; c < p.C; ++c) {
@@ -904,26 +1000,22 @@ hipError_t fused_run(const Prob &p, int precision, const float2 *H, const float2
                      int *status, hipStream_t st) {
     if (!fused_supported(p, precision)) return hipErrorNotSupported;
     if (p.n_sc == 0) return hipSuccess;
-    const int up = pick_up(p.U);
-    const int prec = prec_of(precision);
-    const int maxt = pick_maxt(p, up);
-    for (int k0 = 0; k0 < p.K; k0 += kMaxKFused) {
-        const int kk = p.K - k0 < kMaxKFused ? p.K - k0 : kMaxKFused;
-        const float2 *sk = s + (size_t)k0 * p.n_sc * p.U;
-        float2 *xk = x + (size_t)k0 * p.n_sc * p.B;
-        // factors are identical for every slice; write them once
-        float *so = k0 == 0 ? scale_out : nullptr;
-        int *sto = k0 == 0 ? status : nullptr;
-        hipError_t e;
-        if (up == 16)
-            e = p.arch == kPD ? launch_prec<16, kPD>(prec, maxt, p, kk, H, sk, xk, so, sto, st)
-                              : launch_prec<16, kFD>(prec, maxt, p, kk, H, sk, xk, so, sto, st);
-        else
-            e = p.arch == kPD ? launch_prec<32, kPD>(prec, maxt, p, kk, H, sk, xk, so, sto, st)
-                              : launch_prec<32, kFD>(prec, maxt, p, kk, H, sk, xk, so, sto, st);
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+    // full path: factors are written by the first slice only (ainv unused)
+    return run_mode(p, precision, kFull, p.K, H, s, x, nullptr, scale_out, status, st);
+}
+
+hipError_t fused_prepare(const Prob &p, int precision, const float2 *H, float2 *ainv, float *scale_out, int *status,
+                         hipStream_t st) {
+    if (!fused_supported(p, precision)) return hipErrorNotSupported;
+    if (p.n_sc == 0) return hipSuccess;
+    return run_mode(p, precision, kPrepare, 0, H, nullptr, nullptr, (cx<float> *)ainv, scale_out, status, st);
+}
+
+hipError_t fused_symbols(const Prob &p, int precision, int nk, const float2 *H, const float2 *ainv, const float2 *s,
+                         float2 *x, hipStream_t st) {
+    if (!fused_supported(p, precision)) return hipErrorNotSupported;
+    if (p.n_sc == 0 || nk == 0) return hipSuccess;
+    return run_mode(p, precision, kSymbols, nk, H, s, x, (cx<float> *)ainv, nullptr, nullptr, st);
 }
 
 }  // namespace pc

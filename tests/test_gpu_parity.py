@@ -190,18 +190,23 @@ def test_deterministic(torch, ctx, pc):
         assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("impl,prec,tol", [("fused", "fp32", 1e-5), ("plain", "fp32", 1e-5),
+                                            ("fused", "split_fp16", 1e-5)])
 @pytest.mark.parametrize("arch", ["pd", "fd"])
-def test_frame_symbols_match_one_shot(torch, ctx, pc, arch):
+def test_frame_symbols_match_one_shot(torch, ctx, pc, arch, impl, prec, tol):
+    """Per-frame factors kept resident, symbols precoded one (and several) at a
+    time, equal the oracle's one-shot frame."""
     cell = synth.Cell(B=64, sizes=(32, 32), U=8, n_sc=16, K=14)
     H, s = synth.make_cell(cell, seed=2)
     Hd, sd = _dev(torch, H), _dev(torch, s)
-    f = ctx.frame(arch, Hd, cell.kappa, cell.sizes, "wf", pc.params(fp64_ratio=2.0))
-    xs = [f.symbols(sd[k:k + 1]) for k in range(cell.K)]
+    f = ctx.frame(arch, Hd, cell.kappa, cell.sizes, "wf", pc.params(fp64_ratio=2.0, impl=impl, precision=prec))
+    assert ctx.last_impl == impl
+    xs = [f.symbols(sd[k:k + 1]) for k in range(4)] + [f.symbols(sd[4:])]
     sc, st = f.factors()
     torch.cuda.synchronize()
     xg = torch.cat(xs).cpu().numpy()
     xo, sco, sto = _oracle(arch, H, s, cell.kappa, cell.sizes, "wf")
-    _check(xg, sc.cpu().numpy(), st.cpu().numpy(), xo, sco, sto)
+    _check(xg, sc.cpu().numpy(), st.cpu().numpy(), xo, sco, sto, tol=tol)
     f.release()
 
 
