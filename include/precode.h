@@ -193,6 +193,57 @@ typedef struct precode_job {
 int precode_batch(precode_ctx *ctx, const precode_job *jobs, int n_jobs,
                   int precision, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of per-frame jobs arriving over time.  Each
+ * job is one frame of one cell (its precode_job holds all K symbols in s and
+ * receives all K outputs in x).  Symbol k of a job is released at
+ * arrival_s + k * symbol_period_s (seconds from the start of the call).
+ * precode_serve replays the arrival trace in real time and returns when every
+ * job has completed:
+ *   - an arrived job is admitted (FIFO) when fewer than max_active jobs are in
+ *     flight and its resident state (factors, beta / weights, status; plus
+ *     the plain kernels' workspace for shapes the fused kernel does not take)
+ *     fits the slab of slab_bytes of device memory (the HBM budget);
+ *   - admission enqueues the per-frame part (Gram, factors, beta / weights,
+ *     Sec. IV-B) on one of n_streams streams; released symbols are precoded
+ *     from the resident factors as they are released, jobs overlapping on
+ *     the device across streams;
+ *   - a job's state returns to the slab after its last symbol completes.
+ * The call allocates the slab and streams once; the loop itself never
+ * allocates.  sym_latency (host array of sum_j K_j doubles, job-major, or
+ * NULL) receives each symbol's latency: completion observed on the host minus
+ * release.  The job's scale / status outputs are filled as for precode_pd /
+ * precode_fd.  Returns PRECODE_ENOMEM if a job can never fit the slab.
+ * ------------------------------------------------------------------------- */
+typedef struct precode_serve_job {
+    precode_job job;
+    double arrival_s;       /* arrival time, seconds from the start of the call */
+    double symbol_period_s; /* OFDM symbol period; 0 releases all K at arrival  */
+} precode_serve_job;
+
+typedef struct precode_serve_config {
+    int max_active;    /* jobs admitted at once (slots)                        */
+    int n_streams;     /* HIP streams the loop spreads jobs over (1..64)       */
+    int precision;     /* enum precode_prec for every job                      */
+    size_t slab_bytes; /* device memory for resident state (the HBM budget)    */
+} precode_serve_config;
+
+typedef struct precode_serve_stats {
+    int jobs_done;
+    int peak_active;                   /* most jobs admitted at once            */
+    long long symbols_done;            /* symbol vectors (all subcarriers)      */
+    long long subcarrier_symbols_done; /* subcarrier-symbols precoded           */
+    double wall_s;                     /* first arrival to last completion      */
+    double throughput;                 /* subcarrier-symbols per second         */
+    double lat_p50_s, lat_p99_s, lat_max_s; /* symbol latency                   */
+    double wait_p50_s, wait_p99_s;     /* admission wait (arrival to admission) */
+    size_t peak_bytes;                 /* peak slab use                         */
+} precode_serve_stats;
+
+int precode_serve(precode_ctx *ctx, const precode_serve_job *jobs, int n_jobs,
+                  const precode_serve_config *cfg, double *sym_latency,
+                  precode_serve_stats *stats);
+
 #ifdef __cplusplus
 }
 #endif

@@ -181,6 +181,69 @@ class Context:
                                                      _stream(stream)), "precode_frame_prepare")
         return Frame(self, h.value, arch, H, n_sc, B, U, C)
 
+    def _job_struct(self, j, keep):
+        torch = _torch()
+        H, s = j["H"], j["s"]
+        n_sc, B, U = H.shape
+        K = s.shape[0]
+        arch = {"pd": ARCH_PD, "fd": ARCH_FD}.get(j.get("arch", "pd"), j.get("arch", "pd"))
+        sizes = list(j["sizes"])
+        C = len(sizes)
+        x = j.get("x")
+        if x is None:
+            x = torch.empty((K, n_sc, B), dtype=torch.complex64, device=H.device)
+        ns = n_sc if arch == ARCH_PD else n_sc * C
+        sc = j.get("scale")
+        if sc is None:
+            sc = torch.empty(ns, dtype=torch.float32, device=H.device)
+        st = j.get("status")
+        if st is None:
+            st = torch.empty(ns, dtype=torch.int32, device=H.device)
+        sz = (ctypes.c_int * C)(*sizes)
+        keep.append(sz)
+        a = _lib.Job()
+        a.arch, a.mode, a.B, a.U, a.n_sc, a.K, a.C = arch, _mode(j.get("mode", "wf")), B, U, n_sc, K, C
+        a.cluster_sizes = ctypes.cast(sz, ctypes.POINTER(ctypes.c_int))
+        a.rho = float(j["rho"])
+        a.power, a.Es, a.tau = float(j.get("power", 1.0)), float(j.get("Es", 1.0)), float(j.get("tau", 0.125))
+        a.H, a.s, a.x, a.scale, a.status = _ptr(H), _ptr(s), _ptr(x), _ptr(sc), _ptr(st)
+        return a, (x, sc, st)
+
+    def serve(self, jobs, arrivals, symbol_period_s=1e-3 / 14, max_active=16, n_streams=4, precision="fp32",
+              slab_bytes=1 << 30):
+        """Continuous-batching serving loop (precode_serve).  jobs: list of job
+        dicts as for batch(); arrivals: arrival time (s) of each job.  Returns
+        (outputs [(x, scale, status)], per-symbol latencies [list of arrays],
+        stats dict)."""
+        import numpy as np
+
+        keep = []
+        arr = (_lib.ServeJob * len(jobs))()
+        outs = []
+        for i, j in enumerate(jobs):
+            a, o = self._job_struct(j, keep)
+            arr[i].job = a
+            arr[i].arrival_s = float(arrivals[i])
+            arr[i].symbol_period_s = float(symbol_period_s)
+            outs.append(o)
+        cfg = _lib.ServeConfig()
+        cfg.max_active, cfg.n_streams = int(max_active), int(n_streams)
+        cfg.precision = _PREC[precision] if isinstance(precision, str) else int(precision)
+        cfg.slab_bytes = int(slab_bytes)
+        total = sum(int(j["s"].shape[0]) for j in jobs)
+        lat = np.zeros(max(total, 1), np.float64)
+        stats = _lib.ServeStats()
+        _lib.check(_lib.load().precode_serve(self.handle, arr, len(jobs), ctypes.byref(cfg),
+                                             lat.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                             ctypes.byref(stats)), "precode_serve")
+        per_job, o = [], 0
+        for j in jobs:
+            k = int(j["s"].shape[0])
+            per_job.append(lat[o:o + k].copy())
+            o += k
+        sd = {f: getattr(stats, f) for f, _ in _lib.ServeStats._fields_}
+        return outs, per_job, sd
+
     def batch(self, jobs, precision="fp32", stream=None):
         """Heterogeneous batch: jobs is a list of dicts with keys arch, mode,
         H, s, rho, sizes and optional x, scale, status, power, Es, tau.

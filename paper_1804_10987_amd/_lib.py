@@ -52,6 +52,23 @@ class Job(ctypes.Structure):
     ]
 
 
+class ServeJob(ctypes.Structure):
+    _fields_ = [("job", Job), ("arrival_s", ctypes.c_double), ("symbol_period_s", ctypes.c_double)]
+
+
+class ServeConfig(ctypes.Structure):
+    _fields_ = [("max_active", ctypes.c_int), ("n_streams", ctypes.c_int), ("precision", ctypes.c_int),
+                ("slab_bytes", ctypes.c_size_t)]
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [("jobs_done", ctypes.c_int), ("peak_active", ctypes.c_int), ("symbols_done", ctypes.c_longlong),
+                ("subcarrier_symbols_done", ctypes.c_longlong), ("wall_s", ctypes.c_double),
+                ("throughput", ctypes.c_double), ("lat_p50_s", ctypes.c_double), ("lat_p99_s", ctypes.c_double),
+                ("lat_max_s", ctypes.c_double), ("wait_p50_s", ctypes.c_double), ("wait_p99_s", ctypes.c_double),
+                ("peak_bytes", ctypes.c_size_t)]
+
+
 VP = ctypes.c_void_p
 I = ctypes.c_int
 F = ctypes.c_float
@@ -74,6 +91,8 @@ SIGNATURES = {
     "precode_frame_factors": (I, [VP, VP, VP, VP, VP]),
     "precode_frame_release": (I, [VP, VP]),
     "precode_batch": (I, [VP, ctypes.POINTER(Job), I, I, VP]),
+    "precode_serve": (I, [VP, ctypes.POINTER(ServeJob), I, ctypes.POINTER(ServeConfig),
+                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ServeStats)]),
 }
 
 _lib = None

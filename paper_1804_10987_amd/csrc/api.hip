@@ -184,6 +184,15 @@ int run(precode_ctx *ctx, int arch, const void *H, const void *s, float rho, con
 
 }  // namespace
 
+namespace pc {
+int make_prob_checked(int arch, float rho, const int *sizes, int C, int mode, int B, int U, int n_sc, int K,
+                      const precode_params *q, Prob *out) {
+    const precode_params qq = q ? *q : defaults();
+    return make_prob(arch, rho, sizes, C, mode, B, U, n_sc, K, qq, out);
+}
+int ctx_device(const precode_ctx *ctx) { return ctx->device; }
+}  // namespace pc
+
 extern "C" {
 
 void precode_params_init(precode_params *p) {

@@ -83,6 +83,13 @@ __device__ __forceinline__ cx<T> ld_c64(const float2 *p) {
 
 __device__ __forceinline__ bool finite_f(double v) { return v == v && v - v == 0.0; }
 
+// Argument validation shared by every entry point (api.hip): fills *out or
+// returns the PRECODE_E* code.
+int make_prob_checked(int arch, float rho, const int *sizes, int C, int mode, int B, int U, int n_sc, int K,
+                      const precode_params *q, Prob *out);
+// Device of a context (api.hip).
+int ctx_device(const precode_ctx *ctx);
+
 // Plain kernels (plain.hip).  Workspace: A and Ainv hold n_inst U x U
 // complex<double>-sized slots, scale n_inst doubles, z K * n_inst * U complex64.
 hipError_t plain_prepare(const Prob &p, const float2 *H, float *scale_out, int *status, void *ws_A,
