@@ -33,7 +33,7 @@ def _cells():
         ("pd", synth.Cell(B=64, sizes=(32, 32), U=8, n_sc=24, K=14, snr_db=10.0)),
         ("fd", synth.Cell(B=128, sizes=(32,) * 4, U=12, n_sc=17, K=14, snr_db=5.0)),
         ("pd", synth.Cell(B=96, sizes=(40, 56), U=20, n_sc=11, K=14, snr_db=15.0)),
-        ("fd", synth.Cell(B=48, sizes=(8, 16, 24), U=6, n_sc=9, K=14, snr_db=0.0)),  # B_c<=U: plain / FP64 route
+        ("fd", synth.Cell(B=48, sizes=(4, 20, 24), U=6, n_sc=9, K=14, snr_db=0.0)),  # B_c < U: plain kernels
         ("pd", synth.Cell(B=64, sizes=(64,), U=40, n_sc=5, K=14, snr_db=20.0)),      # U > 32: plain kernels
         ("fd", synth.Cell(B=256, sizes=(32,) * 8, U=16, n_sc=30, K=14, snr_db=10.0)),
     ]
@@ -69,12 +69,14 @@ def test_serving_mix_equals_alone_and_oracle(torch, ctx):
             xo, sco, sto = oracle.pd(H, s, c.kappa, c.sizes)
         else:
             xo, sco, sto = oracle.fd(H, s, c.kappa, c.sizes)
-        xg = x.cpu().numpy()
-        e = np.linalg.norm(xg - xo, axis=-1) / np.linalg.norm(xo, axis=-1)
+        xg = x.cpu().numpy().reshape(xo.shape)
+        e = np.linalg.norm(xg - xo, axis=-1) / np.maximum(np.linalg.norm(xo, axis=-1), 1e-30)
         print("job %d %s B=%d U=%d max rel err %.2e" % (i, arch, c.B, c.U, e.max()), flush=True)
         assert e.max() <= 1e-5
-        assert np.allclose(sc.cpu().numpy().reshape(sco.shape), sco, rtol=1e-5, atol=0)
-        assert ((stt.cpu().numpy().reshape(sto.shape) & 1) == sto).all()
+        sco, sto = np.asarray(sco).ravel(), np.asarray(sto).ravel()
+        assert ((stt.cpu().numpy().ravel() & 1) == sto).all()
+        scg = sc.cpu().numpy().ravel()
+        assert (np.abs(scg - sco) <= 1e-5 * np.abs(sco)).all()
 
 
 def test_serving_admission_by_budget(torch, ctx):
