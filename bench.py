@@ -169,9 +169,69 @@ def main():
             "default_route_ms_per_step": ms_fd, "default_route_impl": fd_impl,
             "plain_fp32_ms_per_step": ms_fd_plain, "speedup_vs_plain": ms_fd_plain / ms_fd32,
         }
+    if not args.quick:
+        out["serving"] = serving_leg(ctx, pc, Hs, Ss, cell, dev, args)
     if not args.no_cpu:
         out["cpu_baseline"], out["rel_err"] = cpu_baseline(cell, Hs[0], Ss[0], Xs[0], betas[0], ctx, pc, stream)
     print(json.dumps(out), flush=True)
+
+
+SYMBOL_PERIOD_S = 1e-3 / 14  # LTE: 14 OFDM symbols per 1 ms subframe
+
+
+def serving_leg(ctx, pc, Hs, Ss, cell, dev, args):
+    """Continuous-batching serving (precode_serve): per-frame jobs arrive as a
+    Poisson process, each frame's 14 symbols are released one symbol period
+    apart and precoded from the resident factors.  Reports per-symbol latency
+    (completion - release) p50/p99 and throughput for the fused kernels and
+    for the plain kernels in the same loop, at swept arrival rates; then the
+    same for a heterogeneous cell mix."""
+    import numpy as np
+    import torch
+
+    import synth
+
+    def run(jobs, arr, impl, period=SYMBOL_PERIOD_S, max_active=16, slab_gib=4):
+        _, lat, st = ctx.serve(jobs, arr, symbol_period_s=period, max_active=max_active, n_streams=4,
+                               impl=impl, slab_bytes=slab_gib << 30)
+        torch.cuda.synchronize()
+        return {"p50_us": st["lat_p50_s"] * 1e6, "p99_us": st["lat_p99_s"] * 1e6,
+                "max_us": st["lat_max_s"] * 1e6, "wait_p99_us": st["wait_p99_s"] * 1e6,
+                "throughput": st["throughput"], "peak_active": st["peak_active"],
+                "peak_slab_mb": st["peak_bytes"] / 2**20}
+
+    n_jobs = 96
+    xs = [torch.empty((cell.K, cell.n_sc, cell.B), dtype=torch.complex64, device=dev) for _ in range(n_jobs)]
+    jobs = [dict(arch="pd", mode="wf", H=Hs[i % len(Hs)], s=Ss[i % len(Ss)], x=xs[i], rho=cell.kappa,
+                 sizes=cell.sizes) for i in range(n_jobs)]
+    res = {"workload": "PD-WF frames of the headline cell (B=256 8x32, U=16, 1200 subcarriers), 14 symbols "
+                       "each released every %.1f us, Poisson frame arrivals" % (SYMBOL_PERIOD_S * 1e6),
+           "jobs": n_jobs, "max_active": 16, "streams": 4, "rates": {}}
+    run(jobs[:8], [0.0] * 8, "auto")  # warm the loop and kernels
+    run(jobs[:8], [0.0] * 8, "plain")
+    for rate in (1000.0, 4000.0, 16000.0):
+        arr = synth.poisson_arrivals(rate, n_jobs, seed=7).tolist()
+        f = run(jobs, arr, "auto")
+        p = run(jobs, arr, "plain")
+        res["rates"]["%g/s" % rate] = {"fused": f, "plain": p, "p99_plain_over_fused": p["p99_us"] / f["p99_us"]}
+    # saturation: every frame at t=0 with all symbols released at once
+    f = run(jobs, [0.0] * n_jobs, "auto", period=0.0)
+    p = run(jobs, [0.0] * n_jobs, "plain", period=0.0)
+    res["saturated"] = {"fused": f, "plain": p, "throughput_fused_over_plain": f["throughput"] / p["throughput"]}
+    del xs, jobs
+    # heterogeneous mix (B in 64..512, cluster sizes 16/32/64, U 4..64, 300/1200/3300 subcarriers)
+    cells = synth.mix(48, seed=11)
+    mjobs = []
+    for i, c in enumerate(cells):
+        H, s = synth.device_cell(c, dev, seed=11, cell_id=i)
+        mjobs.append(dict(arch="pd" if i % 2 == 0 else "fd", mode="wf", H=H, s=s, rho=c.kappa, sizes=c.sizes))
+    arr = synth.poisson_arrivals(2000.0, len(mjobs), seed=11).tolist()
+    # plain-kernel jobs of the mix keep up to ~2.6 GiB each resident (FP64-width workspace); 16 slots
+    f = run(mjobs, arr, "auto", slab_gib=64)
+    p = run(mjobs, arr, "plain", slab_gib=64)
+    res["mix"] = {"cells": len(cells), "rate": "2000/s", "slab_gib": 64, "pd_fd": "alternating", "fused": f, "plain": p,
+                  "p99_plain_over_fused": p["p99_us"] / f["p99_us"]}
+    return res
 
 
 def cpu_baseline(cell, Hd, sd, xd, bd, ctx, pc, stream):

@@ -226,6 +226,7 @@ typedef struct precode_serve_config {
     int n_streams;     /* HIP streams the loop spreads jobs over (1..64)       */
     int precision;     /* enum precode_prec for every job                      */
     size_t slab_bytes; /* device memory for resident state (the HBM budget)    */
+    int impl;          /* enum precode_impl for every job (AUTO, FUSED, PLAIN) */
 } precode_serve_config;
 
 typedef struct precode_serve_stats {

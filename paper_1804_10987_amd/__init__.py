@@ -210,7 +210,7 @@ class Context:
         return a, (x, sc, st)
 
     def serve(self, jobs, arrivals, symbol_period_s=1e-3 / 14, max_active=16, n_streams=4, precision="fp32",
-              slab_bytes=1 << 30):
+              slab_bytes=1 << 30, impl="auto"):
         """Continuous-batching serving loop (precode_serve).  jobs: list of job
         dicts as for batch(); arrivals: arrival time (s) of each job.  Returns
         (outputs [(x, scale, status)], per-symbol latencies [list of arrays],
@@ -230,6 +230,7 @@ class Context:
         cfg.max_active, cfg.n_streams = int(max_active), int(n_streams)
         cfg.precision = _PREC[precision] if isinstance(precision, str) else int(precision)
         cfg.slab_bytes = int(slab_bytes)
+        cfg.impl = _IMPL[impl] if isinstance(impl, str) else int(impl)
         total = sum(int(j["s"].shape[0]) for j in jobs)
         lat = np.zeros(max(total, 1), np.float64)
         stats = _lib.ServeStats()

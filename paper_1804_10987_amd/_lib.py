@@ -58,7 +58,7 @@ class ServeJob(ctypes.Structure):
 
 class ServeConfig(ctypes.Structure):
     _fields_ = [("max_active", ctypes.c_int), ("n_streams", ctypes.c_int), ("precision", ctypes.c_int),
-                ("slab_bytes", ctypes.c_size_t)]
+                ("slab_bytes", ctypes.c_size_t), ("impl", ctypes.c_int)]
 
 
 class ServeStats(ctypes.Structure):

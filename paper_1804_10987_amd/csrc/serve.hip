@@ -136,7 +136,8 @@ using namespace pc;
 extern "C" int precode_serve(precode_ctx *ctx, const precode_serve_job *jobs, int n_jobs,
                              const precode_serve_config *cfg, double *sym_latency, precode_serve_stats *stats) {
     if (!ctx || n_jobs < 0 || (n_jobs > 0 && !jobs) || !cfg || !stats) return PRECODE_EINVAL;
-    if (cfg->max_active < 1 || cfg->n_streams < 1 || cfg->n_streams > 64 || cfg->slab_bytes == 0)
+    if (cfg->max_active < 1 || cfg->n_streams < 1 || cfg->n_streams > 64 || cfg->slab_bytes == 0 ||
+        cfg->impl < PRECODE_IMPL_AUTO || cfg->impl > PRECODE_IMPL_PLAIN)
         return PRECODE_EINVAL;
     memset(stats, 0, sizeof(*stats));
     // validate every job and size its resident state before touching the device
@@ -158,8 +159,9 @@ extern "C" int precode_serve(precode_ctx *ctx, const precode_serve_job *jobs, in
                                             &s.p);
         if (rc) return rc;
         if (j.n_sc > 0 && (!j.H || !j.s || !j.x)) return PRECODE_EINVAL;
-        s.fused = fused_supported(s.p, cfg->precision);
-        if (!s.fused && (cfg->precision == PRECODE_PREC_SPLIT_FP16 || cfg->precision == PRECODE_PREC_SPLIT_BF16))
+        s.fused = cfg->impl != PRECODE_IMPL_PLAIN && fused_supported(s.p, cfg->precision);
+        if (!s.fused && (cfg->impl == PRECODE_IMPL_FUSED || cfg->precision == PRECODE_PREC_SPLIT_FP16 ||
+                         cfg->precision == PRECODE_PREC_SPLIT_BF16))
             return PRECODE_EUNSUPPORTED;
         s.precision = cfg->precision;
         s.n_inst = (size_t)n_inst(s.p);
@@ -178,9 +180,15 @@ extern "C" int precode_serve(precode_ctx *ctx, const precode_serve_job *jobs, in
     if (n_jobs == 0) return PRECODE_OK;
     Slab slab;
     if (!slab.init(cfg->slab_bytes)) return PRECODE_ENOMEM;
-    std::vector<hipStream_t> streams(cfg->n_streams);
-    for (auto &s : streams)
-        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return PRECODE_EDEVICE;
+    std::vector<hipStream_t> streams;
+    for (int i = 0; i < cfg->n_streams; ++i) {
+        hipStream_t s;
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+            for (auto q : streams) (void)hipStreamDestroy(q);
+            return PRECODE_EDEVICE;
+        }
+        streams.push_back(s);
+    }
     std::vector<hipEvent_t> evpool;
     auto get_event = [&]() -> hipEvent_t {
         if (!evpool.empty()) {

@@ -148,3 +148,19 @@ def poisson_arrivals(rate_hz: float, n_jobs: int, seed: int = 0) -> np.ndarray:
     """Arrival times (s) of a Poisson process with the given rate."""
     rng = _rng(5, seed)
     return np.cumsum(rng.exponential(1.0 / rate_hz, size=n_jobs))
+
+
+def device_cell(cell: Cell, device, seed: int = 0, cell_id: int = 0):
+    """(H, s) like make_cell, drawn directly in device memory with a seeded
+    torch generator (i.i.d. CN(0,1) channel, uniform QAM symbols): for large
+    serving mixes where host generation would dominate.  Not bit-identical to
+    make_cell."""
+    import torch
+
+    g = torch.Generator(device=device)
+    g.manual_seed((seed * 1_000_003 + cell_id) & 0x7FFFFFFF)
+    H = torch.randn((cell.n_sc, cell.B, cell.U, 2), generator=g, device=device) * math.sqrt(0.5)
+    m = int(round(math.sqrt(cell.qam)))
+    lv = torch.randint(0, m, (cell.K, cell.n_sc, cell.U, 2), generator=g, device=device).float() * 2 - (m - 1)
+    lv = lv / math.sqrt(2.0 * (m * m - 1) / 3.0)
+    return torch.view_as_complex(H.contiguous()), torch.view_as_complex(lv.contiguous())

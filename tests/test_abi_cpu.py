@@ -103,3 +103,30 @@ def test_null_context_rejected(lib):
     assert lib.precode_ctx_create(0, 0, None) == -1
     assert lib.precode_batch(None, None, 0, 0, None) == -1
     assert out.value is None
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """Every ctypes mirror has the size and field offsets the C compiler gives
+    the header's struct (a host C program prints them)."""
+    import subprocess
+
+    from paper_1804_10987_amd import _lib
+
+    structs = {"precode_params": _lib.Params, "precode_job": _lib.Job, "precode_serve_job": _lib.ServeJob,
+               "precode_serve_config": _lib.ServeConfig, "precode_serve_stats": _lib.ServeStats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "precode.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f, _ in py._fields_:
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (cname, f, cname, f))
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(l.rsplit(" ", 1) for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                        check=True).stdout.splitlines())
+    for cname, py in structs.items():
+        assert int(got[cname + " size"]) == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert int(got[cname + "." + f]) == getattr(py, f).offset, (cname, f)
