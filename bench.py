@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--quick", action="store_true", help="headline path only (for profiling)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB float32 copy kernel 10 times (HBM counter calibration)")
     return ap.parse_args()
 
 
@@ -57,6 +59,17 @@ def main():
     import synth
 
     dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        # elementwise kernel reading 1 GiB and writing 1 GiB per launch: the
+        # reference for scaling the FETCH_SIZE / WRITE_SIZE counters
+        a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(10):
+            torch.mul(a, 1.0, out=b)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_kernel": "torch.mul(a, 1.0, out=b), float32", "read_bytes": a.numel() * 4,
+                          "write_bytes": b.numel() * 4, "launches": 10}), flush=True)
+        return
     cell = synth.config(2)
     B, U, K, n_sc, sizes = cell.B, cell.U, cell.K, cell.n_sc, list(cell.sizes)
     frame_bytes = algorithmic_bytes(B, U, K, n_sc)

@@ -171,10 +171,20 @@ int precode_frame_release(precode_ctx *ctx, precode_frame *frame);
 
 /* ---------------------------------------------------------------------------
  * Heterogeneous batch: n_jobs independent frames (cells with different
- * B, C, U, n_sc, K, mode, regularizer) precoded by ONE persistent fused
- * launch.  Every job is described by one precode_job; pointers are device
- * pointers with the layouts above.  Jobs must use PRECODE_PREC_FP32 or
- * SPLIT precision and shapes the fused kernel supports (U <= 32).
+ * B, C, U, n_sc, K, mode, regularizer; the batching of Sec. IV's per-
+ * subcarrier independence across cells).  Every job is described by one
+ * precode_job; pointers are device pointers with the layouts above and the
+ * outputs are those of precode_pd / precode_fd for the same job.
+ *   - jobs the fused kernel takes (U <= 32, no FP64 route, FD clusters with
+ *     B_c >= U) are cut into slices of at most 64 symbols and run as ONE
+ *     launch per kernel shape class (tile width 16 / 32, PD / FD, channel
+ *     tiles per wave): at most 14 launches however many jobs there are;
+ *   - the remaining jobs run on the plain kernels after them, on `stream`.
+ * The whole batch is validated before anything is enqueued (first error
+ * returned).  With SPLIT precision every job must be fused-capable
+ * (PRECODE_EUNSUPPORTED otherwise).  The slice table is staged through a
+ * pinned host buffer of the context; a call may wait on the host for the
+ * previous call's table copy.
  * ------------------------------------------------------------------------- */
 typedef struct precode_job {
     int arch;                 /* enum precode_arch                         */
@@ -192,6 +202,22 @@ typedef struct precode_job {
 
 int precode_batch(precode_ctx *ctx, const precode_job *jobs, int n_jobs,
                   int precision, void *stream);
+
+/* Batch plan: the launches of one precode_batch recorded once into a HIP
+ * graph, for replay each frame with the same buffers (a serving loop that
+ * reuses its H / s / x ring).  create validates as precode_batch, uploads the
+ * slice table, allocates the plan's own plain-kernel workspace (counted in
+ * the context's budget) and instantiates the graph; every pointer in `jobs`
+ * is baked in and must stay valid, with the same shapes, until destroy.
+ * launch enqueues one replay on `stream` (asynchronous, no allocation, no
+ * host copy).  launches returns the kernel launches one replay holds.
+ * destroy synchronizes the device and frees the plan. */
+typedef struct precode_batch_plan precode_batch_plan;
+int precode_batch_plan_create(precode_ctx *ctx, const precode_job *jobs, int n_jobs,
+                              int precision, precode_batch_plan **out);
+int precode_batch_plan_launch(precode_batch_plan *plan, void *stream);
+int precode_batch_plan_launches(const precode_batch_plan *plan);
+int precode_batch_plan_destroy(precode_batch_plan *plan);
 
 /* ---------------------------------------------------------------------------
  * Serving: continuous batching of per-frame jobs arriving over time.  Each

@@ -245,37 +245,60 @@ class Context:
         sd = {f: getattr(stats, f) for f, _ in _lib.ServeStats._fields_}
         return outs, per_job, sd
 
+    def _job_array(self, jobs):
+        keep = []
+        arr = (_lib.Job * len(jobs))()
+        outs = []
+        for i, j in enumerate(jobs):
+            a, o = self._job_struct(j, keep)
+            arr[i] = a
+            outs.append(o)
+        return arr, outs, keep
+
     def batch(self, jobs, precision="fp32", stream=None):
         """Heterogeneous batch: jobs is a list of dicts with keys arch, mode,
         H, s, rho, sizes and optional x, scale, status, power, Es, tau.
         Outputs are allocated when absent; returns the list of (x, scale, status)."""
-        torch = _torch()
-        arr = (_lib.Job * len(jobs))()
-        keep = []
-        outs = []
-        for i, j in enumerate(jobs):
-            H, s = j["H"], j["s"]
-            n_sc, B, U = H.shape
-            K = s.shape[0]
-            arch = {"pd": ARCH_PD, "fd": ARCH_FD}.get(j.get("arch", "pd"), j.get("arch", "pd"))
-            sizes = list(j["sizes"])
-            C = len(sizes)
-            x = j.get("x") or torch.empty((K, n_sc, B), dtype=torch.complex64, device=H.device)
-            ns = n_sc if arch == ARCH_PD else n_sc * C
-            sc = j.get("scale") or torch.empty(ns, dtype=torch.float32, device=H.device)
-            st = j.get("status") or torch.empty(ns, dtype=torch.int32, device=H.device)
-            sz = (ctypes.c_int * C)(*sizes)
-            keep.append(sz)
-            a = arr[i]
-            a.arch, a.mode, a.B, a.U, a.n_sc, a.K, a.C = arch, _mode(j.get("mode", "wf")), B, U, n_sc, K, C
-            a.cluster_sizes = ctypes.cast(sz, ctypes.POINTER(ctypes.c_int))
-            a.rho = float(j["rho"])
-            a.power, a.Es, a.tau = float(j.get("power", 1.0)), float(j.get("Es", 1.0)), float(j.get("tau", 0.125))
-            a.H, a.s, a.x, a.scale, a.status = _ptr(H), _ptr(s), _ptr(x), _ptr(sc), _ptr(st)
-            outs.append((x, sc, st))
+        arr, outs, keep = self._job_array(jobs)
         prec = _PREC[precision] if isinstance(precision, str) else int(precision)
         _lib.check(_lib.load().precode_batch(self.handle, arr, len(jobs), prec, _stream(stream)), "precode_batch")
         return outs
+
+    def batch_plan(self, jobs, precision="fp32"):
+        """Records the batch's launches into a HIP graph (precode_batch_plan_*);
+        returns a BatchPlan whose launch(stream) replays it with the same
+        buffers.  Outputs are allocated when absent (plan.outputs)."""
+        arr, outs, keep = self._job_array(jobs)
+        prec = _PREC[precision] if isinstance(precision, str) else int(precision)
+        h = ctypes.c_void_p()
+        _lib.check(_lib.load().precode_batch_plan_create(self.handle, arr, len(jobs), prec, ctypes.byref(h)),
+                   "precode_batch_plan_create")
+        return BatchPlan(self, h.value, jobs, outs)
+
+
+class BatchPlan:
+    """A recorded batch (HIP graph); keeps the job tensors alive."""
+
+    def __init__(self, ctx, handle, jobs, outputs):
+        self.ctx, self.handle, self.jobs, self.outputs = ctx, handle, jobs, outputs
+
+    @property
+    def launches(self):
+        return _lib.load().precode_batch_plan_launches(self.handle)
+
+    def launch(self, stream=None):
+        _lib.check(_lib.load().precode_batch_plan_launch(self.handle, _stream(stream)), "precode_batch_plan_launch")
+
+    def destroy(self):
+        if self.handle:
+            _lib.check(_lib.load().precode_batch_plan_destroy(self.handle), "precode_batch_plan_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
 
 
 _default = {}

@@ -91,6 +91,10 @@ SIGNATURES = {
     "precode_frame_factors": (I, [VP, VP, VP, VP, VP]),
     "precode_frame_release": (I, [VP, VP]),
     "precode_batch": (I, [VP, ctypes.POINTER(Job), I, I, VP]),
+    "precode_batch_plan_create": (I, [VP, ctypes.POINTER(Job), I, I, ctypes.POINTER(VP)]),
+    "precode_batch_plan_launch": (I, [VP, VP]),
+    "precode_batch_plan_launches": (I, [VP]),
+    "precode_batch_plan_destroy": (I, [VP]),
     "precode_serve": (I, [VP, ctypes.POINTER(ServeJob), I, ctypes.POINTER(ServeConfig),
                           ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ServeStats)]),
 }

@@ -16,7 +16,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libprecode.so")
 ARCH = "gfx950"
 
-SOURCES = ["api.hip", "plain.hip", "fused.hip", "serve.hip"]
+SOURCES = ["api.hip", "plain.hip", "fused.hip", "batch.hip", "serve.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=" + ARCH,

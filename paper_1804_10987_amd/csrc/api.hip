@@ -5,8 +5,10 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "common.h"
@@ -35,6 +37,22 @@ struct precode_ctx {
     size_t capA, capAinv, capScale, capZ;
     precode_frame *frames;
     int last_impl;
+    // fused batch slice table: device copy, pinned host staging, and events
+    // marking the last copy out of the staging and the last batch reading it
+    void *tab, *tabHost;
+    size_t capTab, capTabHost;
+    hipEvent_t tabCopied, tabRead;
+};
+
+struct precode_batch_plan {
+    precode_ctx *ctx;
+    void *tab;
+    size_t tabBytes;
+    void *wsA, *wsAinv, *wsScale, *wsZ;
+    size_t bA, bS, bZ;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    int launches;
 };
 
 namespace {
@@ -146,6 +164,53 @@ int make_prob(int arch, float rho, const int *sizes, int C, int mode, int B, int
     return PRECODE_OK;
 }
 
+// Validates every job of a batch and splits it into problems for the fused
+// batch launch and jobs for the plain kernels.  Nothing is launched unless the
+// whole batch is valid.
+int classify(const precode_job *jobs, int n_jobs, int precision, std::vector<BatchProblem> *fused,
+             std::vector<std::pair<int, Prob>> *plain) {
+    for (int i = 0; i < n_jobs; ++i) {
+        const precode_job &j = jobs[i];
+        precode_params q = defaults();
+        q.power = j.power;
+        q.Es = j.Es;
+        q.tau = j.tau;
+        q.precision = precision;
+        Prob p;
+        int rc = make_prob(j.arch, j.rho, j.cluster_sizes, j.C, j.mode, j.B, j.U, j.n_sc, j.K, q, &p);
+        if (rc) return rc;
+        if (j.n_sc == 0) continue;
+        if (!j.H || (j.K > 0 && (!j.s || !j.x))) return PRECODE_EINVAL;
+        if (!aligned8(j.H) || !aligned8(j.s) || !aligned8(j.x)) return PRECODE_EINVAL;
+        const bool fuse = j.K > 0 && fused_supported(p, precision);
+        if (!fuse && (precision == PRECODE_PREC_SPLIT_FP16 || precision == PRECODE_PREC_SPLIT_BF16))
+            return PRECODE_EUNSUPPORTED;
+        if (fuse) {
+            BatchProblem b;
+            b.p = p;
+            b.H = (const float2 *)j.H;
+            b.s = (const float2 *)j.s;
+            b.x = (float2 *)j.x;
+            b.scale_out = j.scale;
+            b.status = j.status;
+            fused->push_back(b);
+        } else {
+            plain->push_back(std::make_pair(i, p));
+        }
+    }
+    return PRECODE_OK;
+}
+
+// Plain-kernel path of one validated problem on caller-provided workspace.
+int run_plain(const Prob &p, const precode_job &j, void *wsA, void *wsAinv, void *wsScale, void *wsZ,
+              hipStream_t st) {
+    int rc = dev_err(plain_prepare(p, (const float2 *)j.H, j.scale, j.status, wsA, wsAinv, wsScale, st));
+    if (!rc && p.K > 0)
+        rc = dev_err(plain_symbols(p, p.K, (const float2 *)j.H, (const float2 *)j.s, (float2 *)j.x, wsAinv, wsScale,
+                                   wsZ, st));
+    return rc;
+}
+
 int run(precode_ctx *ctx, int arch, const void *H, const void *s, float rho, const int *sizes, int C, int mode,
         int B, int U, int n_sc, int K, const precode_params *params, void *x, float *scale, int *status,
         void *stream) {
@@ -242,6 +307,10 @@ int precode_ctx_destroy(precode_ctx *ctx) {
     ctx_free(ctx, ctx->wsAinv, ctx->capAinv);
     ctx_free(ctx, ctx->wsScale, ctx->capScale);
     ctx_free(ctx, ctx->wsZ, ctx->capZ);
+    ctx_free(ctx, ctx->tab, ctx->capTab);
+    if (ctx->tabHost) (void)hipHostFree(ctx->tabHost);
+    if (ctx->tabCopied) (void)hipEventDestroy(ctx->tabCopied);
+    if (ctx->tabRead) (void)hipEventDestroy(ctx->tabRead);
     delete ctx;
     return PRECODE_OK;
 }
@@ -371,20 +440,148 @@ int precode_frame_release(precode_ctx *ctx, precode_frame *f) {
 
 int precode_batch(precode_ctx *ctx, const precode_job *jobs, int n_jobs, int precision, void *stream) {
     if (!ctx || n_jobs < 0 || (n_jobs > 0 && !jobs)) return PRECODE_EINVAL;
-    for (int i = 0; i < n_jobs; ++i) {
-        const precode_job &j = jobs[i];
-        precode_params q = defaults();
-        q.power = j.power;
-        q.Es = j.Es;
-        q.tau = j.tau;
-        q.precision = precision;
-        int rc = j.arch == PRECODE_ARCH_PD
-                     ? precode_pd(ctx, j.H, j.s, j.rho, j.cluster_sizes, j.C, j.mode, j.B, j.U, j.n_sc, j.K, &q,
-                                  j.x, j.scale, j.status, stream)
-                     : precode_fd(ctx, j.H, j.s, j.rho, j.cluster_sizes, j.C, j.mode, j.B, j.U, j.n_sc, j.K, &q,
-                                  j.x, j.scale, j.status, stream);
+    std::vector<BatchProblem> fused;
+    std::vector<std::pair<int, Prob>> plain;
+    int rc = classify(jobs, n_jobs, precision, &fused, &plain);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const size_t bytes = fused.empty() ? 0 : fused_batch_table_bytes(fused.data(), (int)fused.size());
+    if (bytes > 0) {
+        if (hipSetDevice(ctx->device) != hipSuccess) return PRECODE_EDEVICE;
+        if (!ctx->tabCopied) {
+            if (hipEventCreateWithFlags(&ctx->tabCopied, hipEventDisableTiming) != hipSuccess ||
+                hipEventCreateWithFlags(&ctx->tabRead, hipEventDisableTiming) != hipSuccess)
+                return PRECODE_EDEVICE;
+            if (hipEventRecord(ctx->tabCopied, st) != hipSuccess || hipEventRecord(ctx->tabRead, st) != hipSuccess)
+                return PRECODE_EDEVICE;
+        }
+        // the staging buffer may still be the source of the previous copy
+        if (hipEventSynchronize(ctx->tabCopied) != hipSuccess) return PRECODE_EDEVICE;
+        if (ctx->capTabHost < bytes) {
+            if (ctx->tabHost) (void)hipHostFree(ctx->tabHost);
+            ctx->tabHost = nullptr;
+            ctx->capTabHost = 0;
+            if (hipHostMalloc(&ctx->tabHost, bytes, hipHostMallocDefault) != hipSuccess) {
+                (void)hipGetLastError();
+                return PRECODE_ENOMEM;
+            }
+            ctx->capTabHost = bytes;
+        }
+        rc = grow(ctx, &ctx->tab, &ctx->capTab, bytes);
         if (rc) return rc;
+        fused_batch_fill(fused.data(), (int)fused.size(), ctx->tabHost);
+        // the device table may still be read by the previous batch's launches
+        hipError_t e = hipStreamWaitEvent(st, ctx->tabRead, 0);
+        if (e == hipSuccess) e = hipMemcpyAsync(ctx->tab, ctx->tabHost, bytes, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipEventRecord(ctx->tabCopied, st);
+        int nl = 0;
+        if (e == hipSuccess) e = fused_batch_launch(fused.data(), (int)fused.size(), precision, ctx->tab, st, &nl);
+        if (e == hipSuccess) e = hipEventRecord(ctx->tabRead, st);
+        if (e != hipSuccess) return PRECODE_EDEVICE;
+        ctx->last_impl = PRECODE_IMPL_FUSED;
     }
+    for (const auto &pp : plain) {
+        const Prob &p = pp.second;
+        rc = grow(ctx, &ctx->wsA, &ctx->capA, plain_ws_bytes_A(p));
+        if (!rc) rc = grow(ctx, &ctx->wsAinv, &ctx->capAinv, plain_ws_bytes_A(p));
+        if (!rc) rc = grow(ctx, &ctx->wsScale, &ctx->capScale, plain_ws_bytes_scale(p));
+        if (!rc) rc = grow(ctx, &ctx->wsZ, &ctx->capZ, plain_ws_bytes_z(p, p.K > 0 ? p.K : 1));
+        if (!rc) rc = run_plain(p, jobs[pp.first], ctx->wsA, ctx->wsAinv, ctx->wsScale, ctx->wsZ, st);
+        if (rc) return rc;
+        if (fused.empty()) ctx->last_impl = PRECODE_IMPL_PLAIN;
+    }
+    return PRECODE_OK;
+}
+
+int precode_batch_plan_create(precode_ctx *ctx, const precode_job *jobs, int n_jobs, int precision,
+                              precode_batch_plan **out) {
+    if (!ctx || !out || n_jobs < 0 || (n_jobs > 0 && !jobs)) return PRECODE_EINVAL;
+    *out = nullptr;
+    std::vector<BatchProblem> fused;
+    std::vector<std::pair<int, Prob>> plain;
+    int rc = classify(jobs, n_jobs, precision, &fused, &plain);
+    if (rc) return rc;
+    if (hipSetDevice(ctx->device) != hipSuccess) return PRECODE_EDEVICE;
+    precode_batch_plan *pl = new (std::nothrow) precode_batch_plan;
+    if (!pl) return PRECODE_ENOMEM;
+    memset(pl, 0, sizeof(*pl));
+    pl->ctx = ctx;
+    auto fail = [&](int code) {
+        precode_batch_plan_destroy(pl);
+        return code;
+    };
+    // the slice table, uploaded once (synchronous copy)
+    pl->tabBytes = fused.empty() ? 0 : fused_batch_table_bytes(fused.data(), (int)fused.size());
+    if (pl->tabBytes > 0) {
+        std::vector<char> host(pl->tabBytes);
+        fused_batch_fill(fused.data(), (int)fused.size(), host.data());
+        rc = ctx_alloc(ctx, &pl->tab, pl->tabBytes);
+        if (rc) return fail(rc);
+        if (hipMemcpy(pl->tab, host.data(), pl->tabBytes, hipMemcpyHostToDevice) != hipSuccess)
+            return fail(PRECODE_EDEVICE);
+    }
+    // plain-kernel workspace of the plan (its jobs run one after another)
+    for (const auto &pp : plain) {
+        pl->bA = std::max(pl->bA, plain_ws_bytes_A(pp.second));
+        pl->bS = std::max(pl->bS, plain_ws_bytes_scale(pp.second));
+        pl->bZ = std::max(pl->bZ, plain_ws_bytes_z(pp.second, pp.second.K > 0 ? pp.second.K : 1));
+    }
+    if (!plain.empty()) {
+        rc = ctx_alloc(ctx, &pl->wsA, pl->bA);
+        if (!rc) rc = ctx_alloc(ctx, &pl->wsAinv, pl->bA);
+        if (!rc) rc = ctx_alloc(ctx, &pl->wsScale, pl->bS);
+        if (!rc) rc = ctx_alloc(ctx, &pl->wsZ, pl->bZ);
+        if (rc) return fail(rc);
+    }
+    // record every launch into one graph
+    hipStream_t cs;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return fail(PRECODE_EDEVICE);
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    int nl = 0;
+    if (e == hipSuccess && pl->tabBytes > 0)
+        e = fused_batch_launch(fused.data(), (int)fused.size(), precision, pl->tab, cs, &nl);
+    for (size_t i = 0; e == hipSuccess && i < plain.size(); ++i) {
+        if (run_plain(plain[i].second, jobs[plain[i].first], pl->wsA, pl->wsAinv, pl->wsScale, pl->wsZ, cs))
+            e = hipErrorUnknown;
+        else
+            nl += plain[i].second.K > 0 ? 4 : 2;
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t ee = hipStreamEndCapture(cs, &g);
+    if (e == hipSuccess) e = ee;
+    (void)hipStreamDestroy(cs);
+    pl->graph = g;
+    if (e == hipSuccess && g) e = hipGraphInstantiate(&pl->exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(PRECODE_EDEVICE);
+    }
+    pl->launches = nl;
+    *out = pl;
+    return PRECODE_OK;
+}
+
+int precode_batch_plan_launch(precode_batch_plan *plan, void *stream) {
+    if (!plan) return PRECODE_EINVAL;
+    if (!plan->exec) return PRECODE_OK;
+    return dev_err(hipGraphLaunch(plan->exec, (hipStream_t)stream));
+}
+
+int precode_batch_plan_launches(const precode_batch_plan *plan) { return plan ? plan->launches : 0; }
+
+int precode_batch_plan_destroy(precode_batch_plan *plan) {
+    if (!plan) return PRECODE_EINVAL;
+    precode_ctx *ctx = plan->ctx;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    ctx_free(ctx, plan->tab, plan->tabBytes);
+    ctx_free(ctx, plan->wsA, plan->bA);
+    ctx_free(ctx, plan->wsAinv, plan->bA);
+    ctx_free(ctx, plan->wsScale, plan->bS);
+    ctx_free(ctx, plan->wsZ, plan->bZ);
+    delete plan;
     return PRECODE_OK;
 }
 

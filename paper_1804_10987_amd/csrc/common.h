@@ -114,4 +114,26 @@ hipError_t fused_prepare(const Prob &p, int precision, const float2 *H, float2 *
 hipError_t fused_symbols(const Prob &p, int precision, int nk, const float2 *H, const float2 *ainv, const float2 *s,
                          float2 *x, hipStream_t st);
 
+// Heterogeneous batch of fused problems (batch.hip): every problem must be
+// fused_supported at `precision` with K >= 1.  The problems are split into
+// slices of at most 64 symbols, grouped by kernel shape class (tile width,
+// PD/FD, channel tiles per wave) and each class runs as one launch over all
+// its subcarriers; a block finds its problem by binary search in a table in
+// device memory.
+struct BatchProblem {
+    Prob p;
+    const float2 *H, *s;
+    float2 *x;
+    float *scale_out;
+    int *status;
+};
+// Bytes of the device table fused_batch_launch reads.
+size_t fused_batch_table_bytes(const BatchProblem *bp, int n);
+// Builds the table into host memory `host` (table bytes) in launch order.
+void fused_batch_fill(const BatchProblem *bp, int n, void *host);
+// Enqueues the class launches reading the table at `dev` (already holding
+// what fused_batch_fill wrote); *launches receives the number of launches.
+hipError_t fused_batch_launch(const BatchProblem *bp, int n, int precision, const void *dev, hipStream_t st,
+                              int *launches);
+
 }  // namespace pc

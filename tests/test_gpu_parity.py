@@ -228,6 +228,92 @@ def test_batch_matches_individual(torch, ctx, pc):
         _check(x.cpu().numpy(), scg, stg, xo, sco, sto)
 
 
+# Mixed batch spanning every launch class and the plain fallback: tile widths
+# 16 / 32, PD / FD, 1..8 channel tiles per wave, symbol slicing (K > 64),
+# FD clusters smaller than U and U > 32 (plain kernels), an empty job.
+MIX = [
+    ("pd", synth.Cell(B=64, sizes=(32, 32), U=8, n_sc=10, K=14)),
+    ("fd", synth.Cell(B=128, sizes=(64, 64), U=16, n_sc=7, K=9, snr_db=3.0)),
+    ("pd", synth.Cell(B=96, sizes=(40, 56), U=12, n_sc=5, K=20)),
+    ("pd", synth.Cell(B=512, sizes=(64,) * 8, U=16, n_sc=6, K=14)),
+    ("pd", synth.Cell(B=160, sizes=(80, 80), U=24, n_sc=4, K=70, channel="kron")),
+    ("fd", synth.Cell(B=192, sizes=(48, 64, 80), U=20, n_sc=5, K=14, snr_db=15.0)),
+    ("pd", synth.Cell(B=1024, sizes=(128,) * 8, U=16, n_sc=3, K=5)),
+    ("fd", synth.Cell(B=40, sizes=(8, 32), U=12, n_sc=6, K=14)),
+    ("pd", synth.Cell(B=128, sizes=(128,), U=40, n_sc=3, K=14)),
+    ("fd", synth.Cell(B=64, sizes=(32, 32), U=8, n_sc=0, K=14)),
+    ("fd", synth.Cell(B=384, sizes=(32,) * 12, U=16, n_sc=9, K=14)),
+]
+
+
+def _mix_jobs(torch, cells, seed=40):
+    jobs, host = [], []
+    for i, (arch, c) in enumerate(cells):
+        H, s = synth.make_cell(c, seed=seed + i)
+        jobs.append(dict(arch=arch, mode="wf", H=_dev(torch, H), s=_dev(torch, s), rho=c.kappa, sizes=c.sizes))
+        host.append((arch, c, H, s))
+    return jobs, host
+
+
+def test_batch_mixed_classes(torch, ctx, pc):
+    jobs, host = _mix_jobs(torch, MIX)
+    outs = ctx.batch(jobs)
+    torch.cuda.synchronize()
+    for (x, sc, st), (arch, c, H, s), j in zip(outs, host, jobs):
+        print("batch job %s B=%d U=%d n_sc=%d K=%d" % (arch, c.B, c.U, c.n_sc, c.K), flush=True)
+        if c.n_sc == 0:
+            continue
+        fn = ctx.pd if arch == "pd" else ctx.fd
+        xi, sci, sti = fn(j["H"], j["s"], c.kappa, c.sizes, "wf")
+        torch.cuda.synchronize()
+        # same kernel body, same arithmetic as the single-problem call
+        e = (x - xi).abs().max().item() / max(xi.abs().max().item(), 1e-30)
+        assert e <= 1e-6, e
+        assert torch.equal(st, sti)
+        xo, sco, sto = _oracle(arch, H, s, c.kappa, c.sizes, "wf")
+        _check(x.cpu().numpy(), sc.cpu().numpy().reshape(sco.shape), st.cpu().numpy().reshape(sto.shape),
+               xo, sco, sto)
+
+
+@pytest.mark.parametrize("prec,tol", [("split_fp16", 1e-5), ("split_bf16", 1e-3)])
+def test_batch_split_precision(torch, ctx, pc, prec, tol):
+    cells = [mc for mc in MIX if mc[1].U <= 32 and mc[1].n_sc > 0 and min(mc[1].sizes) >= mc[1].U]
+    jobs, host = _mix_jobs(torch, cells, seed=60)
+    outs = ctx.batch(jobs, precision=prec)
+    torch.cuda.synchronize()
+    for (x, sc, st), (arch, c, H, s) in zip(outs, host):
+        xo, sco, sto = _oracle(arch, H, s, c.kappa, c.sizes, "wf")
+        _check(x.cpu().numpy(), sc.cpu().numpy().reshape(sco.shape), st.cpu().numpy().reshape(sto.shape),
+               xo, sco, sto, tol=tol)
+    with pytest.raises(pc.PrecodeError):  # a job only the plain kernels take
+        ctx.batch(_mix_jobs(torch, [MIX[7]])[0], precision=prec)
+
+
+def test_batch_plan_graph_replays(torch, ctx, pc):
+    """The recorded graph, replayed three times with eager work and cleared
+    outputs in between, reproduces the eager batch every time."""
+    jobs, host = _mix_jobs(torch, MIX, seed=80)
+    ref = [tuple(t.clone() for t in o) for o in ctx.batch(jobs)]
+    torch.cuda.synchronize()
+    plan = ctx.batch_plan(jobs)
+    assert plan.launches >= 1
+    for rep in range(3):
+        for x, sc, st in plan.outputs:
+            x.zero_()
+            sc.zero_()
+            st.fill_(7)
+        _ = (torch.ones(1 << 20, device="cuda") * 2).sum()  # unrelated eager work
+        torch.cuda.synchronize()
+        plan.launch()
+        torch.cuda.synchronize()
+        for (x, sc, st), (xr, scr, str_), (arch, c, H, s) in zip(plan.outputs, ref, host):
+            if c.n_sc == 0:
+                continue
+            assert torch.equal(x, xr), "replay %d differs" % rep
+            assert torch.equal(sc, scr) and torch.equal(st, str_)
+    plan.destroy()
+
+
 @pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("split_fp16", 1e-5), ("split_bf16", 1e-3)])
 @pytest.mark.parametrize("arch", ["pd", "fd"])
 def test_full_size_sampled(torch, ctx, pc, arch, prec, tol):
