@@ -74,8 +74,11 @@ typedef struct precode_params {
     float tau;         /* FD regularization factor tau_c (eq. regularization);     */
                        /* 0.125, the value the paper's simulations settle on       */
     int precision;     /* enum precode_prec; PRECODE_PREC_FP32                     */
-    int refine_steps;  /* 0 or 1 steps of iterative refinement of z (PD only);     */
-                       /* residual s - (kappa z + H^H H z) accumulated in FP64; 0  */
+    int refine_steps;  /* 0 or 1 steps of iterative refinement of the U x U solve */
+                       /* (PD; FD clusters with B_c >= U): residual               */
+                       /* s - (kappa y + H^H (H y)) accumulated in FP64 from the  */
+                       /* complex64 channel, y += A^-1 r; runs on the plain       */
+                       /* kernels (a request for it is never fused); 0            */
     float fp64_ratio;  /* an instance whose local system has U / B_eff >= ratio is */
                        /* solved on the FP64 route (B_eff = B for PD, B_c for FD); */
                        /* 0.5; a value > 1 disables the route                      */

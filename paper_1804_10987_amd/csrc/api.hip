@@ -20,6 +20,7 @@ struct precode_frame {
     const float2 *H;
     int fused;      // state from the fused prepare pass (else from the plain kernels)
     int precision;
+    int refine;     // refinement steps per symbol (plain kernels)
     void *ainv;     // fused: scale * A^-1 (n_inst x U x U complex64); plain: A^-1 slots (complex<T>)
     void *scale;    // plain-layout scale (T); unused when fused
     float *scale_out;
@@ -242,7 +243,7 @@ int run(precode_ctx *ctx, int arch, const void *H, const void *s, float rho, con
     if (rc) return rc;
     if (K > 0)
         rc = dev_err(plain_symbols(p, K, (const float2 *)H, (const float2 *)s, (float2 *)x, ctx->wsAinv,
-                                   ctx->wsScale, ctx->wsZ, st));
+                                   ctx->wsScale, ctx->wsZ, st, q.refine_steps));
     if (rc == PRECODE_OK) ctx->last_impl = PRECODE_IMPL_PLAIN;
     return rc;
 }
@@ -371,6 +372,7 @@ int precode_frame_prepare(precode_ctx *ctx, int arch, const void *H, float rho, 
     f->H = (const float2 *)H;
     f->fused = fuse;
     f->precision = q.precision;
+    f->refine = q.refine_steps;
     f->scale = (char *)f->ainv + bA;
     f->scale_out = (float *)((char *)f->scale + bS);
     f->status = (int *)((char *)f->scale_out + ((ni * sizeof(float) + 7) & ~(size_t)7));
@@ -411,7 +413,7 @@ int precode_frame_symbols(precode_ctx *ctx, precode_frame *f, const void *s, int
     int rc = grow(ctx, &ctx->wsZ, &ctx->capZ, plain_ws_bytes_z(p, nk));
     if (rc) return rc;
     return dev_err(plain_symbols(p, nk, f->H, (const float2 *)s, (float2 *)x, f->ainv, f->scale, ctx->wsZ,
-                                 (hipStream_t)stream));
+                                 (hipStream_t)stream, f->refine));
 }
 
 int precode_frame_factors(precode_ctx *ctx, precode_frame *f, float *scale, int *status, void *stream) {

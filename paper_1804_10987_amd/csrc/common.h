@@ -95,7 +95,7 @@ int ctx_device(const precode_ctx *ctx);
 hipError_t plain_prepare(const Prob &p, const float2 *H, float *scale_out, int *status, void *ws_A,
                          void *ws_Ainv, void *ws_scale, hipStream_t st);
 hipError_t plain_symbols(const Prob &p, int K, const float2 *H, const float2 *s, float2 *x, void *ws_Ainv,
-                         void *ws_scale, void *ws_z, hipStream_t st);
+                         void *ws_scale, void *ws_z, hipStream_t st, int refine_steps = 0);
 size_t plain_ws_bytes_A(const Prob &p);
 size_t plain_ws_bytes_scale(const Prob &p);
 size_t plain_ws_bytes_z(const Prob &p, int K);

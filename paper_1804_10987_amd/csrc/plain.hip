@@ -9,6 +9,8 @@
 //             PD: beta = sqrt(Es/rho^2 t), scale = 1/beta
 //             FD: w_c = sqrt(rho_c^2/(t Es)), scale = w_c
 //   solve     z = scale A^-1 s                     (per symbol)
+//   refine    (optional) z += sc A^-1 (s - A z / sc), residual in FP64
+//             from the complex64 channel (U x U systems)
 //   precode   x_c = H_c z                          (per symbol)
 //             (FD, B_c < U: x_c = w_c M_c^-1 (H_c s), done in `solve`)
 //
@@ -249,6 +251,73 @@ __global__ void __launch_bounds__(256) plain_solve_k(Prob p, int K, const float2
 }
 
 // --------------------------------------------------------------------------
+// refine: one step of iterative refinement of z = sc A^-1 s for U x U systems
+// (PD, and FD clusters with B_c >= U).  With y = z / sc the solution of
+// A y = s, the residual r = s - (kappa y + H_c^H (H_c y)) is accumulated in
+// FP64 straight from the complex64 channel (never from the stored Gram), and
+// z += sc A^-1 r.  One 64-thread block per (symbol, instance); the H_c y
+// vector is staged in LDS in chunks of kRefChunk rows.
+// --------------------------------------------------------------------------
+constexpr int kRefChunk = 512;
+
+template <typename T>
+__global__ void __launch_bounds__(64) plain_refine_k(Prob p, int K, const float2 *__restrict__ H,
+                                                     const float2 *__restrict__ s, const cx<T> *__restrict__ Ainv,
+                                                     const T *__restrict__ scale_ws, float2 *__restrict__ z) {
+    const size_t ni = (size_t)n_inst(p);
+    const size_t inst = blockIdx.x % ni;
+    const int k = (int)(blockIdx.x / ni);
+    const InstInfo q = inst_info(p, (int)inst);
+    if (q.r64 != is64<T>() || !q.big) return;
+    const T sc = scale_ws[inst * kW<T>()];
+    if (sc == (T)0) return;  // failed instance: z stays 0
+    const int tid = threadIdx.x, U = p.U;
+    __shared__ cx<double> zy[kMaxU], hz[kRefChunk], acc[kMaxU];
+    __shared__ cx<double> r[kMaxU];
+    float2 *zk = z + ((size_t)k * ni + inst) * U;
+    const float2 *sk = s + ((size_t)k * p.n_sc + q.n) * U;
+    const float2 *Hn = H + (size_t)q.n * p.B * U;
+    for (int u = tid; u < U; u += 64) {
+        zy[u] = {(double)zk[u].x, (double)zk[u].y};
+        acc[u] = {0, 0};
+    }
+    __syncthreads();
+    for (int b0 = q.row0; b0 < q.row0 + q.rows; b0 += kRefChunk) {
+        const int nb = min(kRefChunk, q.row0 + q.rows - b0);
+        for (int i = tid; i < nb; i += 64) {
+            cx<double> w = {0, 0};
+            const float2 *hb = Hn + (size_t)(b0 + i) * U;
+            for (int u = 0; u < U; ++u) w = cadd(w, cmul(ld_c64<double>(hb + u), zy[u]));
+            hz[i] = w;
+        }
+        __syncthreads();
+        for (int u = tid; u < U; u += 64) {
+            cx<double> a = acc[u];
+            for (int i = 0; i < nb; ++i) a = cadd(a, ccmul(ld_c64<double>(Hn + (size_t)(b0 + i) * U + u), hz[i]));
+            acc[u] = a;
+        }
+        __syncthreads();
+    }
+    // r = s - (kappa z + H^H H z) / sc
+    const double inv = 1.0 / (double)sc;
+    for (int u = tid; u < U; u += 64) {
+        const cx<double> az = cadd(cscale(zy[u], (double)q.kap), acc[u]);
+        r[u] = csub(ld_c64<double>(sk + u), cscale(az, inv));
+    }
+    __syncthreads();
+    const cx<T> *ai = Ainv + inst * U * U * kW<T>();
+    for (int u = tid; u < U; u += 64) {
+        cx<double> d = {0, 0};
+        for (int v = 0; v < U; ++v) {
+            const cx<T> a = ai[u * U + v];
+            d = cadd(d, cmul(cx<double>{(double)a.re, (double)a.im}, r[v]));
+        }
+        const cx<double> zn = cadd(zy[u], cscale(d, (double)sc));
+        zk[u] = make_float2((float)zn.re, (float)zn.im);
+    }
+}
+
+// --------------------------------------------------------------------------
 // precode: thread per (k, n, b)
 // --------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) plain_precode_k(Prob p, int K, const float2 *__restrict__ H,
@@ -316,7 +385,7 @@ hipError_t plain_prepare(const Prob &p, const float2 *H, float *scale_out, int *
 }
 
 hipError_t plain_symbols(const Prob &p, int K, const float2 *H, const float2 *s, float2 *x, void *ws_Ainv,
-                         void *ws_scale, void *ws_z, hipStream_t st) {
+                         void *ws_scale, void *ws_z, hipStream_t st, int refine_steps) {
     const size_t ni = (size_t)n_inst(p);
     if (ni == 0 || K == 0) return hipSuccess;
     const size_t nsolve = (size_t)K * ni * p.U;
@@ -327,6 +396,15 @@ hipError_t plain_symbols(const Prob &p, int K, const float2 *H, const float2 *s,
     if (any_route(p, true))
         hipLaunchKernelGGL(plain_solve_k<double>, dim3(gs), dim3(256), 0, st, p, K, H, s,
                            (const cx<double> *)ws_Ainv, (const double *)ws_scale, (float2 *)ws_z, x);
+    if (refine_steps > 0) {
+        const unsigned gr = (unsigned)((size_t)K * ni);
+        if (any_route(p, false))
+            hipLaunchKernelGGL(plain_refine_k<float>, dim3(gr), dim3(64), 0, st, p, K, H, s,
+                               (const cx<float> *)ws_Ainv, (const float *)ws_scale, (float2 *)ws_z);
+        if (any_route(p, true))
+            hipLaunchKernelGGL(plain_refine_k<double>, dim3(gr), dim3(64), 0, st, p, K, H, s,
+                               (const cx<double> *)ws_Ainv, (const double *)ws_scale, (float2 *)ws_z);
+    }
     const size_t nx = (size_t)K * p.n_sc * p.B;
     hipLaunchKernelGGL(plain_precode_k, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, st, p, K, H,
                        (const float2 *)ws_z, x);

@@ -228,6 +228,30 @@ def test_batch_matches_individual(torch, ctx, pc):
         _check(x.cpu().numpy(), scg, stg, xo, sco, sto)
 
 
+@pytest.mark.parametrize("arch,cell,ratio", [
+    ("pd", synth.config(1), 2.0),
+    ("fd", synth.Cell(B=64, sizes=(16, 16, 32), U=16, n_sc=24, K=14, snr_db=20.0), 2.0),  # B_c = U: worst conditioned
+    ("fd", synth.Cell(B=64, sizes=(16, 16, 32), U=16, n_sc=24, K=14, snr_db=20.0), 0.5),  # FP64 route on B_c = U
+    ("pd", synth.Cell(B=24, sizes=(24,), U=16, n_sc=12, K=6, snr_db=20.0), 2.0),           # U / B = 0.67 in FP32
+])
+def test_refinement_fp64_residual(torch, ctx, pc, arch, cell, ratio):
+    """One refinement step with the residual in FP64 from the complex64
+    channel: within the FP32 tolerance and never worse than no refinement."""
+    H, s = synth.make_cell(cell, seed=5)
+    Hd, sd = _dev(torch, H), _dev(torch, s)
+    fn = ctx.pd if arch == "pd" else ctx.fd
+    x0, _, _ = fn(Hd, sd, cell.kappa, cell.sizes, "wf", pc.params(fp64_ratio=ratio))
+    x1, sc1, st1 = fn(Hd, sd, cell.kappa, cell.sizes, "wf", pc.params(fp64_ratio=ratio, refine_steps=1))
+    torch.cuda.synchronize()
+    assert ctx.last_impl == "plain"
+    xo, sco, sto = _oracle(arch, H, s, cell.kappa, cell.sizes, "wf")
+    e1 = _check(x1.cpu().numpy(), sc1.cpu().numpy().reshape(sco.shape), st1.cpu().numpy().reshape(sto.shape),
+                xo, sco, sto)
+    e0 = _vec_err(x0.cpu().numpy(), xo).max()
+    print("refinement: max rel err %.3e -> %.3e" % (e0, e1), flush=True)
+    assert e1 <= max(e0, 2e-7)
+
+
 # Mixed batch spanning every launch class and the plain fallback: tile widths
 # 16 / 32, PD / FD, 1..8 channel tiles per wave, symbol slicing (K > 64),
 # FD clusters smaller than U and U > 32 (plain kernels), an empty job.
