@@ -117,6 +117,16 @@ size_t precode_ctx_bytes(const precode_ctx *ctx);
  * (1 = fused, 2 = plain), or 0 if none. */
 int precode_ctx_last_impl(const precode_ctx *ctx);
 
+/* Waves per workgroup (2, 4 or 8) of the most recent fused precode_pd /
+ * precode_fd / precode_batch call on this context, or 0 if none.  The fused
+ * kernel's launch shape is chosen by an autotuner that times every feasible
+ * shape on the first call of each problem shape in the process (the call's
+ * own launch, repeated on its stream, before the call returns) and reuses
+ * the fastest; PRECODE_FUSED_WAVES=2|4|8 in the environment forces a shape,
+ * PRECODE_AUTOTUNE=0 keeps the default (4).  Calls made under stream capture
+ * never tune.  Shapes differ only in the order of the cluster-sum rounding. */
+int precode_ctx_last_waves(const precode_ctx *ctx);
+
 /* ---------------------------------------------------------------------------
  * PD precoding of a frame (Sec. III-B; Theorem 1; Lemma 1).  Per subcarrier
  * n (n < n_sc):

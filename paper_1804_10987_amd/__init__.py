@@ -135,6 +135,11 @@ class Context:
     def last_impl(self) -> str:
         return {0: "none", IMPL_FUSED: "fused", IMPL_PLAIN: "plain"}[_lib.load().precode_ctx_last_impl(self.handle)]
 
+    @property
+    def last_waves(self) -> int:
+        """Waves per workgroup of the last fused launch (autotuned shape)."""
+        return _lib.load().precode_ctx_last_waves(self.handle)
+
     def _run(self, arch, H, s, rho, sizes, mode, prm, x, scale, status, stream):
         torch = _torch()
         n_sc, B, U = H.shape

@@ -83,6 +83,7 @@ SIGNATURES = {
     "precode_ctx_destroy": (I, [VP]),
     "precode_ctx_bytes": (SZ, [VP]),
     "precode_ctx_last_impl": (I, [VP]),
+    "precode_ctx_last_waves": (I, [VP]),
     "precode_pd": (I, [VP, VP, VP, F, IP, I, I, I, I, I, I, ctypes.POINTER(Params), VP, VP, VP, VP]),
     "precode_fd": (I, [VP, VP, VP, F, IP, I, I, I, I, I, I, ctypes.POINTER(Params), VP, VP, VP, VP]),
     "precode_frame_prepare": (I, [VP, I, VP, F, IP, I, I, I, I, I, ctypes.POINTER(Params),

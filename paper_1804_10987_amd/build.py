@@ -16,7 +16,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libprecode.so")
 ARCH = "gfx950"
 
-SOURCES = ["api.hip", "plain.hip", "fused.hip", "batch.hip", "serve.hip"]
+SOURCES = ["api.hip", "plain.hip", "fused.hip", "fused_nw2.hip", "fused_nw4.hip", "fused_nw8.hip", "batch.hip",
+           "serve.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=" + ARCH,
@@ -37,7 +38,7 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found (ROCm is required to build the library)")
 
 
-def build(verbose: bool = False, jobs: int = 4) -> str:
+def build(verbose: bool = False, jobs: int = 8) -> str:
     """Compile every HIP source and link libprecode.so; returns its path."""
     objdir = os.path.join(PKG, "_build")
     os.makedirs(objdir, exist_ok=True)

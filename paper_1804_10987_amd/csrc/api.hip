@@ -38,6 +38,7 @@ struct precode_ctx {
     size_t capA, capAinv, capScale, capZ;
     precode_frame *frames;
     int last_impl;
+    int last_waves;  // waves per workgroup of the last fused launch
     // fused batch slice table: device copy, pinned host staging, and events
     // marking the last copy out of the staging and the last batch reading it
     void *tab, *tabHost;
@@ -230,8 +231,13 @@ int run(precode_ctx *ctx, int arch, const void *H, const void *s, float rho, con
         if (!can_fuse) return PRECODE_EUNSUPPORTED;
     }
     if (q.impl != PRECODE_IMPL_PLAIN && can_fuse) {
-        rc = dev_err(fused_run(p, q.precision, (const float2 *)H, (const float2 *)s, (float2 *)x, scale, status, st));
-        if (rc == PRECODE_OK) ctx->last_impl = PRECODE_IMPL_FUSED;
+        int nw = 0;
+        rc = dev_err(
+            fused_run(p, q.precision, (const float2 *)H, (const float2 *)s, (float2 *)x, scale, status, st, &nw));
+        if (rc == PRECODE_OK) {
+            ctx->last_impl = PRECODE_IMPL_FUSED;
+            ctx->last_waves = nw;
+        }
         return rc;
     }
     rc = grow(ctx, &ctx->wsA, &ctx->capA, plain_ws_bytes_A(p));
@@ -326,6 +332,8 @@ int precode_validate(int arch, float rho, const int *cluster_sizes, int C, int m
 size_t precode_ctx_bytes(const precode_ctx *ctx) { return ctx ? ctx->held : 0; }
 
 int precode_ctx_last_impl(const precode_ctx *ctx) { return ctx ? ctx->last_impl : 0; }
+
+int precode_ctx_last_waves(const precode_ctx *ctx) { return ctx ? ctx->last_waves : 0; }
 
 int precode_pd(precode_ctx *ctx, const void *H, const void *s, float rho, const int *cluster_sizes, int C, int mode,
                int B, int U, int n_sc, int K, const precode_params *params, void *x, float *beta, int *status,
@@ -481,6 +489,7 @@ int precode_batch(precode_ctx *ctx, const precode_job *jobs, int n_jobs, int pre
         if (e == hipSuccess) e = hipEventRecord(ctx->tabRead, st);
         if (e != hipSuccess) return PRECODE_EDEVICE;
         ctx->last_impl = PRECODE_IMPL_FUSED;
+        ctx->last_waves = fused_default_waves();
     }
     for (const auto &pp : plain) {
         const Prob &p = pp.second;

@@ -19,6 +19,9 @@
 namespace pc {
 namespace {
 
+constexpr int NW = 4;  // waves per workgroup of the batch launches
+constexpr int kThreads = 64 * NW;
+
 struct Entry {
     Prob p;
     const float2 *H, *s;
@@ -39,10 +42,10 @@ struct Class {
 
 Class class_of(const Prob &p) {
     const int up = pick_up(p.U);
-    return Class{up, p.arch, pick_maxt(p, up)};
+    return Class{up, p.arch, pick_maxt(p, up, NW)};
 }
 
-int blocks_of(const Prob &p) { return p.n_sc * (p.arch == kPD ? 1 : (p.C + 3) / 4); }
+int blocks_of(const Prob &p) { return p.n_sc * (p.arch == kPD ? 1 : (p.C + NW - 1) / NW); }
 
 // Slices of every problem, in launch order (by class, then problem order).
 struct Plan {
@@ -102,14 +105,14 @@ __global__ void __launch_bounds__(kThreads, (min_waves<UP, MAXT>()))
         else hi = mid - 1;
     }
     const Entry &E = tab[lo];
-    fused_body<UP, ARCH, PREC, MAXT>(E.p, E.p.off, b - E.block0, E.K, kFull, E.H, E.s, E.x, nullptr, E.scale_out,
+    fused_body<UP, ARCH, PREC, MAXT, NW>(E.p, E.p.off, b - E.block0, E.K, kFull, E.H, E.s, E.x, nullptr, E.scale_out,
                                      E.status);
 }
 
 template <int UP, int ARCH, int PREC, int MAXT>
 hipError_t launch(const Entry *tab, int n, int blocks, int kmax, hipStream_t st) {
     const void *fn = (const void *)fused_batch_k<UP, ARCH, PREC, MAXT>;
-    const size_t lds = Lds<UP>::bytes(kmax);
+    const size_t lds = Lds<UP>::bytes(kmax, NW);
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;

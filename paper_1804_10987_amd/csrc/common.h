@@ -103,8 +103,11 @@ size_t plain_ws_bytes_z(const Prob &p, int K);
 // Fused single-launch kernel (fused.hip).  Returns hipErrorNotSupported if the
 // shape is outside what it handles.
 bool fused_supported(const Prob &p, int precision);
+// *nw_used (may be NULL) receives the waves per workgroup the launch used.
 hipError_t fused_run(const Prob &p, int precision, const float2 *H, const float2 *s, float2 *x,
-                     float *scale_out, int *status, hipStream_t st);
+                     float *scale_out, int *status, hipStream_t st, int *nw_used = nullptr);
+// Waves per workgroup of the batch launches.
+int fused_default_waves();
 // Frame split of the fused kernel: prepare writes scale * A^-1 per instance
 // (n_inst x U x U complex64, scale = 1/beta for PD, w_c for FD, zero for a
 // failed instance) with beta / weights and status; symbols precodes nk symbols

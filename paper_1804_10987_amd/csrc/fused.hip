@@ -1,4 +1,5 @@
-// fused.hip -- single-problem launches of the fused PD / FD kernel on gfx950.
+// fused.hip -- single-problem dispatch of the fused PD / FD kernel on gfx950,
+// with the launch-shape autotuner.
 //
 // One launch runs the whole per-subcarrier chain; only the precoded vectors,
 // beta / weights and status are written back (the kernel body is in
@@ -27,6 +28,12 @@
 // per (subcarrier, group of four clusters), one cluster per wave, no
 // workgroup barrier after the symbols are staged.
 //
+// Launch shape: NW = 2, 4 or 8 waves per workgroup (fused_nw{2,4,8}.hip);
+// with fewer waves each wave holds more channel tiles (MAXT), with more the
+// per-subcarrier chain is shorter but more waves wait at its barriers.  The
+// autotuner times every feasible NW on the first call of each problem shape
+// (the call itself, repeated) and caches the fastest for the process.
+//
 // Modes: full (Gram to precode), prepare (per-frame factors scale * A^-1 to
 // device memory for the frame API and serving) and symbols (precode released
 // symbols from stored factors, re-reading only the channel).
@@ -37,76 +44,44 @@
 // ah bh + ah bl + al bh in FP32 (v_mfma_f32_32x32x16_f16 / _bf16).  Operands
 // are scaled by powers of two into the FP16 range first and the FP32 results
 // unscaled exactly.
+#include <stdio.h>
+#include <stdlib.h>
+
+#include <mutex>
+#include <string>
+#include <unordered_map>
+
 #include "fused_kernel.h"
+#include "fused_launch.h"
 
 namespace pc {
 namespace {
 
-template <int UP, int ARCH, int PREC, int MAXT>
-__global__ void __launch_bounds__(kThreads, (min_waves<UP, MAXT>()))
-    fused_k(Prob p, int K, int mode, const float2 *__restrict__ H, const float2 *__restrict__ s,
-            float2 *__restrict__ x, cx<float> *__restrict__ ainv_g, float *__restrict__ scale_out,
-            int *__restrict__ status) {
-    // cluster offsets read in place from the kernel-argument segment (p is the
-    // first argument); indexing the by-value copy would force it to scratch
-    const int *off = (const int *)((const char *)__builtin_amdgcn_kernarg_segment_ptr() + offsetof(Prob, off));
-    fused_body<UP, ARCH, PREC, MAXT>(p, off, blockIdx.x, K, mode, H, s, x, ainv_g, scale_out, status);
+constexpr int kNWs[] = {2, 4, 8};
+constexpr int kDefaultNW = 4;
+
+bool nw_feasible(const Prob &p, int nw) {
+    const int up = pick_up(p.U);
+    if (up == 0 || pick_maxt(p, up, nw) == 0) return false;
+    const size_t lds = up == 16 ? Lds<16>::bytes(kMaxKFused, nw) : Lds<32>::bytes(kMaxKFused, nw);
+    return lds <= kLdsMax - 256;
 }
 
-struct Call {
-    int K, mode;
-    const float2 *H, *s;
-    float2 *x;
-    cx<float> *ainv;
-    float *scale_out;
-    int *status;
-};
-
-template <int UP, int ARCH, int PREC, int MAXT>
-hipError_t launch(const Prob &p, const Call &a, hipStream_t st) {
-    const int K = a.K;
-    const void *fn = (const void *)fused_k<UP, ARCH, PREC, MAXT>;
-    const size_t lds = Lds<UP>::bytes(K);
-    if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-    }
-    const unsigned grid = (unsigned)p.n_sc * (ARCH == kPD ? 1u : (unsigned)((p.C + 3) / 4));
-    hipLaunchKernelGGL((fused_k<UP, ARCH, PREC, MAXT>), dim3(grid), dim3(kThreads), lds, st, p, K, a.mode, a.H,
-                       a.s, a.x, a.ainv, a.scale_out, a.status);
-    return hipGetLastError();
-}
-
-template <int UP, int ARCH, int PREC>
-hipError_t launch_t(int maxt, const Prob &p, const Call &a, hipStream_t st) {
-    switch (maxt) {
-        case 1: return launch<UP, ARCH, PREC, 1>(p, a, st);
-        case 2: return launch<UP, ARCH, PREC, 2>(p, a, st);
-        case 4: return launch<UP, ARCH, PREC, 4>(p, a, st);
-        default:
-            if constexpr (UP == 16) return launch<UP, ARCH, PREC, 8>(p, a, st);
-            return hipErrorNotSupported;
-    }
-}
-
-template <int UP, int ARCH>
-hipError_t launch_prec(int prec, int maxt, const Prob &p, const Call &a, hipStream_t st) {
-    switch (prec) {
-        case kF32: return launch_t<UP, ARCH, kF32>(maxt, p, a, st);
-        case kF16: return launch_t<UP, ARCH, kF16>(maxt, p, a, st);
-        default: return launch_t<UP, ARCH, kBF16>(maxt, p, a, st);
+hipError_t launch_nw(int nw, const Prob &p, int prec, const FusedCall &a, hipStream_t st) {
+    const int maxt = pick_maxt(p, pick_up(p.U), nw);
+    switch (nw) {
+        case 2: return fused_launch_nw2(p, prec, maxt, a, st);
+        case 8: return fused_launch_nw8(p, prec, maxt, a, st);
+        default: return fused_launch_nw4(p, prec, maxt, a, st);
     }
 }
 
 // Launches one mode over symbol slices of at most kMaxKFused.
-hipError_t run_mode(const Prob &p, int precision, int mode, int K, const float2 *H, const float2 *s, float2 *x,
-                    cx<float> *ainv, float *scale_out, int *status, hipStream_t st) {
-    const int up = pick_up(p.U);
-    const int prec = prec_of(precision);
-    const int maxt = pick_maxt(p, up);
+hipError_t run_slices(int nw, const Prob &p, int prec, int mode, int K, const float2 *H, const float2 *s, float2 *x,
+                      cx<float> *ainv, float *scale_out, int *status, hipStream_t st) {
     for (int k0 = 0; k0 < K || (k0 == 0 && mode == kPrepare); k0 += kMaxKFused) {
         const int kk = mode == kPrepare ? 0 : (K - k0 < kMaxKFused ? K - k0 : kMaxKFused);
-        Call a;
+        FusedCall a;
         a.K = kk;
         a.mode = mode;
         a.H = H;
@@ -116,26 +91,112 @@ hipError_t run_mode(const Prob &p, int precision, int mode, int K, const float2 
         // factors are identical for every slice; write them once
         a.scale_out = k0 == 0 ? scale_out : nullptr;
         a.status = k0 == 0 ? status : nullptr;
-        hipError_t e;
-        if (up == 16)
-            e = p.arch == kPD ? launch_prec<16, kPD>(prec, maxt, p, a, st) : launch_prec<16, kFD>(prec, maxt, p, a, st);
-        else
-            e = p.arch == kPD ? launch_prec<32, kPD>(prec, maxt, p, a, st) : launch_prec<32, kFD>(prec, maxt, p, a, st);
+        hipError_t e = launch_nw(nw, p, prec, a, st);
         if (e != hipSuccess) return e;
         if (mode == kPrepare) break;
     }
     return hipSuccess;
 }
 
+// ---- autotuner ------------------------------------------------------------------
+// Process-wide cache: problem shape -> waves per workgroup.  Environment:
+// PRECODE_FUSED_WAVES=2|4|8 forces a shape (when feasible), PRECODE_AUTOTUNE=0
+// disables tuning (default NW).
+std::mutex g_tune_mu;
+std::unordered_map<std::string, int> g_tuned;
+
+std::string tune_key(const Prob &p, int prec, int mode, int K) {
+    std::string k = std::to_string(p.arch) + "/" + std::to_string(p.U) + "/" + std::to_string(p.B) + "/" +
+                    std::to_string(p.n_sc) + "/" + std::to_string(K < kMaxKFused ? K : kMaxKFused) + "/" +
+                    std::to_string(prec) + "/" + std::to_string(mode) + ":";
+    if (p.arch == kFD)
+        for (int c = 0; c < p.C; ++c) k += std::to_string(p.off[c + 1] - p.off[c]) + ",";
+    return k;
+}
+
+int env_int(const char *name, int dflt) {
+    const char *v = getenv(name);
+    return v && *v ? atoi(v) : dflt;
+}
+
+int default_nw(const Prob &p) {
+    if (nw_feasible(p, kDefaultNW)) return kDefaultNW;
+    for (int nw : kNWs)
+        if (nw_feasible(p, nw)) return nw;
+    return 0;
+}
+
+// Chooses the waves per workgroup for this call; may run the call several
+// times on `st` to time the candidates (outputs are rewritten by the real
+// launch that follows).
+int choose_nw(const Prob &p, int prec, int mode, int K, const float2 *H, const float2 *s, float2 *x,
+              cx<float> *ainv, float *scale_out, int *status, hipStream_t st) {
+    const int forced = env_int("PRECODE_FUSED_WAVES", 0);
+    if (forced && nw_feasible(p, forced)) return forced;
+    const int dflt = default_nw(p);
+    if (!env_int("PRECODE_AUTOTUNE", 1)) return dflt;
+    const std::string key = tune_key(p, prec, mode, K);
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        auto it = g_tuned.find(key);
+        if (it != g_tuned.end()) return it->second;
+    }
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) return dflt;
+    int cands[3], nc = 0;
+    for (int nw : kNWs)
+        if (nw_feasible(p, nw)) cands[nc++] = nw;
+    int best = dflt;
+    if (nc > 1) {
+        hipEvent_t e0, e1;
+        if (hipEventCreate(&e0) != hipSuccess) return dflt;
+        if (hipEventCreate(&e1) != hipSuccess) {
+            (void)hipEventDestroy(e0);
+            return dflt;
+        }
+        float best_ms = 0.f;
+        bool ok = true;
+        for (int i = 0; i < nc && ok; ++i) {
+            // first launch of a kernel also loads it: time the repeats only
+            ok = run_slices(cands[i], p, prec, mode, K, H, s, x, ainv, scale_out, status, st) == hipSuccess &&
+                 hipEventRecord(e0, st) == hipSuccess;
+            for (int r = 0; r < 3 && ok; ++r)
+                ok = run_slices(cands[i], p, prec, mode, K, H, s, x, ainv, scale_out, status, st) == hipSuccess;
+            float ms = 0.f;
+            ok = ok && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+                 hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+            if (ok && (i == 0 || ms < best_ms)) {
+                best_ms = ms;
+                best = cands[i];
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (!ok) {
+            (void)hipGetLastError();
+            return dflt;
+        }
+    }
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tuned[key] = best;
+    return best;
+}
+
+hipError_t run_mode(const Prob &p, int precision, int mode, int K, const float2 *H, const float2 *s, float2 *x,
+                    cx<float> *ainv, float *scale_out, int *status, hipStream_t st, int *nw_used) {
+    const int prec = prec_of(precision);
+    const int nw = choose_nw(p, prec, mode, K, H, s, x, ainv, scale_out, status, st);
+    if (nw == 0) return hipErrorNotSupported;
+    if (nw_used) *nw_used = nw;
+    return run_slices(nw, p, prec, mode, K, H, s, x, ainv, scale_out, status, st);
+}
+
 }  // namespace
 
 bool fused_supported(const Prob &p, int precision) {
     if (prec_of(precision) < 0) return false;
-    const int up = pick_up(p.U);
-    if (up == 0) return false;
-    if (pick_maxt(p, up) == 0) return false;
-    const size_t lds = up == 16 ? Lds<16>::bytes(kMaxKFused) : Lds<32>::bytes(kMaxKFused);
-    if (lds > kLdsMax - 256) return false;
+    // the batch launches use the default shape; every entry point needs it
+    if (!nw_feasible(p, kDefaultNW)) return false;
     if (p.arch == kPD) return p.pd_fp64 == 0;
     for (int c = 0; c < p.C; ++c) {
         if (p.fp64[c]) return false;
@@ -144,26 +205,29 @@ bool fused_supported(const Prob &p, int precision) {
     return true;
 }
 
+int fused_default_waves() { return kDefaultNW; }
+
 hipError_t fused_run(const Prob &p, int precision, const float2 *H, const float2 *s, float2 *x, float *scale_out,
-                     int *status, hipStream_t st) {
+                     int *status, hipStream_t st, int *nw_used) {
     if (!fused_supported(p, precision)) return hipErrorNotSupported;
     if (p.n_sc == 0) return hipSuccess;
     // full path: factors are written by the first slice only (ainv unused)
-    return run_mode(p, precision, kFull, p.K, H, s, x, nullptr, scale_out, status, st);
+    return run_mode(p, precision, kFull, p.K, H, s, x, nullptr, scale_out, status, st, nw_used);
 }
 
 hipError_t fused_prepare(const Prob &p, int precision, const float2 *H, float2 *ainv, float *scale_out, int *status,
                          hipStream_t st) {
     if (!fused_supported(p, precision)) return hipErrorNotSupported;
     if (p.n_sc == 0) return hipSuccess;
-    return run_mode(p, precision, kPrepare, 0, H, nullptr, nullptr, (cx<float> *)ainv, scale_out, status, st);
+    return run_mode(p, precision, kPrepare, 0, H, nullptr, nullptr, (cx<float> *)ainv, scale_out, status, st,
+                    nullptr);
 }
 
 hipError_t fused_symbols(const Prob &p, int precision, int nk, const float2 *H, const float2 *ainv, const float2 *s,
                          float2 *x, hipStream_t st) {
     if (!fused_supported(p, precision)) return hipErrorNotSupported;
     if (p.n_sc == 0 || nk == 0) return hipSuccess;
-    return run_mode(p, precision, kSymbols, nk, H, s, x, (cx<float> *)ainv, nullptr, nullptr, st);
+    return run_mode(p, precision, kSymbols, nk, H, s, x, (cx<float> *)ainv, nullptr, nullptr, st, nullptr);
 }
 
 }  // namespace pc

@@ -14,7 +14,6 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int kThreads = 256;
 constexpr int KC = 16;  // symbols per MFMA chunk: 2*KC = 32 rows of X^T
 constexpr int kMaxKFused = 64;
 
@@ -597,7 +596,7 @@ struct Lds {
     // per wave: scratch (SCRF floats; Gram transpose, then partial / Z) and
     // one system slot (SLOT complex)
     static constexpr size_t per_wave = (size_t)SCRF * 4 + (size_t)Shape<UP>::SLOT * 8;
-    static __host__ __device__ constexpr size_t bytes(int K) { return (size_t)K * 2 * UP * 4 + 4 * per_wave; }
+    static __host__ __device__ constexpr size_t bytes(int K, int nw) { return (size_t)K * 2 * UP * 4 + nw * per_wave; }
 };
 
 // Kernel modes: the whole frame, the per-frame part only (factors to
@@ -642,12 +641,13 @@ constexpr int min_waves() {
 }
 
 // ---- the kernel body -----------------------------------------------------------
-// One workgroup (block index blk of its problem) per PD subcarrier, or per FD
-// (subcarrier, group of four clusters).  Wave w owns up to MAXT channel tiles:
-//   PD: tiles t = w, w + 4, ... of 32 rows over the whole array;
-//   FD: the tiles (32 rows each) of cluster 4 * (group) + w.
+// One workgroup of NW waves (block index blk of its problem) per PD
+// subcarrier, or per FD (subcarrier, group of NW clusters).  Wave w owns up to
+// MAXT channel tiles:
+//   PD: tiles t = w, w + NW, ... of 32 rows over the whole array;
+//   FD: the tiles (32 rows each) of cluster NW * (group) + w.
 // off: the problem's cluster offsets (p.off) in memory the kernel can index.
-template <int UP, int ARCH, int PREC, int MAXT>
+template <int UP, int ARCH, int PREC, int MAXT, int NW>
 __device__ __forceinline__ void fused_body(const Prob &p, const int *__restrict__ off, int blk, int K, int mode,
                                            const float2 *__restrict__ H, const float2 *__restrict__ s,
                                            float2 *__restrict__ x, cx<float> *__restrict__ ainv_g,
@@ -655,27 +655,28 @@ __device__ __forceinline__ void fused_body(const Prob &p, const int *__restrict_
     constexpr int SLOT = Shape<UP>::SLOT;
     constexpr int NTT = Shape<UP>::NTT;
     constexpr int SCRF = Lds<UP>::SCRF;
+    constexpr int NT = 64 * NW;
     extern __shared__ float4 smem4[];
     float *Ss = (float *)smem4;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     char *wbase = (char *)(Ss + (size_t)K * 2 * UP);
-    float *scr_of[4];
+    float *scr_of[NW];
 #pragma unroll
-    for (int w = 0; w < 4; ++w) scr_of[w] = (float *)(wbase + w * Lds<UP>::per_wave);
+    for (int w = 0; w < NW; ++w) scr_of[w] = (float *)(wbase + w * Lds<UP>::per_wave);
     float *scr = scr_of[wave];
     cx<float> *sA = (cx<float> *)(scr + SCRF);
     __shared__ float sh_scale, sh_amax;
     __shared__ int sh_ok;
 
     // PD: one workgroup per subcarrier; FD: one workgroup per (subcarrier,
-    // group of four clusters), one cluster per wave
-    const int CQ = ARCH == kPD ? 1 : (p.C + 3) / 4;
+    // group of NW clusters), one cluster per wave
+    const int CQ = ARCH == kPD ? 1 : (p.C + NW - 1) / NW;
     const int B = p.B, U = p.U, n = blk / CQ, cq = blk % CQ;
     const float2 *Hn = H + (size_t)n * B * U;
     const bool vec = U == UP && (((uintptr_t)H) & 15) == 0;
 
     // symbols of this subcarrier
-    for (int e = tid; e < K * UP; e += kThreads) {
+    for (int e = tid; e < K * UP; e += NT) {
         const int k = e / UP, u = e % UP;
         const float2 v = (u < U) ? s[((size_t)k * p.n_sc + n) * U + u] : make_float2(0.f, 0.f);
         *(float2 *)(Ss + k * 2 * UP + 2 * u) = v;
@@ -689,7 +690,7 @@ __device__ __forceinline__ void fused_body(const Prob &p, const int *__restrict_
         float hmax = 0.f;
 #pragma unroll
         for (int q = 0; q < MAXT; ++q) {
-            const int tt = wave + 4 * q;
+            const int tt = wave + NW * q;
             t_row0[q] = 32 * tt;
             t_rows[q] = max(0, min(32, B - 32 * tt));
             hmax = fmaxf(hmax, load_tile<UP, PREC>(Hn, U, t_row0[q], t_rows[q], vec, tiles[q]));
@@ -732,12 +733,12 @@ __device__ __forceinline__ void fused_body(const Prob &p, const int *__restrict_
         gram_store<UP>(acc, part, gunsc, 0.f, U);
         __syncthreads();
         // partial (cluster) sum in fixed order + kappa I, into wave 0's slot
-        for (int e = tid; e < UP * UP; e += kThreads) {
+        for (int e = tid; e < UP * UP; e += NT) {
             const int u = e / UP, v = e % UP;
             const int o = u * Shape<UP>::LDc + v;
             cx<float> sum = ((cx<float> *)scr_of[0])[o];
 #pragma unroll
-            for (int w = 1; w < 4; ++w) sum = cadd(sum, ((cx<float> *)scr_of[w])[o]);
+            for (int w = 1; w < NW; ++w) sum = cadd(sum, ((cx<float> *)scr_of[w])[o]);
             if (u == v && u < U) sum.re += kap;
             A0[o] = sum;
         }
@@ -776,7 +777,7 @@ __device__ __forceinline__ void fused_body(const Prob &p, const int *__restrict_
         __syncthreads();  // symbols staged
         const float kap = fd_kappa(p);
         const float rho_c2 = p.power / (float)p.C;
-        const int c = 4 * cq + wave;
+        const int c = NW * cq + wave;
         if (c < p.C) {
             const int o0 = off[c], o1 = off[c + 1];
             // this cluster's rows as tiles of 32
@@ -851,9 +852,9 @@ int prec_of(int precision) {
     }
 }
 
-// Channel tiles (32 rows) a wave holds in registers.
-int tiles_per_wave(const Prob &p) {
-    if (p.arch == kPD) return ((p.B + 31) / 32 + 3) / 4;
+// Channel tiles (32 rows) a wave holds in registers with nw waves per workgroup.
+int tiles_per_wave(const Prob &p, int nw) {
+    if (p.arch == kPD) return ((p.B + 31) / 32 + nw - 1) / nw;
     int worst = 0;  // FD: a wave holds one cluster at a time
     for (int c = 0; c < p.C; ++c) {
         const int n = (p.off[c + 1] - p.off[c] + 31) / 32;
@@ -862,12 +863,16 @@ int tiles_per_wave(const Prob &p) {
     return worst;
 }
 
-int pick_maxt(const Prob &p, int up) {
-    const int t = tiles_per_wave(p);
-    const int lim = up == 16 ? 8 : 4;
+// Most channel tiles a wave may hold: register capacity at the occupancy
+// min_waves asks for (an 8-wave workgroup already needs two waves per SIMD).
+constexpr int max_tiles(int up, int nw) { return up == 16 ? (nw <= 4 ? 8 : 4) : (nw <= 4 ? 4 : 2); }
+
+int pick_maxt(const Prob &p, int up, int nw) {
+    const int t = tiles_per_wave(p, nw);
+    const int lim = max_tiles(up, nw);
     if (t <= 1) return 1;
     if (t <= 2) return 2;
-    if (t <= 4) return 4;
+    if (t <= 4 && lim >= 4) return 4;
     if (t <= 8 && lim >= 8) return 8;
     return 0;
 }

@@ -1,0 +1,26 @@
+// fused_launch.h -- launches of the fused kernel for one waves-per-workgroup
+// count NW.  Each NW is compiled in its own translation unit
+// (fused_nw{2,4,8}.hip) so the instantiations build in parallel.  Internal.
+#pragma once
+
+#include "common.h"
+
+namespace pc {
+
+struct FusedCall {
+    int K, mode;  // symbols in this launch; kFull / kPrepare / kSymbols
+    const float2 *H, *s;
+    float2 *x;
+    cx<float> *ainv;  // per-instance factors (prepare / symbols modes)
+    float *scale_out;
+    int *status;
+};
+
+// Enqueue one launch of fused_k<UP, ARCH, PREC, MAXT, NW> for problem p
+// (UP from p.U, PREC from prec, MAXT = maxt): n_sc workgroups for PD,
+// n_sc * ceil(C / NW) for FD, NW * 64 threads each.
+hipError_t fused_launch_nw2(const Prob &p, int prec, int maxt, const FusedCall &a, hipStream_t st);
+hipError_t fused_launch_nw4(const Prob &p, int prec, int maxt, const FusedCall &a, hipStream_t st);
+hipError_t fused_launch_nw8(const Prob &p, int prec, int maxt, const FusedCall &a, hipStream_t st);
+
+}  // namespace pc

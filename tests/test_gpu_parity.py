@@ -252,6 +252,40 @@ def test_refinement_fp64_residual(torch, ctx, pc, arch, cell, ratio):
     assert e1 <= max(e0, 2e-7)
 
 
+@pytest.mark.parametrize("nw", [2, 4, 8])
+@pytest.mark.parametrize("name", ["cfg1", "ragged", "u32", "u20_kron", "many_clusters", "k70"])
+def test_launch_shapes(torch, ctx, pc, monkeypatch, nw, name):
+    """Every waves-per-workgroup shape the autotuner may pick, forced."""
+    _, cell, mode = next(c for c in CASES if c[0] == name)
+    monkeypatch.setenv("PRECODE_FUSED_WAVES", str(nw))
+    H, s = synth.make_cell(cell, seed=11)
+    Hd, sd = _dev(torch, H), _dev(torch, s)
+    for arch in ("pd", "fd"):
+        fn = ctx.pd if arch == "pd" else ctx.fd
+        x, sc, st = fn(Hd, sd, cell.kappa, cell.sizes, mode, pc.params(fp64_ratio=2.0))
+        torch.cuda.synchronize()
+        if ctx.last_impl != "fused":
+            continue
+        print("%s %s nw=%d used=%d" % (name, arch, nw, ctx.last_waves), flush=True)
+        xo, sco, sto = _oracle(arch, H, s, cell.kappa, cell.sizes, mode)
+        _check(x.cpu().numpy(), sc.cpu().numpy().reshape(sco.shape), st.cpu().numpy().reshape(sto.shape),
+               xo, sco, sto)
+
+
+def test_autotuned_shape_is_cached_and_deterministic(torch, ctx, pc, monkeypatch):
+    monkeypatch.delenv("PRECODE_FUSED_WAVES", raising=False)
+    monkeypatch.setenv("PRECODE_AUTOTUNE", "1")
+    cell = synth.Cell(B=128, sizes=(32,) * 4, U=16, n_sc=300, K=14)
+    H, s = synth.make_cell(cell, seed=12)
+    Hd, sd = _dev(torch, H), _dev(torch, s)
+    x1, _, _ = ctx.pd(Hd, sd, cell.kappa, cell.sizes)
+    w1 = ctx.last_waves
+    x2, _, _ = ctx.pd(Hd, sd, cell.kappa, cell.sizes)
+    torch.cuda.synchronize()
+    assert w1 in (2, 4, 8) and ctx.last_waves == w1
+    assert torch.equal(x1, x2)
+
+
 # Mixed batch spanning every launch class and the plain fallback: tile widths
 # 16 / 32, PD / FD, 1..8 channel tiles per wave, symbol slicing (K > 64),
 # FD clusters smaller than U and U > 32 (plain kernels), an empty job.
