@@ -147,6 +147,7 @@ def main():
                         "i.i.d. Rayleigh complex64, 16-QAM, SNR 10 dB",
             "arch": "PD", "mode": "WF", "B": B, "C": len(sizes), "U": U, "n_sc": n_sc, "K": K,
             "impl": ctx.last_impl, "precision": "fp32", "frames_rotated": n_frames,
+            "waves_per_workgroup": ctx.last_waves,
         },
         "roofline": {
             "bound": "hbm",
@@ -167,6 +168,14 @@ def main():
         variants[prec] = {"ms_per_step": ms_v, "value": n_sc * K / (ms_v * 1e-3),
                           "achieved_gbs": frame_bytes / (float(np.mean(per_v)) * 1e-3) / 1e9}
     out["pd_precision_variants"] = variants
+    # every launch shape the autotuner chooses from, forced
+    shapes = {}
+    for nw in (2, 4, 8):
+        os.environ["PRECODE_FUSED_WAVES"] = str(nw)
+        ms_s, per_s = time_path(pd_fused, max(10, args.steps // 4), 3)
+        shapes[str(nw)] = {"ms_per_step": ms_s, "launch_ms": float(np.mean(per_s)), "used": ctx.last_waves}
+    del os.environ["PRECODE_FUSED_WAVES"]
+    out["pd_launch_shapes"] = shapes
     if not args.quick:
         steps2 = max(10, args.steps // 4)
         ms_plain, _ = time_path(pd_plain, steps2, 3)
