@@ -300,7 +300,9 @@ def _mix_jobs(torch, cells, seed=40):
     return jobs, host
 
 
-def test_batch_mixed_classes(torch, ctx, pc):
+def test_batch_mixed_classes(torch, ctx, pc, monkeypatch):
+    # the batch launches use 4 waves per workgroup: compare with that shape
+    monkeypatch.setenv("PRECODE_FUSED_WAVES", "4")
     jobs, host = _mix_jobs(torch, MIX)
     outs = ctx.batch(jobs)
     torch.cuda.synchronize()
