@@ -698,12 +698,16 @@ __device__ __forceinline__ void fused_body(const Prob &p, const int *__restrict_
         // power-of-two operand scale of this wave's rows (16-bit MFMA)
         const int eh = PREC == kF32 ? 0 : fp16_exp(wave_max(hmax));
         const float hsc = ldexpf(1.f, eh), hunsc = ldexpf(1.f, -eh), gunsc = ldexpf(1.f, -2 * eh);
-        cx<float> *A0 = (cx<float> *)(scr_of[0] + SCRF);
+        // the wave that factors and solves rotates with the block index so that
+        // the serial steps of co-resident workgroups land on different SIMDs
+        const int mw = blk % NW;
+        float *scr_m = (float *)(wbase + mw * Lds<UP>::per_wave);
+        cx<float> *A0 = (cx<float> *)(scr_m + SCRF);
         if (mode == kSymbols) {
             // per-frame factors from the prepare pass: scale * A^-1
 #pragma unroll
             for (int q = 0; q < MAXT; ++q) tile_split<UP, PREC>(tiles[q], hsc);
-            if (wave == 0) {
+            if (wave == mw) {
                 const float amax = load_factor<UP>(ainv_g + (size_t)n * U * U, U, A0);
                 if (lane == 0) {
                     sh_scale = 1.f;
@@ -732,7 +736,7 @@ __device__ __forceinline__ void fused_body(const Prob &p, const int *__restrict_
         wave_sync();
         gram_store<UP>(acc, part, gunsc, 0.f, U);
         __syncthreads();
-        // partial (cluster) sum in fixed order + kappa I, into wave 0's slot
+        // partial (cluster) sum in fixed order + kappa I, into the master slot
         for (int e = tid; e < UP * UP; e += NT) {
             const int u = e / UP, v = e % UP;
             const int o = u * Shape<UP>::LDc + v;
@@ -743,7 +747,7 @@ __device__ __forceinline__ void fused_body(const Prob &p, const int *__restrict_
             A0[o] = sum;
         }
         __syncthreads();
-        if (wave == 0) {
+        if (wave == mw) {
             float t = 0.f, amax = 0.f;
             const bool ok = wave_factor<UP>(A0, U, kap, &t, &amax);
             const float beta = ok ? sqrtf(p.Es / p.power * t) : 0.f;
@@ -758,10 +762,10 @@ __device__ __forceinline__ void fused_body(const Prob &p, const int *__restrict_
         }
         __syncthreads();
         }
-        cx<float> *Zw = (cx<float> *)scr_of[0];  // free after the partial sum
+        cx<float> *Zw = (cx<float> *)scr_m;  // free after the partial sum
         for (int k0 = 0; mode != kPrepare && k0 < K; k0 += KC) {
             const int kc = min(KC, K - k0);
-            if (wave == 0) wave_solve_chunk<UP, PREC>(A0, Zw, Ss, k0, kc, U, sh_scale, sh_amax, sh_ok != 0);
+            if (wave == mw) wave_solve_chunk<UP, PREC>(A0, Zw, Ss, k0, kc, U, sh_scale, sh_amax, sh_ok != 0);
             __syncthreads();
             ZOp<UP, PREC> z;
             make_zop<UP, PREC>(Zw, KC, 1, kc, z);
