@@ -324,7 +324,9 @@ def test_batch_mixed_classes(torch, ctx, pc, monkeypatch):
 
 @pytest.mark.parametrize("prec,tol", [("split_fp16", 1e-5), ("split_bf16", 1e-3)])
 def test_batch_split_precision(torch, ctx, pc, prec, tol):
-    cells = [mc for mc in MIX if mc[1].U <= 32 and mc[1].n_sc > 0 and min(mc[1].sizes) >= mc[1].U]
+    # fused-capable jobs only: U <= 32, no FP64 route (U / B_eff < 0.5), FD clusters with B_c >= U
+    cells = [mc for mc in MIX if mc[1].U <= 32 and mc[1].n_sc > 0 and
+             2 * mc[1].U < (mc[1].B if mc[0] == "pd" else min(mc[1].sizes))]
     jobs, host = _mix_jobs(torch, cells, seed=60)
     outs = ctx.batch(jobs, precision=prec)
     torch.cuda.synchronize()
