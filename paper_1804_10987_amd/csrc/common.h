@@ -118,11 +118,10 @@ hipError_t fused_symbols(const Prob &p, int precision, int nk, const float2 *H, 
                          float2 *x, hipStream_t st);
 
 // Heterogeneous batch of fused problems (batch.hip): every problem must be
-// fused_supported at `precision` with K >= 1.  The problems are split into
-// slices of at most 64 symbols, grouped by kernel shape class (tile width,
-// PD/FD, channel tiles per wave) and each class runs as one launch over all
-// its subcarriers; a block finds its problem by binary search in a table in
-// device memory.
+// fused_supported at `precision` with K >= 1.  The problems are grouped by
+// tile width (U <= 16 or U <= 32) and each group -- PD and FD alike -- runs as
+// one launch over all its local systems; a block finds its problem by binary
+// search in a table in device memory.
 struct BatchProblem {
     Prob p;
     const float2 *H, *s;

@@ -1,49 +1,49 @@
 // fused.hip -- single-problem dispatch of the fused PD / FD kernel on gfx950,
 // with the launch-shape autotuner.
 //
-// One launch runs the whole per-subcarrier chain; only the precoded vectors,
+// One launch runs the whole per-system chain; only the precoded vectors,
 // beta / weights and status are written back (the kernel body is in
-// fused_kernel.h):
+// fused_kernel.h).  Every wave owns one local system -- a PD subcarrier over
+// the whole array, or one FD cluster of a subcarrier -- and runs it without
+// any workgroup barrier:
 //
 //   Gram        G_c = H_c^H H_c on MFMA over the real embedding
 //               [Re h_u, Im h_u] of the columns: the 2U x 2U real Gram M
 //               gives G = (M_rr + M_ii) + i (M_ri - M_ir) (local Gram,
-//               Sec. III-B; PD sums the cluster Grams as a split-K reduction
-//               over the waves, the on-chip form of the adder tree)
+//               Sec. III-B; for PD the accumulation over every cluster's
+//               rows is the cluster sum of the adder tree).  Rows stream
+//               from HBM in 32-row tiles loaded straight into the MFMA
+//               operand layout, the next tile's loads in flight during the
+//               current tile's MFMAs
 //   regularize  A = G + kappa I (PD) / A_c = G_c + kappa_c I (FD,
 //               kappa_c = tau_c C kappa, Sec. III-C)
-//   invert      A^-1 in registers, one wave per system (Gauss-Jordan
-//               elimination; for Hermitian positive-definite A its pivots are
-//               the squared diagonal of the Cholesky factor)
+//   invert      A^-1 in registers (Gauss-Jordan elimination; for Hermitian
+//               positive-definite A its pivots are the squared diagonal of
+//               the Cholesky factor)
 //   factor      t = tr A^-1 - kappa ||A^-1||_F^2 (Lemma 1);
 //               PD beta = sqrt(Es/rho^2 t); FD w_c = sqrt(rho_c^2/(t Es))
-//   solve       Z = scale * A^-1 S for chunks of 16 symbols, on MFMA
-//   precode     X_c = H_c Z on MFMA from the register-resident channel tiles
-//               (Sec. III-B; FD x_c = w_c H_c A_c^-1 s, Sec. III-C), stored
-//               coalesced
+//   solve       Z = scale * A^-1 S for chunks of 16 symbols, on MFMA, with S
+//               read from global memory
+//   precode     X_c = H_c Z on MFMA (Sec. III-B; FD x_c = w_c H_c A_c^-1 s,
+//               Sec. III-C): the rows are streamed a second time (served by
+//               the cache) in the row layout of the product and the results
+//               stored coalesced
 //
-// PD: one 256-thread workgroup (4 wave64s) per subcarrier; wave w keeps the
-// 32-row channel tiles t = w, w + 4, ... in registers from the Gram to the
-// precode, so the channel is read from HBM exactly once.  FD: one workgroup
-// per (subcarrier, group of four clusters), one cluster per wave, no
-// workgroup barrier after the symbols are staged.
-//
-// Launch shape: NW = 2, 4 or 8 waves per workgroup (fused_nw{2,4,8}.hip);
-// with fewer waves each wave holds more channel tiles (MAXT), with more the
-// per-subcarrier chain is shorter but more waves wait at its barriers.  The
-// autotuner times every feasible NW on the first call of each problem shape
-// (the call itself, repeated) and caches the fastest for the process.
+// Launch shape: NW = 2, 4 or 8 waves (systems) per workgroup
+// (fused_nw{2,4,8}.hip).  The autotuner times every feasible NW on the first
+// call of each problem shape (the call itself, repeated) and caches the
+// fastest for the process.
 //
 // Modes: full (Gram to precode), prepare (per-frame factors scale * A^-1 to
 // device memory for the frame API and serving) and symbols (precode released
 // symbols from stored factors, re-reading only the channel).
 //
-// MFMA precision (template PREC): FP32 (v_mfma_f32_32x32x2f32, exact FP32
-// products) or split 16-bit: every operand x is written as hi + lo with
-// hi = f16(x), lo = f16(x - hi) (or bf16) and a product a b is accumulated as
-// ah bh + ah bl + al bh in FP32 (v_mfma_f32_32x32x16_f16 / _bf16).  Operands
-// are scaled by powers of two into the FP16 range first and the FP32 results
-// unscaled exactly.
+// MFMA precision (PREC): FP32 (v_mfma_f32_32x32x2f32, exact FP32 products)
+// or split 16-bit: every operand x is written as hi + lo with hi = f16(x),
+// lo = f16(x - hi) (or bf16) and a product a b is accumulated as
+// ah bh + ah bl + al bh in FP32 (v_mfma_f32_32x32x16_f16 / _bf16).  Each
+// operand tile is scaled by a power of two into the FP16 range first and the
+// FP32 result unscaled exactly.
 #include <stdio.h>
 #include <stdlib.h>
 
@@ -62,40 +62,32 @@ constexpr int kDefaultNW = 4;
 
 bool nw_feasible(const Prob &p, int nw) {
     const int up = pick_up(p.U);
-    if (up == 0 || pick_maxt(p, up, nw) == 0) return false;
-    const size_t lds = up == 16 ? Lds<16>::bytes(kMaxKFused, nw) : Lds<32>::bytes(kMaxKFused, nw);
+    if (up == 0) return false;
+    const size_t lds = up == 16 ? Lds<16>::bytes(nw) : Lds<32>::bytes(nw);
     return lds <= kLdsMax - 256;
 }
 
 hipError_t launch_nw(int nw, const Prob &p, int prec, const FusedCall &a, hipStream_t st) {
-    const int maxt = pick_maxt(p, pick_up(p.U), nw);
     switch (nw) {
-        case 2: return fused_launch_nw2(p, prec, maxt, a, st);
-        case 8: return fused_launch_nw8(p, prec, maxt, a, st);
-        default: return fused_launch_nw4(p, prec, maxt, a, st);
+        case 2: return fused_launch_nw2(p, prec, a, st);
+        case 8: return fused_launch_nw8(p, prec, a, st);
+        default: return fused_launch_nw4(p, prec, a, st);
     }
 }
 
-// Launches one mode over symbol slices of at most kMaxKFused.
-hipError_t run_slices(int nw, const Prob &p, int prec, int mode, int K, const float2 *H, const float2 *s, float2 *x,
-                      cx<float> *ainv, float *scale_out, int *status, hipStream_t st) {
-    for (int k0 = 0; k0 < K || (k0 == 0 && mode == kPrepare); k0 += kMaxKFused) {
-        const int kk = mode == kPrepare ? 0 : (K - k0 < kMaxKFused ? K - k0 : kMaxKFused);
-        FusedCall a;
-        a.K = kk;
-        a.mode = mode;
-        a.H = H;
-        a.s = s ? s + (size_t)k0 * p.n_sc * p.U : nullptr;
-        a.x = x ? x + (size_t)k0 * p.n_sc * p.B : nullptr;
-        a.ainv = ainv;
-        // factors are identical for every slice; write them once
-        a.scale_out = k0 == 0 ? scale_out : nullptr;
-        a.status = k0 == 0 ? status : nullptr;
-        hipError_t e = launch_nw(nw, p, prec, a, st);
-        if (e != hipSuccess) return e;
-        if (mode == kPrepare) break;
-    }
-    return hipSuccess;
+// One launch of a mode (all K symbols, in chunks of 16 inside the kernel).
+hipError_t run_once(int nw, const Prob &p, int prec, int mode, int K, const float2 *H, const float2 *s, float2 *x,
+                    cx<float> *ainv, float *scale_out, int *status, hipStream_t st) {
+    FusedCall a;
+    a.K = mode == kPrepare ? 0 : K;
+    a.mode = mode;
+    a.H = H;
+    a.s = s;
+    a.x = x;
+    a.ainv = ainv;
+    a.scale_out = scale_out;
+    a.status = status;
+    return launch_nw(nw, p, prec, a, st);
 }
 
 // ---- autotuner ------------------------------------------------------------------
@@ -107,7 +99,7 @@ std::unordered_map<std::string, int> g_tuned;
 
 std::string tune_key(const Prob &p, int prec, int mode, int K) {
     std::string k = std::to_string(p.arch) + "/" + std::to_string(p.U) + "/" + std::to_string(p.B) + "/" +
-                    std::to_string(p.n_sc) + "/" + std::to_string(K < kMaxKFused ? K : kMaxKFused) + "/" +
+                    std::to_string(p.n_sc) + "/" + std::to_string(K) + "/" +
                     std::to_string(prec) + "/" + std::to_string(mode) + ":";
     if (p.arch == kFD)
         for (int c = 0; c < p.C; ++c) k += std::to_string(p.off[c + 1] - p.off[c]) + ",";
@@ -158,10 +150,10 @@ int choose_nw(const Prob &p, int prec, int mode, int K, const float2 *H, const f
         bool ok = true;
         for (int i = 0; i < nc && ok; ++i) {
             // first launch of a kernel also loads it: time the repeats only
-            ok = run_slices(cands[i], p, prec, mode, K, H, s, x, ainv, scale_out, status, st) == hipSuccess &&
+            ok = run_once(cands[i], p, prec, mode, K, H, s, x, ainv, scale_out, status, st) == hipSuccess &&
                  hipEventRecord(e0, st) == hipSuccess;
             for (int r = 0; r < 3 && ok; ++r)
-                ok = run_slices(cands[i], p, prec, mode, K, H, s, x, ainv, scale_out, status, st) == hipSuccess;
+                ok = run_once(cands[i], p, prec, mode, K, H, s, x, ainv, scale_out, status, st) == hipSuccess;
             float ms = 0.f;
             ok = ok && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
                  hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
@@ -188,7 +180,7 @@ hipError_t run_mode(const Prob &p, int precision, int mode, int K, const float2 
     const int nw = choose_nw(p, prec, mode, K, H, s, x, ainv, scale_out, status, st);
     if (nw == 0) return hipErrorNotSupported;
     if (nw_used) *nw_used = nw;
-    return run_slices(nw, p, prec, mode, K, H, s, x, ainv, scale_out, status, st);
+    return run_once(nw, p, prec, mode, K, H, s, x, ainv, scale_out, status, st);
 }
 
 }  // namespace

@@ -15,7 +15,6 @@ typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int KC = 16;  // symbols per MFMA chunk: 2*KC = 32 rows of X^T
-constexpr int kMaxKFused = 64;
 
 enum Prec { kF32 = 0, kF16 = 1, kBF16 = 2 };
 
@@ -54,7 +53,6 @@ template <int UP>
 struct Shape {
     static constexpr int NT = (2 * UP) / 32;       // 32-wide real column tiles
     static constexpr int NTT = NT * (NT + 1) / 2;  // tiles with ti <= tj
-    static constexpr int RS = 2 * UP + 4;          // H row stride in LDS (floats)
     static constexpr int LDc = UP + 2;             // slot leading dim (complex), rows 16B aligned
     static constexpr int SLOT = UP * LDc;          // complex elements per slot
 };
@@ -109,85 +107,94 @@ __device__ __forceinline__ floatx16 mfma32(float a, float b, floatx16 c) {
 }
 
 // ---- Gram ----------------------------------------------------------------------
-// Real Gram of `nrows` rows (row-major floats, stride rs), values scaled by sc:
-// acc[t] += M[32ti+i][32tj+j] = sum_r R[r][32ti+i] R[r][32tj+j], ti <= tj.
-// 32x32 MFMA operands: lane l supplies A[l%32][k] and B[k][l%32] for its
-// contraction slots k; here both are R[row(k)][col], so a lane reads only the
-// column l%32 of its rows (two rows per FP32 instruction, 8 per lane half per
-// 16-bit instruction).
+// Channel rows in the Gram operand layout: the A and B operands of an MFMA
+// step are the same register, lane (j, g) holding real column 32 ti + j of
+//   FP32 (32x32x2, one step per row pair):  v[ti][s] = row 2 s + g;
+//   16-bit (32x32x16, one step per 16 rows): v[ti][8 b + e] = row 16 b + 8 g + e.
+template <int UP>
+struct GramBuf {
+    float v[Shape<UP>::NT][16];
+};
+
+// Loads rows [row0, row0 + nrows) (nrows <= 32) of one subcarrier's channel
+// Hf (real row stride u2 = 2U) from global memory; columns >= u2 and rows
+// >= nrows read as 0.  Lanes of one load instruction read two whole rows.
 template <int UP, int PREC>
-__device__ __forceinline__ void mfma_gram(const float *rows, int rs, int nrows, float sc,
-                                          floatx16 (&acc)[Shape<UP>::NTT]) {
+__device__ __forceinline__ void gram_load(const float *__restrict__ Hf, int u2, int row0, int nrows,
+                                          GramBuf<UP> &b) {
     constexpr int NT = Shape<UP>::NT;
     const int lane = lane_id();
     const int j = lane & 31, g = lane >> 5;
+    // row = rq + rg with rq uniform: one uniform row pointer per register and
+    // one 32-bit lane offset shared by every load
+    const int rg = PREC == kF32 ? g : 8 * g;
+    const int loff = rg * u2 + j;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int rq = PREC == kF32 ? 2 * q : 16 * (q / 8) + (q % 8);
+        const float *rowp = Hf + (size_t)(row0 + rq) * u2;
+        const bool rowok = rq + rg < nrows;
+#pragma unroll
+        for (int ti = 0; ti < NT; ++ti)
+            b.v[ti][q] = (rowok && 32 * ti + j < u2) ? rowp[loff + 32 * ti] : 0.f;
+    }
+}
+
+// acc[t] += real Gram of the buffered rows, t over the tile pairs ti <= tj.
+// 16-bit: the rows are scaled by a power of two into the FP16 range, split
+// hi + lo, and the tile's product is unscaled exactly into acc.
+template <int UP, int PREC>
+__device__ __forceinline__ void gram_mma(const GramBuf<UP> &b, floatx16 (&acc)[Shape<UP>::NTT]) {
+    constexpr int NT = Shape<UP>::NT;
+    constexpr int NTT = Shape<UP>::NTT;
     if constexpr (PREC == kF32) {
-        // groups of G instructions (2 rows each); the LDS reads of the next
-        // group are issued before the MFMAs of the current one
-        constexpr int G = 4;
-        float cur[G][NT], nxt[G][NT];
-        auto load = [&](float (&v)[G][NT], int r) {
 #pragma unroll
-            for (int a = 0; a < G; ++a) {
-                const int row = r + 2 * a + g;
-#pragma unroll
-                for (int ti = 0; ti < NT; ++ti) v[a][ti] = row < nrows ? rows[row * rs + 32 * ti + j] : 0.f;
-            }
-        };
-        load(nxt, 0);
-#pragma unroll 1
-        for (int r = 0; r < nrows; r += 2 * G) {
-#pragma unroll
-            for (int a = 0; a < G; ++a)
-#pragma unroll
-                for (int ti = 0; ti < NT; ++ti) cur[a][ti] = nxt[a][ti];
-            if (r + 2 * G < nrows) load(nxt, r + 2 * G);
-#pragma unroll
-            for (int a = 0; a < G; ++a) {
-                int t = 0;
-#pragma unroll
-                for (int ti = 0; ti < NT; ++ti)
-#pragma unroll
-                    for (int tj = ti; tj < NT; ++tj) {
-                        acc[t] = mfma32(cur[a][ti], cur[a][tj], acc[t]);
-                        ++t;
-                    }
-            }
-        }
-    } else {
-        typedef typename Split<PREC>::V V;
-        // 16 rows per step; the LDS reads of the next step are issued before
-        // the split and MFMAs of the current one
-        float cur[NT][8], nxt[NT][8];
-        auto load = [&](float (&v)[NT][8], int r) {
-#pragma unroll
-            for (int ti = 0; ti < NT; ++ti)
-#pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const int row = r + 8 * g + e;
-                    v[ti][e] = row < nrows ? rows[row * rs + 32 * ti + j] : 0.f;
-                }
-        };
-        load(nxt, 0);
-#pragma unroll 1
-        for (int r = 0; r < nrows; r += 16) {
-#pragma unroll
-            for (int ti = 0; ti < NT; ++ti)
-#pragma unroll
-                for (int e = 0; e < 8; ++e) cur[ti][e] = nxt[ti][e] * sc;
-            if (r + 16 < nrows) load(nxt, r + 16);
-            V hi[NT], lo[NT];
-#pragma unroll
-            for (int ti = 0; ti < NT; ++ti) Split<PREC>::split(cur[ti], hi[ti], lo[ti]);
+        for (int s = 0; s < 16; ++s) {
             int t = 0;
 #pragma unroll
             for (int ti = 0; ti < NT; ++ti)
 #pragma unroll
                 for (int tj = ti; tj < NT; ++tj) {
-                    acc[t] = mfma3<PREC>(hi[ti], lo[ti], hi[tj], lo[tj], acc[t]);
+                    acc[t] = mfma32(b.v[ti][s], b.v[tj][s], acc[t]);
                     ++t;
                 }
         }
+    } else {
+        typedef typename Split<PREC>::V V;
+        float m = 0.f;
+#pragma unroll
+        for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) m = fmaxf(m, fabsf(b.v[ti][q]));
+        const int e2 = fp16_exp(wave_max(m));
+        const float sc = ldexpf(1.f, e2);
+        floatx16 part[NTT];
+#pragma unroll
+        for (int t = 0; t < NTT; ++t) part[t] = floatx16{0};
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            V hi[NT], lo[NT];
+#pragma unroll
+            for (int ti = 0; ti < NT; ++ti) {
+                float w[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) w[e] = b.v[ti][8 * s + e] * sc;
+                Split<PREC>::split(w, hi[ti], lo[ti]);
+            }
+            int t = 0;
+#pragma unroll
+            for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+                for (int tj = ti; tj < NT; ++tj) {
+                    part[t] = mfma3<PREC>(hi[ti], lo[ti], hi[tj], lo[tj], part[t]);
+                    ++t;
+                }
+        }
+        const float un = ldexpf(1.f, -2 * e2);
+#pragma unroll
+        for (int t = 0; t < NTT; ++t)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[t][r] = fmaf(part[t][r], un, acc[t][r]);
     }
 }
 
@@ -257,9 +264,10 @@ struct ZOp {
     float unscale;  // 2^-ez
 };
 
+// For 16-bit MFMA: scales the loaded operand by a power of two into the FP16
+// range and splits it hi + lo (z.unscale undoes the scale).
 template <int UP, int PREC>
-__device__ __forceinline__ void make_zop(const cx<float> *Z, int su, int sk, int kvalid, ZOp<UP, PREC> &z) {
-    load_zop<UP>(Z, su, sk, kvalid, z.f);
+__device__ __forceinline__ void zop_finish(ZOp<UP, PREC> &z) {
     z.unscale = 1.f;
     if constexpr (PREC != kF32) {
         float m = 0.f;
@@ -276,6 +284,31 @@ __device__ __forceinline__ void make_zop(const cx<float> *Z, int su, int sk, int
             Split<PREC>::split(v, z.hi[q], z.lo[q]);
         }
     }
+}
+
+template <int UP, int PREC>
+__device__ __forceinline__ void make_zop(const cx<float> *Z, int su, int sk, int kvalid, ZOp<UP, PREC> &z) {
+    load_zop<UP>(Z, su, sk, kvalid, z.f);
+    zop_finish<UP, PREC>(z);
+}
+
+// The symbol operand straight from global memory: s(u, k) at sk0[k * kstride
+// + u] for u < U, k < kvalid (zero elsewhere).
+template <int UP, int PREC>
+__device__ __forceinline__ void make_zop_s(const float2 *__restrict__ sk0, size_t kstride, int U, int kvalid,
+                                           ZOp<UP, PREC> &z) {
+    const int lane = lane_id();
+    const int i = lane & 31, g = lane >> 5;
+    const int k = i >> 1, q = i & 1;
+#pragma unroll
+    for (int mm = 0; mm < UP; mm += 2) {
+        const int u = (g * UP + mm) >> 1;
+        float2 v = make_float2(0.f, 0.f);
+        if (k < kvalid && u < U) v = sk0[(size_t)k * kstride + u];
+        z.f[mm] = q ? v.y : v.x;
+        z.f[mm + 1] = q ? v.x : -v.y;
+    }
+    zop_finish<UP, PREC>(z);
 }
 
 // X^T tile (32 x 32): rows (k, re/im) for a 16-symbol chunk, columns = rows
@@ -461,17 +494,16 @@ __device__ bool wave_factor(cx<float> *sA, int m, float kap, float *t_out, float
     return ok;
 }
 
-// Z(u, k) = scale * (A^-1 S)(u, k) for one chunk into slot B as [UP][KC].
+// Z(u, k) = scale * (A^-1 S)(u, k) for one chunk of symbols (operand zs)
+// into slot B as [UP][KC]; a failed system (ok false) gets Z = 0.
 template <int UP, int PREC>
-__device__ void wave_solve_chunk(const cx<float> *sA, cx<float> *sB, const float *Ss, int k0, int kc, int m,
+__device__ void wave_solve_chunk(const cx<float> *sA, cx<float> *sB, const ZOp<UP, PREC> &zs, int kc, int m,
                                  float scale, float amax, bool ok) {
     const int lane = lane_id();
     const int j = lane & 31, g = lane >> 5;
-    ZOp<UP, PREC> z;
-    make_zop<UP, PREC>((const cx<float> *)Ss + k0 * UP, 1, UP, kc, z);
     const int ea = PREC == kF32 ? 0 : fp16_exp(amax);
     const floatx16 a = mfma_apply<UP, PREC>((const float *)sA, 2 * Shape<UP>::LDc, m, ldexpf(1.f, ea),
-                                            ldexpf(scale, -ea), z);
+                                            ldexpf(scale, -ea), zs);
     if (j < UP) {
 #pragma unroll
         for (int r = 0; r < 16; r += 2) {
@@ -485,11 +517,11 @@ __device__ void wave_solve_chunk(const cx<float> *sA, cx<float> *sB, const float
     }
 }
 
-// ---- channel tiles in registers -----------------------------------------------
-// A wave keeps the channel rows it precodes in registers, 32 rows per tile, in
-// the B-operand layout of the precode MFMA: lane (j, g) holds row row0 + j,
-// real columns g*UP .. g*UP + UP - 1 (users g*UP/2 .. g*UP/2 + UP/2 - 1).
-// For 16-bit MFMA the tile is kept split (hi + lo of the scaled values).
+// ---- channel tiles for the precode -------------------------------------------
+// 32 channel rows in the B-operand layout of the precode MFMA: lane (j, g)
+// holds row row0 + j, real columns g*UP .. g*UP + UP - 1 (users g*UP/2 ..
+// g*UP/2 + UP/2 - 1).  For 16-bit MFMA the tile is split (hi + lo of the
+// values scaled by a power of two into the FP16 range).
 template <int UP, int PREC>
 struct Tile {
     float f[UP];
@@ -497,13 +529,12 @@ struct Tile {
 };
 
 // Loads rows [row0, row0 + nrows) of a subcarrier's channel Hn (B x U) into a
-// tile (rows >= nrows and users >= U read as 0); returns the lane's max |h|.
+// tile (rows >= nrows and users >= U read as 0).
 template <int UP, int PREC>
-__device__ __forceinline__ float load_tile(const float2 *__restrict__ Hn, int U, int row0, int nrows, bool vec,
-                                           Tile<UP, PREC> &tl) {
+__device__ __forceinline__ void load_tile(const float2 *__restrict__ Hn, int U, int row0, int nrows, bool vec,
+                                          Tile<UP, PREC> &tl) {
     const int lane = lane_id();
     const int j = lane & 31, g = lane >> 5;
-    float mx = 0.f;
     if (j < nrows) {
         const float2 *rp = Hn + (size_t)(row0 + j) * U + g * (UP / 2);
         if (vec) {  // U == UP, 16-byte aligned rows
@@ -524,31 +555,27 @@ __device__ __forceinline__ float load_tile(const float2 *__restrict__ Hn, int U,
                 tl.f[2 * m2 + 1] = v.y;
             }
         }
-#pragma unroll
-        for (int m = 0; m < UP; ++m) mx = fmaxf(mx, fabsf(tl.f[m]));
     } else {
 #pragma unroll
         for (int m = 0; m < UP; ++m) tl.f[m] = 0.f;
     }
-    return mx;
 }
 
-// Writes a tile row-major into the wave's LDS scratch (row stride RS floats).
+// X^T tile: rows (k, re/im) of a 16-symbol chunk, columns = the tile's 32
+// rows.  16-bit: the tile is scaled into the FP16 range and split here and the
+// product unscaled (with the Z unscale).
 template <int UP, int PREC>
-__device__ __forceinline__ void tile_to_lds(const Tile<UP, PREC> &tl, float *scr) {
-    constexpr int RS = Shape<UP>::RS;
-    const int lane = lane_id();
-    const int j = lane & 31, g = lane >> 5;
-    float *rp = scr + j * RS + g * UP;
+__device__ __forceinline__ floatx16 mfma_apply_tile(Tile<UP, PREC> &tl, const ZOp<UP, PREC> &z) {
+    floatx16 acc = {0};
+    if constexpr (PREC == kF32) {
 #pragma unroll
-    for (int m4 = 0; m4 < UP; m4 += 4)
-        *(float4 *)(rp + m4) = make_float4(tl.f[m4], tl.f[m4 + 1], tl.f[m4 + 2], tl.f[m4 + 3]);
-}
-
-// For 16-bit MFMA: splits the tile (scaled by sc) into hi + lo once.
-template <int UP, int PREC>
-__device__ __forceinline__ void tile_split(Tile<UP, PREC> &tl, float sc) {
-    if constexpr (PREC != kF32) {
+        for (int m = 0; m < UP; ++m) acc = mfma32(z.f[m], tl.f[m], acc);
+    } else {
+        float mx = 0.f;
+#pragma unroll
+        for (int m = 0; m < UP; ++m) mx = fmaxf(mx, fabsf(tl.f[m]));
+        const int eh = fp16_exp(wave_max(mx));
+        const float sc = ldexpf(1.f, eh);
 #pragma unroll
         for (int q = 0; q < UP / 8; ++q) {
             float v[8];
@@ -556,47 +583,38 @@ __device__ __forceinline__ void tile_split(Tile<UP, PREC> &tl, float sc) {
             for (int e = 0; e < 8; ++e) v[e] = tl.f[8 * q + e] * sc;
             Split<PREC>::split(v, tl.hi[q], tl.lo[q]);
         }
-    }
-}
-
-// X^T tile from a register channel tile: rows (k, re/im) of a 16-symbol
-// chunk, columns = the tile's 32 rows, times `post` (and the Z unscale).
-template <int UP, int PREC>
-__device__ __forceinline__ floatx16 mfma_apply_tile(const Tile<UP, PREC> &tl, float post, const ZOp<UP, PREC> &z) {
-    floatx16 acc = {0};
-    if constexpr (PREC == kF32) {
-#pragma unroll
-        for (int m = 0; m < UP; ++m) acc = mfma32(z.f[m], tl.f[m], acc);
-        acc *= post;
-    } else {
 #pragma unroll
         for (int q = 0; q < UP / 8; ++q) acc = mfma3<PREC>(z.hi[q], z.lo[q], tl.hi[q], tl.lo[q], acc);
-        acc *= post * z.unscale;
+        acc *= ldexpf(z.unscale, -eh);
     }
     return acc;
 }
 
 // Stores the X^T tile of rows [row0, row0 + nrows), symbols k0 .. k0 + kc - 1.
+// Symbol k = tile_k(r, g) = kr + 2 g: a uniform symbol pointer per register
+// pair and one lane offset.
 __device__ __forceinline__ void store_x(const floatx16 &a, int row0, int nrows, int k0, int kc, int n, int n_sc,
                                         int B, float2 *__restrict__ x) {
     const int lane = lane_id();
     const int j = lane & 31, g = lane >> 5;
+    const size_t kstride = (size_t)n_sc * B;
+    const size_t loff = 2 * g * kstride + j;
     if (j < nrows) {
 #pragma unroll
         for (int r = 0; r < 16; r += 2) {
-            const int k = tile_k(r, g);
-            if (k < kc) x[((size_t)(k0 + k) * n_sc + n) * B + row0 + j] = make_float2(a[r], a[r + 1]);
+            const int kr = tile_k(r, 0);
+            float2 *xp = x + (size_t)(k0 + kr) * kstride + (size_t)n * B + row0;
+            if (kr + 2 * g < kc) xp[loff] = make_float2(a[r], a[r + 1]);
         }
     }
 }
 
+// LDS per wave: the Z chunk (UP x KC complex) and one system slot (SLOT complex).
 template <int UP>
 struct Lds {
-    static constexpr int SCRF = 32 * Shape<UP>::RS > 2 * Shape<UP>::SLOT ? 32 * Shape<UP>::RS : 2 * Shape<UP>::SLOT;
-    // per wave: scratch (SCRF floats; Gram transpose, then partial / Z) and
-    // one system slot (SLOT complex)
-    static constexpr size_t per_wave = (size_t)SCRF * 4 + (size_t)Shape<UP>::SLOT * 8;
-    static __host__ __device__ constexpr size_t bytes(int K, int nw) { return (size_t)K * 2 * UP * 4 + nw * per_wave; }
+    static constexpr size_t zbytes = (size_t)UP * KC * 8;
+    static constexpr size_t per_wave = zbytes + (size_t)Shape<UP>::SLOT * 8;
+    static __host__ __device__ constexpr size_t bytes(int nw) { return nw * per_wave; }
 };
 
 // Kernel modes: the whole frame, the per-frame part only (factors to
@@ -633,216 +651,132 @@ __device__ __forceinline__ float load_factor(const cx<float> *__restrict__ g, in
     return wave_max(mx);
 }
 
-// Minimum waves per SIMD the register allocation targets (more channel tiles
-// per wave need more registers).
-template <int UP, int MAXT>
+// Minimum waves per SIMD the register allocation targets.
+template <int UP>
 constexpr int min_waves() {
-    return UP == 16 ? (MAXT <= 2 ? 4 : (MAXT <= 4 ? 2 : 1)) : (MAXT <= 2 ? 2 : 1);
+    return UP == 16 ? 4 : 2;
+}
+
+// ---- one system per wave --------------------------------------------------------
+// The whole chain of one local system, run by one wave with no workgroup
+// barrier: PD system n = subcarrier n over all B rows; FD system n * C + c =
+// cluster c of subcarrier n over its rows [o_c, o_{c+1}) (B_c >= U).
+//   Gram      streams the rows in 32-row tiles (next tile's loads issued
+//             before the current tile's MFMAs), A = G + kappa I into the slot
+//   factor    A^-1 in registers (Gauss-Jordan), Lemma-1 t, scale
+//             PD 1 / beta, beta = sqrt(Es / rho^2 t); FD w_c = sqrt(rho_c^2 / (t Es))
+//   symbols   per chunk of 16: Z = scale A^-1 S (MFMA, S read from global
+//             memory), then the rows are streamed again (from cache) for
+//             X_c = H_c Z and stored
+// Modes kPrepare / kSymbols store / load scale * A^-1 per system instead.
+template <int UP, int PREC>
+__device__ __forceinline__ void wave_system(const Prob &p, const int *__restrict__ off, int sys, int K, int mode,
+                                            const float2 *__restrict__ H, const float2 *__restrict__ s,
+                                            float2 *__restrict__ x, cx<float> *__restrict__ ainv_g,
+                                            float *__restrict__ scale_out, int *__restrict__ status, cx<float> *Zw,
+                                            cx<float> *sA) {
+    constexpr int SLOT = Shape<UP>::SLOT;
+    constexpr int NTT = Shape<UP>::NTT;
+    const int lane = lane_id();
+    const bool pd = p.arch == kPD;
+    const int B = p.B, U = p.U, C = p.C, n_sc = p.n_sc;
+    const int n = pd ? sys : sys / C;
+    const int c = pd ? 0 : sys - n * C;
+    const int r0 = pd ? 0 : off[c], r1 = pd ? B : off[c + 1];
+    const int ntile = (r1 - r0 + 31) >> 5;
+    const float2 *Hn = H + (size_t)n * B * U;
+    const float *Hf = (const float *)Hn;
+    const bool vec = U == UP && (((uintptr_t)H) & 15) == 0;
+    const float kap = pd ? pd_kappa(p) : fd_kappa(p);
+    cx<float> *fac = ainv_g ? ainv_g + (size_t)sys * U * U : nullptr;
+    float scale = 1.f, amax = 0.f;
+    bool ok = true;
+    if (mode == kSymbols) {
+        amax = load_factor<UP>(fac, U, sA);
+    } else {
+        floatx16 acc[NTT];
+#pragma unroll
+        for (int q = 0; q < NTT; ++q) acc[q] = floatx16{0};
+        GramBuf<UP> b0, b1;
+        gram_load<UP, PREC>(Hf, 2 * U, r0, min(32, r1 - r0), b0);
+        for (int t = 0; t < ntile; t += 2) {
+            const int ra = r0 + 32 * (t + 1), rb = r0 + 32 * (t + 2);
+            if (t + 1 < ntile) gram_load<UP, PREC>(Hf, 2 * U, ra, min(32, r1 - ra), b1);
+            gram_mma<UP, PREC>(b0, acc);
+            if (t + 1 < ntile) {
+                if (t + 2 < ntile) gram_load<UP, PREC>(Hf, 2 * U, rb, min(32, r1 - rb), b0);
+                gram_mma<UP, PREC>(b1, acc);
+            }
+        }
+        for (int e = lane; e < SLOT; e += 64) sA[e] = {0.f, 0.f};
+        wave_sync();
+        gram_store<UP>(acc, sA, 1.f, kap, U);
+        wave_sync();
+        float tr = 0.f;
+        ok = wave_factor<UP>(sA, U, kap, &tr, &amax);
+        float out = 0.f;
+        if (ok) {
+            if (pd) {
+                out = sqrtf(p.Es / p.power * tr);  // beta
+                scale = 1.f / out;
+            } else {
+                out = sqrtf(p.power / (float)C / (tr * p.Es));  // w_c
+                scale = out;
+            }
+        } else {
+            scale = 0.f;
+        }
+        if (lane == 0) {
+            if (scale_out) scale_out[sys] = out;
+            if (status) status[sys] = ok ? PRECODE_ST_OK : PRECODE_ST_FAIL;
+        }
+        if (mode == kPrepare) {
+            store_factor<UP>(sA, U, scale, fac);
+            return;
+        }
+    }
+    for (int k0 = 0; k0 < K; k0 += KC) {
+        const int kc = min(KC, K - k0);
+        {
+            ZOp<UP, PREC> zs;
+            make_zop_s<UP, PREC>(s + ((size_t)k0 * n_sc + n) * U, (size_t)n_sc * U, U, kc, zs);
+            wave_solve_chunk<UP, PREC>(sA, Zw, zs, kc, U, scale, amax, ok);
+        }
+        wave_sync();
+        ZOp<UP, PREC> z;
+        make_zop<UP, PREC>(Zw, KC, 1, kc, z);
+        Tile<UP, PREC> ta, tb;
+        load_tile<UP, PREC>(Hn, U, r0, min(32, r1 - r0), vec, ta);
+        for (int t = 0; t < ntile; t += 2) {
+            const int ra = r0 + 32 * t, rb = r0 + 32 * (t + 1), rc = r0 + 32 * (t + 2);
+            if (t + 1 < ntile) load_tile<UP, PREC>(Hn, U, rb, min(32, r1 - rb), vec, tb);
+            store_x(mfma_apply_tile<UP, PREC>(ta, z), ra, min(32, r1 - ra), k0, kc, n, n_sc, B, x);
+            if (t + 1 < ntile) {
+                if (t + 2 < ntile) load_tile<UP, PREC>(Hn, U, rc, min(32, r1 - rc), vec, ta);
+                store_x(mfma_apply_tile<UP, PREC>(tb, z), rb, min(32, r1 - rb), k0, kc, n, n_sc, B, x);
+            }
+        }
+        wave_sync();  // Zw is rewritten by the next chunk
+    }
 }
 
 // ---- the kernel body -----------------------------------------------------------
-// One workgroup of NW waves (block index blk of its problem) per PD
-// subcarrier, or per FD (subcarrier, group of NW clusters).  Wave w owns up to
-// MAXT channel tiles:
-//   PD: tiles t = w, w + NW, ... of 32 rows over the whole array;
-//   FD: the tiles (32 rows each) of cluster NW * (group) + w.
+// Workgroups of NW waves; wave w of block blk runs system blk * NW + w (PD:
+// consecutive subcarriers; FD: consecutive clusters of a subcarrier).
 // off: the problem's cluster offsets (p.off) in memory the kernel can index.
-template <int UP, int ARCH, int PREC, int MAXT, int NW>
+template <int UP, int PREC, int NW>
 __device__ __forceinline__ void fused_body(const Prob &p, const int *__restrict__ off, int blk, int K, int mode,
                                            const float2 *__restrict__ H, const float2 *__restrict__ s,
                                            float2 *__restrict__ x, cx<float> *__restrict__ ainv_g,
                                            float *__restrict__ scale_out, int *__restrict__ status) {
-    constexpr int SLOT = Shape<UP>::SLOT;
-    constexpr int NTT = Shape<UP>::NTT;
-    constexpr int SCRF = Lds<UP>::SCRF;
-    constexpr int NT = 64 * NW;
     extern __shared__ float4 smem4[];
-    float *Ss = (float *)smem4;
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    char *wbase = (char *)(Ss + (size_t)K * 2 * UP);
-    float *scr_of[NW];
-#pragma unroll
-    for (int w = 0; w < NW; ++w) scr_of[w] = (float *)(wbase + w * Lds<UP>::per_wave);
-    float *scr = scr_of[wave];
-    cx<float> *sA = (cx<float> *)(scr + SCRF);
-    __shared__ float sh_scale, sh_amax;
-    __shared__ int sh_ok;
-
-    // PD: one workgroup per subcarrier; FD: one workgroup per (subcarrier,
-    // group of NW clusters), one cluster per wave
-    const int CQ = ARCH == kPD ? 1 : (p.C + NW - 1) / NW;
-    const int B = p.B, U = p.U, n = blk / CQ, cq = blk % CQ;
-    const float2 *Hn = H + (size_t)n * B * U;
-    const bool vec = U == UP && (((uintptr_t)H) & 15) == 0;
-
-    // symbols of this subcarrier
-    for (int e = tid; e < K * UP; e += NT) {
-        const int k = e / UP, u = e % UP;
-        const float2 v = (u < U) ? s[((size_t)k * p.n_sc + n) * U + u] : make_float2(0.f, 0.f);
-        *(float2 *)(Ss + k * 2 * UP + 2 * u) = v;
-    }
-    Tile<UP, PREC> tiles[MAXT];
-    int t_row0[MAXT], t_rows[MAXT];
-
-    if (ARCH == kPD) {
-        const float kap = pd_kappa(p);
-        // this wave's tiles: t = wave, wave + 4, ... of 32 rows
-        float hmax = 0.f;
-#pragma unroll
-        for (int q = 0; q < MAXT; ++q) {
-            const int tt = wave + NW * q;
-            t_row0[q] = 32 * tt;
-            t_rows[q] = max(0, min(32, B - 32 * tt));
-            hmax = fmaxf(hmax, load_tile<UP, PREC>(Hn, U, t_row0[q], t_rows[q], vec, tiles[q]));
-        }
-        // power-of-two operand scale of this wave's rows (16-bit MFMA)
-        const int eh = PREC == kF32 ? 0 : fp16_exp(wave_max(hmax));
-        const float hsc = ldexpf(1.f, eh), hunsc = ldexpf(1.f, -eh), gunsc = ldexpf(1.f, -2 * eh);
-        // the wave that factors and solves rotates with the block index so that
-        // the serial steps of co-resident workgroups land on different SIMDs
-        const int mw = blk % NW;
-        float *scr_m = (float *)(wbase + mw * Lds<UP>::per_wave);
-        cx<float> *A0 = (cx<float> *)(scr_m + SCRF);
-        if (mode == kSymbols) {
-            // per-frame factors from the prepare pass: scale * A^-1
-#pragma unroll
-            for (int q = 0; q < MAXT; ++q) tile_split<UP, PREC>(tiles[q], hsc);
-            if (wave == mw) {
-                const float amax = load_factor<UP>(ainv_g + (size_t)n * U * U, U, A0);
-                if (lane == 0) {
-                    sh_scale = 1.f;
-                    sh_ok = 1;
-                    sh_amax = amax;
-                }
-            }
-            __syncthreads();
-        } else {
-        // split-K Gram over this wave's tiles (transposed through the scratch)
-        floatx16 acc[NTT];
-#pragma unroll
-        for (int q = 0; q < NTT; ++q) acc[q] = floatx16{0};
-#pragma unroll
-        for (int q = 0; q < MAXT; ++q) {
-            if (t_rows[q] > 0) {
-                tile_to_lds<UP, PREC>(tiles[q], scr);
-                wave_sync();
-                mfma_gram<UP, PREC>(scr, Shape<UP>::RS, t_rows[q], hsc, acc);
-                wave_sync();
-            }
-            tile_split<UP, PREC>(tiles[q], hsc);
-        }
-        cx<float> *part = (cx<float> *)scr;
-        for (int e = lane; e < SLOT; e += 64) part[e] = {0.f, 0.f};
-        wave_sync();
-        gram_store<UP>(acc, part, gunsc, 0.f, U);
-        __syncthreads();
-        // partial (cluster) sum in fixed order + kappa I, into the master slot
-        for (int e = tid; e < UP * UP; e += NT) {
-            const int u = e / UP, v = e % UP;
-            const int o = u * Shape<UP>::LDc + v;
-            cx<float> sum = ((cx<float> *)scr_of[0])[o];
-#pragma unroll
-            for (int w = 1; w < NW; ++w) sum = cadd(sum, ((cx<float> *)scr_of[w])[o]);
-            if (u == v && u < U) sum.re += kap;
-            A0[o] = sum;
-        }
-        __syncthreads();
-        if (wave == mw) {
-            float t = 0.f, amax = 0.f;
-            const bool ok = wave_factor<UP>(A0, U, kap, &t, &amax);
-            const float beta = ok ? sqrtf(p.Es / p.power * t) : 0.f;
-            if (lane == 0) {
-                sh_scale = ok ? 1.f / beta : 0.f;
-                sh_ok = ok;
-                sh_amax = amax;
-                if (scale_out) scale_out[n] = beta;
-                if (status) status[n] = ok ? PRECODE_ST_OK : PRECODE_ST_FAIL;
-            }
-            if (mode == kPrepare) store_factor<UP>(A0, U, ok ? 1.f / beta : 0.f, ainv_g + (size_t)n * U * U);
-        }
-        __syncthreads();
-        }
-        cx<float> *Zw = (cx<float> *)scr_m;  // free after the partial sum
-        for (int k0 = 0; mode != kPrepare && k0 < K; k0 += KC) {
-            const int kc = min(KC, K - k0);
-            if (wave == mw) wave_solve_chunk<UP, PREC>(A0, Zw, Ss, k0, kc, U, sh_scale, sh_amax, sh_ok != 0);
-            __syncthreads();
-            ZOp<UP, PREC> z;
-            make_zop<UP, PREC>(Zw, KC, 1, kc, z);
-#pragma unroll
-            for (int q = 0; q < MAXT; ++q)
-                if (t_rows[q] > 0) {
-                    const floatx16 a = mfma_apply_tile<UP, PREC>(tiles[q], hunsc, z);
-                    store_x(a, t_row0[q], t_rows[q], k0, kc, n, p.n_sc, B, x);
-                }
-            __syncthreads();
-        }
-    } else {
-        __syncthreads();  // symbols staged
-        const float kap = fd_kappa(p);
-        const float rho_c2 = p.power / (float)p.C;
-        const int c = NW * cq + wave;
-        if (c < p.C) {
-            const int o0 = off[c], o1 = off[c + 1];
-            // this cluster's rows as tiles of 32
-            float hmax = 0.f;
-#pragma unroll
-            for (int q = 0; q < MAXT; ++q) {
-                t_row0[q] = o0 + 32 * q;
-                t_rows[q] = max(0, min(32, o1 - t_row0[q]));
-                hmax = fmaxf(hmax, load_tile<UP, PREC>(Hn, U, t_row0[q], t_rows[q], vec, tiles[q]));
-            }
-            const int eh = PREC == kF32 ? 0 : fp16_exp(wave_max(hmax));
-            const float hsc = ldexpf(1.f, eh), hunsc = ldexpf(1.f, -eh), gunsc = ldexpf(1.f, -2 * eh);
-            cx<float> *fac = ainv_g + ((size_t)n * p.C + c) * U * U;
-            float w = 1.f, amax = 0.f;
-            bool ok = true;
-            if (mode == kSymbols) {
-#pragma unroll
-                for (int q = 0; q < MAXT; ++q) tile_split<UP, PREC>(tiles[q], hsc);
-                amax = load_factor<UP>(fac, U, sA);
-            } else {
-                for (int e = lane; e < SLOT; e += 64) sA[e] = {0.f, 0.f};
-                floatx16 acc[NTT];
-#pragma unroll
-                for (int q = 0; q < NTT; ++q) acc[q] = floatx16{0};
-#pragma unroll
-                for (int q = 0; q < MAXT; ++q)
-                    if (t_rows[q] > 0) {
-                        tile_to_lds<UP, PREC>(tiles[q], scr);
-                        wave_sync();
-                        mfma_gram<UP, PREC>(scr, Shape<UP>::RS, t_rows[q], hsc, acc);
-                        wave_sync();
-                        tile_split<UP, PREC>(tiles[q], hsc);
-                    }
-                gram_store<UP>(acc, sA, gunsc, kap, U);
-                wave_sync();
-                float t = 0.f;
-                ok = wave_factor<UP>(sA, U, kap, &t, &amax);
-                w = ok ? sqrtf(rho_c2 / (t * p.Es)) : 0.f;
-                if (lane == 0) {
-                    if (scale_out) scale_out[(size_t)n * p.C + c] = w;
-                    if (status) status[(size_t)n * p.C + c] = ok ? PRECODE_ST_OK : PRECODE_ST_FAIL;
-                }
-                if (mode == kPrepare) store_factor<UP>(sA, U, w, fac);
-            }
-            cx<float> *Zw = (cx<float> *)scr;
-            for (int k0 = 0; mode != kPrepare && k0 < K; k0 += KC) {
-                const int kc = min(KC, K - k0);
-                wave_sync();
-                wave_solve_chunk<UP, PREC>(sA, Zw, Ss, k0, kc, U, w, amax, ok);
-                wave_sync();
-                ZOp<UP, PREC> z;
-                make_zop<UP, PREC>(Zw, KC, 1, kc, z);
-#pragma unroll
-                for (int q = 0; q < MAXT; ++q)
-                    if (t_rows[q] > 0) {
-                        const floatx16 a = mfma_apply_tile<UP, PREC>(tiles[q], hunsc, z);
-                        store_x(a, t_row0[q], t_rows[q], k0, kc, n, p.n_sc, B, x);
-                    }
-            }
-        }
-    }
+    const int wave = threadIdx.x >> 6;
+    const int n_sys = p.arch == kPD ? p.n_sc : p.n_sc * p.C;
+    const int sys = blk * NW + wave;
+    if (sys >= n_sys) return;
+    char *wb = (char *)smem4 + (size_t)wave * Lds<UP>::per_wave;
+    wave_system<UP, PREC>(p, off, sys, K, mode, H, s, x, ainv_g, scale_out, status, (cx<float> *)wb,
+                          (cx<float> *)(wb + Lds<UP>::zbytes));
 }
 
 int pick_up(int U) { return U <= 16 ? 16 : (U <= 32 ? 32 : 0); }
@@ -856,29 +790,10 @@ int prec_of(int precision) {
     }
 }
 
-// Channel tiles (32 rows) a wave holds in registers with nw waves per workgroup.
-int tiles_per_wave(const Prob &p, int nw) {
-    if (p.arch == kPD) return ((p.B + 31) / 32 + nw - 1) / nw;
-    int worst = 0;  // FD: a wave holds one cluster at a time
-    for (int c = 0; c < p.C; ++c) {
-        const int n = (p.off[c + 1] - p.off[c] + 31) / 32;
-        worst = n > worst ? n : worst;
-    }
-    return worst;
-}
-
-// Most channel tiles a wave may hold: register capacity at the occupancy
-// min_waves asks for (an 8-wave workgroup already needs two waves per SIMD).
-constexpr int max_tiles(int up, int nw) { return up == 16 ? (nw <= 4 ? 8 : 4) : (nw <= 4 ? 4 : 2); }
-
-int pick_maxt(const Prob &p, int up, int nw) {
-    const int t = tiles_per_wave(p, nw);
-    const int lim = max_tiles(up, nw);
-    if (t <= 1) return 1;
-    if (t <= 2) return 2;
-    if (t <= 4 && lim >= 4) return 4;
-    if (t <= 8 && lim >= 8) return 8;
-    return 0;
+// Workgroups of nw waves a problem's launch needs.
+int blocks_for(const Prob &p, int nw) {
+    const long long ns = p.arch == kPD ? (long long)p.n_sc : (long long)p.n_sc * p.C;
+    return (int)((ns + nw - 1) / nw);
 }
 
 constexpr size_t kLdsMax = 160 * 1024;

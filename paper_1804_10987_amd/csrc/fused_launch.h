@@ -16,11 +16,11 @@ struct FusedCall {
     int *status;
 };
 
-// Enqueue one launch of fused_k<UP, ARCH, PREC, MAXT, NW> for problem p
-// (UP from p.U, PREC from prec, MAXT = maxt): n_sc workgroups for PD,
-// n_sc * ceil(C / NW) for FD, NW * 64 threads each.
-hipError_t fused_launch_nw2(const Prob &p, int prec, int maxt, const FusedCall &a, hipStream_t st);
-hipError_t fused_launch_nw4(const Prob &p, int prec, int maxt, const FusedCall &a, hipStream_t st);
-hipError_t fused_launch_nw8(const Prob &p, int prec, int maxt, const FusedCall &a, hipStream_t st);
+// Enqueue one launch of fused_k<UP, PREC, NW> for problem p (UP from p.U,
+// PREC from prec): one wave per system (n_sc for PD, n_sc * C for FD), NW
+// waves per workgroup.
+hipError_t fused_launch_nw2(const Prob &p, int prec, const FusedCall &a, hipStream_t st);
+hipError_t fused_launch_nw4(const Prob &p, int prec, const FusedCall &a, hipStream_t st);
+hipError_t fused_launch_nw8(const Prob &p, int prec, const FusedCall &a, hipStream_t st);
 
 }  // namespace pc
