@@ -39,6 +39,7 @@ struct Plan {
     std::vector<int> cls;     // class (tile width) of each run
     std::vector<int> first;   // first entry of each run, plus the end
     std::vector<int> blocks;  // grid of each run
+    std::vector<int> rows;    // largest system of each run (rows, multiple of 32)
 };
 
 Plan make_plan(const BatchProblem *bp, int n) {
@@ -54,6 +55,7 @@ Plan make_plan(const BatchProblem *bp, int n) {
             pl.cls.push_back(c);
             pl.first.push_back((int)pl.e.size());
             pl.blocks.push_back(0);
+            pl.rows.push_back(0);
         }
         if (q.p.n_sc == 0) continue;
         Entry en;
@@ -66,14 +68,16 @@ Plan make_plan(const BatchProblem *bp, int n) {
         en.K = q.p.K;
         en.block0 = pl.blocks.back();
         pl.blocks.back() += blocks_for(q.p, NW);
+        pl.rows.back() = std::max(pl.rows.back(), system_rows(q.p));
         pl.e.push_back(en);
     }
     pl.first.push_back((int)pl.e.size());
     return pl;
 }
 
-template <int UP, int PREC>
-__global__ void __launch_bounds__(64 * NW, (min_waves<UP>())) fused_batch_k(const Entry *__restrict__ tab, int n) {
+template <int UP, int PREC, bool STAGE>
+__global__ void __launch_bounds__(64 * NW, (min_waves<UP, STAGE>()))
+    fused_batch_k(const Entry *__restrict__ tab, int n, int stage_rows) {
     const int b = blockIdx.x;
     int lo = 0, hi = n - 1;  // last problem with block0 <= b
     while (lo < hi) {
@@ -82,28 +86,35 @@ __global__ void __launch_bounds__(64 * NW, (min_waves<UP>())) fused_batch_k(cons
         else hi = mid - 1;
     }
     const Entry &E = tab[lo];
-    fused_body<UP, PREC, NW>(E.p, E.p.off, b - E.block0, E.K, kFull, E.H, E.s, E.x, nullptr, E.scale_out,
-                             E.status);
+    fused_body<UP, PREC, NW, STAGE>(E.p, E.p.off, b - E.block0, E.K, kFull, stage_rows, E.H, E.s, E.x, nullptr,
+                             E.scale_out, E.status);
 }
 
-template <int UP, int PREC>
-hipError_t launch(const Entry *tab, int n, int blocks, hipStream_t st) {
-    const void *fn = (const void *)fused_batch_k<UP, PREC>;
-    const size_t lds = Lds<UP>::bytes(NW);
+template <int UP, int PREC, bool STAGE>
+hipError_t launch1(const Entry *tab, int n, int blocks, int stage, hipStream_t st) {
+    const void *fn = (const void *)fused_batch_k<UP, PREC, STAGE>;
+    const size_t lds = Lds<UP>::bytes(NW, stage);
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((fused_batch_k<UP, PREC>), dim3(blocks), dim3(64 * NW), lds, st, tab, n);
+    hipLaunchKernelGGL((fused_batch_k<UP, PREC, STAGE>), dim3(blocks), dim3(64 * NW), lds, st, tab, n, stage);
     return hipGetLastError();
 }
 
+template <int UP, int PREC>
+hipError_t launch(const Entry *tab, int n, int blocks, int rows, hipStream_t st) {
+    const int stage = stage_rows_for(UP, rows, NW);
+    return stage > 0 ? launch1<UP, PREC, true>(tab, n, blocks, stage, st)
+                     : launch1<UP, PREC, false>(tab, n, blocks, 0, st);
+}
+
 template <int UP>
-hipError_t launch_prec(int prec, const Entry *tab, int n, int blocks, hipStream_t st) {
+hipError_t launch_prec(int prec, const Entry *tab, int n, int blocks, int rows, hipStream_t st) {
     switch (prec) {
-        case kF32: return launch<UP, kF32>(tab, n, blocks, st);
-        case kF16: return launch<UP, kF16>(tab, n, blocks, st);
-        default: return launch<UP, kBF16>(tab, n, blocks, st);
+        case kF32: return launch<UP, kF32>(tab, n, blocks, rows, st);
+        case kF16: return launch<UP, kF16>(tab, n, blocks, rows, st);
+        default: return launch<UP, kBF16>(tab, n, blocks, rows, st);
     }
 }
 
@@ -130,8 +141,8 @@ hipError_t fused_batch_launch(const BatchProblem *bp, int n, int precision, cons
     for (size_t r = 0; r < pl.cls.size(); ++r) {
         const int f = pl.first[r], cnt = pl.first[r + 1] - f;
         if (cnt == 0) continue;
-        const hipError_t e = pl.cls[r] == 16 ? launch_prec<16>(prec, tab + f, cnt, pl.blocks[r], st)
-                                             : launch_prec<32>(prec, tab + f, cnt, pl.blocks[r], st);
+        const hipError_t e = pl.cls[r] == 16 ? launch_prec<16>(prec, tab + f, cnt, pl.blocks[r], pl.rows[r], st)
+                                             : launch_prec<32>(prec, tab + f, cnt, pl.blocks[r], pl.rows[r], st);
         if (e != hipSuccess) return e;
         ++nl;
     }

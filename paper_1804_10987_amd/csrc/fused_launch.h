@@ -8,7 +8,8 @@
 namespace pc {
 
 struct FusedCall {
-    int K, mode;  // symbols in this launch; kFull / kPrepare / kSymbols
+    int K, mode;     // symbols in this launch; kFull / kPrepare / kSymbols
+    int stage_rows;  // LDS rows staged per wave (kFull only; 0: none)
     const float2 *H, *s;
     float2 *x;
     cx<float> *ainv;  // per-instance factors (prepare / symbols modes)
