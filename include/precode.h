@@ -189,8 +189,10 @@ int precode_frame_release(precode_ctx *ctx, precode_frame *frame);
  * precode_job; pointers are device pointers with the layouts above and the
  * outputs are those of precode_pd / precode_fd for the same job.
  *   - jobs the fused kernel takes (U <= 32, no FP64 route, FD clusters with
- *     B_c >= U) run as ONE launch per tile width (U <= 16, U <= 32), PD and
- *     FD jobs together: at most 2 launches however many jobs there are;
+ *     B_c >= U) run as ONE launch per kernel shape class (tile width U <= 16
+ *     or U <= 32, times the channel tiles a wave keeps in registers: 1, 2,
+ *     4, 8 or streamed), PD and FD jobs together: at most 9 launches however
+ *     many jobs there are;
  *   - the remaining jobs run on the plain kernels after them, on `stream`.
  * The whole batch is validated before anything is enqueued (first error
  * returned).  With SPLIT precision every job must be fused-capable

@@ -2,9 +2,10 @@
 // different B, cluster sizes, U and subcarrier counts) in as few launches as
 // the kernel's shape classes allow.
 //
-// Problems are grouped by tile width UP (16 for U <= 16, 32 for U <= 32);
-// each group -- PD and FD problems alike -- is one launch whose grid is the
-// sum of its problems' workgroups (one wave per local system, NW systems per
+// Problems are grouped by tile width UP (16 for U <= 16, 32 for U <= 32) and
+// channel tiles per wave held in registers (1, 2, 4, 8 or streamed); each
+// group -- PD and FD problems alike -- is one launch whose grid is the sum of
+// its problems' workgroups (one wave per local system, NW systems per
 // workgroup).  The problem table sits in device memory; a workgroup finds its
 // problem by binary search over the problems' first block index and then runs
 // the same body as the single-problem kernel.
@@ -30,16 +31,21 @@ struct Entry {
     int block0;  // first block of this problem within its class launch
 };
 
-// Launch class of a problem: its tile width.
-int class_of(const Prob &p) { return pick_up(p.U); }
+// Launch class of a problem: tile width and register tiles per wave.
+struct Class {
+    int up, maxt;
+    bool operator==(const Class &o) const { return up == o.up && maxt == o.maxt; }
+    bool operator<(const Class &o) const { return up != o.up ? up < o.up : maxt < o.maxt; }
+};
+
+Class class_of(const Prob &p) { return Class{pick_up(p.U), pick_maxt(p)}; }
 
 // Problems in launch order (by class, then problem order).
 struct Plan {
     std::vector<Entry> e;
-    std::vector<int> cls;     // class (tile width) of each run
+    std::vector<Class> cls;   // class of each run
     std::vector<int> first;   // first entry of each run, plus the end
     std::vector<int> blocks;  // grid of each run
-    std::vector<int> rows;    // largest system of each run (rows, multiple of 32)
 };
 
 Plan make_plan(const BatchProblem *bp, int n) {
@@ -50,12 +56,11 @@ Plan make_plan(const BatchProblem *bp, int n) {
     Plan pl;
     for (int oi = 0; oi < n; ++oi) {
         const BatchProblem &q = bp[order[oi]];
-        const int c = class_of(q.p);
-        if (pl.cls.empty() || pl.cls.back() != c) {
+        const Class c = class_of(q.p);
+        if (pl.cls.empty() || !(pl.cls.back() == c)) {
             pl.cls.push_back(c);
             pl.first.push_back((int)pl.e.size());
             pl.blocks.push_back(0);
-            pl.rows.push_back(0);
         }
         if (q.p.n_sc == 0) continue;
         Entry en;
@@ -68,16 +73,15 @@ Plan make_plan(const BatchProblem *bp, int n) {
         en.K = q.p.K;
         en.block0 = pl.blocks.back();
         pl.blocks.back() += blocks_for(q.p, NW);
-        pl.rows.back() = std::max(pl.rows.back(), system_rows(q.p));
         pl.e.push_back(en);
     }
     pl.first.push_back((int)pl.e.size());
     return pl;
 }
 
-template <int UP, int PREC, bool STAGE>
-__global__ void __launch_bounds__(64 * NW, (min_waves<UP, STAGE>()))
-    fused_batch_k(const Entry *__restrict__ tab, int n, int stage_rows) {
+template <int UP, int PREC, int MAXT>
+__global__ void __launch_bounds__(64 * NW, (min_waves<UP, MAXT, PREC>()))
+    fused_batch_k(const Entry *__restrict__ tab, int n) {
     const int b = blockIdx.x;
     int lo = 0, hi = n - 1;  // last problem with block0 <= b
     while (lo < hi) {
@@ -86,35 +90,41 @@ __global__ void __launch_bounds__(64 * NW, (min_waves<UP, STAGE>()))
         else hi = mid - 1;
     }
     const Entry &E = tab[lo];
-    fused_body<UP, PREC, NW, STAGE>(E.p, E.p.off, b - E.block0, E.K, kFull, stage_rows, E.H, E.s, E.x, nullptr,
-                             E.scale_out, E.status);
+    fused_body<UP, PREC, NW, MAXT>(E.p, E.p.off, b - E.block0, E.K, kFull, E.H, E.s, E.x, nullptr, E.scale_out,
+                                   E.status);
 }
 
-template <int UP, int PREC, bool STAGE>
-hipError_t launch1(const Entry *tab, int n, int blocks, int stage, hipStream_t st) {
-    const void *fn = (const void *)fused_batch_k<UP, PREC, STAGE>;
-    const size_t lds = Lds<UP>::bytes(NW, stage);
+template <int UP, int PREC, int MAXT>
+hipError_t launch(const Entry *tab, int n, int blocks, hipStream_t st) {
+    const void *fn = (const void *)fused_batch_k<UP, PREC, MAXT>;
+    const size_t lds = Lds<UP>::bytes(NW);
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((fused_batch_k<UP, PREC, STAGE>), dim3(blocks), dim3(64 * NW), lds, st, tab, n, stage);
+    hipLaunchKernelGGL((fused_batch_k<UP, PREC, MAXT>), dim3(blocks), dim3(64 * NW), lds, st, tab, n);
     return hipGetLastError();
 }
 
 template <int UP, int PREC>
-hipError_t launch(const Entry *tab, int n, int blocks, int rows, hipStream_t st) {
-    const int stage = stage_rows_for(UP, rows, NW);
-    return stage > 0 ? launch1<UP, PREC, true>(tab, n, blocks, stage, st)
-                     : launch1<UP, PREC, false>(tab, n, blocks, 0, st);
+hipError_t launch_t(int maxt, const Entry *tab, int n, int blocks, hipStream_t st) {
+    switch (maxt) {
+        case 0: return launch<UP, PREC, 0>(tab, n, blocks, st);
+        case 1: return launch<UP, PREC, 1>(tab, n, blocks, st);
+        case 2: return launch<UP, PREC, 2>(tab, n, blocks, st);
+        case 4: return launch<UP, PREC, 4>(tab, n, blocks, st);
+        default:
+            if constexpr (max_tiles(UP) >= 8) return launch<UP, PREC, 8>(tab, n, blocks, st);
+            return hipErrorNotSupported;
+    }
 }
 
 template <int UP>
-hipError_t launch_prec(int prec, const Entry *tab, int n, int blocks, int rows, hipStream_t st) {
+hipError_t launch_prec(int prec, int maxt, const Entry *tab, int n, int blocks, hipStream_t st) {
     switch (prec) {
-        case kF32: return launch<UP, kF32>(tab, n, blocks, rows, st);
-        case kF16: return launch<UP, kF16>(tab, n, blocks, rows, st);
-        default: return launch<UP, kBF16>(tab, n, blocks, rows, st);
+        case kF32: return launch_t<UP, kF32>(maxt, tab, n, blocks, st);
+        case kF16: return launch_t<UP, kF16>(maxt, tab, n, blocks, st);
+        default: return launch_t<UP, kBF16>(maxt, tab, n, blocks, st);
     }
 }
 
@@ -141,8 +151,9 @@ hipError_t fused_batch_launch(const BatchProblem *bp, int n, int precision, cons
     for (size_t r = 0; r < pl.cls.size(); ++r) {
         const int f = pl.first[r], cnt = pl.first[r + 1] - f;
         if (cnt == 0) continue;
-        const hipError_t e = pl.cls[r] == 16 ? launch_prec<16>(prec, tab + f, cnt, pl.blocks[r], pl.rows[r], st)
-                                             : launch_prec<32>(prec, tab + f, cnt, pl.blocks[r], pl.rows[r], st);
+        const Class c = pl.cls[r];
+        const hipError_t e = c.up == 16 ? launch_prec<16>(prec, c.maxt, tab + f, cnt, pl.blocks[r], st)
+                                        : launch_prec<32>(prec, c.maxt, tab + f, cnt, pl.blocks[r], st);
         if (e != hipSuccess) return e;
         ++nl;
     }

@@ -63,7 +63,7 @@ constexpr int kDefaultNW = 4;
 bool nw_feasible(const Prob &p, int nw) {
     const int up = pick_up(p.U);
     if (up == 0) return false;
-    const size_t lds = up == 16 ? Lds<16>::bytes(nw, 0) : Lds<32>::bytes(nw, 0);
+    const size_t lds = up == 16 ? Lds<16>::bytes(nw) : Lds<32>::bytes(nw);
     return lds <= kLdsUsable;
 }
 
@@ -81,9 +81,7 @@ hipError_t run_once(int nw, const Prob &p, int prec, int mode, int K, const floa
     FusedCall a;
     a.K = mode == kPrepare ? 0 : K;
     a.mode = mode;
-    // the full path keeps the channel rows in LDS between the Gram and the
-    // precode when they fit
-    a.stage_rows = mode == kFull ? stage_rows_for(pick_up(p.U), system_rows(p), nw) : 0;
+    a.maxt = pick_maxt(p);
     a.H = H;
     a.s = s;
     a.x = x;

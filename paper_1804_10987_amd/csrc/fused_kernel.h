@@ -614,56 +614,9 @@ template <int UP>
 struct Lds {
     static constexpr size_t zbytes = (size_t)UP * KC * 8;
     static constexpr size_t sbytes = (size_t)Shape<UP>::SLOT * 8;
-    // per wave: Z chunk, system slot, and (when staged) the system's rows
-    static __host__ __device__ constexpr size_t per_wave(int stage_rows) {
-        return zbytes + sbytes + (size_t)stage_rows * 2 * UP * 4;
-    }
-    static __host__ __device__ constexpr size_t bytes(int nw, int stage_rows) { return nw * per_wave(stage_rows); }
+    static constexpr size_t per_wave = zbytes + sbytes;  // Z chunk and system slot
+    static __host__ __device__ constexpr size_t bytes(int nw) { return nw * per_wave; }
 };
-
-// ---- channel rows staged in LDS -------------------------------------------------
-// Row r of a staged system occupies 2 UP floats; its 16-byte chunks are
-// permuted (chunk c at c ^ ((r / RPB) & (CPR - 1)), RPB rows per 256-byte
-// bank row, CPR chunks per row) so that the precode's row-per-lane 16-byte
-// reads of 16 consecutive rows hit distinct banks.
-template <int UP>
-__device__ __forceinline__ int stage_off(int r, int col) {  // float offset of (row, real column)
-    constexpr int CPR = UP / 2;
-    constexpr int RPB = 32 / UP;
-    const int c = col >> 2;
-    return r * 2 * UP + ((c ^ ((r / RPB) & (CPR - 1))) << 2) + (col & 3);
-}
-
-// Writes the Gram buffer of the tile at rows [row0, row0 + 32) of the system
-// (relative row index) into the stage (rows past the system hold zeros).
-template <int UP, int PREC>
-__device__ __forceinline__ void stage_store(const GramBuf<UP> &b, float *st, int row0) {
-    constexpr int NT = Shape<UP>::NT;
-    const int lane = lane_id();
-    const int j = lane & 31, g = lane >> 5;
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const int row = row0 + (PREC == kF32 ? 2 * q + g : 16 * (q / 8) + 8 * g + (q % 8));
-#pragma unroll
-        for (int ti = 0; ti < NT; ++ti) st[stage_off<UP>(row, 32 * ti + j)] = b.v[ti][q];
-    }
-}
-
-// Reads a staged 32-row tile into the precode layout (lane (j, g): row
-// row0 + j, real columns g*UP .. g*UP + UP - 1).
-template <int UP, int PREC>
-__device__ __forceinline__ void stage_load(const float *st, int row0, Tile<UP, PREC> &tl) {
-    const int lane = lane_id();
-    const int j = lane & 31, g = lane >> 5;
-#pragma unroll
-    for (int m4 = 0; m4 < UP; m4 += 4) {
-        const float4 v = *(const float4 *)(st + stage_off<UP>(row0 + j, g * UP + m4));
-        tl.f[m4] = v.x;
-        tl.f[m4 + 1] = v.y;
-        tl.f[m4 + 2] = v.z;
-        tl.f[m4 + 3] = v.w;
-    }
-}
 
 // Kernel modes: the whole frame, the per-frame part only (factors to
 // global memory), or the per-symbol part from stored factors.
@@ -699,11 +652,15 @@ __device__ __forceinline__ float load_factor(const cx<float> *__restrict__ g, in
     return wave_max(mx);
 }
 
-// Minimum waves per SIMD the register allocation targets (a staged launch is
-// held to a few waves per CU by its LDS anyway).
-template <int UP, bool STAGE>
+// Channel tiles a wave may keep in registers (MAXT; 0 streams the rows twice).
+constexpr int max_tiles(int up) { return up == 16 ? 8 : 4; }
+
+// Minimum waves per SIMD the register allocation targets: more tiles held
+// in registers need more registers per wave.
+template <int UP, int MAXT, int PREC>
 constexpr int min_waves() {
-    return UP == 16 ? (STAGE ? 3 : 4) : (STAGE ? 1 : 2);
+    if (UP == 16) return MAXT == 0 ? 4 : MAXT == 1 ? (PREC == kF32 ? 4 : 3) : MAXT == 2 ? 3 : 2;
+    return MAXT <= 1 ? 2 : 1;
 }
 
 // ---- one system per wave --------------------------------------------------------
@@ -718,12 +675,12 @@ constexpr int min_waves() {
 //             memory), then the rows are streamed again (from cache) for
 //             X_c = H_c Z and stored
 // Modes kPrepare / kSymbols store / load scale * A^-1 per system instead.
-template <int UP, int PREC, bool STAGE>
+template <int UP, int PREC, int MAXT>
 __device__ __forceinline__ void wave_system(const Prob &p, const int *__restrict__ off, int sys, int K, int mode,
                                             const float2 *__restrict__ H, const float2 *__restrict__ s,
                                             float2 *__restrict__ x, cx<float> *__restrict__ ainv_g,
                                             float *__restrict__ scale_out, int *__restrict__ status, cx<float> *Zw,
-                                            cx<float> *sA, float *st) {
+                                            cx<float> *sA) {
     constexpr int SLOT = Shape<UP>::SLOT;
     constexpr int NTT = Shape<UP>::NTT;
     const int lane = lane_id();
@@ -740,6 +697,19 @@ __device__ __forceinline__ void wave_system(const Prob &p, const int *__restrict
     cx<float> *fac = ainv_g ? ainv_g + (size_t)sys * U * U : nullptr;
     float scale = 1.f, amax = 0.f;
     bool ok = true;
+    // MAXT > 0: the rows stay in registers from the first load to the
+    // precode (loads of every tile issued up front; the Gram's column-layout
+    // loads of the same lines are then served by the cache)
+    Tile<UP, PREC> tiles[MAXT > 0 ? MAXT : 1];
+    if constexpr (MAXT > 0) {
+        if (mode != kPrepare) {
+#pragma unroll
+            for (int q = 0; q < MAXT; ++q) {
+                const int rq = r0 + 32 * q;
+                load_tile<UP, PREC>(Hn, U, rq, q < ntile ? min(32, r1 - rq) : 0, vec, tiles[q]);
+            }
+        }
+    }
     if (mode == kSymbols) {
         amax = load_factor<UP>(fac, U, sA);
     } else {
@@ -752,11 +722,9 @@ __device__ __forceinline__ void wave_system(const Prob &p, const int *__restrict
             const int ra = r0 + 32 * (t + 1), rb = r0 + 32 * (t + 2);
             if (t + 1 < ntile) gram_load<UP, PREC>(Hf, 2 * U, ra, min(32, r1 - ra), b1);
             gram_mma<UP, PREC>(b0, acc);
-            if (STAGE) stage_store<UP, PREC>(b0, st, 32 * t);
             if (t + 1 < ntile) {
                 if (t + 2 < ntile) gram_load<UP, PREC>(Hf, 2 * U, rb, min(32, r1 - rb), b0);
                 gram_mma<UP, PREC>(b1, acc);
-                if (STAGE) stage_store<UP, PREC>(b1, st, 32 * (t + 1));
             }
         }
         for (int e = lane; e < SLOT; e += 64) sA[e] = {0.f, 0.f};
@@ -796,13 +764,11 @@ __device__ __forceinline__ void wave_system(const Prob &p, const int *__restrict
         wave_sync();
         ZOp<UP, PREC> z;
         make_zop<UP, PREC>(Zw, KC, 1, kc, z);
-        if (STAGE) {
-            // rows staged by the Gram pass
-            for (int t = 0; t < ntile; ++t) {
-                Tile<UP, PREC> tl;
-                stage_load<UP, PREC>(st, 32 * t, tl);
-                const int ra = r0 + 32 * t;
-                store_x(mfma_apply_tile<UP, PREC>(tl, z), ra, min(32, r1 - ra), k0, kc, n, n_sc, B, x);
+        if constexpr (MAXT > 0) {
+#pragma unroll
+            for (int q = 0; q < MAXT; ++q) {
+                const int rq = r0 + 32 * q;
+                if (q < ntile) store_x(mfma_apply_tile<UP, PREC>(tiles[q], z), rq, min(32, r1 - rq), k0, kc, n, n_sc, B, x);
             }
             wave_sync();
             continue;
@@ -826,12 +792,11 @@ __device__ __forceinline__ void wave_system(const Prob &p, const int *__restrict
 // Workgroups of NW waves; wave w of block blk runs system blk * NW + w (PD:
 // consecutive subcarriers; FD: consecutive clusters of a subcarrier).
 // off: the problem's cluster offsets (p.off) in memory the kernel can index.
-// STAGE (full mode only): the Gram pass keeps the system's rows in LDS,
-// stage_rows per wave (at least the system's rows rounded up to 32), and the
-// precode reads them there; otherwise it re-reads them from global memory.
-template <int UP, int PREC, int NW, bool STAGE>
+// MAXT: channel tiles (32 rows) of the largest system that a wave keeps in
+// registers (0: the precode streams the rows a second time).
+template <int UP, int PREC, int NW, int MAXT>
 __device__ __forceinline__ void fused_body(const Prob &p, const int *__restrict__ off, int blk, int K, int mode,
-                                           int stage_rows, const float2 *__restrict__ H,
+                                           const float2 *__restrict__ H,
                                            const float2 *__restrict__ s, float2 *__restrict__ x,
                                            cx<float> *__restrict__ ainv_g, float *__restrict__ scale_out,
                                            int *__restrict__ status) {
@@ -840,10 +805,9 @@ __device__ __forceinline__ void fused_body(const Prob &p, const int *__restrict_
     const int n_sys = p.arch == kPD ? p.n_sc : p.n_sc * p.C;
     const int sys = blk * NW + wave;
     if (sys >= n_sys) return;
-    char *wb = (char *)smem4 + (size_t)wave * Lds<UP>::per_wave(stage_rows);
-    float *st = STAGE ? (float *)(wb + Lds<UP>::zbytes + Lds<UP>::sbytes) : nullptr;
-    wave_system<UP, PREC, STAGE>(p, off, sys, K, mode, H, s, x, ainv_g, scale_out, status, (cx<float> *)wb,
-                          (cx<float> *)(wb + Lds<UP>::zbytes), st);
+    char *wb = (char *)smem4 + (size_t)wave * Lds<UP>::per_wave;
+    wave_system<UP, PREC, MAXT>(p, off, sys, K, mode, H, s, x, ainv_g, scale_out, status, (cx<float> *)wb,
+                                (cx<float> *)(wb + Lds<UP>::zbytes));
 }
 
 int pick_up(int U) { return U <= 16 ? 16 : (U <= 32 ? 32 : 0); }
@@ -866,20 +830,21 @@ int blocks_for(const Prob &p, int nw) {
 constexpr size_t kLdsMax = 160 * 1024;
 constexpr size_t kLdsUsable = kLdsMax - 256;
 
-// Rows of the largest local system of a problem, rounded up to 32.
-int system_rows(const Prob &p) {
+// Tiles (32 rows) of the largest local system of a problem.
+int system_tiles(const Prob &p) {
     int r = p.arch == kPD ? p.B : 0;
     if (p.arch == kFD)
         for (int c = 0; c < p.C; ++c) r = p.off[c + 1] - p.off[c] > r ? p.off[c + 1] - p.off[c] : r;
-    return (r + 31) & ~31;
+    return (r + 31) >> 5;
 }
 
-// LDS stage rows for a full-mode launch of nw waves per workgroup (0: not
-// staged): systems of more than one tile whose rows fit.
-int stage_rows_for(int up, int rows, int nw) {
-    if (rows <= 32) return 0;
-    const size_t b = up == 16 ? Lds<16>::bytes(nw, rows) : Lds<32>::bytes(nw, rows);
-    return b <= kLdsUsable ? rows : 0;
+// Register tiles per wave for a problem: the next power of two of its
+// largest system's tiles, or 0 (stream) past max_tiles.
+int pick_maxt(const Prob &p) {
+    const int t = system_tiles(p), lim = max_tiles(pick_up(p.U));
+    int m = 1;
+    while (m < t) m <<= 1;
+    return m <= lim ? m : 0;
 }
 
 }  // namespace

@@ -8,8 +8,8 @@
 namespace pc {
 
 struct FusedCall {
-    int K, mode;     // symbols in this launch; kFull / kPrepare / kSymbols
-    int stage_rows;  // LDS rows staged per wave (kFull only; 0: none)
+    int K, mode;  // symbols in this launch; kFull / kPrepare / kSymbols
+    int maxt;     // channel tiles per wave held in registers (0: streamed)
     const float2 *H, *s;
     float2 *x;
     cx<float> *ainv;  // per-instance factors (prepare / symbols modes)
@@ -17,9 +17,9 @@ struct FusedCall {
     int *status;
 };
 
-// Enqueue one launch of fused_k<UP, PREC, NW> for problem p (UP from p.U,
-// PREC from prec): one wave per system (n_sc for PD, n_sc * C for FD), NW
-// waves per workgroup.
+// Enqueue one launch of fused_k<UP, PREC, MAXT, NW> for problem p (UP from
+// p.U, PREC from prec, MAXT = a.maxt): one wave per system (n_sc for PD,
+// n_sc * C for FD), NW waves per workgroup.
 hipError_t fused_launch_nw2(const Prob &p, int prec, const FusedCall &a, hipStream_t st);
 hipError_t fused_launch_nw4(const Prob &p, int prec, const FusedCall &a, hipStream_t st);
 hipError_t fused_launch_nw8(const Prob &p, int prec, const FusedCall &a, hipStream_t st);
