@@ -54,6 +54,7 @@ struct Shape {
     static constexpr int NT = (2 * UP) / 32;       // 32-wide real column tiles
     static constexpr int NTT = NT * (NT + 1) / 2;  // tiles with ti <= tj
     static constexpr int LDc = UP + 2;             // slot leading dim (complex), rows 16B aligned
+    static constexpr int RS = 2 * UP + 4;          // transpose scratch row stride (floats)
     static constexpr int SLOT = UP * LDc;          // complex elements per slot
 };
 
@@ -295,7 +296,7 @@ __device__ __forceinline__ void make_zop(const cx<float> *Z, int su, int sk, int
 // The symbol operand straight from global memory: s(u, k) at sk0[k * kstride
 // + u] for u < U, k < kvalid (zero elsewhere).
 template <int UP, int PREC>
-__device__ __forceinline__ void make_zop_s(const float2 *__restrict__ sk0, size_t kstride, int U, int kvalid,
+__device__ __forceinline__ void load_zop_s(const float2 *__restrict__ sk0, size_t kstride, int U, int kvalid,
                                            ZOp<UP, PREC> &z) {
     const int lane = lane_id();
     const int i = lane & 31, g = lane >> 5;
@@ -308,6 +309,12 @@ __device__ __forceinline__ void make_zop_s(const float2 *__restrict__ sk0, size_
         z.f[mm] = q ? v.y : v.x;
         z.f[mm + 1] = q ? v.x : -v.y;
     }
+}
+
+template <int UP, int PREC>
+__device__ __forceinline__ void make_zop_s(const float2 *__restrict__ sk0, size_t kstride, int U, int kvalid,
+                                           ZOp<UP, PREC> &z) {
+    load_zop_s<UP, PREC>(sk0, kstride, U, kvalid, z);
     zop_finish<UP, PREC>(z);
 }
 
@@ -590,6 +597,28 @@ __device__ __forceinline__ floatx16 mfma_apply_tile(Tile<UP, PREC> &tl, const ZO
     return acc;
 }
 
+// The Gram operand buffer of a register tile, transposed through the wave's
+// LDS scratch (rows stored row-major with stride RS, read back by column).
+template <int UP, int PREC>
+__device__ __forceinline__ void tile_to_gram(const Tile<UP, PREC> &tl, float *scr, GramBuf<UP> &b) {
+    constexpr int NT = Shape<UP>::NT;
+    constexpr int RS = Shape<UP>::RS;
+    const int lane = lane_id();
+    const int j = lane & 31, g = lane >> 5;
+    float *rp = scr + j * RS + g * UP;
+#pragma unroll
+    for (int m4 = 0; m4 < UP; m4 += 4)
+        *(float4 *)(rp + m4) = make_float4(tl.f[m4], tl.f[m4 + 1], tl.f[m4 + 2], tl.f[m4 + 3]);
+    wave_sync();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int row = PREC == kF32 ? 2 * q + g : 16 * (q / 8) + 8 * g + (q % 8);
+#pragma unroll
+        for (int ti = 0; ti < NT; ++ti) b.v[ti][q] = scr[row * RS + 32 * ti + j];
+    }
+    wave_sync();  // the scratch is rewritten by the next tile
+}
+
 // Stores the X^T tile of rows [row0, row0 + nrows), symbols k0 .. k0 + kc - 1.
 // Symbol k = tile_k(r, g) = kr + 2 g: a uniform symbol pointer per register
 // pair and one lane offset.
@@ -614,7 +643,10 @@ template <int UP>
 struct Lds {
     static constexpr size_t zbytes = (size_t)UP * KC * 8;
     static constexpr size_t sbytes = (size_t)Shape<UP>::SLOT * 8;
-    static constexpr size_t per_wave = zbytes + sbytes;  // Z chunk and system slot
+    static constexpr size_t tbytes = (size_t)32 * Shape<UP>::RS * 4;
+    // per wave: the Z chunk and the system slot, which the Gram's tile
+    // transpose scratch overlays before either is written
+    static constexpr size_t per_wave = zbytes + sbytes > tbytes ? zbytes + sbytes : tbytes;
     static __host__ __device__ constexpr size_t bytes(int nw) { return nw * per_wave; }
 };
 
@@ -659,8 +691,8 @@ constexpr int max_tiles(int up) { return up == 16 ? 8 : 4; }
 // in registers need more registers per wave.
 template <int UP, int MAXT, int PREC>
 constexpr int min_waves() {
-    if (UP == 16) return MAXT == 0 ? 4 : MAXT == 1 ? (PREC == kF32 ? 4 : 3) : MAXT == 2 ? 3 : 2;
-    return MAXT <= 1 ? 2 : 1;
+    if (UP == 16) return MAXT == 0 ? 3 : MAXT == 1 ? (PREC == kF32 ? 4 : 3) : MAXT == 2 ? 3 : 2;
+    return MAXT == 1 ? 2 : 1;
 }
 
 // ---- one system per wave --------------------------------------------------------
@@ -702,29 +734,45 @@ __device__ __forceinline__ void wave_system(const Prob &p, const int *__restrict
     // loads of the same lines are then served by the cache)
     Tile<UP, PREC> tiles[MAXT > 0 ? MAXT : 1];
     if constexpr (MAXT > 0) {
-        if (mode != kPrepare) {
 #pragma unroll
-            for (int q = 0; q < MAXT; ++q) {
-                const int rq = r0 + 32 * q;
-                load_tile<UP, PREC>(Hn, U, rq, q < ntile ? min(32, r1 - rq) : 0, vec, tiles[q]);
-            }
+        for (int q = 0; q < MAXT; ++q) {
+            const int rq = r0 + 32 * q;
+            load_tile<UP, PREC>(Hn, U, rq, q < ntile ? min(32, r1 - rq) : 0, vec, tiles[q]);
         }
     }
+    // the first chunk's symbols, loaded while the channel arrives (split
+    // into the 16-bit operand only when used)
+    ZOp<UP, PREC> zs0;
+    if (mode != kPrepare) load_zop_s<UP, PREC>(s + (size_t)n * U, (size_t)n_sc * U, U, min(KC, K), zs0);
     if (mode == kSymbols) {
         amax = load_factor<UP>(fac, U, sA);
     } else {
         floatx16 acc[NTT];
 #pragma unroll
         for (int q = 0; q < NTT; ++q) acc[q] = floatx16{0};
-        GramBuf<UP> b0, b1;
-        gram_load<UP, PREC>(Hf, 2 * U, r0, min(32, r1 - r0), b0);
-        for (int t = 0; t < ntile; t += 2) {
-            const int ra = r0 + 32 * (t + 1), rb = r0 + 32 * (t + 2);
-            if (t + 1 < ntile) gram_load<UP, PREC>(Hf, 2 * U, ra, min(32, r1 - ra), b1);
-            gram_mma<UP, PREC>(b0, acc);
-            if (t + 1 < ntile) {
-                if (t + 2 < ntile) gram_load<UP, PREC>(Hf, 2 * U, rb, min(32, r1 - rb), b0);
-                gram_mma<UP, PREC>(b1, acc);
+        if constexpr (MAXT > 0) {
+            // from the register tiles, transposed through LDS (the scratch
+            // overlays Z and the slot, both unused until the Gram is done)
+            float *scr = (float *)Zw;
+#pragma unroll
+            for (int q = 0; q < MAXT; ++q) {
+                if (q < ntile) {
+                    GramBuf<UP> b;
+                    tile_to_gram<UP, PREC>(tiles[q], scr, b);
+                    gram_mma<UP, PREC>(b, acc);
+                }
+            }
+        } else {
+            GramBuf<UP> b0, b1;
+            gram_load<UP, PREC>(Hf, 2 * U, r0, min(32, r1 - r0), b0);
+            for (int t = 0; t < ntile; t += 2) {
+                const int ra = r0 + 32 * (t + 1), rb = r0 + 32 * (t + 2);
+                if (t + 1 < ntile) gram_load<UP, PREC>(Hf, 2 * U, ra, min(32, r1 - ra), b1);
+                gram_mma<UP, PREC>(b0, acc);
+                if (t + 1 < ntile) {
+                    if (t + 2 < ntile) gram_load<UP, PREC>(Hf, 2 * U, rb, min(32, r1 - rb), b0);
+                    gram_mma<UP, PREC>(b1, acc);
+                }
             }
         }
         for (int e = lane; e < SLOT; e += 64) sA[e] = {0.f, 0.f};
@@ -756,7 +804,10 @@ __device__ __forceinline__ void wave_system(const Prob &p, const int *__restrict
     }
     for (int k0 = 0; k0 < K; k0 += KC) {
         const int kc = min(KC, K - k0);
-        {
+        if (k0 == 0) {
+            zop_finish<UP, PREC>(zs0);
+            wave_solve_chunk<UP, PREC>(sA, Zw, zs0, kc, U, scale, amax, ok);
+        } else {
             ZOp<UP, PREC> zs;
             make_zop_s<UP, PREC>(s + ((size_t)k0 * n_sc + n) * U, (size_t)n_sc * U, U, kc, zs);
             wave_solve_chunk<UP, PREC>(sA, Zw, zs, kc, U, scale, amax, ok);
