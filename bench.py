@@ -170,7 +170,7 @@ def main():
     out["pd_precision_variants"] = variants
     # every launch shape the autotuner chooses from, forced
     shapes = {}
-    for nw in (2, 4, 8):
+    for nw in (1, 2, 4):
         os.environ["PRECODE_FUSED_WAVES"] = str(nw)
         ms_s, per_s = time_path(pd_fused, max(10, args.steps // 4), 3)
         shapes[str(nw)] = {"ms_per_step": ms_s, "launch_ms": float(np.mean(per_s)), "used": ctx.last_waves}

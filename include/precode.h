@@ -117,13 +117,15 @@ size_t precode_ctx_bytes(const precode_ctx *ctx);
  * (1 = fused, 2 = plain), or 0 if none. */
 int precode_ctx_last_impl(const precode_ctx *ctx);
 
-/* Waves per workgroup (2, 4 or 8) of the most recent fused precode_pd /
+/* Waves per workgroup (1, 2 or 4) of the most recent fused precode_pd /
  * precode_fd / precode_batch call on this context, or 0 if none.  The fused
  * kernel's launch shape is chosen by an autotuner that times every feasible
  * shape on the first call of each problem shape in the process (the call's
  * own launch, repeated on its stream, before the call returns) and reuses
- * the fastest; PRECODE_FUSED_WAVES=2|4|8 in the environment forces a shape,
- * PRECODE_AUTOTUNE=0 keeps the default (4).  Calls made under stream capture
+ * the fastest; PRECODE_FUSED_WAVES=1|2|4 in the environment forces a shape,
+ * PRECODE_AUTOTUNE=0 keeps the default (4); PRECODE_FUSED_STREAM=1 makes
+ * every wave stream its channel rows twice instead of keeping them in
+ * registers.  Calls made under stream capture
  * never tune.  Shapes differ only in the order of the cluster-sum rounding. */
 int precode_ctx_last_waves(const precode_ctx *ctx);
 
@@ -191,8 +193,8 @@ int precode_frame_release(precode_ctx *ctx, precode_frame *frame);
  *   - jobs the fused kernel takes (U <= 32, no FP64 route, FD clusters with
  *     B_c >= U) run as ONE launch per kernel shape class (tile width U <= 16
  *     or U <= 32, times the channel tiles a wave keeps in registers: 1, 2,
- *     4, 8 or streamed), PD and FD jobs together: at most 9 launches however
- *     many jobs there are;
+ *     4, 8 or streamed, times the load width), PD and FD jobs together: at
+ *     most 18 launches however many jobs there are;
  *   - the remaining jobs run on the plain kernels after them, on `stream`.
  * The whole batch is validated before anything is enqueued (first error
  * returned).  With SPLIT precision every job must be fused-capable

@@ -137,7 +137,7 @@ class Context:
 
     @property
     def last_waves(self) -> int:
-        """Waves per workgroup of the last fused launch (autotuned shape)."""
+        """Waves per workgroup (1, 2 or 4) of the last fused launch (autotuned shape)."""
         return _lib.load().precode_ctx_last_waves(self.handle)
 
     def _run(self, arch, H, s, rho, sizes, mode, prm, x, scale, status, stream):

@@ -3,7 +3,8 @@
 // the kernel's shape classes allow.
 //
 // Problems are grouped by tile width UP (16 for U <= 16, 32 for U <= 32) and
-// channel tiles per wave held in registers (1, 2, 4, 8 or streamed); each
+// channel tiles per wave held in registers (1, 2, 4, 8 or streamed) and load
+// width (U == UP with an aligned channel, or not); each
 // group -- PD and FD problems alike -- is one launch whose grid is the sum of
 // its problems' workgroups (one wave per local system, NW systems per
 // workgroup).  The problem table sits in device memory; a workgroup finds its
@@ -33,12 +34,14 @@ struct Entry {
 
 // Launch class of a problem: tile width and register tiles per wave.
 struct Class {
-    int up, maxt;
-    bool operator==(const Class &o) const { return up == o.up && maxt == o.maxt; }
-    bool operator<(const Class &o) const { return up != o.up ? up < o.up : maxt < o.maxt; }
+    int up, maxt, vec;
+    bool operator==(const Class &o) const { return up == o.up && maxt == o.maxt && vec == o.vec; }
+    bool operator<(const Class &o) const {
+        return up != o.up ? up < o.up : (maxt != o.maxt ? maxt < o.maxt : vec < o.vec);
+    }
 };
 
-Class class_of(const Prob &p) { return Class{pick_up(p.U), pick_maxt(p)}; }
+Class class_of(const BatchProblem &q) { return Class{pick_up(q.p.U), pick_maxt(q.p), pick_vec(q.p, q.H) ? 1 : 0}; }
 
 // Problems in launch order (by class, then problem order).
 struct Plan {
@@ -52,11 +55,11 @@ Plan make_plan(const BatchProblem *bp, int n) {
     std::vector<int> order(n);
     for (int i = 0; i < n; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(),
-                     [&](int a, int b) { return class_of(bp[a].p) < class_of(bp[b].p); });
+                     [&](int a, int b) { return class_of(bp[a]) < class_of(bp[b]); });
     Plan pl;
     for (int oi = 0; oi < n; ++oi) {
         const BatchProblem &q = bp[order[oi]];
-        const Class c = class_of(q.p);
+        const Class c = class_of(q);
         if (pl.cls.empty() || !(pl.cls.back() == c)) {
             pl.cls.push_back(c);
             pl.first.push_back((int)pl.e.size());
@@ -79,7 +82,7 @@ Plan make_plan(const BatchProblem *bp, int n) {
     return pl;
 }
 
-template <int UP, int PREC, int MAXT>
+template <int UP, int PREC, int MAXT, bool VEC>
 __global__ void __launch_bounds__(64 * NW, (min_waves<UP, MAXT, PREC>()))
     fused_batch_k(const Entry *__restrict__ tab, int n) {
     const int b = blockIdx.x;
@@ -90,41 +93,44 @@ __global__ void __launch_bounds__(64 * NW, (min_waves<UP, MAXT, PREC>()))
         else hi = mid - 1;
     }
     const Entry &E = tab[lo];
-    fused_body<UP, PREC, NW, MAXT>(E.p, E.p.off, b - E.block0, E.K, kFull, E.H, E.s, E.x, nullptr, E.scale_out,
+    fused_body<UP, PREC, NW, MAXT, VEC>(E.p, E.p.off, b - E.block0, E.K, kFull, E.H, E.s, E.x, nullptr, E.scale_out,
                                    E.status);
 }
 
-template <int UP, int PREC, int MAXT>
+template <int UP, int PREC, int MAXT, bool VEC>
 hipError_t launch(const Entry *tab, int n, int blocks, hipStream_t st) {
-    const void *fn = (const void *)fused_batch_k<UP, PREC, MAXT>;
+    const void *fn = (const void *)fused_batch_k<UP, PREC, MAXT, VEC>;
     const size_t lds = Lds<UP>::bytes(NW);
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((fused_batch_k<UP, PREC, MAXT>), dim3(blocks), dim3(64 * NW), lds, st, tab, n);
+    hipLaunchKernelGGL((fused_batch_k<UP, PREC, MAXT, VEC>), dim3(blocks), dim3(64 * NW), lds, st, tab, n);
     return hipGetLastError();
 }
 
-template <int UP, int PREC>
-hipError_t launch_t(int maxt, const Entry *tab, int n, int blocks, hipStream_t st) {
+template <int UP, int PREC, bool VEC>
+hipError_t launch_v(int maxt, const Entry *tab, int n, int blocks, hipStream_t st) {
     switch (maxt) {
-        case 0: return launch<UP, PREC, 0>(tab, n, blocks, st);
-        case 1: return launch<UP, PREC, 1>(tab, n, blocks, st);
-        case 2: return launch<UP, PREC, 2>(tab, n, blocks, st);
-        case 4: return launch<UP, PREC, 4>(tab, n, blocks, st);
+        case 0: return launch<UP, PREC, 0, VEC>(tab, n, blocks, st);
+        case 1: return launch<UP, PREC, 1, VEC>(tab, n, blocks, st);
+        case 2: return launch<UP, PREC, 2, VEC>(tab, n, blocks, st);
+        case 4: return launch<UP, PREC, 4, VEC>(tab, n, blocks, st);
         default:
-            if constexpr (max_tiles(UP) >= 8) return launch<UP, PREC, 8>(tab, n, blocks, st);
+            if constexpr (max_tiles(UP) >= 8) return launch<UP, PREC, 8, VEC>(tab, n, blocks, st);
             return hipErrorNotSupported;
     }
 }
 
 template <int UP>
-hipError_t launch_prec(int prec, int maxt, const Entry *tab, int n, int blocks, hipStream_t st) {
+hipError_t launch_prec(int prec, int maxt, int vec, const Entry *tab, int n, int blocks, hipStream_t st) {
     switch (prec) {
-        case kF32: return launch_t<UP, kF32>(maxt, tab, n, blocks, st);
-        case kF16: return launch_t<UP, kF16>(maxt, tab, n, blocks, st);
-        default: return launch_t<UP, kBF16>(maxt, tab, n, blocks, st);
+        case kF32: return vec ? launch_v<UP, kF32, true>(maxt, tab, n, blocks, st)
+                              : launch_v<UP, kF32, false>(maxt, tab, n, blocks, st);
+        case kF16: return vec ? launch_v<UP, kF16, true>(maxt, tab, n, blocks, st)
+                              : launch_v<UP, kF16, false>(maxt, tab, n, blocks, st);
+        default: return vec ? launch_v<UP, kBF16, true>(maxt, tab, n, blocks, st)
+                            : launch_v<UP, kBF16, false>(maxt, tab, n, blocks, st);
     }
 }
 
@@ -152,8 +158,8 @@ hipError_t fused_batch_launch(const BatchProblem *bp, int n, int precision, cons
         const int f = pl.first[r], cnt = pl.first[r + 1] - f;
         if (cnt == 0) continue;
         const Class c = pl.cls[r];
-        const hipError_t e = c.up == 16 ? launch_prec<16>(prec, c.maxt, tab + f, cnt, pl.blocks[r], st)
-                                        : launch_prec<32>(prec, c.maxt, tab + f, cnt, pl.blocks[r], st);
+        const hipError_t e = c.up == 16 ? launch_prec<16>(prec, c.maxt, c.vec, tab + f, cnt, pl.blocks[r], st)
+                                        : launch_prec<32>(prec, c.maxt, c.vec, tab + f, cnt, pl.blocks[r], st);
         if (e != hipSuccess) return e;
         ++nl;
     }

@@ -29,8 +29,8 @@
 //               the cache) in the row layout of the product and the results
 //               stored coalesced
 //
-// Launch shape: NW = 2, 4 or 8 waves (systems) per workgroup
-// (fused_nw{2,4,8}.hip).  The autotuner times every feasible NW on the first
+// Launch shape: NW = 1, 2 or 4 waves (systems) per workgroup
+// (fused_nw{1,2,4}.hip).  The autotuner times every feasible NW on the first
 // call of each problem shape (the call itself, repeated) and caches the
 // fastest for the process.
 //
@@ -57,7 +57,7 @@
 namespace pc {
 namespace {
 
-constexpr int kNWs[] = {2, 4, 8};
+constexpr int kNWs[] = {1, 2, 4};
 constexpr int kDefaultNW = 4;
 
 bool nw_feasible(const Prob &p, int nw) {
@@ -67,10 +67,15 @@ bool nw_feasible(const Prob &p, int nw) {
     return lds <= kLdsUsable;
 }
 
+int env_int(const char *name, int dflt) {
+    const char *v = getenv(name);
+    return v && *v ? atoi(v) : dflt;
+}
+
 hipError_t launch_nw(int nw, const Prob &p, int prec, const FusedCall &a, hipStream_t st) {
     switch (nw) {
+        case 1: return fused_launch_nw1(p, prec, a, st);
         case 2: return fused_launch_nw2(p, prec, a, st);
-        case 8: return fused_launch_nw8(p, prec, a, st);
         default: return fused_launch_nw4(p, prec, a, st);
     }
 }
@@ -81,7 +86,8 @@ hipError_t run_once(int nw, const Prob &p, int prec, int mode, int K, const floa
     FusedCall a;
     a.K = mode == kPrepare ? 0 : K;
     a.mode = mode;
-    a.maxt = pick_maxt(p);
+    a.maxt = env_int("PRECODE_FUSED_STREAM", 0) ? 0 : pick_maxt(p);
+    a.vec = pick_vec(p, H);
     a.H = H;
     a.s = s;
     a.x = x;
@@ -93,7 +99,7 @@ hipError_t run_once(int nw, const Prob &p, int prec, int mode, int K, const floa
 
 // ---- autotuner ------------------------------------------------------------------
 // Process-wide cache: problem shape -> waves per workgroup.  Environment:
-// PRECODE_FUSED_WAVES=2|4|8 forces a shape (when feasible), PRECODE_AUTOTUNE=0
+// PRECODE_FUSED_WAVES=1|2|4 forces a shape (when feasible), PRECODE_AUTOTUNE=0
 // disables tuning (default NW).
 std::mutex g_tune_mu;
 std::unordered_map<std::string, int> g_tuned;
@@ -107,10 +113,6 @@ std::string tune_key(const Prob &p, int prec, int mode, int K) {
     return k;
 }
 
-int env_int(const char *name, int dflt) {
-    const char *v = getenv(name);
-    return v && *v ? atoi(v) : dflt;
-}
 
 int default_nw(const Prob &p) {
     if (nw_feasible(p, kDefaultNW)) return kDefaultNW;

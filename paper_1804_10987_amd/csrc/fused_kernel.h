@@ -126,18 +126,35 @@ __device__ __forceinline__ void gram_load(const float *__restrict__ Hf, int u2, 
     constexpr int NT = Shape<UP>::NT;
     const int lane = lane_id();
     const int j = lane & 31, g = lane >> 5;
-    // row = rq + rg with rq uniform: one uniform row pointer per register and
-    // one 32-bit lane offset shared by every load
     const int rg = PREC == kF32 ? g : 8 * g;
-    const int loff = rg * u2 + j;
+    // loads only (see load_tile): rows past the tile read its last row,
+    // columns past 2U read column 0; gram_mask zeroes both before use
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
         const int rq = PREC == kF32 ? 2 * q : 16 * (q / 8) + (q % 8);
-        const float *rowp = Hf + (size_t)(row0 + rq) * u2;
-        const bool rowok = rq + rg < nrows;
+        const int rsel = rq + rg < nrows ? rq + rg : nrows - 1;
+        const float *rowp = Hf + (size_t)(row0 + rsel) * u2;
+#pragma unroll
+        for (int ti = 0; ti < NT; ++ti) {
+            const int col = 32 * ti + j;
+            b.v[ti][q] = rowp[col < u2 ? col : 0];
+        }
+    }
+}
+
+// Zeroes the rows >= nrows and columns >= u2 of a loaded Gram buffer.
+template <int UP, int PREC>
+__device__ __forceinline__ void gram_mask(GramBuf<UP> &b, int u2, int nrows) {
+    constexpr int NT = Shape<UP>::NT;
+    const int lane = lane_id();
+    const int j = lane & 31, g = lane >> 5;
+    const int rg = PREC == kF32 ? g : 8 * g;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int rq = PREC == kF32 ? 2 * q : 16 * (q / 8) + (q % 8);
 #pragma unroll
         for (int ti = 0; ti < NT; ++ti)
-            b.v[ti][q] = (rowok && 32 * ti + j < u2) ? rowp[loff + 32 * ti] : 0.f;
+            b.v[ti][q] = (rq + rg < nrows && 32 * ti + j < u2) ? b.v[ti][q] : 0.f;
     }
 }
 
@@ -293,28 +310,41 @@ __device__ __forceinline__ void make_zop(const cx<float> *Z, int su, int sk, int
     zop_finish<UP, PREC>(z);
 }
 
-// The symbol operand straight from global memory: s(u, k) at sk0[k * kstride
-// + u] for u < U, k < kvalid (zero elsewhere).
+// Symbols s(u, k) at sk0[k * kstride + u] as loaded for the symbol operand:
+// lane (i, g) holds symbol k = i / 2, users (g UP + mm) / 2, mm even.  Loads
+// only, from clamped in-range addresses (see load_tile); sym_to_zop masks.
+template <int UP>
+struct SymRaw {
+    float2 v[UP / 2];
+};
+
+template <int UP>
+__device__ __forceinline__ void load_sym(const float2 *__restrict__ sk0, size_t kstride, int U, int kvalid,
+                                         SymRaw<UP> &r) {
+    const int lane = lane_id();
+    const int i = lane & 31, g = lane >> 5;
+    const int k = i >> 1;
+    const int kk = k < kvalid ? k : (kvalid > 0 ? kvalid - 1 : 0);
+#pragma unroll
+    for (int m = 0; m < UP / 2; ++m) {
+        const int u = g * (UP / 2) + m;
+        r.v[m] = sk0[(size_t)kk * kstride + (u < U ? u : U - 1)];
+    }
+}
+
+// The symbol operand (zero for u >= U, k >= kvalid), split for 16-bit MFMA.
 template <int UP, int PREC>
-__device__ __forceinline__ void load_zop_s(const float2 *__restrict__ sk0, size_t kstride, int U, int kvalid,
-                                           ZOp<UP, PREC> &z) {
+__device__ __forceinline__ void sym_to_zop(const SymRaw<UP> &r, int U, int kvalid, ZOp<UP, PREC> &z) {
     const int lane = lane_id();
     const int i = lane & 31, g = lane >> 5;
     const int k = i >> 1, q = i & 1;
 #pragma unroll
-    for (int mm = 0; mm < UP; mm += 2) {
-        const int u = (g * UP + mm) >> 1;
-        float2 v = make_float2(0.f, 0.f);
-        if (k < kvalid && u < U) v = sk0[(size_t)k * kstride + u];
-        z.f[mm] = q ? v.y : v.x;
-        z.f[mm + 1] = q ? v.x : -v.y;
+    for (int m = 0; m < UP / 2; ++m) {
+        const int u = g * (UP / 2) + m;
+        const float2 v = (k < kvalid && u < U) ? r.v[m] : make_float2(0.f, 0.f);
+        z.f[2 * m] = q ? v.y : v.x;
+        z.f[2 * m + 1] = q ? v.x : -v.y;
     }
-}
-
-template <int UP, int PREC>
-__device__ __forceinline__ void make_zop_s(const float2 *__restrict__ sk0, size_t kstride, int U, int kvalid,
-                                           ZOp<UP, PREC> &z) {
-    load_zop_s<UP, PREC>(sk0, kstride, U, kvalid, z);
     zop_finish<UP, PREC>(z);
 }
 
@@ -535,36 +565,42 @@ struct Tile {
     typename Split<PREC == kF32 ? kF16 : PREC>::V hi[UP / 8], lo[UP / 8];
 };
 
-// Loads rows [row0, row0 + nrows) of a subcarrier's channel Hn (B x U) into a
-// tile (rows >= nrows and users >= U read as 0).
-template <int UP, int PREC>
-__device__ __forceinline__ void load_tile(const float2 *__restrict__ Hn, int U, int row0, int nrows, bool vec,
+// Loads rows [row0, row0 + nrows) (0 <= nrows <= 32; row0 a valid row) of a
+// subcarrier's channel Hn (B x U) into a tile.  The loads go straight into
+// the tile registers with nothing consuming them, so the loads of all of a
+// wave's tiles stay in flight together (any instruction using a loaded value,
+// or a branch around a load, makes the compiler wait for it there).  Lanes
+// past nrows read the last row and users past U read user U - 1: the tile
+// holds finite copies of real entries there, which the Gram masks out
+// (tile_to_gram), the precode never stores, and the zero-padded symbol
+// operand multiplies by zero.
+// VEC (U == UP, 16-byte aligned channel): 16-byte loads at immediate offsets
+// from one row address per tile; otherwise one 8-byte load per user.
+template <int UP, int PREC, bool VEC>
+__device__ __forceinline__ void load_tile(const float2 *__restrict__ Hn, int U, int row0, int nrows,
                                           Tile<UP, PREC> &tl) {
     const int lane = lane_id();
     const int j = lane & 31, g = lane >> 5;
-    if (j < nrows) {
-        const float2 *rp = Hn + (size_t)(row0 + j) * U + g * (UP / 2);
-        if (vec) {  // U == UP, 16-byte aligned rows
+    const int jr = j < nrows ? j : (nrows > 0 ? nrows - 1 : 0);
+    if constexpr (VEC) {
+        const float4 *rp = (const float4 *)(Hn + (size_t)(row0 + jr) * UP + g * (UP / 2));
 #pragma unroll
-            for (int m4 = 0; m4 < UP; m4 += 4) {
-                const float4 v = *(const float4 *)(rp + m4 / 2);
-                tl.f[m4] = v.x;
-                tl.f[m4 + 1] = v.y;
-                tl.f[m4 + 2] = v.z;
-                tl.f[m4 + 3] = v.w;
-            }
-        } else {
-#pragma unroll
-            for (int m2 = 0; m2 < UP / 2; ++m2) {
-                const int u = g * (UP / 2) + m2;
-                const float2 v = u < U ? rp[m2] : make_float2(0.f, 0.f);
-                tl.f[2 * m2] = v.x;
-                tl.f[2 * m2 + 1] = v.y;
-            }
+        for (int m4 = 0; m4 < UP / 4; ++m4) {
+            const float4 v = rp[m4];
+            tl.f[4 * m4] = v.x;
+            tl.f[4 * m4 + 1] = v.y;
+            tl.f[4 * m4 + 2] = v.z;
+            tl.f[4 * m4 + 3] = v.w;
         }
     } else {
+        const float2 *rp = Hn + (size_t)(row0 + jr) * U;
 #pragma unroll
-        for (int m = 0; m < UP; ++m) tl.f[m] = 0.f;
+        for (int m2 = 0; m2 < UP / 2; ++m2) {
+            const int u = g * (UP / 2) + m2;
+            const float2 v = rp[u < U ? u : U - 1];
+            tl.f[2 * m2] = v.x;
+            tl.f[2 * m2 + 1] = v.y;
+        }
     }
 }
 
@@ -599,16 +635,23 @@ __device__ __forceinline__ floatx16 mfma_apply_tile(Tile<UP, PREC> &tl, const ZO
 
 // The Gram operand buffer of a register tile, transposed through the wave's
 // LDS scratch (rows stored row-major with stride RS, read back by column).
+// Rows >= nrows and users >= U are zeroed here (the tile holds copies there).
 template <int UP, int PREC>
-__device__ __forceinline__ void tile_to_gram(const Tile<UP, PREC> &tl, float *scr, GramBuf<UP> &b) {
+__device__ __forceinline__ void tile_to_gram(const Tile<UP, PREC> &tl, int nrows, int U, float *scr,
+                                             GramBuf<UP> &b) {
     constexpr int NT = Shape<UP>::NT;
     constexpr int RS = Shape<UP>::RS;
     const int lane = lane_id();
     const int j = lane & 31, g = lane >> 5;
+    const bool live = j < nrows;
     float *rp = scr + j * RS + g * UP;
 #pragma unroll
-    for (int m4 = 0; m4 < UP; m4 += 4)
-        *(float4 *)(rp + m4) = make_float4(tl.f[m4], tl.f[m4 + 1], tl.f[m4 + 2], tl.f[m4 + 3]);
+    for (int m4 = 0; m4 < UP; m4 += 4) {
+        float v[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = (live && g * (UP / 2) + (m4 + e) / 2 < U) ? tl.f[m4 + e] : 0.f;
+        *(float4 *)(rp + m4) = make_float4(v[0], v[1], v[2], v[3]);
+    }
     wave_sync();
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
@@ -707,7 +750,7 @@ constexpr int min_waves() {
 //             memory), then the rows are streamed again (from cache) for
 //             X_c = H_c Z and stored
 // Modes kPrepare / kSymbols store / load scale * A^-1 per system instead.
-template <int UP, int PREC, int MAXT>
+template <int UP, int PREC, int MAXT, bool VEC>
 __device__ __forceinline__ void wave_system(const Prob &p, const int *__restrict__ off, int sys, int K, int mode,
                                             const float2 *__restrict__ H, const float2 *__restrict__ s,
                                             float2 *__restrict__ x, cx<float> *__restrict__ ainv_g,
@@ -724,7 +767,6 @@ __device__ __forceinline__ void wave_system(const Prob &p, const int *__restrict
     const int ntile = (r1 - r0 + 31) >> 5;
     const float2 *Hn = H + (size_t)n * B * U;
     const float *Hf = (const float *)Hn;
-    const bool vec = U == UP && (((uintptr_t)H) & 15) == 0;
     const float kap = pd ? pd_kappa(p) : fd_kappa(p);
     cx<float> *fac = ainv_g ? ainv_g + (size_t)sys * U * U : nullptr;
     float scale = 1.f, amax = 0.f;
@@ -737,14 +779,16 @@ __device__ __forceinline__ void wave_system(const Prob &p, const int *__restrict
 #pragma unroll
         for (int q = 0; q < MAXT; ++q) {
             const int rq = r0 + 32 * q;
-            load_tile<UP, PREC>(Hn, U, rq, q < ntile ? min(32, r1 - rq) : 0, vec, tiles[q]);
+            // tiles past the system load (and zero) its first rows: no branch
+            load_tile<UP, PREC, VEC>(Hn, U, q < ntile ? rq : r0, q < ntile ? min(32, r1 - rq) : 0, tiles[q]);
         }
     }
-    // the first chunk's symbols, loaded while the channel arrives (split
-    // into the 16-bit operand only when used)
-    ZOp<UP, PREC> zs0;
-    if (mode != kPrepare) load_zop_s<UP, PREC>(s + (size_t)n * U, (size_t)n_sc * U, U, min(KC, K), zs0);
+    // the first chunk's symbols: loaded after the Gram, in flight during the
+    // factorization (kept out of the Gram's register budget)
+    SymRaw<UP> sym0;
+    const bool pre_sym = mode != kPrepare && K > 0;
     if (mode == kSymbols) {
+        if (pre_sym) load_sym<UP>(s + (size_t)n * U, (size_t)n_sc * U, U, min(KC, K), sym0);
         amax = load_factor<UP>(fac, U, sA);
     } else {
         floatx16 acc[NTT];
@@ -758,23 +802,29 @@ __device__ __forceinline__ void wave_system(const Prob &p, const int *__restrict
             for (int q = 0; q < MAXT; ++q) {
                 if (q < ntile) {
                     GramBuf<UP> b;
-                    tile_to_gram<UP, PREC>(tiles[q], scr, b);
+                    tile_to_gram<UP, PREC>(tiles[q], min(32, r1 - (r0 + 32 * q)), U, scr, b);
                     gram_mma<UP, PREC>(b, acc);
                 }
+                // one tile at a time: keeps the scheduler from overlapping
+                // several tiles' buffers on top of the resident tiles
+                __builtin_amdgcn_sched_barrier(0);
             }
         } else {
             GramBuf<UP> b0, b1;
             gram_load<UP, PREC>(Hf, 2 * U, r0, min(32, r1 - r0), b0);
             for (int t = 0; t < ntile; t += 2) {
-                const int ra = r0 + 32 * (t + 1), rb = r0 + 32 * (t + 2);
+                const int r = r0 + 32 * t, ra = r + 32, rb = r + 64;
                 if (t + 1 < ntile) gram_load<UP, PREC>(Hf, 2 * U, ra, min(32, r1 - ra), b1);
+                gram_mask<UP, PREC>(b0, 2 * U, min(32, r1 - r));
                 gram_mma<UP, PREC>(b0, acc);
                 if (t + 1 < ntile) {
                     if (t + 2 < ntile) gram_load<UP, PREC>(Hf, 2 * U, rb, min(32, r1 - rb), b0);
+                    gram_mask<UP, PREC>(b1, 2 * U, min(32, r1 - ra));
                     gram_mma<UP, PREC>(b1, acc);
                 }
             }
         }
+        if (pre_sym) load_sym<UP>(s + (size_t)n * U, (size_t)n_sc * U, U, min(KC, K), sym0);
         for (int e = lane; e < SLOT; e += 64) sA[e] = {0.f, 0.f};
         wave_sync();
         gram_store<UP>(acc, sA, 1.f, kap, U);
@@ -804,12 +854,12 @@ __device__ __forceinline__ void wave_system(const Prob &p, const int *__restrict
     }
     for (int k0 = 0; k0 < K; k0 += KC) {
         const int kc = min(KC, K - k0);
-        if (k0 == 0) {
-            zop_finish<UP, PREC>(zs0);
-            wave_solve_chunk<UP, PREC>(sA, Zw, zs0, kc, U, scale, amax, ok);
-        } else {
+        {
+            SymRaw<UP> sym;
+            if (k0 == 0) sym = sym0;
+            else load_sym<UP>(s + ((size_t)k0 * n_sc + n) * U, (size_t)n_sc * U, U, kc, sym);
             ZOp<UP, PREC> zs;
-            make_zop_s<UP, PREC>(s + ((size_t)k0 * n_sc + n) * U, (size_t)n_sc * U, U, kc, zs);
+            sym_to_zop<UP, PREC>(sym, U, kc, zs);
             wave_solve_chunk<UP, PREC>(sA, Zw, zs, kc, U, scale, amax, ok);
         }
         wave_sync();
@@ -820,18 +870,19 @@ __device__ __forceinline__ void wave_system(const Prob &p, const int *__restrict
             for (int q = 0; q < MAXT; ++q) {
                 const int rq = r0 + 32 * q;
                 if (q < ntile) store_x(mfma_apply_tile<UP, PREC>(tiles[q], z), rq, min(32, r1 - rq), k0, kc, n, n_sc, B, x);
+                __builtin_amdgcn_sched_barrier(0);
             }
             wave_sync();
             continue;
         }
         Tile<UP, PREC> ta, tb;
-        load_tile<UP, PREC>(Hn, U, r0, min(32, r1 - r0), vec, ta);
+        load_tile<UP, PREC, VEC>(Hn, U, r0, min(32, r1 - r0), ta);
         for (int t = 0; t < ntile; t += 2) {
             const int ra = r0 + 32 * t, rb = r0 + 32 * (t + 1), rc = r0 + 32 * (t + 2);
-            if (t + 1 < ntile) load_tile<UP, PREC>(Hn, U, rb, min(32, r1 - rb), vec, tb);
+            if (t + 1 < ntile) load_tile<UP, PREC, VEC>(Hn, U, rb, min(32, r1 - rb), tb);
             store_x(mfma_apply_tile<UP, PREC>(ta, z), ra, min(32, r1 - ra), k0, kc, n, n_sc, B, x);
             if (t + 1 < ntile) {
-                if (t + 2 < ntile) load_tile<UP, PREC>(Hn, U, rc, min(32, r1 - rc), vec, ta);
+                if (t + 2 < ntile) load_tile<UP, PREC, VEC>(Hn, U, rc, min(32, r1 - rc), ta);
                 store_x(mfma_apply_tile<UP, PREC>(tb, z), rb, min(32, r1 - rb), k0, kc, n, n_sc, B, x);
             }
         }
@@ -844,20 +895,24 @@ __device__ __forceinline__ void wave_system(const Prob &p, const int *__restrict
 // consecutive subcarriers; FD: consecutive clusters of a subcarrier).
 // off: the problem's cluster offsets (p.off) in memory the kernel can index.
 // MAXT: channel tiles (32 rows) of the largest system that a wave keeps in
-// registers (0: the precode streams the rows a second time).
-template <int UP, int PREC, int NW, int MAXT>
+// registers (0: the precode streams the rows a second time).  VEC: U == UP
+// and a 16-byte aligned channel (wider loads).
+template <int UP, int PREC, int NW, int MAXT, bool VEC>
 __device__ __forceinline__ void fused_body(const Prob &p, const int *__restrict__ off, int blk, int K, int mode,
                                            const float2 *__restrict__ H,
                                            const float2 *__restrict__ s, float2 *__restrict__ x,
                                            cx<float> *__restrict__ ainv_g, float *__restrict__ scale_out,
                                            int *__restrict__ status) {
     extern __shared__ float4 smem4[];
-    const int wave = threadIdx.x >> 6;
+    // the wave index is uniform: keep it (and the system's indices and base
+    // addresses) in scalar registers, so that the cluster offsets are scalar
+    // loads and no vector load has to be waited for before the channel loads
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int n_sys = p.arch == kPD ? p.n_sc : p.n_sc * p.C;
     const int sys = blk * NW + wave;
     if (sys >= n_sys) return;
     char *wb = (char *)smem4 + (size_t)wave * Lds<UP>::per_wave;
-    wave_system<UP, PREC, MAXT>(p, off, sys, K, mode, H, s, x, ainv_g, scale_out, status, (cx<float> *)wb,
+    wave_system<UP, PREC, MAXT, VEC>(p, off, sys, K, mode, H, s, x, ainv_g, scale_out, status, (cx<float> *)wb,
                                 (cx<float> *)(wb + Lds<UP>::zbytes));
 }
 
@@ -888,6 +943,9 @@ int system_tiles(const Prob &p) {
         for (int c = 0; c < p.C; ++c) r = p.off[c + 1] - p.off[c] > r ? p.off[c + 1] - p.off[c] : r;
     return (r + 31) >> 5;
 }
+
+// Whether the 16-byte tile loads apply (U == UP, 16-byte aligned channel).
+bool pick_vec(const Prob &p, const void *H) { return p.U == pick_up(p.U) && (((uintptr_t)H) & 15) == 0; }
 
 // Register tiles per wave for a problem: the next power of two of its
 // largest system's tiles, or 0 (stream) past max_tiles.
