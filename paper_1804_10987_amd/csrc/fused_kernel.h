@@ -727,14 +727,19 @@ __device__ __forceinline__ float load_factor(const cx<float> *__restrict__ g, in
     return wave_max(mx);
 }
 
+// Tiles in flight when a wave streams its rows (MAXT = 0).
+constexpr int kDepth = 4;
+
 // Channel tiles a wave may keep in registers (MAXT; 0 streams the rows twice).
-constexpr int max_tiles(int up) { return up == 16 ? 8 : 4; }
+// (More than 4 tiles of 16 users would spill at the occupancy the launch
+// needs; such systems stream.)
+constexpr int max_tiles(int up) { return 4; }
 
 // Minimum waves per SIMD the register allocation targets: more tiles held
 // in registers need more registers per wave.
 template <int UP, int MAXT, int PREC>
 constexpr int min_waves() {
-    if (UP == 16) return MAXT == 0 ? 3 : MAXT == 1 ? (PREC == kF32 ? 4 : 3) : MAXT == 2 ? 3 : 2;
+    if (UP == 16) return MAXT == 0 ? 2 : MAXT == 1 ? (PREC == kF32 ? 4 : 3) : MAXT == 2 ? 3 : 2;
     return MAXT == 1 ? 2 : 1;
 }
 
@@ -810,17 +815,25 @@ __device__ __forceinline__ void wave_system(const Prob &p, const int *__restrict
                 __builtin_amdgcn_sched_barrier(0);
             }
         } else {
-            GramBuf<UP> b0, b1;
-            gram_load<UP, PREC>(Hf, 2 * U, r0, min(32, r1 - r0), b0);
-            for (int t = 0; t < ntile; t += 2) {
-                const int r = r0 + 32 * t, ra = r + 32, rb = r + 64;
-                if (t + 1 < ntile) gram_load<UP, PREC>(Hf, 2 * U, ra, min(32, r1 - ra), b1);
-                gram_mask<UP, PREC>(b0, 2 * U, min(32, r1 - r));
-                gram_mma<UP, PREC>(b0, acc);
-                if (t + 1 < ntile) {
-                    if (t + 2 < ntile) gram_load<UP, PREC>(Hf, 2 * U, rb, min(32, r1 - rb), b0);
-                    gram_mask<UP, PREC>(b1, 2 * U, min(32, r1 - ra));
-                    gram_mma<UP, PREC>(b1, acc);
+            // ring of kDepth tile buffers: the loads of the next kDepth - 1
+            // tiles are in flight while a tile's MFMAs run (tile indices
+            // past the end reload the last tile: no branch around a load)
+            GramBuf<UP> ring[kDepth];
+#pragma unroll
+            for (int i = 0; i < kDepth - 1; ++i) {
+                const int ti = min(i, ntile - 1), r = r0 + 32 * ti;
+                gram_load<UP, PREC>(Hf, 2 * U, r, min(32, r1 - r), ring[i]);
+            }
+            for (int t = 0; t < ntile; t += kDepth) {
+#pragma unroll
+                for (int i = 0; i < kDepth; ++i) {
+                    const int tl = min(t + i + kDepth - 1, ntile - 1), rl = r0 + 32 * tl;
+                    gram_load<UP, PREC>(Hf, 2 * U, rl, min(32, r1 - rl), ring[(i + kDepth - 1) % kDepth]);
+                    if (t + i < ntile) {
+                        const int r = r0 + 32 * (t + i);
+                        gram_mask<UP, PREC>(ring[i], 2 * U, min(32, r1 - r));
+                        gram_mma<UP, PREC>(ring[i], acc);
+                    }
                 }
             }
         }
@@ -875,15 +888,22 @@ __device__ __forceinline__ void wave_system(const Prob &p, const int *__restrict
             wave_sync();
             continue;
         }
-        Tile<UP, PREC> ta, tb;
-        load_tile<UP, PREC, VEC>(Hn, U, r0, min(32, r1 - r0), ta);
-        for (int t = 0; t < ntile; t += 2) {
-            const int ra = r0 + 32 * t, rb = r0 + 32 * (t + 1), rc = r0 + 32 * (t + 2);
-            if (t + 1 < ntile) load_tile<UP, PREC, VEC>(Hn, U, rb, min(32, r1 - rb), tb);
-            store_x(mfma_apply_tile<UP, PREC>(ta, z), ra, min(32, r1 - ra), k0, kc, n, n_sc, B, x);
-            if (t + 1 < ntile) {
-                if (t + 2 < ntile) load_tile<UP, PREC, VEC>(Hn, U, rc, min(32, r1 - rc), ta);
-                store_x(mfma_apply_tile<UP, PREC>(tb, z), rb, min(32, r1 - rb), k0, kc, n, n_sc, B, x);
+        // the rows streamed again through a ring of kDepth tiles
+        Tile<UP, PREC> ring[kDepth];
+#pragma unroll
+        for (int i = 0; i < kDepth - 1; ++i) {
+            const int ti = min(i, ntile - 1), r = r0 + 32 * ti;
+            load_tile<UP, PREC, VEC>(Hn, U, r, min(32, r1 - r), ring[i]);
+        }
+        for (int t = 0; t < ntile; t += kDepth) {
+#pragma unroll
+            for (int i = 0; i < kDepth; ++i) {
+                const int tl = min(t + i + kDepth - 1, ntile - 1), rl = r0 + 32 * tl;
+                load_tile<UP, PREC, VEC>(Hn, U, rl, min(32, r1 - rl), ring[(i + kDepth - 1) % kDepth]);
+                if (t + i < ntile) {
+                    const int r = r0 + 32 * (t + i);
+                    store_x(mfma_apply_tile<UP, PREC>(ring[i], z), r, min(32, r1 - r), k0, kc, n, n_sc, B, x);
+                }
             }
         }
         wave_sync();  // Zw is rewritten by the next chunk
