@@ -739,7 +739,7 @@ constexpr int max_tiles(int up) { return 4; }
 // in registers need more registers per wave.
 template <int UP, int MAXT, int PREC>
 constexpr int min_waves() {
-    if (UP == 16) return MAXT == 0 ? 2 : MAXT == 1 ? (PREC == kF32 ? 4 : 3) : MAXT == 2 ? 3 : 2;
+    if (UP == 16) return MAXT == 0 ? 2 : MAXT == 1 ? (PREC == kF32 ? 4 : 3) : MAXT == 2 ? (PREC == kF32 ? 3 : 2) : 2;
     return MAXT == 1 ? 2 : 1;
 }
 
@@ -824,16 +824,17 @@ __device__ __forceinline__ void wave_system(const Prob &p, const int *__restrict
                 const int ti = min(i, ntile - 1), r = r0 + 32 * ti;
                 gram_load<UP, PREC>(Hf, 2 * U, r, min(32, r1 - r), ring[i]);
             }
+            // the loop body is one basic block (tiles past the end are
+            // masked to zero, not skipped): the compiler then waits for each
+            // tile's loads only, not for every load at the loop head
             for (int t = 0; t < ntile; t += kDepth) {
 #pragma unroll
                 for (int i = 0; i < kDepth; ++i) {
                     const int tl = min(t + i + kDepth - 1, ntile - 1), rl = r0 + 32 * tl;
                     gram_load<UP, PREC>(Hf, 2 * U, rl, min(32, r1 - rl), ring[(i + kDepth - 1) % kDepth]);
-                    if (t + i < ntile) {
-                        const int r = r0 + 32 * (t + i);
-                        gram_mask<UP, PREC>(ring[i], 2 * U, min(32, r1 - r));
-                        gram_mma<UP, PREC>(ring[i], acc);
-                    }
+                    const int r = r0 + 32 * (t + i);
+                    gram_mask<UP, PREC>(ring[i], 2 * U, t + i < ntile ? min(32, r1 - r) : 0);
+                    gram_mma<UP, PREC>(ring[i], acc);
                 }
             }
         }
@@ -900,10 +901,11 @@ __device__ __forceinline__ void wave_system(const Prob &p, const int *__restrict
             for (int i = 0; i < kDepth; ++i) {
                 const int tl = min(t + i + kDepth - 1, ntile - 1), rl = r0 + 32 * tl;
                 load_tile<UP, PREC, VEC>(Hn, U, rl, min(32, r1 - rl), ring[(i + kDepth - 1) % kDepth]);
-                if (t + i < ntile) {
-                    const int r = r0 + 32 * (t + i);
-                    store_x(mfma_apply_tile<UP, PREC>(ring[i], z), r, min(32, r1 - r), k0, kc, n, n_sc, B, x);
-                }
+                // no branch around the product (see the Gram ring); a tile
+                // past the end stores no rows
+                const int r = r0 + 32 * (t + i);
+                store_x(mfma_apply_tile<UP, PREC>(ring[i], z), r, t + i < ntile ? min(32, r1 - r) : 0, k0, kc, n,
+                        n_sc, B, x);
             }
         }
         wave_sync();  // Zw is rewritten by the next chunk
