@@ -93,7 +93,7 @@ __global__ void __launch_bounds__(64 * NW, (min_waves<UP, MAXT, PREC>()))
         else hi = mid - 1;
     }
     const Entry &E = tab[lo];
-    fused_body<UP, PREC, NW, MAXT, VEC>(E.p, E.p.off, b - E.block0, E.K, kFull, E.H, E.s, E.x, nullptr, E.scale_out,
+    fused_body<UP, PREC, NW, MAXT, VEC, false>(E.p, E.p.off, b - E.block0, E.K, kFull, E.H, E.s, E.x, nullptr, E.scale_out,
                                    E.status);
 }
 
@@ -116,9 +116,7 @@ hipError_t launch_v(int maxt, const Entry *tab, int n, int blocks, hipStream_t s
         case 1: return launch<UP, PREC, 1, VEC>(tab, n, blocks, st);
         case 2: return launch<UP, PREC, 2, VEC>(tab, n, blocks, st);
         case 4: return launch<UP, PREC, 4, VEC>(tab, n, blocks, st);
-        default:
-            if constexpr (max_tiles(UP) >= 8) return launch<UP, PREC, 8, VEC>(tab, n, blocks, st);
-            return hipErrorNotSupported;
+        default: return hipErrorNotSupported;
     }
 }
 

@@ -88,6 +88,16 @@ hipError_t run_once(int nw, const Prob &p, int prec, int mode, int K, const floa
     a.mode = mode;
     a.maxt = env_int("PRECODE_FUSED_STREAM", 0) ? 0 : pick_maxt(p);
     a.vec = pick_vec(p, H);
+    // a PD system too large for one wave's registers: the waves of a
+    // workgroup share the subcarrier instead of streaming its rows
+    a.split = false;
+    if (a.maxt == 0 && nw >= 2 && !env_int("PRECODE_FUSED_STREAM", 0)) {
+        const int m = pick_split_maxt(p, nw);
+        if (m > 0) {
+            a.split = true;
+            a.maxt = m;
+        }
+    }
     a.H = H;
     a.s = s;
     a.x = x;

@@ -912,6 +912,124 @@ __device__ __forceinline__ void wave_system(const Prob &p, const int *__restrict
     }
 }
 
+// ---- one PD subcarrier per workgroup (split over the rows) ----------------------
+// For PD systems too large for one wave's registers: the NW waves of a
+// workgroup share subcarrier blk.  Wave w keeps the channel tiles t = w,
+// w + NW, ... (MAXT of them) in registers from the first load to the
+// precode (all loads issued up front), forms their partial Gram (the split
+// rows are the cluster sum of the adder tree in another order), and all
+// partials are summed in LDS in fixed wave order.  One master wave, rotating
+// with the block index so co-resident workgroups use different SIMDs,
+// factors and solves; every wave then precodes its own rows.
+template <int UP, int PREC, int NW, int MAXT, bool VEC>
+__device__ __forceinline__ void wg_pd_split(const Prob &p, int blk, int K, int mode, const float2 *__restrict__ H,
+                                            const float2 *__restrict__ s, float2 *__restrict__ x,
+                                            cx<float> *__restrict__ ainv_g, float *__restrict__ scale_out,
+                                            int *__restrict__ status, char *lds) {
+    constexpr int SLOT = Shape<UP>::SLOT;
+    constexpr int NTT = Shape<UP>::NTT;
+    constexpr int LDc = Shape<UP>::LDc;
+    constexpr int NT = 64 * NW;
+    __shared__ float sh_scale, sh_amax;
+    __shared__ int sh_ok;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int mw = blk % NW;
+    const int B = p.B, U = p.U, n_sc = p.n_sc, n = blk;
+    const int ntile = (B + 31) >> 5;
+    const float2 *Hn = H + (size_t)n * B * U;
+    auto zw_of = [&](int w) { return (cx<float> *)(lds + (size_t)w * Lds<UP>::per_wave); };
+    auto slot_of = [&](int w) { return (cx<float> *)(lds + (size_t)w * Lds<UP>::per_wave + Lds<UP>::zbytes); };
+    cx<float> *Zm = zw_of(mw), *Am = slot_of(mw);
+    cx<float> *fac = ainv_g ? ainv_g + (size_t)n * U * U : nullptr;
+
+    Tile<UP, PREC> tiles[MAXT];
+#pragma unroll
+    for (int q = 0; q < MAXT; ++q) {
+        const int tt = wave + NW * q;
+        const bool v = tt < ntile;
+        load_tile<UP, PREC, VEC>(Hn, U, v ? 32 * tt : 0, v ? min(32, B - 32 * tt) : 0, tiles[q]);
+    }
+    const float kap = pd_kappa(p);
+    if (mode == kSymbols) {
+        if (wave == mw) {
+            const float amax = load_factor<UP>(fac, U, Am);
+            if (lane == 0) {
+                sh_scale = 1.f;
+                sh_amax = amax;
+                sh_ok = 1;
+            }
+        }
+    } else {
+        floatx16 acc[NTT];
+#pragma unroll
+        for (int q = 0; q < NTT; ++q) acc[q] = floatx16{0};
+        float *scr = (float *)zw_of(wave);
+#pragma unroll
+        for (int q = 0; q < MAXT; ++q) {
+            const int tt = wave + NW * q;
+            if (tt < ntile) {
+                GramBuf<UP> b;
+                tile_to_gram<UP, PREC>(tiles[q], min(32, B - 32 * tt), U, scr, b);
+                gram_mma<UP, PREC>(b, acc);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        cx<float> *part = slot_of(wave);
+        for (int e = lane; e < SLOT; e += 64) part[e] = {0.f, 0.f};
+        wave_sync();
+        gram_store<UP>(acc, part, 1.f, 0.f, U);
+        __syncthreads();
+        // partial sums in fixed wave order, + kappa I, into the master's slot
+        // (each entry is read and written by one thread)
+        for (int e = tid; e < UP * UP; e += NT) {
+            const int o = (e / UP) * LDc + (e % UP);
+            cx<float> sum = slot_of(0)[o];
+#pragma unroll
+            for (int w = 1; w < NW; ++w) sum = cadd(sum, slot_of(w)[o]);
+            if (e / UP == e % UP && e / UP < U) sum.re += kap;
+            Am[o] = sum;
+        }
+        __syncthreads();
+        if (wave == mw) {
+            float tr = 0.f, amax = 0.f;
+            const bool ok = wave_factor<UP>(Am, U, kap, &tr, &amax);
+            const float beta = ok ? sqrtf(p.Es / p.power * tr) : 0.f;
+            if (lane == 0) {
+                sh_scale = ok ? 1.f / beta : 0.f;
+                sh_amax = amax;
+                sh_ok = ok;
+                if (scale_out) scale_out[n] = beta;
+                if (status) status[n] = ok ? PRECODE_ST_OK : PRECODE_ST_FAIL;
+            }
+            if (mode == kPrepare) store_factor<UP>(Am, U, ok ? 1.f / beta : 0.f, fac);
+        }
+        if (mode == kPrepare) return;
+    }
+    __syncthreads();
+    for (int k0 = 0; k0 < K; k0 += KC) {
+        const int kc = min(KC, K - k0);
+        if (wave == mw) {
+            SymRaw<UP> sym;
+            load_sym<UP>(s + ((size_t)k0 * n_sc + n) * U, (size_t)n_sc * U, U, kc, sym);
+            ZOp<UP, PREC> zs;
+            sym_to_zop<UP, PREC>(sym, U, kc, zs);
+            wave_solve_chunk<UP, PREC>(Am, Zm, zs, kc, U, sh_scale, sh_amax, sh_ok != 0);
+        }
+        __syncthreads();
+        ZOp<UP, PREC> z;
+        make_zop<UP, PREC>(Zm, KC, 1, kc, z);
+#pragma unroll
+        for (int q = 0; q < MAXT; ++q) {
+            const int tt = wave + NW * q;
+            if (tt < ntile)
+                store_x(mfma_apply_tile<UP, PREC>(tiles[q], z), 32 * tt, min(32, B - 32 * tt), k0, kc, n, n_sc, B, x);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        __syncthreads();  // Zm is rewritten by the next chunk
+    }
+}
+
 // ---- the kernel body -----------------------------------------------------------
 // Workgroups of NW waves; wave w of block blk runs system blk * NW + w (PD:
 // consecutive subcarriers; FD: consecutive clusters of a subcarrier).
@@ -919,13 +1037,19 @@ __device__ __forceinline__ void wave_system(const Prob &p, const int *__restrict
 // MAXT: channel tiles (32 rows) of the largest system that a wave keeps in
 // registers (0: the precode streams the rows a second time).  VEC: U == UP
 // and a 16-byte aligned channel (wider loads).
-template <int UP, int PREC, int NW, int MAXT, bool VEC>
+// SPLIT (PD only): one subcarrier per workgroup, MAXT tiles per wave
+// (wg_pd_split); otherwise one system per wave.
+template <int UP, int PREC, int NW, int MAXT, bool VEC, bool SPLIT>
 __device__ __forceinline__ void fused_body(const Prob &p, const int *__restrict__ off, int blk, int K, int mode,
                                            const float2 *__restrict__ H,
                                            const float2 *__restrict__ s, float2 *__restrict__ x,
                                            cx<float> *__restrict__ ainv_g, float *__restrict__ scale_out,
                                            int *__restrict__ status) {
     extern __shared__ float4 smem4[];
+    if constexpr (SPLIT) {
+        wg_pd_split<UP, PREC, NW, MAXT, VEC>(p, blk, K, mode, H, s, x, ainv_g, scale_out, status, (char *)smem4);
+        return;
+    }
     // the wave index is uniform: keep it (and the system's indices and base
     // addresses) in scalar registers, so that the cluster offsets are scalar
     // loads and no vector load has to be waited for before the channel loads
@@ -949,8 +1073,9 @@ int prec_of(int precision) {
     }
 }
 
-// Workgroups of nw waves a problem's launch needs.
-int blocks_for(const Prob &p, int nw) {
+// Workgroups of nw waves a problem's launch needs (split: one per subcarrier).
+int blocks_for(const Prob &p, int nw, bool split = false) {
+    if (split) return p.n_sc;
     const long long ns = p.arch == kPD ? (long long)p.n_sc : (long long)p.n_sc * p.C;
     return (int)((ns + nw - 1) / nw);
 }
@@ -968,6 +1093,16 @@ int system_tiles(const Prob &p) {
 
 // Whether the 16-byte tile loads apply (U == UP, 16-byte aligned channel).
 bool pick_vec(const Prob &p, const void *H) { return p.U == pick_up(p.U) && (((uintptr_t)H) & 15) == 0; }
+
+// Split launch for a PD problem whose rows do not fit one wave's registers:
+// tiles per wave with nw waves per subcarrier, or 0 if they do not fit either.
+int pick_split_maxt(const Prob &p, int nw) {
+    if (p.arch != kPD) return 0;
+    const int t = (system_tiles(p) + nw - 1) / nw, lim = max_tiles(pick_up(p.U));
+    int m = 1;
+    while (m < t) m <<= 1;
+    return m <= lim ? m : 0;
+}
 
 // Register tiles per wave for a problem: the next power of two of its
 // largest system's tiles, or 0 (stream) past max_tiles.

@@ -11,6 +11,7 @@ struct FusedCall {
     int K, mode;  // symbols in this launch; kFull / kPrepare / kSymbols
     int maxt;     // channel tiles per wave held in registers (0: streamed)
     bool vec;     // U == tile width and a 16-byte aligned channel
+    bool split;   // PD: one subcarrier per workgroup, maxt tiles per wave
     const float2 *H, *s;
     float2 *x;
     cx<float> *ainv;  // per-instance factors (prepare / symbols modes)
