@@ -85,6 +85,9 @@ CASES = [
     ("k70", synth.Cell(B=64, sizes=(32, 32), U=8, n_sc=6, K=70), "wf"),
     ("many_clusters", synth.Cell(B=96, sizes=(12,) * 8, U=6, n_sc=11, K=14, qam=64), "wf"),
     ("u20_kron", synth.Cell(B=160, sizes=(40, 40, 80), U=20, n_sc=13, K=17, channel="kron", r=0.5), "wf"),
+    # PD rows past one wave's registers: split over the waves of a workgroup
+    ("b256", synth.Cell(B=256, sizes=(32,) * 8, U=16, n_sc=20, K=14), "wf"),
+    ("b300_ragged", synth.Cell(B=300, sizes=(100, 200), U=12, n_sc=9, K=19, snr_db=5.0), "wf"),
 ]
 
 
@@ -273,6 +276,46 @@ def test_refinement_fp64_residual(torch, ctx, pc, arch, cell, ratio, envelope):
         _check(x1.cpu().numpy(), scg1, st1.cpu().numpy().reshape(sto.shape), xo, sco, sto)
 
 
+@pytest.mark.parametrize("nw", [1, 2, 4])
+@pytest.mark.parametrize("name", ["cfg1", "ragged", "u32", "u20_kron", "many_clusters", "k70", "b256",
+                                  "b300_ragged"])
+def test_launch_shapes(torch, ctx, pc, monkeypatch, nw, name):
+    """Every launch shape the autotuner may pick, forced: one system per wave
+    in workgroups of 1, 2 or 4 waves, and (PD rows past one wave's registers)
+    a subcarrier split over the 2 or 4 waves of a workgroup; plus the
+    streamed rows."""
+    _, cell, mode = next(c for c in CASES if c[0] == name)
+    monkeypatch.setenv("PRECODE_FUSED_WAVES", str(nw))
+    H, s = synth.make_cell(cell, seed=11)
+    Hd, sd = _dev(torch, H), _dev(torch, s)
+    for stream in ("0", "1"):
+        monkeypatch.setenv("PRECODE_FUSED_STREAM", stream)
+        for arch in ("pd", "fd"):
+            fn = ctx.pd if arch == "pd" else ctx.fd
+            x, sc, st = fn(Hd, sd, cell.kappa, cell.sizes, mode, pc.params(fp64_ratio=2.0))
+            torch.cuda.synchronize()
+            if ctx.last_impl != "fused":
+                continue
+            print("%s %s nw=%d stream=%s used=%d" % (name, arch, nw, stream, ctx.last_waves), flush=True)
+            xo, sco, sto = _oracle(arch, H, s, cell.kappa, cell.sizes, mode)
+            _check(x.cpu().numpy(), sc.cpu().numpy().reshape(sco.shape), st.cpu().numpy().reshape(sto.shape),
+                   xo, sco, sto)
+
+
+def test_autotuned_shape_is_cached_and_deterministic(torch, ctx, pc, monkeypatch):
+    monkeypatch.delenv("PRECODE_FUSED_WAVES", raising=False)
+    monkeypatch.setenv("PRECODE_AUTOTUNE", "1")
+    cell = synth.Cell(B=256, sizes=(32,) * 8, U=16, n_sc=300, K=14)
+    H, s = synth.make_cell(cell, seed=12)
+    Hd, sd = _dev(torch, H), _dev(torch, s)
+    x1, _, _ = ctx.pd(Hd, sd, cell.kappa, cell.sizes)
+    w1 = ctx.last_waves
+    x2, _, _ = ctx.pd(Hd, sd, cell.kappa, cell.sizes)
+    torch.cuda.synchronize()
+    assert w1 in (1, 2, 4) and ctx.last_waves == w1
+    assert torch.equal(x1, x2)
+
+
 # Mixed batch spanning every launch class and the plain fallback: tile widths
 # 16 / 32, PD / FD, 1..8 channel tiles per wave, symbol slicing (K > 64),
 # FD clusters smaller than U and U > 32 (plain kernels), an empty job.
@@ -301,8 +344,9 @@ def _mix_jobs(torch, cells, seed=40):
 
 
 def test_batch_mixed_classes(torch, ctx, pc, monkeypatch):
-    # the batch launches use 4 waves per workgroup: compare with that shape
-    monkeypatch.setenv("PRECODE_FUSED_WAVES", "4")
+    # the batch launches run one system per wave: compare with single calls
+    # in that mode (one wave per workgroup never splits a subcarrier)
+    monkeypatch.setenv("PRECODE_FUSED_WAVES", "1")
     jobs, host = _mix_jobs(torch, MIX)
     outs = ctx.batch(jobs)
     torch.cuda.synchronize()
