@@ -151,7 +151,8 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "fused_k<16, PD>",
+            "kernel": "fused_k (FP32, one PD subcarrier per workgroup of %d waves)" % ctx.last_waves
+                      if ctx.last_waves > 1 else "fused_k (FP32, one PD subcarrier per wave)",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
