@@ -28,6 +28,35 @@ HBM_PEAK_GBS = 8000.0
 LLC_BYTES = 256 << 20
 
 
+PROFILE = os.path.join(ROOT, "profiles", "fused_pd_b256_u16_n1200.md")
+KERNEL_SOURCES = ["fused_kernel.h", "fused_nw.inc", "fused_launch.h", "fused.hip", "common.h"]
+
+
+def kernel_digest():
+    """First 16 hex digits of the sha256 of the fused kernel's sources."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1804_10987_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the headline kernel from the committed
+    rocprofv3 counter summary, or None when the kernel's sources changed
+    since those counters were taken (or there is no summary)."""
+    try:
+        fields = dict(l.split(": ", 1) for l in open(PROFILE).read().splitlines() if ": " in l and
+                      l.split(": ", 1)[0] in ("traffic_bytes_per_launch", "kernel_source_digest", "traffic_kernel"))
+    except OSError:
+        return None, None
+    if fields.get("kernel_source_digest", "").strip() != kernel_digest():
+        return None, None
+    return int(fields["traffic_bytes_per_launch"]), fields.get("traffic_kernel", "").strip()
+
+
 def algorithmic_bytes(B, U, K, n_sc):
     """HBM bytes the method must move per frame: the channel once, the symbols
     and the precoded vectors once (complex64)."""
@@ -159,6 +188,10 @@ def main():
     value = n_sc * K / (ms * 1e-3)
     launch_ms = ms
     achieved = frame_bytes / (launch_ms * 1e-3) / 1e9
+    traffic, traffic_kernel = measured_traffic()
+    traffic_src = ("rocprofv3 FETCH_SIZE + WRITE_SIZE of %s, scaled by a copy kernel's counts; %s"
+                   % (traffic_kernel, os.path.relpath(PROFILE, ROOT))) if traffic else \
+        "no counters for the current kernel sources"
     # per-frame latency of eager calls (host enqueue included)
     _, per = time_path(pd_fused, max(20, args.steps // 4), 2)
     per = np.array(per)
@@ -192,7 +225,8 @@ def main():
             "frac": achieved / HBM_PEAK_GBS,
             "algorithmic_bytes_per_launch": frame_bytes,
             "launch_ms": launch_ms,
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_source": traffic_src,
         },
         "latency": {"eager_frame_p50_ms": float(np.percentile(per, 50)),
                     "eager_frame_p99_ms": float(np.percentile(per, 99)),
