@@ -3,7 +3,7 @@
 // the kernel's shape classes allow.
 //
 // Problems are grouped by tile width UP (16 for U <= 16, 32 for U <= 32) and
-// channel tiles per wave held in registers (1, 2, 4, 8 or streamed) and load
+// channel tiles per wave held in registers (1, 2, 4 or streamed) and load
 // width (U == UP with an aligned channel, or not); each
 // group -- PD and FD problems alike -- is one launch whose grid is the sum of
 // its problems' workgroups (one wave per local system, NW systems per
