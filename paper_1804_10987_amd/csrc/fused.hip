@@ -29,8 +29,12 @@
 //               the cache) in the row layout of the product and the results
 //               stored coalesced
 //
-// Launch shape: NW = 1, 2 or 4 waves (systems) per workgroup
-// (fused_nw{1,2,4}.hip).  The autotuner times every feasible NW on the first
+// Launch shape: NW = 1, 2 or 4 waves per workgroup (fused_nw{1,2,4}.hip),
+// each wave one system.  For PD with NW >= 2 whose rows do not fit one wave's
+// registers, the NW waves instead share one subcarrier (split): each keeps
+// its share of the channel tiles in registers from load to precode, the
+// partial Grams are summed in LDS in fixed wave order, and one master wave
+// factors and solves.  The autotuner times every feasible NW on the first
 // call of each problem shape (the call itself, repeated) and caches the
 // fastest for the process.
 //

@@ -397,43 +397,81 @@ __device__ __forceinline__ floatx16 mfma_apply(const float *rows, int rs, int nv
 __device__ __forceinline__ int tile_k(int r, int g) { return 4 * (r / 4) + 2 * g + ((r % 4) >> 1); }
 
 // ---- inversion ----------------------------------------------------------------
-// Broadcast within the lanes of one matrix row of the register layout below:
-// lane (r, c) receives the value of lane (r, k).  For UP = 16 a row is a DPP
-// row of 16 lanes (row_newbcast); for UP = 32 it is a half-wave.
-template <int UP, int k>
-__device__ __forceinline__ float bcast_row(float v) {
-    if constexpr (UP == 16) {
-        return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x150 + k, 0xf,
-                                                                      0xf, false));
-    } else {
-        return __shfl(v, (lane_id() & ~(UP - 1)) | k);
+// Register layout of an UP x UP system: lane (r, c) = (lane / UP, lane % UP)
+// holds column c of rows i = s*R + r (R = 64 / UP row groups, NS = UP / R
+// slots).  For UP = 16 a row group is one DPP row of 16 lanes; for UP = 32 it
+// is a half-wave (two DPP rows).  The broadcasts below move register data
+// only (DPP and the gfx950 permlane swaps): no LDS round trip.
+
+__device__ __forceinline__ unsigned fbits(float v) { return __builtin_bit_cast(unsigned, v); }
+__device__ __forceinline__ float ffrom(unsigned v) { return __builtin_bit_cast(float, v); }
+
+// Lane l receives v of lane 16 (l / 16) + k (DPP row_newbcast).
+template <int k>
+__device__ __forceinline__ float dpp_bcast16(float v) {
+    return ffrom(__builtin_amdgcn_mov_dpp((int)fbits(v), 0x150 + k, 0xf, 0xf, true));
+}
+
+__device__ __forceinline__ float dpp_bcast16_dyn(float v, int k) {
+    switch (k) {
+        case 0: return dpp_bcast16<0>(v);
+        case 1: return dpp_bcast16<1>(v);
+        case 2: return dpp_bcast16<2>(v);
+        case 3: return dpp_bcast16<3>(v);
+        case 4: return dpp_bcast16<4>(v);
+        case 5: return dpp_bcast16<5>(v);
+        case 6: return dpp_bcast16<6>(v);
+        case 7: return dpp_bcast16<7>(v);
+        case 8: return dpp_bcast16<8>(v);
+        case 9: return dpp_bcast16<9>(v);
+        case 10: return dpp_bcast16<10>(v);
+        case 11: return dpp_bcast16<11>(v);
+        case 12: return dpp_bcast16<12>(v);
+        case 13: return dpp_bcast16<13>(v);
+        case 14: return dpp_bcast16<14>(v);
+        default: return dpp_bcast16<15>(v);
     }
 }
 
+// permlane16_swap(v, v) gives {[r0, r0, r2, r2], [r1, r1, r3, r3]} over the
+// four DPP rows r0..r3 of v; permlane32_swap(v, v) gives {[lo, lo], [hi, hi]}
+// over the two half-waves.
+__device__ __forceinline__ float even_rows16(float v, bool odd) {
+    const auto p = __builtin_amdgcn_permlane16_swap(fbits(v), fbits(v), false, false);
+    return ffrom(odd ? p[1] : p[0]);
+}
+__device__ __forceinline__ float half32(float v, bool hi) {
+    const auto q = __builtin_amdgcn_permlane32_swap(fbits(v), fbits(v), false, false);
+    return ffrom(hi ? q[1] : q[0]);
+}
+
+// Within each row group: lane (r, c) receives the value of lane (r, k).
+// k is a constant after unrolling.
 template <int UP>
-__device__ __forceinline__ float bcast_row_dyn(float v, int k) {
+__device__ __forceinline__ float bcast_col(float v, int k) {
     if constexpr (UP == 16) {
-        switch (k) {
-            case 0: return bcast_row<16, 0>(v);
-            case 1: return bcast_row<16, 1>(v);
-            case 2: return bcast_row<16, 2>(v);
-            case 3: return bcast_row<16, 3>(v);
-            case 4: return bcast_row<16, 4>(v);
-            case 5: return bcast_row<16, 5>(v);
-            case 6: return bcast_row<16, 6>(v);
-            case 7: return bcast_row<16, 7>(v);
-            case 8: return bcast_row<16, 8>(v);
-            case 9: return bcast_row<16, 9>(v);
-            case 10: return bcast_row<16, 10>(v);
-            case 11: return bcast_row<16, 11>(v);
-            case 12: return bcast_row<16, 12>(v);
-            case 13: return bcast_row<16, 13>(v);
-            case 14: return bcast_row<16, 14>(v);
-            default: return bcast_row<16, 15>(v);
-        }
+        return dpp_bcast16_dyn(v, k);
     } else {
-        return __shfl(v, (lane_id() & ~(UP - 1)) | k);
+        return even_rows16(dpp_bcast16_dyn(v, k & 15), k >= 16);
     }
+}
+
+// Across row groups: lane (r, c) receives the value of lane (rk, c).
+template <int UP>
+__device__ __forceinline__ float bcast_group(float v, int rk) {
+    if constexpr (UP == 16) {
+        return half32(even_rows16(v, rk & 1), rk >= 2);
+    } else {
+        return half32(v, rk != 0);
+    }
+}
+
+// Across row groups through the LDS crossbar (ds_bpermute, no memory
+// access): lane (r, c) receives the value of lane (rk, c).  Fewer VALU slots
+// than bcast_group; its latency is hidden when issued ahead of use.
+template <int UP>
+__device__ __forceinline__ float bperm_group(float v, int c4, int rk) {
+    return ffrom(__builtin_amdgcn_ds_bpermute(rk * UP * 4 + c4, (int)fbits(v)));
 }
 
 // In-register inversion of the m x m Hermitian positive-definite system held
@@ -442,14 +480,105 @@ __device__ __forceinline__ float bcast_row_dyn(float v, int k) {
 // every other row, so that after m steps the slot holds A^-1.  For a Hermitian
 // positive-definite A the pivots are the squared diagonal of its Cholesky
 // factor and need no row exchanges.
-// Layout: lane (r, c) = (lane / UP, lane % UP) holds column c, rows
-// i = s*R + r (R = 64 / UP row groups, NS = UP / R slots).  Row k reaches every
-// lane through a bpermute, column k through bcast_row, the pivot through
-// readlane.  Returns false when a pivot is not finite or not above kRelPivot32
+// Per step and slot the update a_ic -= a_ik * mult_c is four fused
+// multiply-adds whose a_ik operand is a DPP broadcast of column k; they are
+// ordered so that each reads column k before this step changes it (mult_k is
+// real, so the first two leave column k as it was).  Row k + 1 is fetched
+// (bperm_group) as soon as its slot is updated, ahead of the other slots.
+// Returns false when a pivot is not finite or not above kRelPivot32 times its
+// original diagonal entry (numerically singular; a NaN pivot fails the test
+// too).  On success writes A^-1 back to the slot and returns tr A^-1, ||A^-1||_F^2 and max |A^-1_ij|.
+template <int UP>
+__device__ bool wave_inverse(cx<float> *S, int m, float *tr_out, float *fro_out, float *max_out) {
+    static_assert(UP == 16, "straight-line inversion: UP = 16 only");
+    constexpr int R = 64 / UP;
+    constexpr int NS = UP / R;
+    constexpr int LDc = Shape<UP>::LDc;
+    const int lane = lane_id();
+    const int r = lane / UP, c = lane % UP, c4 = 4 * c;
+    float re[NS], im[NS];
+    // rows and columns >= m are replaced by the identity, so that all UP
+    // steps run unconditionally (straight-line code the scheduler can overlap
+    // across steps) and leave the leading m x m block exactly as m steps would
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int i = s * R + r;
+        const cx<float> v = S[i * LDc + c];
+        const bool in = i < m && c < m;
+        re[s] = in ? v.re : (i == c ? 1.f : 0.f);
+        im[s] = in ? v.im : 0.f;
+    }
+    const float d0 = c < m ? S[c * LDc + c].re : 1.f;  // original diagonal entry of column c
+    float pv = 1.f;  // lane (r, c) keeps pivot c, checked against d0 after the last step
+    // row 0, column c
+    float akc_re = bperm_group<UP>(re[0], c4, 0);
+    float akc_im = bperm_group<UP>(im[0], c4, 0);
+#pragma unroll
+    for (int k = 0; k < UP; ++k) {
+        const int sk = k / R;  // slot of row k
+        const int rk = k % R;  // row group of row k
+        const float piv = bcast_col<UP>(akc_re, k);
+        const bool iscol = c == k;
+        pv = iscol ? piv : pv;
+        const float inv = __builtin_amdgcn_rcpf(piv);
+        // multiplier row: a_kc / a_kk for c != k and 1 + 1/a_kk for c = k,
+        // so that one update a_ic - a_ik * mult_c also turns column k into
+        // -a_ik / a_kk; row k itself becomes a_kc / a_kk (pivot 1/a_kk)
+        const float mre = iscol ? 1.f + inv : akc_re * inv;
+        const float mim = iscol ? 0.f : akc_im * inv;
+        const float rowre = iscol ? inv : mre, rowim = mim;
+        const float nmre = -mre, nmim = -mim;
+        const int k1 = k + 1, s1 = k1 / R;
+        auto update = [&](int s) {
+            float x = re[s], y = im[s];
+            y = fmaf(bcast_col<UP>(x, k), nmim, y);  // column k of y unchanged (mim_k = 0)
+            x = fmaf(bcast_col<UP>(y, k), mim, x);   // column k of x unchanged
+            y = fmaf(bcast_col<UP>(y, k), nmre, y);
+            x = fmaf(bcast_col<UP>(x, k), nmre, x);
+            if (s == sk) {
+                const bool isrow = r == rk;
+                x = isrow ? rowre : x;
+                y = isrow ? rowim : y;
+            }
+            re[s] = x;
+            im[s] = y;
+        };
+        if (k1 < UP) {
+            update(s1);
+            akc_re = bperm_group<UP>(re[s1], c4, k1 % R);
+            akc_im = bperm_group<UP>(im[s1], c4, k1 % R);
+        }
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+            if (k1 >= UP || s != s1) update(s);
+    }
+    // every pivot finite and above kRelPivot32 times its original diagonal entry
+    const bool ok = __all((pv > kRelPivot32 * d0) && (pv < INFINITY));
+    float tr = 0.f, fro = 0.f, mx = 0.f;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int i = s * R + r;
+        if (i < m && c < m) {
+            fro += re[s] * re[s] + im[s] * im[s];
+            mx = fmaxf(mx, fmaxf(fabsf(re[s]), fabsf(im[s])));
+            if (i == c) tr += re[s];
+        }
+        S[i * LDc + c] = {re[s], im[s]};
+    }
+    *tr_out = wave_sum(tr);
+    *fro_out = wave_sum(fro);
+    *max_out = wave_max(mx);
+    return ok;
+}
+
+// The same inversion for UP = 32 with one branch per step (a straight-line
+// body of 32 steps over 16 slots takes the compiler far too long inside the
+// larger kernels): row k reaches every lane through a bpermute, column k
+// through bcast_col, the pivot through readlane.  Returns false when a pivot is not finite or not above kRelPivot32
 // times the original diagonal entry (numerically singular).  On success writes
 // A^-1 back to the slot and returns tr A^-1, ||A^-1||_F^2 and max |A^-1_ij|.
 template <int UP>
-__device__ bool wave_inverse(cx<float> *S, int m, float *tr_out, float *fro_out, float *max_out) {
+__device__ bool wave_inverse_steps(cx<float> *S, int m, float *tr_out, float *fro_out, float *max_out) {
     constexpr int R = 64 / UP;
     constexpr int NS = UP / R;
     constexpr int LDc = Shape<UP>::LDc;
@@ -485,8 +614,8 @@ __device__ bool wave_inverse(cx<float> *S, int m, float *tr_out, float *fro_out,
             const float rowre = iscol ? inv : mre, rowim = mim;
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
-                const float aik_re = bcast_row_dyn<UP>(re[s], k);
-                const float aik_im = bcast_row_dyn<UP>(im[s], k);
+                const float aik_re = bcast_col<UP>(re[s], k);
+                const float aik_im = bcast_col<UP>(im[s], k);
                 const float nre = re[s] - (aik_re * mre - aik_im * mim);
                 const float nim = im[s] - (aik_re * mim + aik_im * mre);
                 if (s == sk) {
@@ -523,7 +652,11 @@ __device__ bool wave_inverse(cx<float> *S, int m, float *tr_out, float *fro_out,
 template <int UP>
 __device__ bool wave_factor(cx<float> *sA, int m, float kap, float *t_out, float *amax) {
     float tr = 0.f, fro = 0.f;
-    bool ok = wave_inverse<UP>(sA, m, &tr, &fro, amax);
+    bool ok;
+    if constexpr (UP == 16)
+        ok = wave_inverse<UP>(sA, m, &tr, &fro, amax);
+    else
+        ok = wave_inverse_steps<UP>(sA, m, &tr, &fro, amax);
     const float t = tr - kap * fro;
     ok = ok && (t > 0.f) && (t < INFINITY);
     wave_sync();
@@ -691,6 +824,8 @@ struct Lds {
     // transpose scratch overlays before either is written
     static constexpr size_t per_wave = zbytes + sbytes > tbytes ? zbytes + sbytes : tbytes;
     static __host__ __device__ constexpr size_t bytes(int nw) { return nw * per_wave; }
+    // the split kernel's raw partial Gram accumulators also fit per wave
+    static_assert(per_wave >= (size_t)Shape<UP>::NTT * 64 * 16 * 4, "raw Gram area");
 };
 
 // Kernel modes: the whole frame, the per-frame part only (factors to
@@ -926,10 +1061,7 @@ __device__ __forceinline__ void wg_pd_split(const Prob &p, int blk, int K, int m
                                             const float2 *__restrict__ s, float2 *__restrict__ x,
                                             cx<float> *__restrict__ ainv_g, float *__restrict__ scale_out,
                                             int *__restrict__ status, char *lds) {
-    constexpr int SLOT = Shape<UP>::SLOT;
     constexpr int NTT = Shape<UP>::NTT;
-    constexpr int LDc = Shape<UP>::LDc;
-    constexpr int NT = 64 * NW;
     __shared__ float sh_scale, sh_amax;
     __shared__ int sh_ok;
     const int tid = threadIdx.x, lane = tid & 63;
@@ -940,6 +1072,7 @@ __device__ __forceinline__ void wg_pd_split(const Prob &p, int blk, int K, int m
     const float2 *Hn = H + (size_t)n * B * U;
     auto zw_of = [&](int w) { return (cx<float> *)(lds + (size_t)w * Lds<UP>::per_wave); };
     auto slot_of = [&](int w) { return (cx<float> *)(lds + (size_t)w * Lds<UP>::per_wave + Lds<UP>::zbytes); };
+    auto raw_of = [&](int w) { return (float *)(lds + (size_t)w * Lds<UP>::per_wave); };
     cx<float> *Zm = zw_of(mw), *Am = slot_of(mw);
     cx<float> *fac = ainv_g ? ainv_g + (size_t)n * U * U : nullptr;
 
@@ -951,8 +1084,13 @@ __device__ __forceinline__ void wg_pd_split(const Prob &p, int blk, int K, int m
         load_tile<UP, PREC, VEC>(Hn, U, v ? 32 * tt : 0, v ? min(32, B - 32 * tt) : 0, tiles[q]);
     }
     const float kap = pd_kappa(p);
+    // the first chunk's symbols, loaded by the master while it factors
+    SymRaw<UP> sym0;
+    const bool pre_sym = mode != kPrepare && K > 0;
+    const float2 *s0 = s + (size_t)n * U;
     if (mode == kSymbols) {
         if (wave == mw) {
+            if (pre_sym) load_sym<UP>(s0, (size_t)n_sc * U, U, min(KC, K), sym0);
             const float amax = load_factor<UP>(fac, U, Am);
             if (lane == 0) {
                 sh_scale = 1.f;
@@ -975,23 +1113,38 @@ __device__ __forceinline__ void wg_pd_split(const Prob &p, int blk, int K, int m
             }
             __builtin_amdgcn_sched_barrier(0);
         }
-        cx<float> *part = slot_of(wave);
-        for (int e = lane; e < SLOT; e += 64) part[e] = {0.f, 0.f};
+        // every wave's partial accumulators, raw, to its LDS area; the master
+        // adds them in fixed wave order and stores G + kappa I into its slot
         wave_sync();
-        gram_store<UP>(acc, part, 1.f, 0.f, U);
-        __syncthreads();
-        // partial sums in fixed wave order, + kappa I, into the master's slot
-        // (each entry is read and written by one thread)
-        for (int e = tid; e < UP * UP; e += NT) {
-            const int o = (e / UP) * LDc + (e % UP);
-            cx<float> sum = slot_of(0)[o];
 #pragma unroll
-            for (int w = 1; w < NW; ++w) sum = cadd(sum, slot_of(w)[o]);
-            if (e / UP == e % UP && e / UP < U) sum.re += kap;
-            Am[o] = sum;
-        }
+        for (int q = 0; q < NTT; ++q)
+#pragma unroll
+            for (int r4 = 0; r4 < 4; ++r4)
+                *(float4 *)(raw_of(wave) + ((q * 4 + r4) * 64 + lane) * 4) =
+                    make_float4(acc[q][4 * r4], acc[q][4 * r4 + 1], acc[q][4 * r4 + 2], acc[q][4 * r4 + 3]);
         __syncthreads();
         if (wave == mw) {
+            if (pre_sym) load_sym<UP>(s0, (size_t)n_sc * U, U, min(KC, K), sym0);
+            floatx16 sum[NTT];
+#pragma unroll
+            for (int w = 0; w < NW; ++w)
+#pragma unroll
+                for (int q = 0; q < NTT; ++q)
+#pragma unroll
+                    for (int r4 = 0; r4 < 4; ++r4) {
+                        const float4 v = *(const float4 *)(raw_of(w) + ((q * 4 + r4) * 64 + lane) * 4);
+                        if (w == 0) {
+                            sum[q][4 * r4] = v.x, sum[q][4 * r4 + 1] = v.y;
+                            sum[q][4 * r4 + 2] = v.z, sum[q][4 * r4 + 3] = v.w;
+                        } else {
+                            sum[q][4 * r4] += v.x, sum[q][4 * r4 + 1] += v.y;
+                            sum[q][4 * r4 + 2] += v.z, sum[q][4 * r4 + 3] += v.w;
+                        }
+                    }
+            // the master's slot overlays raw areas: all reads above are done
+            wave_sync();
+            gram_store<UP>(sum, Am, 1.f, kap, U);
+            wave_sync();
             float tr = 0.f, amax = 0.f;
             const bool ok = wave_factor<UP>(Am, U, kap, &tr, &amax);
             const float beta = ok ? sqrtf(p.Es / p.power * tr) : 0.f;
@@ -1010,10 +1163,14 @@ __device__ __forceinline__ void wg_pd_split(const Prob &p, int blk, int K, int m
     for (int k0 = 0; k0 < K; k0 += KC) {
         const int kc = min(KC, K - k0);
         if (wave == mw) {
-            SymRaw<UP> sym;
-            load_sym<UP>(s + ((size_t)k0 * n_sc + n) * U, (size_t)n_sc * U, U, kc, sym);
             ZOp<UP, PREC> zs;
-            sym_to_zop<UP, PREC>(sym, U, kc, zs);
+            if (k0 == 0) {
+                sym_to_zop<UP, PREC>(sym0, U, kc, zs);
+            } else {
+                SymRaw<UP> sym;
+                load_sym<UP>(s + ((size_t)k0 * n_sc + n) * U, (size_t)n_sc * U, U, kc, sym);
+                sym_to_zop<UP, PREC>(sym, U, kc, zs);
+            }
             wave_solve_chunk<UP, PREC>(Am, Zm, zs, kc, U, sh_scale, sh_amax, sh_ok != 0);
         }
         __syncthreads();
