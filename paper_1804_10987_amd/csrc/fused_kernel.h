@@ -32,16 +32,55 @@ __device__ __forceinline__ float readlane_f(float v, int lane) {
     return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
 }
 
+__device__ __forceinline__ unsigned fbits(float v) { return __builtin_bit_cast(unsigned, v); }
+__device__ __forceinline__ float ffrom(unsigned v) { return __builtin_bit_cast(float, v); }
+
+// The two results of a gfx950 permlane swap of v with itself, as floats:
+// permlane16_swap gives [r0, r0, r2, r2] and [r1, r1, r3, r3] over the four
+// DPP rows r0..r3 of v; permlane32_swap gives [lo, lo] and [hi, hi] over the
+// two half-waves.  (The elements are copied out by value: a bit cast applied
+// directly to an element of the returned vector reads element 0.)
+__device__ __forceinline__ void swap16(float v, float &a, float &b) {
+    const auto p = __builtin_amdgcn_permlane16_swap(fbits(v), fbits(v), false, false);
+    const unsigned p0 = p[0], p1 = p[1];
+    a = ffrom(p0);
+    b = ffrom(p1);
+}
+__device__ __forceinline__ void swap32(float v, float &a, float &b) {
+    const auto q = __builtin_amdgcn_permlane32_swap(fbits(v), fbits(v), false, false);
+    const unsigned q0 = q[0], q1 = q[1];
+    a = ffrom(q0);
+    b = ffrom(q1);
+}
+
+// Wave-wide sum and max from DPP (within rows of 16 lanes) and the permlane
+// swaps (across rows), no LDS.  Every lane ends with the same bits: each step
+// adds a lane's value to its partner's, and both partners form the same
+// (commutative) sum.
+template <int CTRL>
+__device__ __forceinline__ float dpp_c(float v) {
+    return ffrom(__builtin_amdgcn_mov_dpp((int)fbits(v), CTRL, 0xf, 0xf, true));
+}
 __device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
+    v += dpp_c<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_c<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp_c<0x141>(v);  // row_half_mirror
+    v += dpp_c<0x140>(v);  // row_mirror
+    float a, b;
+    swap16(v, a, b);
+    swap32(a + b, a, b);
+    return a + b;
 }
 
 __device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
-    return v;
+    v = fmaxf(v, dpp_c<0xB1>(v));
+    v = fmaxf(v, dpp_c<0x4E>(v));
+    v = fmaxf(v, dpp_c<0x141>(v));
+    v = fmaxf(v, dpp_c<0x140>(v));
+    float a, b;
+    swap16(v, a, b);
+    swap32(fmaxf(a, b), a, b);
+    return fmaxf(a, b);
 }
 
 // Power-of-two exponent e with m * 2^e in [2^13, 2^14) (0 for m = 0): the
@@ -73,6 +112,16 @@ struct Split<kF16> {
             lo[e] = (_Float16)(x[e] - (float)h);
         }
     }
+    // hi = f16(x sc), lo = f16(x sc - hi), each one fused multiply-add with
+    // a single rounding to FP16 (x sc - hi is exact)
+    static __device__ __forceinline__ void split_scaled(const float *x, float sc, V &hi, V &lo) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const _Float16 h = (_Float16)fmaf(x[e], sc, 0.f);
+            hi[e] = h;
+            lo[e] = (_Float16)fmaf(x[e], sc, -(float)h);
+        }
+    }
     static __device__ __forceinline__ floatx16 mfma(V a, V b, floatx16 c) {
         return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
     }
@@ -89,6 +138,8 @@ struct Split<kBF16> {
             lo[e] = (__bf16)(x[e] - (float)h);
         }
     }
+    // BF16 has the FP32 exponent range: no scale is needed (sc = 1)
+    static __device__ __forceinline__ void split_scaled(const float *x, float, V &hi, V &lo) { split(x, hi, lo); }
     static __device__ __forceinline__ floatx16 mfma(V a, V b, floatx16 c) {
         return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
     }
@@ -159,10 +210,12 @@ __device__ __forceinline__ void gram_mask(GramBuf<UP> &b, int u2, int nrows) {
 }
 
 // acc[t] += real Gram of the buffered rows, t over the tile pairs ti <= tj.
-// 16-bit: the rows are scaled by a power of two into the FP16 range, split
-// hi + lo, and the tile's product is unscaled exactly into acc.
+// 16-bit: the rows are scaled by a power of two 2^e into the FP16 range
+// (BF16: e = 0), split hi + lo, and the tile's product is unscaled exactly
+// into acc.  Returns e (0 for FP32), which also suits the same rows in the
+// precode layout (their magnitudes are the same).
 template <int UP, int PREC>
-__device__ __forceinline__ void gram_mma(const GramBuf<UP> &b, floatx16 (&acc)[Shape<UP>::NTT]) {
+__device__ __forceinline__ int gram_mma(const GramBuf<UP> &b, floatx16 (&acc)[Shape<UP>::NTT]) {
     constexpr int NT = Shape<UP>::NT;
     constexpr int NTT = Shape<UP>::NTT;
     if constexpr (PREC == kF32) {
@@ -177,14 +230,18 @@ __device__ __forceinline__ void gram_mma(const GramBuf<UP> &b, floatx16 (&acc)[S
                     ++t;
                 }
         }
+        return 0;
     } else {
         typedef typename Split<PREC>::V V;
-        float m = 0.f;
+        int e2 = 0;
+        if constexpr (PREC == kF16) {
+            float m = 0.f;
 #pragma unroll
-        for (int ti = 0; ti < NT; ++ti)
+            for (int ti = 0; ti < NT; ++ti)
 #pragma unroll
-            for (int q = 0; q < 16; ++q) m = fmaxf(m, fabsf(b.v[ti][q]));
-        const int e2 = fp16_exp(wave_max(m));
+                for (int q = 0; q < 16; ++q) m = fmaxf(m, fabsf(b.v[ti][q]));
+            e2 = fp16_exp(wave_max(m));
+        }
         const float sc = ldexpf(1.f, e2);
         floatx16 part[NTT];
 #pragma unroll
@@ -193,12 +250,7 @@ __device__ __forceinline__ void gram_mma(const GramBuf<UP> &b, floatx16 (&acc)[S
         for (int s = 0; s < 2; ++s) {
             V hi[NT], lo[NT];
 #pragma unroll
-            for (int ti = 0; ti < NT; ++ti) {
-                float w[8];
-#pragma unroll
-                for (int e = 0; e < 8; ++e) w[e] = b.v[ti][8 * s + e] * sc;
-                Split<PREC>::split(w, hi[ti], lo[ti]);
-            }
+            for (int ti = 0; ti < NT; ++ti) Split<PREC>::split_scaled(&b.v[ti][8 * s], sc, hi[ti], lo[ti]);
             int t = 0;
 #pragma unroll
             for (int ti = 0; ti < NT; ++ti)
@@ -213,6 +265,7 @@ __device__ __forceinline__ void gram_mma(const GramBuf<UP> &b, floatx16 (&acc)[S
         for (int t = 0; t < NTT; ++t)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[t][r] = fmaf(part[t][r], un, acc[t][r]);
+        return e2;
     }
 }
 
@@ -403,9 +456,6 @@ __device__ __forceinline__ int tile_k(int r, int g) { return 4 * (r / 4) + 2 * g
 // is a half-wave (two DPP rows).  The broadcasts below move register data
 // only (DPP and the gfx950 permlane swaps): no LDS round trip.
 
-__device__ __forceinline__ unsigned fbits(float v) { return __builtin_bit_cast(unsigned, v); }
-__device__ __forceinline__ float ffrom(unsigned v) { return __builtin_bit_cast(float, v); }
-
 // Lane l receives v of lane 16 (l / 16) + k (DPP row_newbcast).
 template <int k>
 __device__ __forceinline__ float dpp_bcast16(float v) {
@@ -433,16 +483,17 @@ __device__ __forceinline__ float dpp_bcast16_dyn(float v, int k) {
     }
 }
 
-// permlane16_swap(v, v) gives {[r0, r0, r2, r2], [r1, r1, r3, r3]} over the
-// four DPP rows r0..r3 of v; permlane32_swap(v, v) gives {[lo, lo], [hi, hi]}
-// over the two half-waves.
+// Row r0 or r1 of each half-wave (swap16), or one half-wave (swap32), to all
+// the lanes of its half-wave or of the wave.
 __device__ __forceinline__ float even_rows16(float v, bool odd) {
-    const auto p = __builtin_amdgcn_permlane16_swap(fbits(v), fbits(v), false, false);
-    return ffrom(odd ? p[1] : p[0]);
+    float a, b;
+    swap16(v, a, b);
+    return odd ? b : a;
 }
 __device__ __forceinline__ float half32(float v, bool hi) {
-    const auto q = __builtin_amdgcn_permlane32_swap(fbits(v), fbits(v), false, false);
-    return ffrom(hi ? q[1] : q[0]);
+    float a, b;
+    swap32(v, a, b);
+    return hi ? b : a;
 }
 
 // Within each row group: lane (r, c) receives the value of lane (r, k).
@@ -696,7 +747,21 @@ template <int UP, int PREC>
 struct Tile {
     float f[UP];
     typename Split<PREC == kF32 ? kF16 : PREC>::V hi[UP / 8], lo[UP / 8];
+    int e;  // packed tiles: hi + lo = f * 2^e
 };
+
+// 16-bit register tiles are split once, right after their Gram (with the
+// exponent the Gram chose), and kept packed until the precode: the FP32
+// values are dead from then on.
+template <int UP, int PREC>
+__device__ __forceinline__ void tile_pack(Tile<UP, PREC> &tl, int e) {
+    if constexpr (PREC != kF32) {
+        const float sc = ldexpf(1.f, e);
+#pragma unroll
+        for (int q = 0; q < UP / 8; ++q) Split<PREC>::split_scaled(&tl.f[8 * q], sc, tl.hi[q], tl.lo[q]);
+        tl.e = e;
+    }
+}
 
 // Loads rows [row0, row0 + nrows) (0 <= nrows <= 32; row0 a valid row) of a
 // subcarrier's channel Hn (B x U) into a tile.  The loads go straight into
@@ -737,6 +802,20 @@ __device__ __forceinline__ void load_tile(const float2 *__restrict__ Hn, int U, 
     }
 }
 
+// Exponent for packing a tile whose Gram is not formed (per-symbol mode):
+// from the tile's own values (its copies of valid entries included).
+template <int UP, int PREC>
+__device__ __forceinline__ int tile_exp(const Tile<UP, PREC> &tl) {
+    if constexpr (PREC == kF16) {
+        float m = 0.f;
+#pragma unroll
+        for (int q = 0; q < UP; ++q) m = fmaxf(m, fabsf(tl.f[q]));
+        return fp16_exp(wave_max(m));
+    } else {
+        return 0;
+    }
+}
+
 // X^T tile: rows (k, re/im) of a 16-symbol chunk, columns = the tile's 32
 // rows.  16-bit: the tile is scaled into the FP16 range and split here and the
 // product unscaled (with the Z unscale).
@@ -747,21 +826,25 @@ __device__ __forceinline__ floatx16 mfma_apply_tile(Tile<UP, PREC> &tl, const ZO
 #pragma unroll
         for (int m = 0; m < UP; ++m) acc = mfma32(z.f[m], tl.f[m], acc);
     } else {
-        float mx = 0.f;
-#pragma unroll
-        for (int m = 0; m < UP; ++m) mx = fmaxf(mx, fabsf(tl.f[m]));
-        const int eh = fp16_exp(wave_max(mx));
-        const float sc = ldexpf(1.f, eh);
-#pragma unroll
-        for (int q = 0; q < UP / 8; ++q) {
-            float v[8];
-#pragma unroll
-            for (int e = 0; e < 8; ++e) v[e] = tl.f[8 * q + e] * sc;
-            Split<PREC>::split(v, tl.hi[q], tl.lo[q]);
-        }
+        tile_pack<UP, PREC>(tl, tile_exp<UP, PREC>(tl));
 #pragma unroll
         for (int q = 0; q < UP / 8; ++q) acc = mfma3<PREC>(z.hi[q], z.lo[q], tl.hi[q], tl.lo[q], acc);
-        acc *= ldexpf(z.unscale, -eh);
+        acc *= ldexpf(z.unscale, -tl.e);
+    }
+    return acc;
+}
+
+// X^T tile from a packed register tile (16-bit) or the FP32 tile.
+template <int UP, int PREC>
+__device__ __forceinline__ floatx16 mfma_apply_packed(const Tile<UP, PREC> &tl, const ZOp<UP, PREC> &z) {
+    floatx16 acc = {0};
+    if constexpr (PREC == kF32) {
+#pragma unroll
+        for (int m = 0; m < UP; ++m) acc = mfma32(z.f[m], tl.f[m], acc);
+    } else {
+#pragma unroll
+        for (int q = 0; q < UP / 8; ++q) acc = mfma3<PREC>(z.hi[q], z.lo[q], tl.hi[q], tl.lo[q], acc);
+        acc *= ldexpf(z.unscale, -tl.e);
     }
     return acc;
 }
@@ -874,7 +957,7 @@ constexpr int max_tiles(int up) { return 4; }
 // in registers need more registers per wave.
 template <int UP, int MAXT, int PREC>
 constexpr int min_waves() {
-    if (UP == 16) return MAXT == 0 ? 2 : MAXT == 1 ? (PREC == kF32 ? 4 : 3) : MAXT == 2 ? (PREC == kF32 ? 3 : 2) : 2;
+    if (UP == 16) return MAXT == 0 ? 2 : MAXT == 1 ? (PREC == kF32 ? 4 : 3) : MAXT == 2 ? 3 : 2;
     return MAXT == 1 ? 2 : 1;
 }
 
@@ -930,6 +1013,10 @@ __device__ __forceinline__ void wave_system(const Prob &p, const int *__restrict
     if (mode == kSymbols) {
         if (pre_sym) load_sym<UP>(s + (size_t)n * U, (size_t)n_sc * U, U, min(KC, K), sym0);
         amax = load_factor<UP>(fac, U, sA);
+        if constexpr (MAXT > 0) {
+#pragma unroll
+            for (int q = 0; q < MAXT; ++q) tile_pack<UP, PREC>(tiles[q], tile_exp<UP, PREC>(tiles[q]));
+        }
     } else {
         floatx16 acc[NTT];
 #pragma unroll
@@ -943,7 +1030,7 @@ __device__ __forceinline__ void wave_system(const Prob &p, const int *__restrict
                 if (q < ntile) {
                     GramBuf<UP> b;
                     tile_to_gram<UP, PREC>(tiles[q], min(32, r1 - (r0 + 32 * q)), U, scr, b);
-                    gram_mma<UP, PREC>(b, acc);
+                    tile_pack<UP, PREC>(tiles[q], gram_mma<UP, PREC>(b, acc));
                 }
                 // one tile at a time: keeps the scheduler from overlapping
                 // several tiles' buffers on top of the resident tiles
@@ -1018,7 +1105,8 @@ __device__ __forceinline__ void wave_system(const Prob &p, const int *__restrict
 #pragma unroll
             for (int q = 0; q < MAXT; ++q) {
                 const int rq = r0 + 32 * q;
-                if (q < ntile) store_x(mfma_apply_tile<UP, PREC>(tiles[q], z), rq, min(32, r1 - rq), k0, kc, n, n_sc, B, x);
+                if (q < ntile)
+                    store_x(mfma_apply_packed<UP, PREC>(tiles[q], z), rq, min(32, r1 - rq), k0, kc, n, n_sc, B, x);
                 __builtin_amdgcn_sched_barrier(0);
             }
             wave_sync();
@@ -1098,6 +1186,8 @@ __device__ __forceinline__ void wg_pd_split(const Prob &p, int blk, int K, int m
                 sh_ok = 1;
             }
         }
+#pragma unroll
+        for (int q = 0; q < MAXT; ++q) tile_pack<UP, PREC>(tiles[q], tile_exp<UP, PREC>(tiles[q]));
     } else {
         floatx16 acc[NTT];
 #pragma unroll
@@ -1109,7 +1199,7 @@ __device__ __forceinline__ void wg_pd_split(const Prob &p, int blk, int K, int m
             if (tt < ntile) {
                 GramBuf<UP> b;
                 tile_to_gram<UP, PREC>(tiles[q], min(32, B - 32 * tt), U, scr, b);
-                gram_mma<UP, PREC>(b, acc);
+                tile_pack<UP, PREC>(tiles[q], gram_mma<UP, PREC>(b, acc));
             }
             __builtin_amdgcn_sched_barrier(0);
         }
@@ -1180,7 +1270,8 @@ __device__ __forceinline__ void wg_pd_split(const Prob &p, int blk, int K, int m
         for (int q = 0; q < MAXT; ++q) {
             const int tt = wave + NW * q;
             if (tt < ntile)
-                store_x(mfma_apply_tile<UP, PREC>(tiles[q], z), 32 * tt, min(32, B - 32 * tt), k0, kc, n, n_sc, B, x);
+                store_x(mfma_apply_packed<UP, PREC>(tiles[q], z), 32 * tt, min(32, B - 32 * tt), k0, kc, n, n_sc, B,
+                        x);
             __builtin_amdgcn_sched_barrier(0);
         }
         __syncthreads();  // Zm is rewritten by the next chunk
