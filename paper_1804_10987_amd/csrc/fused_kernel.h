@@ -269,6 +269,34 @@ __device__ __forceinline__ int gram_mma(const GramBuf<UP> &b, floatx16 (&acc)[Sh
     }
 }
 
+// 16-bit Gram of the buffered rows with a given exponent e: the products of
+// the rows scaled by 2^e accumulate in acc directly (acc holds 2^(2e) times
+// the Gram; the caller unscales once).  FP32: plain gram_mma.
+template <int UP, int PREC>
+__device__ __forceinline__ void gram_mma_scaled(const GramBuf<UP> &b, floatx16 (&acc)[Shape<UP>::NTT], int e) {
+    if constexpr (PREC == kF32) {
+        (void)gram_mma<UP, PREC>(b, acc);
+    } else {
+        constexpr int NT = Shape<UP>::NT;
+        typedef typename Split<PREC>::V V;
+        const float sc = ldexpf(1.f, e);
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            V hi[NT], lo[NT];
+#pragma unroll
+            for (int ti = 0; ti < NT; ++ti) Split<PREC>::split_scaled(&b.v[ti][8 * s], sc, hi[ti], lo[ti]);
+            int t = 0;
+#pragma unroll
+            for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+                for (int tj = ti; tj < NT; ++tj) {
+                    acc[t] = mfma3<PREC>(hi[ti], lo[ti], hi[tj], lo[tj], acc[t]);
+                    ++t;
+                }
+        }
+    }
+}
+
 // Turns the real Gram tiles into the complex U x U matrix in an LDS slot:
 // G[u][v] = post * ((M[2u][2v] + M[2u+1][2v+1]) + i (M[2u][2v+1] - M[2u+1][2v])),
 // plus diag_add on the diagonal for u < m.  Output layout of the 32x32 MFMA:
@@ -834,6 +862,23 @@ __device__ __forceinline__ floatx16 mfma_apply_tile(Tile<UP, PREC> &tl, const ZO
     return acc;
 }
 
+// One FP16 exponent for all of a wave's register tiles (those with index
+// below nvalid; the others hold copies of the system's rows as well): the
+// max over their values, so that every tile scaled by 2^e stays in range.
+template <int UP, int PREC, int MAXT>
+__device__ __forceinline__ int tiles_exp(const Tile<UP, PREC> (&tl)[MAXT]) {
+    if constexpr (PREC == kF16) {
+        float m = 0.f;
+#pragma unroll
+        for (int q = 0; q < MAXT; ++q)
+#pragma unroll
+            for (int i = 0; i < UP; ++i) m = fmaxf(m, fabsf(tl[q].f[i]));
+        return fp16_exp(wave_max(m));
+    } else {
+        return 0;
+    }
+}
+
 // X^T tile from a packed register tile (16-bit) or the FP32 tile.
 template <int UP, int PREC>
 __device__ __forceinline__ floatx16 mfma_apply_packed(const Tile<UP, PREC> &tl, const ZOp<UP, PREC> &z) {
@@ -954,10 +999,14 @@ constexpr int kDepth = 4;
 constexpr int max_tiles(int up) { return 4; }
 
 // Minimum waves per SIMD the register allocation targets: more tiles held
-// in registers need more registers per wave.
-template <int UP, int MAXT, int PREC>
+// in registers need more registers per wave.  The split PD kernel with 4
+// tiles per wave fits 3 (so that 2-wave workgroups of a 1200-subcarrier
+// frame are all resident at once); the one-system-per-wave kernel with 4
+// tiles needs the room of 2.
+template <int UP, int MAXT, int PREC, bool SPLIT = false>
 constexpr int min_waves() {
-    if (UP == 16) return MAXT == 0 ? 2 : MAXT == 1 ? (PREC == kF32 ? 4 : 3) : MAXT == 2 ? 3 : 2;
+    if (UP == 16)
+        return MAXT == 0 ? 2 : MAXT == 1 ? (PREC == kF32 ? 4 : 3) : MAXT == 2 ? 3 : (SPLIT ? 3 : 2);
     return MAXT == 1 ? 2 : 1;
 }
 
@@ -1010,17 +1059,15 @@ __device__ __forceinline__ void wave_system(const Prob &p, const int *__restrict
     // factorization (kept out of the Gram's register budget)
     SymRaw<UP> sym0;
     const bool pre_sym = mode != kPrepare && K > 0;
-    if (mode == kSymbols) {
-        if (pre_sym) load_sym<UP>(s + (size_t)n * U, (size_t)n_sc * U, U, min(KC, K), sym0);
-        amax = load_factor<UP>(fac, U, sA);
-        if constexpr (MAXT > 0) {
+    // 16-bit register tiles: one exponent for the wave's tiles, and the
+    // tiles are packed at a single point for every mode (packing in two
+    // branches keeps both forms of the tiles live across the join)
+    int ew = 0;
+    if constexpr (MAXT > 0) ew = tiles_exp<UP, PREC, MAXT>(tiles);
+    floatx16 acc[NTT];
 #pragma unroll
-            for (int q = 0; q < MAXT; ++q) tile_pack<UP, PREC>(tiles[q], tile_exp<UP, PREC>(tiles[q]));
-        }
-    } else {
-        floatx16 acc[NTT];
-#pragma unroll
-        for (int q = 0; q < NTT; ++q) acc[q] = floatx16{0};
+    for (int q = 0; q < NTT; ++q) acc[q] = floatx16{0};
+    if (mode != kSymbols) {
         if constexpr (MAXT > 0) {
             // from the register tiles, transposed through LDS (the scratch
             // overlays Z and the slot, both unused until the Gram is done)
@@ -1030,7 +1077,7 @@ __device__ __forceinline__ void wave_system(const Prob &p, const int *__restrict
                 if (q < ntile) {
                     GramBuf<UP> b;
                     tile_to_gram<UP, PREC>(tiles[q], min(32, r1 - (r0 + 32 * q)), U, scr, b);
-                    tile_pack<UP, PREC>(tiles[q], gram_mma<UP, PREC>(b, acc));
+                    gram_mma_scaled<UP, PREC>(b, acc, ew);
                 }
                 // one tile at a time: keeps the scheduler from overlapping
                 // several tiles' buffers on top of the resident tiles
@@ -1059,6 +1106,20 @@ __device__ __forceinline__ void wave_system(const Prob &p, const int *__restrict
                     gram_mma<UP, PREC>(ring[i], acc);
                 }
             }
+        }
+    }
+    if constexpr (MAXT > 0) {
+#pragma unroll
+        for (int q = 0; q < MAXT; ++q) tile_pack<UP, PREC>(tiles[q], ew);
+    }
+    if (mode == kSymbols) {
+        if (pre_sym) load_sym<UP>(s + (size_t)n * U, (size_t)n_sc * U, U, min(KC, K), sym0);
+        amax = load_factor<UP>(fac, U, sA);
+    } else {
+        if constexpr (MAXT > 0 && PREC != kF32) {
+            const float un = ldexpf(1.f, -2 * ew);
+#pragma unroll
+            for (int t2 = 0; t2 < NTT; ++t2) acc[t2] *= un;
         }
         if (pre_sym) load_sym<UP>(s + (size_t)n * U, (size_t)n_sc * U, U, min(KC, K), sym0);
         for (int e = lane; e < SLOT; e += 64) sA[e] = {0.f, 0.f};
@@ -1094,9 +1155,11 @@ __device__ __forceinline__ void wave_system(const Prob &p, const int *__restrict
             SymRaw<UP> sym;
             if (k0 == 0) sym = sym0;
             else load_sym<UP>(s + ((size_t)k0 * n_sc + n) * U, (size_t)n_sc * U, U, kc, sym);
-            ZOp<UP, PREC> zs;
-            sym_to_zop<UP, PREC>(sym, U, kc, zs);
-            wave_solve_chunk<UP, PREC>(sA, Zw, zs, kc, U, scale, amax, ok);
+            // the solve is small: FP32 MFMA at every precision (exact
+            // products, and no split operands next to the resident tiles)
+            ZOp<UP, kF32> zs;
+            sym_to_zop<UP, kF32>(sym, U, kc, zs);
+            wave_solve_chunk<UP, kF32>(sA, Zw, zs, kc, U, scale, amax, ok);
         }
         wave_sync();
         ZOp<UP, PREC> z;
@@ -1186,12 +1249,15 @@ __device__ __forceinline__ void wg_pd_split(const Prob &p, int blk, int K, int m
                 sh_ok = 1;
             }
         }
+    }
+    // 16-bit: one exponent for the wave's tiles; they are packed at a single
+    // point for every mode (packing in two branches keeps both forms of the
+    // tiles live across the join)
+    const int ew = tiles_exp<UP, PREC, MAXT>(tiles);
+    floatx16 acc[NTT];
 #pragma unroll
-        for (int q = 0; q < MAXT; ++q) tile_pack<UP, PREC>(tiles[q], tile_exp<UP, PREC>(tiles[q]));
-    } else {
-        floatx16 acc[NTT];
-#pragma unroll
-        for (int q = 0; q < NTT; ++q) acc[q] = floatx16{0};
+    for (int q = 0; q < NTT; ++q) acc[q] = floatx16{0};
+    if (mode != kSymbols) {
         float *scr = (float *)zw_of(wave);
 #pragma unroll
         for (int q = 0; q < MAXT; ++q) {
@@ -1199,9 +1265,18 @@ __device__ __forceinline__ void wg_pd_split(const Prob &p, int blk, int K, int m
             if (tt < ntile) {
                 GramBuf<UP> b;
                 tile_to_gram<UP, PREC>(tiles[q], min(32, B - 32 * tt), U, scr, b);
-                tile_pack<UP, PREC>(tiles[q], gram_mma<UP, PREC>(b, acc));
+                gram_mma_scaled<UP, PREC>(b, acc, ew);
             }
             __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < MAXT; ++q) tile_pack<UP, PREC>(tiles[q], ew);
+    if (mode != kSymbols) {
+        if constexpr (PREC != kF32) {
+            const float un = ldexpf(1.f, -2 * ew);
+#pragma unroll
+            for (int t2 = 0; t2 < NTT; ++t2) acc[t2] *= un;
         }
         // every wave's partial accumulators, raw, to its LDS area; the master
         // adds them in fixed wave order and stores G + kappa I into its slot
@@ -1253,15 +1328,15 @@ __device__ __forceinline__ void wg_pd_split(const Prob &p, int blk, int K, int m
     for (int k0 = 0; k0 < K; k0 += KC) {
         const int kc = min(KC, K - k0);
         if (wave == mw) {
-            ZOp<UP, PREC> zs;
+            ZOp<UP, kF32> zs;  // FP32 solve at every precision (see wave_system)
             if (k0 == 0) {
-                sym_to_zop<UP, PREC>(sym0, U, kc, zs);
+                sym_to_zop<UP, kF32>(sym0, U, kc, zs);
             } else {
                 SymRaw<UP> sym;
                 load_sym<UP>(s + ((size_t)k0 * n_sc + n) * U, (size_t)n_sc * U, U, kc, sym);
-                sym_to_zop<UP, PREC>(sym, U, kc, zs);
+                sym_to_zop<UP, kF32>(sym, U, kc, zs);
             }
-            wave_solve_chunk<UP, PREC>(Am, Zm, zs, kc, U, sh_scale, sh_amax, sh_ok != 0);
+            wave_solve_chunk<UP, kF32>(Am, Zm, zs, kc, U, sh_scale, sh_amax, sh_ok != 0);
         }
         __syncthreads();
         ZOp<UP, PREC> z;
