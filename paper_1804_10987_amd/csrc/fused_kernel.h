@@ -318,7 +318,8 @@ __device__ __forceinline__ void gram_store(const floatx16 (&acc)[Shape<UP>::NTT]
 #pragma unroll
             for (int r = 0; r < 16; r += 2) {
                 const float own0 = acc[t][r], own1 = acc[t][r + 1];
-                const float par0 = __shfl_xor(own0, 1), par1 = __shfl_xor(own1, 1);
+                // partner lane l ^ 1 (DPP quad_perm [1,0,3,2])
+                const float par0 = dpp_c<0xB1>(own0), par1 = dpp_c<0xB1>(own1);
                 if (even) {
                     const int i = 8 * (r / 4) + 4 * g + (r % 4);
                     const int u = (32 * ti + i) >> 1, v = (32 * tj + jj) >> 1;
