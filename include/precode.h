@@ -252,7 +252,9 @@ int precode_batch_plan_destroy(precode_batch_plan *plan);
  *     the device across streams;
  *   - a job's state returns to the slab after its last symbol completes.
  * The call allocates the slab and streams once; the loop itself never
- * allocates.  sym_latency (host array of sum_j K_j doubles, job-major, or
+ * allocates, and runs no launch-shape timing (see precode_ctx_last_waves): a
+ * shape the process has not tuned yet uses the default launch shape.
+ * sym_latency (host array of sum_j K_j doubles, job-major, or
  * NULL) receives each symbol's latency: completion observed on the host minus
  * release.  The job's scale / status outputs are filled as for precode_pd /
  * precode_fd.  Returns PRECODE_ENOMEM if a job can never fit the slab.

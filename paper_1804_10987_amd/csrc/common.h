@@ -108,6 +108,12 @@ hipError_t fused_run(const Prob &p, int precision, const float2 *H, const float2
                      float *scale_out, int *status, hipStream_t st, int *nw_used = nullptr);
 // Waves per workgroup of the batch launches.
 int fused_default_waves();
+// Launch-shape autotuning on the first call of a problem shape (on by
+// default), per host thread.  A serving loop turns it off while it runs:
+// timing the candidates synchronizes the stream, a stall its latency cannot
+// absorb; calls then use a shape the process has already tuned, else the
+// default shape.
+void fused_set_autotune(bool on);
 // Frame split of the fused kernel: prepare writes scale * A^-1 per instance
 // (n_inst x U x U complex64, scale = 1/beta for PD, w_c for FD, zero for a
 // failed instance) with beta / weights and status; symbols precodes nk symbols

@@ -128,6 +128,8 @@ std::string tune_key(const Prob &p, int prec, int mode, int K) {
 }
 
 
+thread_local bool t_autotune = true;
+
 int default_nw(const Prob &p) {
     if (nw_feasible(p, kDefaultNW)) return kDefaultNW;
     for (int nw : kNWs)
@@ -150,6 +152,7 @@ int choose_nw(const Prob &p, int prec, int mode, int K, const float2 *H, const f
         auto it = g_tuned.find(key);
         if (it != g_tuned.end()) return it->second;
     }
+    if (!t_autotune) return dflt;
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(st, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) return dflt;
     int cands[3], nc = 0;
@@ -227,6 +230,8 @@ bool fused_supported(const Prob &p, int precision) {
 }
 
 int fused_default_waves() { return kDefaultNW; }
+
+void fused_set_autotune(bool on) { t_autotune = on; }
 
 hipError_t fused_run(const Prob &p, int precision, const float2 *H, const float2 *s, float2 *x, float *scale_out,
                      int *status, hipStream_t st, int *nw_used) {

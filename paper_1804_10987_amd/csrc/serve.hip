@@ -140,6 +140,11 @@ extern "C" int precode_serve(precode_ctx *ctx, const precode_serve_job *jobs, in
         cfg->impl < PRECODE_IMPL_AUTO || cfg->impl > PRECODE_IMPL_PLAIN)
         return PRECODE_EINVAL;
     memset(stats, 0, sizeof(*stats));
+    // no launch-shape timing inside the loop (it would synchronize a stream)
+    struct NoTune {
+        NoTune() { fused_set_autotune(false); }
+        ~NoTune() { fused_set_autotune(true); }
+    } no_tune;
     // validate every job and size its resident state before touching the device
     std::vector<JobState> st(n_jobs);
     std::vector<size_t> sym_off(n_jobs + 1, 0);
