@@ -259,11 +259,15 @@ def main():
         ms_fd, _ = time_graph(lambda f: fd_run(f), steps2, 3)
         fd_impl = ctx.last_impl
         ms_fd_plain, _ = time_graph(lambda f: fd_run(f, ratio=2.0, impl="plain"), max(8, steps2 // 2), 2)
+        ms_fd_plain64, _ = time_graph(lambda f: fd_run(f, impl="plain"), max(8, steps2 // 2), 2)
         out["fd"] = {
             "fused_fp32_ms_per_step": ms_fd32, "fused_fp32_value": n_sc * K / (ms_fd32 * 1e-3),
             "fused_fp32_achieved_gbs": frame_bytes / (ms_fd32 * 1e-3) / 1e9,
-            "default_route_ms_per_step": ms_fd, "default_route_impl": fd_impl,
             "plain_fp32_ms_per_step": ms_fd_plain, "speedup_vs_plain": ms_fd_plain / ms_fd32,
+            "note": "clusters of 32 with U = 16 meet U / B_c >= 0.5: the default routing takes the FP64 route",
+            "default_route_ms_per_step": ms_fd, "default_route_impl": fd_impl,
+            "default_route_value": n_sc * K / (ms_fd * 1e-3),
+            "plain_fp64_route_ms_per_step": ms_fd_plain64, "fp64_route_speedup_vs_plain": ms_fd_plain64 / ms_fd,
         }
     if not args.quick:
         out["serving"] = serving_leg(ctx, pc, Hs, Ss, cell, dev, args)

@@ -16,8 +16,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libprecode.so")
 ARCH = "gfx950"
 
-SOURCES = ["api.hip", "plain.hip", "fused.hip", "fused_nw1.hip", "fused_nw2.hip", "fused_nw4.hip", "batch.hip",
-           "serve.hip"]
+SOURCES = ["api.hip", "plain.hip", "fused.hip", "fused_nw1.hip", "fused_nw2.hip", "fused_nw4.hip", "fused_f64.hip",
+           "batch.hip", "serve.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=" + ARCH,

@@ -226,9 +226,20 @@ int run(precode_ctx *ctx, int arch, const void *H, const void *s, float rho, con
     if (!aligned8(H) || !aligned8(s) || !aligned8(x)) return PRECODE_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     const bool can_fuse = K > 0 && q.refine_steps == 0 && fused_supported(p, q.precision);
-    if (q.impl == PRECODE_IMPL_FUSED && !can_fuse) return PRECODE_EUNSUPPORTED;
+    // the FP64 route fused (its Gram, inversion and solve in FP64) when every
+    // local system takes it and fits
+    const bool can_f64 = !can_fuse && q.refine_steps == 0 && fused_f64_supported(p, q.precision, K);
+    if (q.impl == PRECODE_IMPL_FUSED && !can_fuse && !can_f64) return PRECODE_EUNSUPPORTED;
     if (q.precision == PRECODE_PREC_SPLIT_FP16 || q.precision == PRECODE_PREC_SPLIT_BF16) {
-        if (!can_fuse) return PRECODE_EUNSUPPORTED;
+        if (!can_fuse && !can_f64) return PRECODE_EUNSUPPORTED;
+    }
+    if (q.impl != PRECODE_IMPL_PLAIN && can_f64) {
+        rc = dev_err(fused_f64_run(p, (const float2 *)H, (const float2 *)s, (float2 *)x, scale, status, st));
+        if (rc == PRECODE_OK) {
+            ctx->last_impl = PRECODE_IMPL_FUSED;
+            ctx->last_waves = 4;
+        }
+        return rc;
     }
     if (q.impl != PRECODE_IMPL_PLAIN && can_fuse) {
         int nw = 0;

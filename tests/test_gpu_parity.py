@@ -151,6 +151,44 @@ def test_fp64_route_square(torch, ctx, pc):
     _check(xg, scg, stg, xo, sco, sto, tol=1e-6)
 
 
+@pytest.mark.parametrize("cell", [
+    synth.Cell(B=256, sizes=(32,) * 8, U=16, n_sc=37, K=14, snr_db=10.0),         # U / B_c = 0.5
+    synth.Cell(B=64, sizes=(16,) * 4, U=16, n_sc=23, K=19, snr_db=20.0),          # B_c = U
+    synth.Cell(B=47, sizes=(11, 14, 22), U=11, n_sc=15, K=5, snr_db=5.0, qam=16),  # ragged, U < 16
+], ids=["b256_bc32_u16", "bc16_u16", "ragged_u11"])
+@pytest.mark.parametrize("mode", ["wf", "zf"])
+def test_fd_fp64_route_fused(torch, ctx, pc, cell, mode):
+    """FD whose every cluster takes the FP64 route (U / B_c >= 0.5) with
+    U <= B_c <= 32 runs in one fused launch (Gram, inversion and solve in FP64,
+    precode on FP32 MFMA): against the oracle and against the plain FP64
+    kernels; every instance flagged FP64."""
+    H, s = synth.make_cell(cell, seed=21)
+    xg, scg, stg = _run(torch, ctx, pc, "fd", H, s, cell.kappa, cell.sizes, mode)
+    assert ctx.last_impl == "fused" and ctx.last_waves == 4
+    assert ((stg & 2) == 2).all()
+    xo, sco, sto = _oracle("fd", H, s, cell.kappa, cell.sizes, mode)
+    _check(xg, scg, stg, xo, sco, sto)
+    xp, scp, stp = _run(torch, ctx, pc, "fd", H, s, cell.kappa, cell.sizes, mode, impl="plain")
+    assert ctx.last_impl == "plain" and (stp == stg).all()
+    assert _vec_err(xg, xp).max() <= TOL
+
+
+def test_fd_fp64_route_fused_singular(torch, ctx, pc):
+    """ZF on the fused FP64 route with a silent user in one cluster: that
+    cluster's system is singular, flagged FAIL | FP64 with zero output; the
+    others match the oracle."""
+    cell = synth.Cell(B=64, sizes=(32, 32), U=16, n_sc=5, K=3)
+    H, s = synth.make_cell(cell, seed=4)
+    H[3, 32:, 5] = 0.0
+    xg, scg, stg = _run(torch, ctx, pc, "fd", H, s, 0.0, cell.sizes, "zf")
+    assert ctx.last_impl == "fused"
+    assert stg[3, 1] == 3 and scg[3, 1] == 0.0 and not np.any(xg[:, 3, 32:])
+    xo, sco, sto = _oracle("fd", H, s, 0.0, cell.sizes, "zf")
+    assert sto[3, 1] == 1
+    keep = [n for n in range(cell.n_sc) if n != 3]
+    assert _vec_err(xg[:, keep], xo[:, keep]).max() <= TOL
+
+
 @pytest.mark.parametrize("impl", ["fused", "plain"])
 @pytest.mark.parametrize("defect", ["duplicate", "zero"])
 def test_singular_zf_sets_status(torch, ctx, pc, impl, defect):
