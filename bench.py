@@ -33,7 +33,7 @@ LLC_BYTES = 256 << 20
 
 
 PROFILE = os.path.join(ROOT, "profiles", "fused_pd_b256_u16_n1200.md")
-KERNEL_SOURCES = ["fused_kernel.h", "fused_nw.inc", "fused_launch.h", "fused.hip", "common.h"]
+KERNEL_SOURCES = ["fused_kernel.h", "fused_nw.inc", "fused_launch.h", "common.h"]
 
 
 def kernel_digest():
