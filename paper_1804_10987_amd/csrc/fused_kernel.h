@@ -554,6 +554,58 @@ __device__ __forceinline__ float bperm_group(float v, int c4, int rk) {
     return ffrom(__builtin_amdgcn_ds_bpermute(rk * UP * 4 + c4, (int)fbits(v)));
 }
 
+// The update of step k of the UP = 16 inversion for slots of the register
+// layout, as v_fmac_f32_dpp with column k broadcast in the DPP operand
+// (row_newbcast:k):  y += a_k(x) (-mim);  x += a_k(y) mim;  y += a_k(y) (-mre);
+// x += a_k(x) (-mre), where a_k(v) is v's column-k value.  Each one reads
+// column k before this step changes it (mult_k is real: the first two leave
+// column k as it was).  The DPP read-after-VALU-write distances (2 wait
+// states) are explicit: an s_nop opens each block, and the one-slot block
+// spaces its dependent pairs with s_nop; the three-slot block interleaves the
+// slots term by term so that each read is 2 or more instructions after its
+// write.
+#define GJ_FMAC(d, s, m) "v_fmac_f32_dpp " d ", " s ", " m " row_newbcast:%[k] row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+template <int K>
+__device__ __forceinline__ void gj_upd1(float &x, float &y, float mim, float nmim, float nmre) {
+    asm("s_nop 1\n\t" GJ_FMAC("%[y]", "%[x]", "%[nmim]") "s_nop 1\n\t" GJ_FMAC("%[x]", "%[y]", "%[mim]")
+            GJ_FMAC("%[y]", "%[y]", "%[nmre]") "s_nop 0\n\t" GJ_FMAC("%[x]", "%[x]", "%[nmre]")
+        : [x] "+v"(x), [y] "+v"(y)
+        : [mim] "v"(mim), [nmim] "v"(nmim), [nmre] "v"(nmre), [k] "i"(K));
+}
+template <int K>
+__device__ __forceinline__ void gj_upd3(float &x0, float &y0, float &x1, float &y1, float &x2, float &y2, float mim,
+                                        float nmim, float nmre) {
+    asm("s_nop 1\n\t" GJ_FMAC("%[y0]", "%[x0]", "%[nmim]") GJ_FMAC("%[y1]", "%[x1]", "%[nmim]")
+            GJ_FMAC("%[y2]", "%[x2]", "%[nmim]") GJ_FMAC("%[x0]", "%[y0]", "%[mim]")
+                GJ_FMAC("%[x1]", "%[y1]", "%[mim]") GJ_FMAC("%[x2]", "%[y2]", "%[mim]")
+                    GJ_FMAC("%[y0]", "%[y0]", "%[nmre]") GJ_FMAC("%[y1]", "%[y1]", "%[nmre]")
+                        GJ_FMAC("%[y2]", "%[y2]", "%[nmre]") GJ_FMAC("%[x0]", "%[x0]", "%[nmre]")
+                            GJ_FMAC("%[x1]", "%[x1]", "%[nmre]") GJ_FMAC("%[x2]", "%[x2]", "%[nmre]")
+        : [x0] "+v"(x0), [y0] "+v"(y0), [x1] "+v"(x1), [y1] "+v"(y1), [x2] "+v"(x2), [y2] "+v"(y2)
+        : [mim] "v"(mim), [nmim] "v"(nmim), [nmre] "v"(nmre), [k] "i"(K));
+}
+#undef GJ_FMAC
+
+#define GJ_DISPATCH(F, k, ...)                 \
+    switch (k) {                               \
+        case 0: F<0>(__VA_ARGS__); break;      \
+        case 1: F<1>(__VA_ARGS__); break;      \
+        case 2: F<2>(__VA_ARGS__); break;      \
+        case 3: F<3>(__VA_ARGS__); break;      \
+        case 4: F<4>(__VA_ARGS__); break;      \
+        case 5: F<5>(__VA_ARGS__); break;      \
+        case 6: F<6>(__VA_ARGS__); break;      \
+        case 7: F<7>(__VA_ARGS__); break;      \
+        case 8: F<8>(__VA_ARGS__); break;      \
+        case 9: F<9>(__VA_ARGS__); break;      \
+        case 10: F<10>(__VA_ARGS__); break;    \
+        case 11: F<11>(__VA_ARGS__); break;    \
+        case 12: F<12>(__VA_ARGS__); break;    \
+        case 13: F<13>(__VA_ARGS__); break;    \
+        case 14: F<14>(__VA_ARGS__); break;    \
+        default: F<15>(__VA_ARGS__); break;    \
+    }
+
 // In-register inversion of the m x m Hermitian positive-definite system held
 // in an LDS slot (full matrix), one wave, by Gauss-Jordan elimination without
 // pivoting: step k divides row k by the pivot and eliminates column k from
@@ -561,9 +613,7 @@ __device__ __forceinline__ float bperm_group(float v, int c4, int rk) {
 // positive-definite A the pivots are the squared diagonal of its Cholesky
 // factor and need no row exchanges.
 // Per step and slot the update a_ic -= a_ik * mult_c is four fused
-// multiply-adds whose a_ik operand is a DPP broadcast of column k; they are
-// ordered so that each reads column k before this step changes it (mult_k is
-// real, so the first two leave column k as it was).  Row k + 1 is fetched
+// multiply-adds with a DPP operand (gj_upd1 / gj_upd3).  Row k + 1 is fetched
 // (bperm_group) as soon as its slot is updated, ahead of the other slots.
 // Returns false when a pivot is not finite or not above kRelPivot32 times its
 // original diagonal entry (numerically singular; a NaN pivot fails the test
@@ -609,28 +659,26 @@ __device__ bool wave_inverse(cx<float> *S, int m, float *tr_out, float *fro_out,
         const float rowre = iscol ? inv : mre, rowim = mim;
         const float nmre = -mre, nmim = -mim;
         const int k1 = k + 1, s1 = k1 / R;
-        auto update = [&](int s) {
-            float x = re[s], y = im[s];
-            y = fmaf(bcast_col<UP>(x, k), nmim, y);  // column k of y unchanged (mim_k = 0)
-            x = fmaf(bcast_col<UP>(y, k), mim, x);   // column k of x unchanged
-            y = fmaf(bcast_col<UP>(y, k), nmre, y);
-            x = fmaf(bcast_col<UP>(x, k), nmre, x);
+        auto row_select = [&](int s) {
             if (s == sk) {
                 const bool isrow = r == rk;
-                x = isrow ? rowre : x;
-                y = isrow ? rowim : y;
+                re[s] = isrow ? rowre : re[s];
+                im[s] = isrow ? rowim : im[s];
             }
-            re[s] = x;
-            im[s] = y;
         };
+        // slot a first (the one holding row k + 1, fetched right after it is
+        // final), then the other three
+        const int a = k1 < UP ? s1 : 0, b0 = a == 0 ? 1 : 0, b1 = a <= 1 ? 2 : 1, b2 = a <= 2 ? 3 : 2;
+        GJ_DISPATCH(gj_upd1, k, re[a], im[a], mim, nmim, nmre);
+        row_select(a);
         if (k1 < UP) {
-            update(s1);
-            akc_re = bperm_group<UP>(re[s1], c4, k1 % R);
-            akc_im = bperm_group<UP>(im[s1], c4, k1 % R);
+            akc_re = bperm_group<UP>(re[a], c4, k1 % R);
+            akc_im = bperm_group<UP>(im[a], c4, k1 % R);
         }
-#pragma unroll
-        for (int s = 0; s < NS; ++s)
-            if (k1 >= UP || s != s1) update(s);
+        GJ_DISPATCH(gj_upd3, k, re[b0], im[b0], re[b1], im[b1], re[b2], im[b2], mim, nmim, nmre);
+        row_select(b0);
+        row_select(b1);
+        row_select(b2);
     }
     // every pivot finite and above kRelPivot32 times its original diagonal entry
     const bool ok = __all((pv > kRelPivot32 * d0) && (pv < INFINITY));
