@@ -911,21 +911,29 @@ __device__ __forceinline__ floatx16 mfma_apply_tile(Tile<UP, PREC> &tl, const ZO
     return acc;
 }
 
-// One FP16 exponent for all of a wave's register tiles (those with index
-// below nvalid; the others hold copies of the system's rows as well): the
-// max over their values, so that every tile scaled by 2^e stays in range.
-template <int UP, int PREC, int MAXT>
-__device__ __forceinline__ int tiles_exp(const Tile<UP, PREC> (&tl)[MAXT]) {
+// The Gram of register tile tl (16-bit): FP16 scales each tile by the
+// running exponent ea, the smallest per-tile exponent so far (the largest
+// values so far), so that a tile's products start as soon as that tile has
+// arrived; when a tile lowers ea, the products accumulated so far are
+// rescaled exactly first (acc holds 2^(2 ea) times the Gram).  The tile keeps
+// its own exponent (tl.e) for its precode split.  BF16 and FP32: no scale.
+template <int UP, int PREC>
+__device__ __forceinline__ void gram_tile(const GramBuf<UP> &b, Tile<UP, PREC> &tl,
+                                          floatx16 (&acc)[Shape<UP>::NTT], int &ea, bool &have) {
     if constexpr (PREC == kF16) {
-        float m = 0.f;
+        const int eq = __builtin_amdgcn_readfirstlane(tile_exp<UP, PREC>(tl));
+        tl.e = eq;
+        if (!have || eq < ea) {
+            if (have) {
+                const float f = ldexpf(1.f, 2 * (eq - ea));
 #pragma unroll
-        for (int q = 0; q < MAXT; ++q)
-#pragma unroll
-            for (int i = 0; i < UP; ++i) m = fmaxf(m, fabsf(tl[q].f[i]));
-        return fp16_exp(wave_max(m));
-    } else {
-        return 0;
+                for (int t2 = 0; t2 < Shape<UP>::NTT; ++t2) acc[t2] *= f;
+            }
+            ea = eq;
+            have = true;
+        }
     }
+    gram_mma_scaled<UP, PREC>(b, acc, ea);
 }
 
 // X^T tile from a packed register tile (16-bit) or the FP32 tile.
@@ -1108,11 +1116,14 @@ __device__ __forceinline__ void wave_system(const Prob &p, const int *__restrict
     // factorization (kept out of the Gram's register budget)
     SymRaw<UP> sym0;
     const bool pre_sym = mode != kPrepare && K > 0;
-    // 16-bit register tiles: one exponent for the wave's tiles, and the
-    // tiles are packed at a single point for every mode (packing in two
-    // branches keeps both forms of the tiles live across the join)
+    // 16-bit register tiles: the Gram runs on a running exponent (gram_tile),
+    // and the tiles are packed, each with its own exponent, at a single point
+    // for every mode (packing in two branches keeps both forms of the tiles
+    // live across the join)
     int ew = 0;
-    if constexpr (MAXT > 0) ew = tiles_exp<UP, PREC, MAXT>(tiles);
+    bool have_e = false;
+#pragma unroll
+    for (int q = 0; q < (MAXT > 0 ? MAXT : 1); ++q) tiles[q].e = 0;
     floatx16 acc[NTT];
 #pragma unroll
     for (int q = 0; q < NTT; ++q) acc[q] = floatx16{0};
@@ -1126,7 +1137,7 @@ __device__ __forceinline__ void wave_system(const Prob &p, const int *__restrict
                 if (q < ntile) {
                     GramBuf<UP> b;
                     tile_to_gram<UP, PREC>(tiles[q], min(32, r1 - (r0 + 32 * q)), U, scr, b);
-                    gram_mma_scaled<UP, PREC>(b, acc, ew);
+                    gram_tile<UP, PREC>(b, tiles[q], acc, ew, have_e);
                 }
                 // one tile at a time: keeps the scheduler from overlapping
                 // several tiles' buffers on top of the resident tiles
@@ -1158,8 +1169,12 @@ __device__ __forceinline__ void wave_system(const Prob &p, const int *__restrict
         }
     }
     if constexpr (MAXT > 0) {
+        if (mode == kSymbols) {
 #pragma unroll
-        for (int q = 0; q < MAXT; ++q) tile_pack<UP, PREC>(tiles[q], ew);
+            for (int q = 0; q < MAXT; ++q) tiles[q].e = tile_exp<UP, PREC>(tiles[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < MAXT; ++q) tile_pack<UP, PREC>(tiles[q], tiles[q].e);
     }
     if (mode == kSymbols) {
         if (pre_sym) load_sym<UP>(s + (size_t)n * U, (size_t)n_sc * U, U, min(KC, K), sym0);
@@ -1299,10 +1314,14 @@ __device__ __forceinline__ void wg_pd_split(const Prob &p, int blk, int K, int m
             }
         }
     }
-    // 16-bit: one exponent for the wave's tiles; they are packed at a single
-    // point for every mode (packing in two branches keeps both forms of the
-    // tiles live across the join)
-    const int ew = tiles_exp<UP, PREC, MAXT>(tiles);
+    // 16-bit: the Gram runs on a running exponent (gram_tile); the tiles are
+    // packed, each with its own exponent, at a single point for every mode
+    // (packing in two branches keeps both forms of the tiles live across the
+    // join)
+    int ew = 0;
+    bool have_e = false;
+#pragma unroll
+    for (int q = 0; q < MAXT; ++q) tiles[q].e = 0;
     floatx16 acc[NTT];
 #pragma unroll
     for (int q = 0; q < NTT; ++q) acc[q] = floatx16{0};
@@ -1314,13 +1333,16 @@ __device__ __forceinline__ void wg_pd_split(const Prob &p, int blk, int K, int m
             if (tt < ntile) {
                 GramBuf<UP> b;
                 tile_to_gram<UP, PREC>(tiles[q], min(32, B - 32 * tt), U, scr, b);
-                gram_mma_scaled<UP, PREC>(b, acc, ew);
+                gram_tile<UP, PREC>(b, tiles[q], acc, ew, have_e);
             }
             __builtin_amdgcn_sched_barrier(0);
         }
+    } else {
+#pragma unroll
+        for (int q = 0; q < MAXT; ++q) tiles[q].e = tile_exp<UP, PREC>(tiles[q]);
     }
 #pragma unroll
-    for (int q = 0; q < MAXT; ++q) tile_pack<UP, PREC>(tiles[q], ew);
+    for (int q = 0; q < MAXT; ++q) tile_pack<UP, PREC>(tiles[q], tiles[q].e);
     if (mode != kSymbols) {
         if constexpr (PREC != kF32) {
             const float un = ldexpf(1.f, -2 * ew);
