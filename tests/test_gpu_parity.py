@@ -173,6 +173,23 @@ def test_fd_fp64_route_fused(torch, ctx, pc, cell, mode):
     assert _vec_err(xg, xp).max() <= TOL
 
 
+@pytest.mark.parametrize("mode", ["wf", "zf"])
+def test_pd_fp64_route_fused(torch, ctx, pc, mode):
+    """PD with U / B = 0.5 and B <= 32 (every subcarrier on the FP64 route)
+    runs on the fused FP64 kernel, 17 symbols (two chunks): against the oracle
+    and the plain FP64 kernels; precision FP64 keeps the plain kernels."""
+    cell = synth.Cell(B=24, sizes=(12, 12), U=12, n_sc=19, K=17, snr_db=15.0)
+    H, s = synth.make_cell(cell, seed=13)
+    xg, scg, stg = _run(torch, ctx, pc, "pd", H, s, cell.kappa, cell.sizes, mode)
+    assert ctx.last_impl == "fused" and (stg == 2).all()
+    xo, sco, sto = _oracle("pd", H, s, cell.kappa, cell.sizes, mode)
+    _check(xg, scg, stg, xo, sco, sto)
+    xp, scp, stp = _run(torch, ctx, pc, "pd", H, s, cell.kappa, cell.sizes, mode, impl="plain")
+    assert (stp == stg).all() and _vec_err(xg, xp).max() <= TOL
+    _run(torch, ctx, pc, "pd", H, s, cell.kappa, cell.sizes, mode, precision="fp64")
+    assert ctx.last_impl == "plain"
+
+
 def test_fd_fp64_route_fused_singular(torch, ctx, pc):
     """ZF on the fused FP64 route with a silent user in one cluster: that
     cluster's system is singular, flagged FAIL | FP64 with zero output; the
