@@ -367,7 +367,9 @@ def test_autotuned_shape_is_cached_and_deterministic(torch, ctx, pc, monkeypatch
     w1 = ctx.last_waves
     x2, _, _ = ctx.pd(Hd, sd, cell.kappa, cell.sizes)
     torch.cuda.synchronize()
-    assert w1 in (1, 2, 4) and ctx.last_waves == w1
+    # 256 rows of 16 users are 8 tiles: one wave per subcarrier would stream
+    # them twice, so only the split shapes (2 or 4 waves) are candidates
+    assert w1 in (2, 4) and ctx.last_waves == w1
     assert torch.equal(x1, x2)
 
 
