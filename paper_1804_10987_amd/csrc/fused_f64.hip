@@ -75,7 +75,12 @@ __device__ bool wave_inverse_f64(double (&re)[4], double (&im)[4], int m, double
         const double piv = dpp_bcast16_d(akc_re, k);
         const bool iscol = c == k;
         pv = iscol ? piv : pv;
-        const double inv = 1.0 / piv;
+        // 1 / piv: hardware reciprocal and two Newton steps (the error
+        // squares per step: below an ulp of FP64); a zero or non-finite
+        // pivot fails the pivot test anyway
+        double inv = __builtin_amdgcn_rcp(piv);
+        inv = fma(inv, fma(-piv, inv, 1.0), inv);
+        inv = fma(inv, fma(-piv, inv, 1.0), inv);
         const double mre = iscol ? 1.0 + inv : akc_re * inv;
         const double mim = iscol ? 0.0 : akc_im * inv;
         const double rowre = iscol ? inv : mre, rowim = mim;
