@@ -155,7 +155,8 @@ def test_fp64_route_square(torch, ctx, pc):
     synth.Cell(B=256, sizes=(32,) * 8, U=16, n_sc=37, K=14, snr_db=10.0),         # U / B_c = 0.5
     synth.Cell(B=64, sizes=(16,) * 4, U=16, n_sc=23, K=19, snr_db=20.0),          # B_c = U
     synth.Cell(B=47, sizes=(11, 14, 22), U=11, n_sc=15, K=5, snr_db=5.0, qam=16),  # ragged, U < 16
-], ids=["b256_bc32_u16", "bc16_u16", "ragged_u11"])
+    synth.Cell(B=5, sizes=(1, 2, 2), U=1, n_sc=7, K=3, snr_db=0.0),                 # U = 1, tiny clusters
+], ids=["b256_bc32_u16", "bc16_u16", "ragged_u11", "u1_tiny"])
 @pytest.mark.parametrize("mode", ["wf", "zf"])
 def test_fd_fp64_route_fused(torch, ctx, pc, cell, mode):
     """FD whose every cluster takes the FP64 route (U / B_c >= 0.5) with
