@@ -136,7 +136,16 @@ std::string tune_key(const Prob &p, int prec, int mode, int K) {
 
 thread_local bool t_autotune = true;
 
+// The shape of an untuned call (tuning off, stream capture): the fewest
+// waves per workgroup that keep the system's rows in register tiles (split
+// over the workgroup for large PD cells), else the default.
 int default_nw(const Prob &p) {
+    for (int nw : kNWs) {
+        int mt;
+        bool sp;
+        pick_tiles(p, nw, &mt, &sp);
+        if (mt > 0 && nw_feasible(p, nw)) return nw;
+    }
     if (nw_feasible(p, kDefaultNW)) return kDefaultNW;
     for (int nw : kNWs)
         if (nw_feasible(p, nw)) return nw;
