@@ -74,6 +74,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--quick", action="store_true", help="headline path only (for profiling)")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--cell", type=int, default=2, choices=(2, 3),
+                    help="2: the headline cell (B=256 as 8x32, U=16, 1200 subcarriers); 3: B=512 as 16x32, U=32, "
+                         "3300 subcarriers, correlated channel (for profiling; the headline line is cell 2)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB float32 copy kernel 10 times (HBM counter calibration)")
     return ap.parse_args()
@@ -103,7 +107,7 @@ def main():
         print(json.dumps({"copy_kernel": "torch.mul(a, 1.0, out=b), float32", "read_bytes": a.numel() * 4,
                           "write_bytes": b.numel() * 4, "launches": 10}), flush=True)
         return
-    cell = synth.config(2)
+    cell = synth.config(args.cell)
     B, U, K, n_sc, sizes = cell.B, cell.U, cell.K, cell.n_sc, list(cell.sizes)
     frame_bytes = algorithmic_bytes(B, U, K, n_sc)
     n_frames = max(2, math.ceil(2 * LLC_BYTES / frame_bytes))
@@ -192,7 +196,7 @@ def main():
     value = n_sc * K / (ms * 1e-3)
     launch_ms = ms
     achieved = frame_bytes / (launch_ms * 1e-3) / 1e9
-    traffic, traffic_kernel = measured_traffic()
+    traffic, traffic_kernel = measured_traffic() if args.cell == 2 else (None, None)
     traffic_src = ("rocprofv3 FETCH_SIZE + WRITE_SIZE of %s, scaled by a copy kernel's counts; %s"
                    % (traffic_kernel, os.path.relpath(PROFILE, ROOT))) if traffic else \
         "no counters for the current kernel sources"
@@ -213,8 +217,10 @@ def main():
         "dtype": "fp16 hi+lo split MFMA (3 products), fp32 accumulate; fp32 inversion and solve",
         "data": "synthetic",
         "config": {
-            "workload": "PD-WF, B=256 as 8 clusters x 32, U=16, 1200 subcarriers x 14 symbols, "
-                        "i.i.d. Rayleigh complex64, 16-QAM, SNR 10 dB",
+            "workload": "PD-WF, B=%d as %d clusters x %d, U=%d, %d subcarriers x %d symbols, %s complex64, "
+                        "%d-QAM, SNR %g dB" % (B, len(sizes), sizes[0], U, n_sc, K,
+                                               "i.i.d. Rayleigh" if cell.channel == "rayleigh" else
+                                               "Kronecker-correlated (r = %g)" % cell.r, cell.qam, cell.snr_db),
             "arch": "PD", "mode": "WF", "B": B, "C": len(sizes), "U": U, "n_sc": n_sc, "K": K,
             "impl": ctx.last_impl, "precision": HEAD_PREC, "frames_rotated": n_frames,
             "waves_per_workgroup": ctx.last_waves,
@@ -264,12 +270,13 @@ def main():
             "fused_fp32_ms_per_step": ms_fd32, "fused_fp32_value": n_sc * K / (ms_fd32 * 1e-3),
             "fused_fp32_achieved_gbs": frame_bytes / (ms_fd32 * 1e-3) / 1e9,
             "plain_fp32_ms_per_step": ms_fd_plain, "speedup_vs_plain": ms_fd_plain / ms_fd32,
-            "note": "clusters of 32 with U = 16 meet U / B_c >= 0.5: the default routing takes the FP64 route",
+            "note": "clusters of %d with U = %d meet U / B_c >= 0.5: the default routing takes the FP64 route"
+                    % (sizes[0], U),
             "default_route_ms_per_step": ms_fd, "default_route_impl": fd_impl,
             "default_route_value": n_sc * K / (ms_fd * 1e-3),
             "plain_fp64_route_ms_per_step": ms_fd_plain64, "fp64_route_speedup_vs_plain": ms_fd_plain64 / ms_fd,
         }
-    if not args.quick:
+    if not args.quick and not args.no_serving:
         out["serving"] = serving_leg(ctx, pc, Hs, Ss, cell, dev, args)
     if not args.no_cpu:
         out["cpu_baseline"], out["rel_err"] = cpu_baseline(cell, Hs[0], Ss[0], Xs[0], betas[0], ctx, pc, stream,

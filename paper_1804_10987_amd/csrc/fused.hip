@@ -63,6 +63,9 @@ namespace {
 
 constexpr int kNWs[] = {1, 2, 4};
 constexpr int kDefaultNW = 4;
+// the last-level (Infinity) cache: a channel no larger stays resident across
+// back-to-back calls on the same inputs
+constexpr size_t kCacheBytes = size_t(256) << 20;
 
 bool nw_feasible(const Prob &p, int nw) {
     const int up = pick_up(p.U);
@@ -171,16 +174,20 @@ int choose_nw(const Prob &p, int prec, int mode, int K, const float2 *H, const f
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(st, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) return dflt;
     // candidates; shapes that stream the rows twice are dropped when another
-    // keeps them in registers: the timing repeats the call on the same
-    // inputs, which then sit in the cache and hide the second pass's HBM
-    // traffic
+    // keeps them in registers and the channel fits the cache: the timing
+    // repeats the call on the same inputs, which then sit in the cache and
+    // hide the second pass's HBM traffic.  A larger channel is re-read from
+    // HBM on every call, so the timing is fair to every shape (with 32
+    // users, 512 antennas and 3300 subcarriers the streamed shapes take
+    // 0.33 ms and the register-tile split 0.54 ms).
     int cands[3], nc = 0;
+    const bool cache_hot = size_t(p.n_sc) * size_t(p.B) * size_t(p.U) * sizeof(float2) <= kCacheBytes;
     bool any_tiles = false;
     for (int nw : kNWs) {
         int mt;
         bool sp;
         pick_tiles(p, nw, &mt, &sp);
-        if (nw_feasible(p, nw) && mt > 0) any_tiles = true;
+        if (nw_feasible(p, nw) && mt > 0 && cache_hot) any_tiles = true;
     }
     for (int nw : kNWs) {
         int mt;

@@ -484,3 +484,38 @@ def test_full_size_sampled(torch, ctx, pc, arch, prec, tol):
     e = _check(x.cpu().numpy()[:, idx], sc.cpu().numpy().reshape((cell.n_sc,) + sco.shape[1:])[idx],
                st.cpu().numpy().reshape((cell.n_sc,) + sto.shape[1:])[idx], xo, sco, sto, tol=tol)
     print("max rel err %.3e" % e, flush=True)
+
+
+@pytest.fixture(scope="module")
+def cell_u32(torch):
+    """B=512 as 16 x 32, U=32, 3300 subcarriers x 14 symbols, channel with
+    exponential antenna correlation r = 0.5; 16 sampled subcarriers for the
+    oracle."""
+    cell = synth.config(3)
+    H, s = synth.make_cell(cell, seed=0)
+    idx = np.sort(np.random.default_rng(3).choice(cell.n_sc, size=16, replace=False))
+    return cell, H[idx].copy(), s[:, idx].copy(), _dev(torch, H), _dev(torch, s), idx
+
+
+@pytest.mark.parametrize("impl,prec,ratio,tol", [
+    ("fused", "fp32", 2.0, 1e-5), ("fused", "split_fp16", 2.0, 1e-5), ("fused", "split_bf16", 2.0, 1e-3),
+    ("auto", "fp32", 0.5, 1e-5)], ids=["fused-fp32", "fused-split_fp16", "fused-split_bf16", "default_route"])
+@pytest.mark.parametrize("arch", ["pd", "fd"])
+def test_full_size_sampled_u32(torch, ctx, pc, cell_u32, arch, impl, prec, ratio, tol):
+    """The 32-user workload at full size; the oracle checks the sampled
+    subcarriers.  With the default ratio 0.5, FD's square local systems
+    (B_c = U = 32) take the FP64 route."""
+    cell, Hs, ss, Hd, sd, idx = cell_u32
+    print("u32 full size: arch %s impl %s prec %s ratio %g" % (arch, impl, prec, ratio), flush=True)
+    fn = ctx.pd if arch == "pd" else ctx.fd
+    x, sc, st = fn(Hd, sd, cell.kappa, cell.sizes, "wf", pc.params(fp64_ratio=ratio, precision=prec, impl=impl))
+    torch.cuda.synchronize()
+    if impl == "fused":
+        assert ctx.last_impl == "fused"
+    xo, sco, sto = _oracle(arch, Hs, ss, cell.kappa, cell.sizes, "wf")
+    stg = st.cpu().numpy().reshape((cell.n_sc,) + sto.shape[1:])[idx]
+    if arch == "fd":
+        assert ((stg & 2) == (2 if ratio <= 1.0 else 0)).all()
+    e = _check(x.cpu().numpy()[:, idx], sc.cpu().numpy().reshape((cell.n_sc,) + sco.shape[1:])[idx], stg,
+               xo, sco, sto, tol=tol)
+    print("max rel err %.3e" % e, flush=True)
