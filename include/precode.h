@@ -124,7 +124,9 @@ int precode_ctx_last_impl(const precode_ctx *ctx);
  * own launch, repeated on its stream, before the call returns) and reuses
  * the fastest; PRECODE_FUSED_WAVES=1|2|4 in the environment forces a shape,
  * PRECODE_AUTOTUNE=0 keeps the default shape (the fewest waves per
- * workgroup that keep the rows in registers); PRECODE_FUSED_STREAM=1 makes
+ * workgroup that keep the rows in registers; at 17 to 32 users the fewest
+ * that stream them, for PD systems whose rows need a whole workgroup);
+ * PRECODE_FUSED_STREAM=1 makes
  * every wave stream its channel rows twice instead of keeping them in
  * registers.  Calls made under stream capture
  * never tune.  Shapes differ only in the order of the cluster-sum rounding. */

@@ -139,16 +139,27 @@ std::string tune_key(const Prob &p, int prec, int mode, int K) {
 
 thread_local bool t_autotune = true;
 
-// The shape of an untuned call (tuning off, stream capture): the fewest
-// waves per workgroup that keep the system's rows in register tiles (split
-// over the workgroup for large PD cells), else the default.
+// The shape of an untuned call (tuning off, stream capture, serving): the
+// fewest waves per workgroup that keep the system's rows in register tiles
+// (split over the workgroup for large PD cells), else the default.  At 32
+// users the split holds one wave per SIMD and loses to streaming the rows
+// (512 antennas, 3300 subcarriers: 0.52 ms against 0.32 ms), so there the
+// fewest waves that stream are taken instead.
 int default_nw(const Prob &p) {
+    const bool up32 = pick_up(p.U) == 32;
     for (int nw : kNWs) {
         int mt;
         bool sp;
         pick_tiles(p, nw, &mt, &sp);
-        if (mt > 0 && nw_feasible(p, nw)) return nw;
+        if (mt > 0 && !(sp && up32) && nw_feasible(p, nw)) return nw;
     }
+    if (up32)
+        for (int nw : kNWs) {
+            int mt;
+            bool sp;
+            pick_tiles(p, nw, &mt, &sp);
+            if (!sp && nw_feasible(p, nw)) return nw;
+        }
     if (nw_feasible(p, kDefaultNW)) return kDefaultNW;
     for (int nw : kNWs)
         if (nw_feasible(p, nw)) return nw;

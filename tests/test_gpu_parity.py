@@ -374,6 +374,21 @@ def test_autotuned_shape_is_cached_and_deterministic(torch, ctx, pc, monkeypatch
     assert torch.equal(x1, x2)
 
 
+@pytest.mark.parametrize("u,expect", [(16, 2), (32, 1)])
+def test_untuned_default_shape(torch, ctx, pc, monkeypatch, u, expect):
+    """With tuning off (as under stream capture and in serving) PD takes the
+    fewest waves per workgroup that keep the rows in register tiles at 16
+    users, and the fewest that stream them at 32 users."""
+    monkeypatch.delenv("PRECODE_FUSED_WAVES", raising=False)
+    monkeypatch.setenv("PRECODE_AUTOTUNE", "0")
+    cell = synth.Cell(B=256, sizes=(32,) * 8, U=u, n_sc=23, K=14)
+    H, s = synth.make_cell(cell, seed=13)
+    xg, scg, stg = _run(torch, ctx, pc, "pd", H, s, cell.kappa, cell.sizes, "wf")
+    assert ctx.last_impl == "fused" and ctx.last_waves == expect
+    xo, sco, sto = _oracle("pd", H, s, cell.kappa, cell.sizes, "wf")
+    _check(xg, scg, stg, xo, sco, sto)
+
+
 # Mixed batch spanning every launch class and the plain fallback: tile widths
 # 16 / 32, PD / FD, 1..8 channel tiles per wave, symbol slicing (K > 64),
 # FD clusters smaller than U and U > 32 (plain kernels), an empty job.
