@@ -148,19 +148,35 @@ def main():
         per = [a.elapsed_time(b) for a, b in ev]
         return total / steps, per
 
-    def time_graph(fn, steps, warmup):
+    def time_graph(fn, steps, warmup, n_streams=1):
         """The timed region as HIP graph replays: fn(frame) for every rotating
         frame recorded once into a graph (after `warmup` eager calls, which
         also settle the launch-shape autotuner) and replayed; returns
-        (ms per frame, frames timed).  No host call sits between launches."""
+        (ms per frame, frames timed).  No host call sits between launches.
+        With n_streams > 1 the frames go round-robin to that many streams
+        forked from and joined back into the graph's stream, so one frame's
+        launch may overlap the next one's (each frame has its own buffers)."""
         for i in range(warmup):
             fn(i % n_frames)
         torch.cuda.synchronize()
         g = torch.cuda.CUDAGraph()
         cs = torch.cuda.Stream()
+        side = [torch.cuda.Stream() for _ in range(n_streams)] if n_streams > 1 else []
         with torch.cuda.graph(g, stream=cs):
+            fork = torch.cuda.Event()
+            fork.record(cs)
+            for s_ in side:
+                s_.wait_event(fork)
             for f in range(n_frames):
-                fn(f)
+                if side:
+                    with torch.cuda.stream(side[f % n_streams]):
+                        fn(f)
+                else:
+                    fn(f)
+            for s_ in side:
+                join = torch.cuda.Event()
+                join.record(s_)
+                cs.wait_event(join)
         torch.cuda.synchronize()
         g.replay()
         torch.cuda.synchronize()
@@ -248,6 +264,14 @@ def main():
         variants[prec] = {"ms_per_step": ms_v, "value": n_sc * K / (ms_v * 1e-3),
                           "achieved_gbs": frame_bytes / (ms_v * 1e-3) / 1e9, "waves_per_workgroup": ctx.last_waves}
     out["pd_precision_variants"] = variants
+    # consecutive frames on two streams: the next frame's loads overlap the
+    # previous frame's inversion and tail (not the headline: each launch's
+    # own duration grows under the overlap)
+    ms_2s, _ = time_graph(pd_fused, args.steps, 3, n_streams=2)
+    out["pd_two_streams"] = {"ms_per_frame": ms_2s, "value": n_sc * K / (ms_2s * 1e-3),
+                             "achieved_gbs": frame_bytes / (ms_2s * 1e-3) / 1e9,
+                             "note": "frames round-robin on 2 streams inside one graph, one launch per frame; "
+                                     "throughput over the timed region"}
     # every launch shape the autotuner chooses from, forced
     shapes = {}
     for nw in (1, 2, 4):
