@@ -252,7 +252,9 @@ int precode_batch_plan_destroy(precode_batch_plan *plan);
  *   - admission enqueues the per-frame part (Gram, factors, beta / weights,
  *     Sec. IV-B) on one of n_streams streams; released symbols are precoded
  *     from the resident factors as they are released, jobs overlapping on
- *     the device across streams;
+ *     the device across streams; a job with symbol_period_s == 0 whose shape
+ *     the fused kernel takes is instead precoded in one launch from Gram to
+ *     precode (its channel read once);
  *   - a job's state returns to the slab after its last symbol completes.
  * The call allocates the slab and streams once; the loop itself never
  * allocates, and runs no launch-shape timing (see precode_ctx_last_waves): a

@@ -13,7 +13,10 @@
 //              the job's stream as soon as it is admitted
 //   symbols    symbols whose release time has passed are precoded from the
 //              resident factors, all newly released symbols of a job in one
-//              launch; jobs on different streams overlap on the device
+//              launch; jobs on different streams overlap on the device.  A
+//              job with a zero symbol period (every symbol released at
+//              arrival) on the fused kernels takes one launch from Gram to
+//              precode instead of prepare + symbols
 //   retire     when a job's last symbol completes its state returns to the slab
 //              and waiting jobs can be admitted
 //
@@ -259,8 +262,16 @@ extern "C" int precode_serve(precode_ctx *ctx, const precode_serve_job *jobs, in
             s.scale_out = (float *)m;
             m += (ni * sizeof(float) + 255) & ~(size_t)255;
             s.status = (int *)m;
+            // a job whose symbols are all released at arrival (zero symbol
+            // period) is precoded in one launch that keeps the channel in
+            // registers from the Gram to the precode, so the channel is read
+            // once instead of once for the factors and again for the symbols
+            const bool one_launch = s.fused && j.n_sc > 0 && j.K > 0 && s.src->symbol_period_s <= 0;
             if (j.n_sc > 0) {
-                if (s.fused)
+                if (one_launch)
+                    e = fused_run(s.p, s.precision, (const float2 *)j.H, (const float2 *)j.s, (float2 *)j.x,
+                                  s.scale_out, s.status, stream);
+                else if (s.fused)
                     e = fused_prepare(s.p, s.precision, (const float2 *)j.H, s.ainv, s.scale_out, s.status, stream);
                 else
                     e = plain_prepare(s.p, (const float2 *)j.H, s.scale_out, s.status, s.wsA, s.ainv, s.wsScale,
@@ -269,6 +280,19 @@ extern "C" int precode_serve(precode_ctx *ctx, const precode_serve_job *jobs, in
                     e = hipMemcpyAsync(j.scale, s.scale_out, ni * sizeof(float), hipMemcpyDeviceToDevice, stream);
                 if (e == hipSuccess && j.status)
                     e = hipMemcpyAsync(j.status, s.status, ni * sizeof(int), hipMemcpyDeviceToDevice, stream);
+            }
+            if (e == hipSuccess && one_launch) {
+                Launch L;
+                L.ev = get_event();
+                L.k0 = 0;
+                L.nk = j.K;
+                e = L.ev ? hipEventRecord(L.ev, stream) : hipErrorOutOfMemory;
+                if (e == hipSuccess) {
+                    s.inflight.push_back(L);
+                    s.next = j.K;
+                } else if (L.ev) {
+                    evpool.push_back(L.ev);
+                }
             }
             if (e != hipSuccess) {
                 rc_out = PRECODE_EDEVICE;

@@ -49,6 +49,21 @@ def _jobs(torch, cells, seed=0):
     return jobs, host
 
 
+def _check_oracle(i, arch, c, H, s, x, sc, stt):
+    if arch == "pd":
+        xo, sco, sto = oracle.pd(H, s, c.kappa, c.sizes)
+    else:
+        xo, sco, sto = oracle.fd(H, s, c.kappa, c.sizes)
+    xg = x.cpu().numpy().reshape(xo.shape)
+    e = np.linalg.norm(xg - xo, axis=-1) / np.maximum(np.linalg.norm(xo, axis=-1), 1e-30)
+    print("job %d %s B=%d U=%d max rel err %.2e" % (i, arch, c.B, c.U, e.max()), flush=True)
+    assert e.max() <= 1e-5
+    sco, sto = np.asarray(sco).ravel(), np.asarray(sto).ravel()
+    assert ((stt.cpu().numpy().ravel() & 1) == sto).all()
+    scg = sc.cpu().numpy().ravel()
+    assert (np.abs(scg - sco) <= 1e-5 * np.abs(sco)).all()
+
+
 def test_serving_mix_equals_alone_and_oracle(torch, ctx):
     cells = _cells()
     jobs, host = _jobs(torch, cells)
@@ -65,18 +80,28 @@ def test_serving_mix_equals_alone_and_oracle(torch, ctx):
         torch.cuda.synchronize()
         assert torch.equal(x, xa), "job %d differs alone vs in the mix" % i
         assert torch.equal(sc, sca)
-        if arch == "pd":
-            xo, sco, sto = oracle.pd(H, s, c.kappa, c.sizes)
-        else:
-            xo, sco, sto = oracle.fd(H, s, c.kappa, c.sizes)
-        xg = x.cpu().numpy().reshape(xo.shape)
-        e = np.linalg.norm(xg - xo, axis=-1) / np.maximum(np.linalg.norm(xo, axis=-1), 1e-30)
-        print("job %d %s B=%d U=%d max rel err %.2e" % (i, arch, c.B, c.U, e.max()), flush=True)
-        assert e.max() <= 1e-5
-        sco, sto = np.asarray(sco).ravel(), np.asarray(sto).ravel()
-        assert ((stt.cpu().numpy().ravel() & 1) == sto).all()
-        scg = sc.cpu().numpy().ravel()
-        assert (np.abs(scg - sco) <= 1e-5 * np.abs(sco)).all()
+        _check_oracle(i, arch, c, H, s, x, sc, stt)
+
+
+def test_serving_zero_period_one_launch(torch, ctx):
+    """Every symbol released at arrival: the jobs on the fused kernels take
+    one launch from Gram to precode.  Each result is bitwise the same alone
+    and in the mix, and matches the oracle."""
+    cells = _cells()
+    jobs, host = _jobs(torch, cells, seed=5)
+    arrivals = [0.0, 0.0001, 0.0001, 0.0003, 0.0004, 0.0004]
+    print("serving mix of %d jobs, zero symbol period" % len(jobs), flush=True)
+    outs, lat, st = ctx.serve(jobs, arrivals, symbol_period_s=0.0, max_active=4, n_streams=3)
+    torch.cuda.synchronize()
+    assert st["jobs_done"] == len(jobs)
+    assert st["symbols_done"] == 14 * len(jobs)
+    assert all((l >= 0).all() for l in lat)
+    for i, ((arch, c, H, s), (x, sc, stt)) in enumerate(zip(host, outs)):
+        (xa, sca, sta), = ctx.serve([jobs[i]], [0.0], symbol_period_s=0.0, max_active=1, n_streams=1)[0]
+        torch.cuda.synchronize()
+        assert torch.equal(x, xa), "job %d differs alone vs in the mix" % i
+        assert torch.equal(sc, sca)
+        _check_oracle(i, arch, c, H, s, x, sc, stt)
 
 
 def test_serving_admission_by_budget(torch, ctx):
