@@ -264,14 +264,16 @@ def main():
         variants[prec] = {"ms_per_step": ms_v, "value": n_sc * K / (ms_v * 1e-3),
                           "achieved_gbs": frame_bytes / (ms_v * 1e-3) / 1e9, "waves_per_workgroup": ctx.last_waves}
     out["pd_precision_variants"] = variants
-    # consecutive frames on two streams: the next frame's loads overlap the
-    # previous frame's inversion and tail (not the headline: each launch's
-    # own duration grows under the overlap)
-    ms_2s, _ = time_graph(pd_fused, args.steps, 3, n_streams=2)
-    out["pd_two_streams"] = {"ms_per_frame": ms_2s, "value": n_sc * K / (ms_2s * 1e-3),
-                             "achieved_gbs": frame_bytes / (ms_2s * 1e-3) / 1e9,
-                             "note": "frames round-robin on 2 streams inside one graph, one launch per frame; "
-                                     "throughput over the timed region"}
+    if not args.quick:
+        # consecutive frames on two streams: the next frame's loads overlap the
+        # previous frame's inversion and tail (not the headline: each launch's
+        # own duration grows under the overlap, so it stays out of the
+        # profiling runs that time the headline kernel)
+        ms_2s, _ = time_graph(pd_fused, args.steps, 3, n_streams=2)
+        out["pd_two_streams"] = {"ms_per_frame": ms_2s, "value": n_sc * K / (ms_2s * 1e-3),
+                                 "achieved_gbs": frame_bytes / (ms_2s * 1e-3) / 1e9,
+                                 "note": "frames round-robin on 2 streams inside one graph, one launch per frame; "
+                                         "throughput over the timed region"}
     # every launch shape the autotuner chooses from, forced
     shapes = {}
     for nw in (1, 2, 4):

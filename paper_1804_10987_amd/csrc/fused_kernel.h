@@ -1360,6 +1360,10 @@ __device__ __forceinline__ void wg_pd_split(const Prob &p, int blk, int K, int m
                     make_float4(acc[q][4 * r4], acc[q][4 * r4 + 1], acc[q][4 * r4 + 2], acc[q][4 * r4 + 3]);
         __syncthreads();
         if (wave == mw) {
+            // the master's partial sums, inversion and solve are the serial
+            // chain every wave of the workgroup waits on: it issues ahead of
+            // co-resident waves until the first chunk is solved
+            __builtin_amdgcn_s_setprio(3);
             if (pre_sym) load_sym<UP>(s0, (size_t)n_sc * U, U, min(KC, K), sym0);
             floatx16 sum[NTT];
 #pragma unroll
@@ -1408,6 +1412,7 @@ __device__ __forceinline__ void wg_pd_split(const Prob &p, int blk, int K, int m
                 sym_to_zop<UP, kF32>(sym, U, kc, zs);
             }
             wave_solve_chunk<UP, kF32>(Am, Zm, zs, kc, U, sh_scale, sh_amax, sh_ok != 0);
+            __builtin_amdgcn_s_setprio(0);
         }
         __syncthreads();
         ZOp<UP, PREC> z;
