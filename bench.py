@@ -149,13 +149,15 @@ def main():
         return total / steps, per
 
     def time_graph(fn, steps, warmup, n_streams=1):
-        """The timed region as HIP graph replays: fn(frame) for every rotating
-        frame recorded once into a graph (after `warmup` eager calls, which
-        also settle the launch-shape autotuner) and replayed; returns
-        (ms per frame, frames timed).  No host call sits between launches.
-        With n_streams > 1 the frames go round-robin to that many streams
-        forked from and joined back into the graph's stream, so one frame's
-        launch may overlap the next one's (each frame has its own buffers)."""
+        """The timed region as one HIP graph replay of exactly `steps` frames:
+        fn(frame) for frames 0, 1, ... rotating over the frame buffers,
+        recorded once into a graph (after `warmup` eager calls, which also
+        settle the launch-shape autotuner), replayed once untimed, then once
+        timed; returns (ms per frame, frames timed).  No host call sits
+        between launches.  With n_streams > 1 the frames go round-robin to
+        that many streams forked from and joined back into the graph's stream,
+        so one frame's launch may overlap the next one's (each frame has its
+        own buffers)."""
         for i in range(warmup):
             fn(i % n_frames)
         torch.cuda.synchronize()
@@ -167,9 +169,10 @@ def main():
             fork.record(cs)
             for s_ in side:
                 s_.wait_event(fork)
-            for f in range(n_frames):
+            for i in range(steps):
+                f = i % n_frames
                 if side:
-                    with torch.cuda.stream(side[f % n_streams]):
+                    with torch.cuda.stream(side[i % n_streams]):
                         fn(f)
                 else:
                     fn(f)
@@ -180,15 +183,13 @@ def main():
         torch.cuda.synchronize()
         g.replay()
         torch.cuda.synchronize()
-        reps = max(1, -(-steps // n_frames))
         t0 = torch.cuda.Event(enable_timing=True)
         t1 = torch.cuda.Event(enable_timing=True)
         t0.record()
-        for _ in range(reps):
-            g.replay()
+        g.replay()
         t1.record()
         torch.cuda.synchronize()
-        return t0.elapsed_time(t1) / (reps * n_frames), reps * n_frames
+        return t0.elapsed_time(t1) / steps, steps
 
     def pd_fused(f, prec=HEAD_PREC):
         ctx.pd(Hs[f], Ss[f], cell.kappa, sizes, "wf", pc.params(precision=prec, impl="fused"),
@@ -368,10 +369,38 @@ def serving_leg(ctx, pc, Hs, Ss, cell, dev, args):
     return res
 
 
+def cpu_model():
+    """The host CPU's model name (lscpu's "Model name", from /proc/cpuinfo)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def time_oracle(cell, H, s, threads, min_s):
+    """Subcarrier-symbols per second of the FP64 oracle on `threads` host
+    threads over the given frame (H, s), repeated until min_s of wall time."""
+    import oracle
+
+    reps = 0
+    t0 = time.perf_counter()
+    while True:
+        oracle.pd(H, s, cell.kappa, cell.sizes, threads=threads)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= min_s:
+            break
+    return reps * H.shape[0] * s.shape[0] / el, reps, el
+
+
 def cpu_baseline(cell, Hd, sd, xd, bd, ctx, pc, stream, precs):
     """The FP64 oracle on the host cores over the same frame (repeated until
-    about 2 s of wall time), and the GPU's error against it on that frame for
-    each precision in precs."""
+    about 2 s of wall time), on one core, and on bounded samples of the tiny
+    and the precision workloads; and the GPU's error against it on that
+    frame for each precision in precs."""
     import numpy as np
     import torch
 
@@ -388,22 +417,29 @@ def cpu_baseline(cell, Hd, sd, xd, bd, ctx, pc, stream, precs):
     threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     threads = min(threads, int(os.environ.get("OMP_NUM_THREADS", threads)))
     oracle.build(force=False)
-    reps = 0
-    t0 = time.perf_counter()
-    while True:
-        xo, bo, st = oracle.pd(H, s, cell.kappa, cell.sizes, threads=threads)
-        reps += 1
-        el = time.perf_counter() - t0
-        if el >= 2.0:
-            break
-    value = reps * cell.n_sc * cell.K / el
+    xo, bo, st = oracle.pd(H, s, cell.kappa, cell.sizes, threads=threads)
+    value, reps, el = time_oracle(cell, H, s, threads, 2.0)
+    one, reps1, el1 = time_oracle(cell, H[:300], s[:, :300], 1, 2.0)
+    others = {}
+    for i, frac in ((1, 1), (3, 8)):
+        c = synth.config(i)
+        Hc, sc_ = synth.make_cell(c, seed=0, frame=0)
+        n = max(1, c.n_sc // frac)
+        v, r, e_ = time_oracle(c, Hc[:n], sc_[:, :n], threads, 1.0)
+        others[str(i)] = {"value": v, "cores": threads,
+                          "sample": "%d x %d subcarriers x %d symbols (B=%d, U=%d), %.2f s wall"
+                                    % (r, n, c.K, c.B, c.U, e_)}
     rel = {"vs": "FP64 oracle, full frame 0; per (subcarrier, symbol) ||x - x_oracle|| / ||x_oracle||"}
     for prec, (xg, bg) in gpu.items():
         e = np.linalg.norm(xg - xo, axis=-1) / np.linalg.norm(xo, axis=-1)
         rel[prec] = {"max": float(e.max()), "p99": float(np.percentile(e, 99)), "p50": float(np.percentile(e, 50)),
                      "beta_max": float(np.max(np.abs(bg - bo) / bo))}
     return ({"value": value, "unit": "subcarrier-symbols/s", "cores": threads, "kind": "oracle",
-             "sample": "%d full frame(s) (1200 subcarriers x 14 symbols), %.2f s wall" % (reps, el)}, rel)
+             "sample": "%d full frame(s) (1200 subcarriers x 14 symbols), %.2f s wall" % (reps, el),
+             "cpu_model": cpu_model(),
+             "one_core": {"value": one, "cores": 1,
+                          "sample": "%d x 300 subcarriers x 14 symbols, %.2f s wall" % (reps1, el1)},
+             "workloads": others}, rel)
 
 
 if __name__ == "__main__":

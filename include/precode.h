@@ -25,7 +25,13 @@
  *    (eq. precodingfactor); it is ignored for ZF (kappa = 0).
  *  - Calls are asynchronous on `stream` (a hipStream_t passed as void*;
  *    NULL = the default stream) and return after enqueueing.  A context is
- *    not thread-safe: use one context per host thread.
+ *    not thread-safe: use one context per host thread.  The plain kernels'
+ *    workspace is one per context: plain-path calls of one context on
+ *    different streams are ordered by the library (each waits for the
+ *    previous one's use of it), so they do not overlap on the device.  Under
+ *    stream capture that workspace must already be large enough (an earlier
+ *    uncaptured call of the same or a larger shape), else
+ *    PRECODE_EUNSUPPORTED; a captured call is ordered by its capture only.
  *  - Errors detectable on the host are returned before anything is
  *    launched.  Per-instance numerical failures are reported asynchronously
  *    through `status` (see PRECODE_ST_*), never through the return code.
@@ -47,10 +53,19 @@ extern "C" {
 #define PRECODE_EDEVICE (-4)      /* a HIP runtime error                          */
 
 /* ---- per-instance status values (bit flags, written asynchronously) ---- */
+/* An instance whose FP32 factorization fails (a pivot not above 2^-20 of
+ * its original diagonal entry, a non-finite value, or Lemma 1's t <= 0) is
+ * solved again on the FP64 route in the same call: FP64 Gram, Cholesky
+ * factorization, solve and precode (Theorem 1 only needs A invertible).  It
+ * is flagged PRECODE_ST_FAIL only if the FP64 factorization fails as well
+ * (a pivot not above 2^-40 of its original diagonal entry, or t <= 0). */
 #define PRECODE_ST_OK 0   /* solved                                          */
-#define PRECODE_ST_FAIL 1 /* non-positive pivot / non-finite value / zero    */
-                          /* power: x is set to 0, beta / weight to 0        */
-#define PRECODE_ST_FP64 2 /* solved on the FP64 route (Gram + factorization) */
+#define PRECODE_ST_FAIL 1 /* numerically singular on the FP64 route as well  */
+                          /* (always with PRECODE_ST_FP64): x is set to 0,   */
+                          /* beta / weight to 0                              */
+#define PRECODE_ST_FP64 2 /* solved on the FP64 route: routed there by       */
+                          /* fp64_ratio / precision FP64, or retried there   */
+                          /* after its FP32 factorization failed             */
 
 /* ---- enums ---------------------------------------------------------------- */
 enum precode_mode { PRECODE_ZF = 0, PRECODE_WF = 1 };

@@ -33,9 +33,14 @@ struct precode_ctx {
     int device;
     size_t budget;
     size_t held;
-    // plain-kernel workspace (grow-only)
+    // plain-kernel workspace (grow-only), shared by every plain-path call of
+    // the context: wsDone marks the end of the last call's use of it on
+    // wsStream, and a call on another stream waits for it first
     void *wsA, *wsAinv, *wsScale, *wsZ;
     size_t capA, capAinv, capScale, capZ;
+    hipEvent_t wsDone;
+    hipStream_t wsStream;
+    int wsUsed;
     precode_frame *frames;
     int last_impl;
     int last_waves;  // waves per workgroup of the last fused launch
@@ -87,10 +92,22 @@ void ctx_free(precode_ctx *ctx, void *ptr, size_t bytes) {
     ctx->held -= bytes;
 }
 
+bool capturing(hipStream_t st) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return cs != hipStreamCaptureStatusNone;
+}
+
 // Grow a workspace buffer to at least `need` bytes.  The caller's stream may
 // still be using the old buffer, so the device is synchronized before a free.
-int grow(precode_ctx *ctx, void **buf, size_t *cap, size_t need) {
+// Under stream capture nothing may synchronize or allocate: the workspace
+// must already be large enough (an earlier uncaptured call of the shape).
+int grow(precode_ctx *ctx, void **buf, size_t *cap, size_t need, hipStream_t st) {
     if (*cap >= need) return PRECODE_OK;
+    if (capturing(st)) return PRECODE_EUNSUPPORTED;
     if (*buf) {
         (void)hipDeviceSynchronize();
         ctx_free(ctx, *buf, *cap);
@@ -100,6 +117,24 @@ int grow(precode_ctx *ctx, void **buf, size_t *cap, size_t need) {
     int rc = ctx_alloc(ctx, buf, need);
     if (rc == PRECODE_OK) *cap = need;
     return rc;
+}
+
+// Orders this call's use of the shared plain-path workspace after the last
+// one, which may have been enqueued on another stream.  Inside a stream
+// capture the captured stream's own order applies (no external wait).
+int ws_acquire(precode_ctx *ctx, hipStream_t st) {
+    if (!ctx->wsUsed || ctx->wsStream == st || capturing(st)) return PRECODE_OK;
+    return hipStreamWaitEvent(st, ctx->wsDone, 0) == hipSuccess ? PRECODE_OK : PRECODE_EDEVICE;
+}
+
+int ws_release(precode_ctx *ctx, hipStream_t st) {
+    if (capturing(st)) return PRECODE_OK;
+    if (!ctx->wsDone && hipEventCreateWithFlags(&ctx->wsDone, hipEventDisableTiming) != hipSuccess)
+        return PRECODE_EDEVICE;
+    if (hipEventRecord(ctx->wsDone, st) != hipSuccess) return PRECODE_EDEVICE;
+    ctx->wsStream = st;
+    ctx->wsUsed = 1;
+    return PRECODE_OK;
 }
 
 precode_params defaults() {
@@ -251,16 +286,18 @@ int run(precode_ctx *ctx, int arch, const void *H, const void *s, float rho, con
         }
         return rc;
     }
-    rc = grow(ctx, &ctx->wsA, &ctx->capA, plain_ws_bytes_A(p));
-    if (!rc) rc = grow(ctx, &ctx->wsAinv, &ctx->capAinv, plain_ws_bytes_A(p));
-    if (!rc) rc = grow(ctx, &ctx->wsScale, &ctx->capScale, plain_ws_bytes_scale(p));
-    if (!rc) rc = grow(ctx, &ctx->wsZ, &ctx->capZ, plain_ws_bytes_z(p, K > 0 ? K : 1));
+    rc = grow(ctx, &ctx->wsA, &ctx->capA, plain_ws_bytes_A(p), st);
+    if (!rc) rc = grow(ctx, &ctx->wsAinv, &ctx->capAinv, plain_ws_bytes_A(p), st);
+    if (!rc) rc = grow(ctx, &ctx->wsScale, &ctx->capScale, plain_ws_bytes_scale(p), st);
+    if (!rc) rc = grow(ctx, &ctx->wsZ, &ctx->capZ, plain_ws_bytes_z(p, K > 0 ? K : 1), st);
+    if (!rc) rc = ws_acquire(ctx, st);
     if (rc) return rc;
     rc = dev_err(plain_prepare(p, (const float2 *)H, scale, status, ctx->wsA, ctx->wsAinv, ctx->wsScale, st));
-    if (rc) return rc;
-    if (K > 0)
+    if (!rc && K > 0)
         rc = dev_err(plain_symbols(p, K, (const float2 *)H, (const float2 *)s, (float2 *)x, ctx->wsAinv,
                                    ctx->wsScale, ctx->wsZ, st, q.refine_steps));
+    const int rr = ws_release(ctx, st);
+    if (!rc) rc = rr;
     if (rc == PRECODE_OK) ctx->last_impl = PRECODE_IMPL_PLAIN;
     return rc;
 }
@@ -329,6 +366,7 @@ int precode_ctx_destroy(precode_ctx *ctx) {
     if (ctx->tabHost) (void)hipHostFree(ctx->tabHost);
     if (ctx->tabCopied) (void)hipEventDestroy(ctx->tabCopied);
     if (ctx->tabRead) (void)hipEventDestroy(ctx->tabRead);
+    if (ctx->wsDone) (void)hipEventDestroy(ctx->wsDone);
     delete ctx;
     return PRECODE_OK;
 }
@@ -400,10 +438,14 @@ int precode_frame_prepare(precode_ctx *ctx, int arch, const void *H, float rho, 
             rc = dev_err(fused_prepare(p, q.precision, (const float2 *)H, (float2 *)f->ainv, f->scale_out, f->status,
                                        (hipStream_t)stream));
         } else {
-            rc = grow(ctx, &ctx->wsA, &ctx->capA, bA);
-            if (!rc)
+            rc = grow(ctx, &ctx->wsA, &ctx->capA, bA, (hipStream_t)stream);
+            if (!rc) rc = ws_acquire(ctx, (hipStream_t)stream);
+            if (!rc) {
                 rc = dev_err(plain_prepare(p, (const float2 *)H, f->scale_out, f->status, ctx->wsA, f->ainv,
                                            f->scale, (hipStream_t)stream));
+                const int rr = ws_release(ctx, (hipStream_t)stream);
+                if (!rc) rc = rr;
+            }
         }
     }
     if (rc) {
@@ -427,12 +469,16 @@ int precode_frame_symbols(precode_ctx *ctx, precode_frame *f, const void *s, int
     Prob p = f->prob;
     p.K = nk;
     if (f->fused)
-        return dev_err(fused_symbols(p, f->precision, nk, f->H, (const float2 *)f->ainv, (const float2 *)s,
-                                     (float2 *)x, (hipStream_t)stream));
-    int rc = grow(ctx, &ctx->wsZ, &ctx->capZ, plain_ws_bytes_z(p, nk));
+        return dev_err(fused_symbols(p, f->precision, nk, f->H, (const float2 *)f->ainv, f->status,
+                                     (const float2 *)s, (float2 *)x, (hipStream_t)stream));
+    hipStream_t st = (hipStream_t)stream;
+    int rc = grow(ctx, &ctx->wsZ, &ctx->capZ, plain_ws_bytes_z(p, nk), st);
+    if (!rc) rc = ws_acquire(ctx, st);
     if (rc) return rc;
-    return dev_err(plain_symbols(p, nk, f->H, (const float2 *)s, (float2 *)x, f->ainv, f->scale, ctx->wsZ,
-                                 (hipStream_t)stream, f->refine));
+    rc = dev_err(plain_symbols(p, nk, f->H, (const float2 *)s, (float2 *)x, f->ainv, f->scale, ctx->wsZ, st,
+                               f->refine));
+    const int rr = ws_release(ctx, st);
+    return rc ? rc : rr;
 }
 
 int precode_frame_factors(precode_ctx *ctx, precode_frame *f, float *scale, int *status, void *stream) {
@@ -488,7 +534,7 @@ int precode_batch(precode_ctx *ctx, const precode_job *jobs, int n_jobs, int pre
             }
             ctx->capTabHost = bytes;
         }
-        rc = grow(ctx, &ctx->tab, &ctx->capTab, bytes);
+        rc = grow(ctx, &ctx->tab, &ctx->capTab, bytes, st);
         if (rc) return rc;
         fused_batch_fill(fused.data(), (int)fused.size(), ctx->tabHost);
         // the device table may still be read by the previous batch's launches
@@ -504,11 +550,16 @@ int precode_batch(precode_ctx *ctx, const precode_job *jobs, int n_jobs, int pre
     }
     for (const auto &pp : plain) {
         const Prob &p = pp.second;
-        rc = grow(ctx, &ctx->wsA, &ctx->capA, plain_ws_bytes_A(p));
-        if (!rc) rc = grow(ctx, &ctx->wsAinv, &ctx->capAinv, plain_ws_bytes_A(p));
-        if (!rc) rc = grow(ctx, &ctx->wsScale, &ctx->capScale, plain_ws_bytes_scale(p));
-        if (!rc) rc = grow(ctx, &ctx->wsZ, &ctx->capZ, plain_ws_bytes_z(p, p.K > 0 ? p.K : 1));
-        if (!rc) rc = run_plain(p, jobs[pp.first], ctx->wsA, ctx->wsAinv, ctx->wsScale, ctx->wsZ, st);
+        rc = grow(ctx, &ctx->wsA, &ctx->capA, plain_ws_bytes_A(p), st);
+        if (!rc) rc = grow(ctx, &ctx->wsAinv, &ctx->capAinv, plain_ws_bytes_A(p), st);
+        if (!rc) rc = grow(ctx, &ctx->wsScale, &ctx->capScale, plain_ws_bytes_scale(p), st);
+        if (!rc) rc = grow(ctx, &ctx->wsZ, &ctx->capZ, plain_ws_bytes_z(p, p.K > 0 ? p.K : 1), st);
+        if (!rc) rc = ws_acquire(ctx, st);
+        if (!rc) {
+            rc = run_plain(p, jobs[pp.first], ctx->wsA, ctx->wsAinv, ctx->wsScale, ctx->wsZ, st);
+            const int rr = ws_release(ctx, st);
+            if (!rc) rc = rr;
+        }
         if (rc) return rc;
         if (fused.empty()) ctx->last_impl = PRECODE_IMPL_PLAIN;
     }

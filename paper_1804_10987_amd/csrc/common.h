@@ -121,13 +121,15 @@ int fused_default_waves();
 // default shape.
 void fused_set_autotune(bool on);
 // Frame split of the fused kernel: prepare writes scale * A^-1 per instance
-// (n_inst x U x U complex64, scale = 1/beta for PD, w_c for FD, zero for a
-// failed instance) with beta / weights and status; symbols precodes nk symbols
-// from it.
+// (n_inst x U x U complex64, scale = 1/beta for PD, w_c for FD; zero for an
+// instance on the FP64 route or failed) with beta / weights and status;
+// symbols precodes nk symbols from it, reading prepare's status: an instance
+// whose status is PRECODE_ST_FP64 (its FP32 factorization failed, the FP64
+// one succeeded) is solved on the FP64 route again at every symbol pass.
 hipError_t fused_prepare(const Prob &p, int precision, const float2 *H, float2 *ainv, float *scale_out, int *status,
                          hipStream_t st);
-hipError_t fused_symbols(const Prob &p, int precision, int nk, const float2 *H, const float2 *ainv, const float2 *s,
-                         float2 *x, hipStream_t st);
+hipError_t fused_symbols(const Prob &p, int precision, int nk, const float2 *H, const float2 *ainv,
+                         const int *status, const float2 *s, float2 *x, hipStream_t st);
 
 // Heterogeneous batch of fused problems (batch.hip): every problem must be
 // fused_supported at `precision` with K >= 1.  The problems are grouped by

@@ -297,11 +297,12 @@ hipError_t fused_prepare(const Prob &p, int precision, const float2 *H, float2 *
                     nullptr);
 }
 
-hipError_t fused_symbols(const Prob &p, int precision, int nk, const float2 *H, const float2 *ainv, const float2 *s,
-                         float2 *x, hipStream_t st) {
+hipError_t fused_symbols(const Prob &p, int precision, int nk, const float2 *H, const float2 *ainv,
+                         const int *status, const float2 *s, float2 *x, hipStream_t st) {
     if (!fused_supported(p, precision)) return hipErrorNotSupported;
     if (p.n_sc == 0 || nk == 0) return hipSuccess;
-    return run_mode(p, precision, kSymbols, nk, H, s, x, (cx<float> *)ainv, nullptr, nullptr, st, nullptr);
+    // status is only read in this mode
+    return run_mode(p, precision, kSymbols, nk, H, s, x, (cx<float> *)ainv, nullptr, (int *)status, st, nullptr);
 }
 
 }  // namespace pc

@@ -52,6 +52,12 @@ __device__ __forceinline__ double bperm_group_d(double v, int c4, int rk) {
     return __builtin_bit_cast(double, (unsigned long long)lo | ((unsigned long long)hi << 32));
 }
 
+__device__ __forceinline__ double wave_max_d(double v) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+
 __device__ __forceinline__ double wave_sum_d(double v) {
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) v += __shfl_xor(v, o);
@@ -179,16 +185,31 @@ __device__ __forceinline__ void f64_system(const Prob &p, const int *__restrict_
     }
     // d0 of column c lives in lane (c & 3, c) slot c >> 2; broadcast it down the column
     d0 = bperm_group_d(d0, 4 * c, c & 3);
+    // invert 2^-e A with its largest diagonal entry in [0.5, 1), so that no
+    // pivot exceeds 1 and 1 + 1/pivot in the update keeps 1/pivot exact to an
+    // ulp; A^-1 = 2^-e (2^-e A)^-1
+    const double dmax = wave_max_d(c < U ? d0 : 0.0);
+    int e = 0;
+    if (dmax > 0.0 && dmax < (double)INFINITY) e = ilogb(dmax) + 1;
+    const double sc = ldexp(1.0, -e);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const bool in = 4 * q + r < U && c < U;
+        gre[q] = in ? gre[q] * sc : gre[q];
+        gim[q] = in ? gim[q] * sc : gim[q];
+    }
+    d0 = c < U ? d0 * sc : d0;
     bool ok = wave_inverse_f64(gre, gim, U, d0);
     double tr = 0.0, fro = 0.0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int i = 4 * q + r;
+        const double vr = gre[q] * sc, vi = gim[q] * sc;
         if (i < U && c < U) {
-            fro += gre[q] * gre[q] + gim[q] * gim[q];
-            if (i == c) tr += gre[q];
+            fro += vr * vr + vi * vi;
+            if (i == c) tr += vr;
         }
-        ainv[i * kF64Up + c] = {gre[q], gim[q]};
+        ainv[i * kF64Up + c] = {vr, vi};
     }
     tr = wave_sum_d(tr);
     fro = wave_sum_d(fro);

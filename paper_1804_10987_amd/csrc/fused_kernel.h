@@ -5,12 +5,28 @@
 #include <stddef.h>
 
 #include "common.h"
+#include "retry_f64.h"
 
 namespace pc {
 
 namespace {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef float floatx2 __attribute__((ext_vector_type(2)));
+
+// Channel tile loads are a row's last read in a launch (register tiles are
+// read once; streamed rows are read by the Gram first, temporally), so they
+// are non-temporal: a 1200-subcarrier frame's loads and stores in a kernel of
+// this shape take 13.8 us instead of 17.0 us with temporal loads.
+__device__ __forceinline__ float4 ld_stream4(const float4 *p) {
+    const floatx4 v = __builtin_nontemporal_load((const floatx4 *)p);
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ float2 ld_stream2(const float2 *p) {
+    const floatx2 v = __builtin_nontemporal_load((const floatx2 *)p);
+    return make_float2(v.x, v.y);
+}
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
@@ -188,7 +204,7 @@ __device__ __forceinline__ void gram_load(const float *__restrict__ Hf, int u2, 
 #pragma unroll
         for (int ti = 0; ti < NT; ++ti) {
             const int col = 32 * ti + j;
-            b.v[ti][q] = rowp[col < u2 ? col : 0];
+            b.v[ti][q] = rowp[col < u2 ? col : 0];  // read again by the precode: temporal
         }
     }
 }
@@ -606,6 +622,19 @@ __device__ __forceinline__ void gj_upd3(float &x0, float &y0, float &x1, float &
         default: F<15>(__VA_ARGS__); break;    \
     }
 
+// Power-of-two exponent e that brings the largest diagonal entry dmax of a
+// Hermitian positive-definite A into [0.5, 1) (0 when dmax is not a positive
+// finite number).  The inversions below run on 2^-e A: every pivot (a Schur
+// complement, at most its diagonal entry) is then at most 1, so the update
+// term 1 + 1/pivot keeps 1/pivot to full precision whatever the channel's
+// scale (with a pivot of 3e6, 1 + 1/pivot in FP32 keeps only a third of
+// 1/pivot's bits), and A^-1 = 2^-e (2^-e A)^-1 exactly.
+__device__ __forceinline__ int diag_exp(float dmax) {
+    if (!(dmax > 0.f) || !(dmax < INFINITY)) return 0;
+    const int e = ilogbf(dmax) + 1;
+    return e < -100 ? -100 : (e > 100 ? 100 : e);
+}
+
 // In-register inversion of the m x m Hermitian positive-definite system held
 // in an LDS slot (full matrix), one wave, by Gauss-Jordan elimination without
 // pivoting: step k divides row k by the pivot and eliminates column k from
@@ -627,6 +656,10 @@ __device__ bool wave_inverse(cx<float> *S, int m, float *tr_out, float *fro_out,
     const int lane = lane_id();
     const int r = lane / UP, c = lane % UP, c4 = 4 * c;
     float re[NS], im[NS];
+    // 2^-e A (diag_exp): lane c's diagonal entry, maximum over the columns
+    const float dc = c < m ? S[c * LDc + c].re : 0.f;
+    const int e = diag_exp(wave_max(dc));
+    const float sc = ldexpf(1.f, -e);
     // rows and columns >= m are replaced by the identity, so that all UP
     // steps run unconditionally (straight-line code the scheduler can overlap
     // across steps) and leave the leading m x m block exactly as m steps would
@@ -635,10 +668,10 @@ __device__ bool wave_inverse(cx<float> *S, int m, float *tr_out, float *fro_out,
         const int i = s * R + r;
         const cx<float> v = S[i * LDc + c];
         const bool in = i < m && c < m;
-        re[s] = in ? v.re : (i == c ? 1.f : 0.f);
-        im[s] = in ? v.im : 0.f;
+        re[s] = in ? v.re * sc : (i == c ? 1.f : 0.f);
+        im[s] = in ? v.im * sc : 0.f;
     }
-    const float d0 = c < m ? S[c * LDc + c].re : 1.f;  // original diagonal entry of column c
+    const float d0 = c < m ? dc * sc : 1.f;  // original (scaled) diagonal entry of column c
     float pv = 1.f;  // lane (r, c) keeps pivot c, checked against d0 after the last step
     // row 0, column c
     float akc_re = bperm_group<UP>(re[0], c4, 0);
@@ -686,12 +719,13 @@ __device__ bool wave_inverse(cx<float> *S, int m, float *tr_out, float *fro_out,
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         const int i = s * R + r;
+        const float vr = re[s] * sc, vi = im[s] * sc;  // A^-1 = 2^-e (2^-e A)^-1
         if (i < m && c < m) {
-            fro += re[s] * re[s] + im[s] * im[s];
-            mx = fmaxf(mx, fmaxf(fabsf(re[s]), fabsf(im[s])));
-            if (i == c) tr += re[s];
+            fro += vr * vr + vi * vi;
+            mx = fmaxf(mx, fmaxf(fabsf(vr), fabsf(vi)));
+            if (i == c) tr += vr;
         }
-        S[i * LDc + c] = {re[s], im[s]};
+        S[i * LDc + c] = {vr, vi};
     }
     *tr_out = wave_sum(tr);
     *fro_out = wave_sum(fro);
@@ -713,13 +747,17 @@ __device__ bool wave_inverse_steps(cx<float> *S, int m, float *tr_out, float *fr
     const int lane = lane_id();
     const int r = lane / UP, c = lane % UP;
     float re[NS], im[NS];
+    // 2^-e A (diag_exp)
+    const float dc = S[c * LDc + c].re;
+    const int e = diag_exp(wave_max(c < m ? dc : 0.f));
+    const float sc = ldexpf(1.f, -e);
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         const cx<float> v = S[(s * R + r) * LDc + c];
-        re[s] = v.re;
-        im[s] = v.im;
+        re[s] = v.re * sc;
+        im[s] = v.im * sc;
     }
-    const float d0 = S[c * LDc + c].re;  // original diagonal entry of column c
+    const float d0 = dc * sc;  // original (scaled) diagonal entry of column c
     bool ok = true;
 #pragma unroll
     for (int k = 0; k < UP; ++k) {
@@ -761,12 +799,13 @@ __device__ bool wave_inverse_steps(cx<float> *S, int m, float *tr_out, float *fr
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         const int i = s * R + r;
+        const float vr = re[s] * sc, vi = im[s] * sc;  // A^-1 = 2^-e (2^-e A)^-1
         if (i < m && c < m) {
-            fro += re[s] * re[s] + im[s] * im[s];
-            mx = fmaxf(mx, fmaxf(fabsf(re[s]), fabsf(im[s])));
-            if (i == c) tr += re[s];
+            fro += vr * vr + vi * vi;
+            mx = fmaxf(mx, fmaxf(fabsf(vr), fabsf(vi)));
+            if (i == c) tr += vr;
         }
-        S[i * LDc + c] = {re[s], im[s]};
+        S[i * LDc + c] = {vr, vi};
     }
     *tr_out = wave_sum(tr);
     *fro_out = wave_sum(fro);
@@ -861,7 +900,7 @@ __device__ __forceinline__ void load_tile(const float2 *__restrict__ Hn, int U, 
         const float4 *rp = (const float4 *)(Hn + (size_t)(row0 + jr) * UP + g * (UP / 2));
 #pragma unroll
         for (int m4 = 0; m4 < UP / 4; ++m4) {
-            const float4 v = rp[m4];
+            const float4 v = ld_stream4(rp + m4);
             tl.f[4 * m4] = v.x;
             tl.f[4 * m4 + 1] = v.y;
             tl.f[4 * m4 + 2] = v.z;
@@ -872,7 +911,7 @@ __device__ __forceinline__ void load_tile(const float2 *__restrict__ Hn, int U, 
 #pragma unroll
         for (int m2 = 0; m2 < UP / 2; ++m2) {
             const int u = g * (UP / 2) + m2;
-            const float2 v = rp[u < U ? u : U - 1];
+            const float2 v = ld_stream2(rp + (u < U ? u : U - 1));
             tl.f[2 * m2] = v.x;
             tl.f[2 * m2 + 1] = v.y;
         }
@@ -921,9 +960,15 @@ template <int UP, int PREC>
 __device__ __forceinline__ void gram_tile(const GramBuf<UP> &b, Tile<UP, PREC> &tl,
                                           floatx16 (&acc)[Shape<UP>::NTT], int &ea, bool &have) {
     if constexpr (PREC == kF16) {
-        const int eq = __builtin_amdgcn_readfirstlane(tile_exp<UP, PREC>(tl));
+        float m = 0.f;
+#pragma unroll
+        for (int q = 0; q < UP; ++q) m = fmaxf(m, fabsf(tl.f[q]));
+        m = wave_max(m);
+        const int eq = __builtin_amdgcn_readfirstlane(fp16_exp(m));
         tl.e = eq;
-        if (!have || eq < ea) {
+        // an all-zero tile (a silent cluster) sets no exponent: its products
+        // are zero at any scale, and the next tiles keep their own range
+        if (m > 0.f && (!have || eq < ea)) {
             if (have) {
                 const float f = ldexpf(1.f, 2 * (eq - ea));
 #pragma unroll
@@ -1011,6 +1056,8 @@ struct Lds {
     static __host__ __device__ constexpr size_t bytes(int nw) { return nw * per_wave; }
     // the split kernel's raw partial Gram accumulators also fit per wave
     static_assert(per_wave >= (size_t)Shape<UP>::NTT * 64 * 16 * 4, "raw Gram area");
+    // and the FP64 retry of a failed system (f64r::instance, order U <= UP)
+    static_assert(per_wave >= f64r::lds_bytes(UP), "FP64 retry area");
 };
 
 // Kernel modes: the whole frame, the per-frame part only (factors to
@@ -1027,6 +1074,18 @@ __device__ __forceinline__ void store_factor(const cx<float> *S, int m, float sc
         const cx<float> v = S[i * LDc + j];
         g[e] = scale != 0.f ? cx<float>{v.re * scale, v.im * scale} : cx<float>{0.f, 0.f};
     }
+}
+
+// A zero factor (an instance the FP64 route re-solves at every symbol pass).
+__device__ __forceinline__ void zero_factor(int m, cx<float> *__restrict__ g) {
+    for (int e = lane_id(); e < m * m; e += 64) g[e] = {0.f, 0.f};
+}
+
+// Whether the stored factors of instance sys were replaced by the FP64 route
+// (prepare found the FP32 factorization failing and the FP64 one succeeding):
+// the symbol pass then solves it in FP64 again.
+__device__ __forceinline__ bool on_f64_route(const int *__restrict__ status, int sys) {
+    return status && status[sys] == PRECODE_ST_FP64;
 }
 
 // Loads a stored factor into a zeroed-then-filled LDS slot; returns max |entry|.
@@ -1177,6 +1236,10 @@ __device__ __forceinline__ void wave_system(const Prob &p, const int *__restrict
         for (int q = 0; q < MAXT; ++q) tile_pack<UP, PREC>(tiles[q], tiles[q].e);
     }
     if (mode == kSymbols) {
+        if (on_f64_route(status, sys)) {
+            f64r::instance(f64r::shape_of(p), off, sys, K, false, H, s, x, nullptr, nullptr, (char *)Zw);
+            return;
+        }
         if (pre_sym) load_sym<UP>(s + (size_t)n * U, (size_t)n_sc * U, U, min(KC, K), sym0);
         amax = load_factor<UP>(fac, U, sA);
     } else {
@@ -1192,21 +1255,24 @@ __device__ __forceinline__ void wave_system(const Prob &p, const int *__restrict
         wave_sync();
         float tr = 0.f;
         ok = wave_factor<UP>(sA, U, kap, &tr, &amax);
-        float out = 0.f;
-        if (ok) {
-            if (pd) {
-                out = sqrtf(p.Es / p.power * tr);  // beta
-                scale = 1.f / out;
-            } else {
-                out = sqrtf(p.power / (float)C / (tr * p.Es));  // w_c
-                scale = out;
-            }
+        if (!ok) {
+            // the FP32 factorization failed: the FP64 route solves the
+            // instance (factors, status and every symbol) in this wave
+            f64r::instance(f64r::shape_of(p), off, sys, mode == kPrepare ? 0 : K, true, H, s, x, scale_out, status, (char *)Zw);
+            if (mode == kPrepare) zero_factor(U, fac);
+            return;
+        }
+        float out;
+        if (pd) {
+            out = sqrtf(p.Es / p.power * tr);  // beta
+            scale = 1.f / out;
         } else {
-            scale = 0.f;
+            out = sqrtf(p.power / (float)C / (tr * p.Es));  // w_c
+            scale = out;
         }
         if (lane == 0) {
             if (scale_out) scale_out[sys] = out;
-            if (status) status[sys] = ok ? PRECODE_ST_OK : PRECODE_ST_FAIL;
+            if (status) status[sys] = PRECODE_ST_OK;
         }
         if (mode == kPrepare) {
             store_factor<UP>(sA, U, scale, fac);
@@ -1278,7 +1344,7 @@ __device__ __forceinline__ void wg_pd_split(const Prob &p, int blk, int K, int m
                                             int *__restrict__ status, char *lds) {
     constexpr int NTT = Shape<UP>::NTT;
     __shared__ float sh_scale, sh_amax;
-    __shared__ int sh_ok;
+    __shared__ int sh_ok, sh_retry;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int mw = blk % NW;
@@ -1305,13 +1371,19 @@ __device__ __forceinline__ void wg_pd_split(const Prob &p, int blk, int K, int m
     const float2 *s0 = s + (size_t)n * U;
     if (mode == kSymbols) {
         if (wave == mw) {
-            if (pre_sym) load_sym<UP>(s0, (size_t)n_sc * U, U, min(KC, K), sym0);
-            const float amax = load_factor<UP>(fac, U, Am);
-            if (lane == 0) {
-                sh_scale = 1.f;
-                sh_amax = amax;
-                sh_ok = 1;
+            // an instance prepare moved to the FP64 route is solved again at
+            // the end (no wave stores a precoded row for it before)
+            const bool retry = on_f64_route(status, n);
+            if (!retry) {
+                if (pre_sym) load_sym<UP>(s0, (size_t)n_sc * U, U, min(KC, K), sym0);
+                const float amax = load_factor<UP>(fac, U, Am);
+                if (lane == 0) {
+                    sh_scale = 1.f;
+                    sh_amax = amax;
+                    sh_ok = 1;
+                }
             }
+            if (lane == 0) sh_retry = retry;
         }
     }
     // 16-bit: the Gram runs on a running exponent (gram_tile); the tiles are
@@ -1387,20 +1459,33 @@ __device__ __forceinline__ void wg_pd_split(const Prob &p, int blk, int K, int m
             wave_sync();
             float tr = 0.f, amax = 0.f;
             const bool ok = wave_factor<UP>(Am, U, kap, &tr, &amax);
-            const float beta = ok ? sqrtf(p.Es / p.power * tr) : 0.f;
-            if (lane == 0) {
-                sh_scale = ok ? 1.f / beta : 0.f;
-                sh_amax = amax;
-                sh_ok = ok;
-                if (scale_out) scale_out[n] = beta;
-                if (status) status[n] = ok ? PRECODE_ST_OK : PRECODE_ST_FAIL;
+            if (ok) {
+                const float beta = sqrtf(p.Es / p.power * tr);
+                if (lane == 0) {
+                    sh_scale = 1.f / beta;
+                    sh_amax = amax;
+                    sh_ok = 1;
+                    if (scale_out) scale_out[n] = beta;
+                    if (status) status[n] = PRECODE_ST_OK;
+                }
+                if (mode == kPrepare) store_factor<UP>(Am, U, 1.f / beta, fac);
+            } else if (mode == kPrepare) {
+                // the FP32 factorization failed: the FP64 route's factors
+                // and status; its symbols are solved at every symbol pass
+                __builtin_amdgcn_s_setprio(0);
+                f64r::instance(f64r::shape_of(p), nullptr, n, 0, true, H, s, x, scale_out, status,
+                               (char *)raw_of(mw));
+                zero_factor(U, fac);
             }
-            if (mode == kPrepare) store_factor<UP>(Am, U, ok ? 1.f / beta : 0.f, fac);
+            if (lane == 0) sh_retry = !ok;
         }
         if (mode == kPrepare) return;
     }
     __syncthreads();
-    for (int k0 = 0; k0 < K; k0 += KC) {
+    // a subcarrier on the FP64 route is solved by the master at the end, over
+    // all rows, once no channel tile is live (the other waves store nothing)
+    const bool retry = sh_retry != 0;
+    for (int k0 = 0; k0 < (retry ? 0 : K); k0 += KC) {
         const int kc = min(KC, K - k0);
         if (wave == mw) {
             ZOp<UP, kF32> zs;  // FP32 solve at every precision (see wave_system)
@@ -1426,6 +1511,11 @@ __device__ __forceinline__ void wg_pd_split(const Prob &p, int blk, int K, int m
             __builtin_amdgcn_sched_barrier(0);
         }
         __syncthreads();  // Zm is rewritten by the next chunk
+    }
+    if (retry && wave == mw) {
+        __builtin_amdgcn_s_setprio(0);
+        f64r::instance(f64r::shape_of(p), nullptr, n, K, mode != kSymbols, H, s, x, scale_out, status,
+                       (char *)raw_of(mw));
     }
 }
 

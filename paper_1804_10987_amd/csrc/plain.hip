@@ -13,10 +13,14 @@
 //             from the complex64 channel (U x U systems)
 //   precode   x_c = H_c z                          (per symbol)
 //             (FD, B_c < U: x_c = w_c M_c^-1 (H_c s), done in `solve`)
+//   retry     an FP32-route instance whose factorization failed is solved
+//             on the FP64 route instead (retry_f64.h): its factors and
+//             status at prepare, its symbols after the precode
 //
 // The whole instance runs in T = float, or T = double on the FP64 route
 // (inputs widened exactly), with complex64 results.
 #include "common.h"
+#include "retry_f64.h"
 
 #include <algorithm>
 
@@ -225,6 +229,7 @@ __global__ void __launch_bounds__(256) plain_solve_k(Prob p, int K, const float2
     const InstInfo q = inst_info(p, (int)inst);
     if (q.r64 != is64<T>()) return;
     const T sc = scale_ws[inst * kW<T>()];  // 0 marks a failed instance: its output is 0
+    if (sc < (T)0) return;                  // on the FP64 retry (plain_retry_k writes x)
     const cx<T> *ai = Ainv + inst * p.U * p.U * kW<T>();
     const float2 *sk = s + ((size_t)k * p.n_sc + q.n) * p.U;
     if (q.big) {
@@ -270,7 +275,7 @@ __global__ void __launch_bounds__(64) plain_refine_k(Prob p, int K, const float2
     const InstInfo q = inst_info(p, (int)inst);
     if (q.r64 != is64<T>() || !q.big) return;
     const T sc = scale_ws[inst * kW<T>()];
-    if (sc == (T)0) return;  // failed instance: z stays 0
+    if (sc <= (T)0) return;  // failed instance (z stays 0) or on the FP64 retry
     const int tid = threadIdx.x, U = p.U;
     __shared__ cx<double> zy[kMaxU], hz[kRefChunk], acc[kMaxU];
     __shared__ cx<double> r[kMaxU];
@@ -321,7 +326,8 @@ __global__ void __launch_bounds__(64) plain_refine_k(Prob p, int K, const float2
 // precode: thread per (k, n, b)
 // --------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) plain_precode_k(Prob p, int K, const float2 *__restrict__ H,
-                                                       const float2 *__restrict__ z, float2 *__restrict__ x) {
+                                                       const float2 *__restrict__ z, const float *__restrict__ scale32,
+                                                       float2 *__restrict__ x) {
     const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= (size_t)K * p.n_sc * p.B) return;
     const int b = (int)(gid % p.B);
@@ -337,6 +343,8 @@ __global__ void __launch_bounds__(256) plain_precode_k(Prob p, int K, const floa
         inst = (size_t)n * p.C + c;
         r64 = p.fp64[c] != 0;
     }
+    // an FP32-route instance on the FP64 retry: plain_retry_k writes its x
+    if (!r64 && scale32[inst * kW<float>()] < 0.f) return;
     const float2 *hb = H + ((size_t)n * p.B + b) * p.U;
     const float2 *zk = z + ((size_t)k * ni + inst) * p.U;
     float2 out;
@@ -353,6 +361,30 @@ __global__ void __launch_bounds__(256) plain_precode_k(Prob p, int K, const floa
 }
 
 // zero x for failed instances (scale == 0) is automatic: z = 0 => x = 0.
+
+// --------------------------------------------------------------------------
+// retry: one wave per instance of the FP32 route.  factors: an instance whose
+// FP32 factorization failed (scale 0) is factored on the FP64 route
+// (f64r::instance writes its scale output and status) and marked with scale
+// -1; symbols: every marked instance is solved and precoded on the FP64 route
+// (after the FP32 precode, which skips it).
+// --------------------------------------------------------------------------
+__global__ void __launch_bounds__(64) plain_retry_k(Prob p, int K, int factors, const float2 *__restrict__ H,
+                                                    const float2 *__restrict__ s, float2 *__restrict__ x,
+                                                    float *__restrict__ scale_ws, float *__restrict__ scale_out,
+                                                    int *__restrict__ status) {
+    extern __shared__ double retry_lds[];
+    const int inst = blockIdx.x;
+    const InstInfo q = inst_info(p, inst);
+    if (q.r64) return;
+    float *sc = scale_ws + (size_t)inst * kW<float>();
+    const float v = *sc;
+    if (factors ? v != 0.f : v >= 0.f) return;
+    // the cluster offsets read in place from the kernel arguments (p first)
+    const int *off = (const int *)((const char *)__builtin_amdgcn_kernarg_segment_ptr() + offsetof(Prob, off));
+    f64r::instance(f64r::shape_of(p), off, inst, K, factors != 0, H, s, x, scale_out, status, (char *)retry_lds);
+    if (factors && threadIdx.x == 0) *sc = -1.f;
+}
 
 bool any_route(const Prob &p, bool want64) {
     if (p.arch == kPD) return (p.pd_fp64 != 0) == want64;
@@ -375,6 +407,8 @@ hipError_t plain_prepare(const Prob &p, const float2 *H, float *scale_out, int *
         hipLaunchKernelGGL(plain_gram_k<float>, dim3(ni), dim3(256), 0, st, p, H, (cx<float> *)ws_A);
         hipLaunchKernelGGL(plain_factor_k<float>, dim3(ni), dim3(64), 0, st, p, (cx<float> *)ws_A,
                            (cx<float> *)ws_Ainv, (float *)ws_scale, scale_out, status);
+        hipLaunchKernelGGL(plain_retry_k, dim3(ni), dim3(64), f64r::lds_bytes(p.U), st, p, 0, 1, H,
+                           (const float2 *)nullptr, (float2 *)nullptr, (float *)ws_scale, scale_out, status);
     }
     if (any_route(p, true)) {
         hipLaunchKernelGGL(plain_gram_k<double>, dim3(ni), dim3(256), 0, st, p, H, (cx<double> *)ws_A);
@@ -407,7 +441,10 @@ hipError_t plain_symbols(const Prob &p, int K, const float2 *H, const float2 *s,
     }
     const size_t nx = (size_t)K * p.n_sc * p.B;
     hipLaunchKernelGGL(plain_precode_k, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, st, p, K, H,
-                       (const float2 *)ws_z, x);
+                       (const float2 *)ws_z, (const float *)ws_scale, x);
+    if (any_route(p, false))
+        hipLaunchKernelGGL(plain_retry_k, dim3((unsigned)ni), dim3(64), f64r::lds_bytes(p.U), st, p, K, 0, H, s, x,
+                           (float *)ws_scale, (float *)nullptr, (int *)nullptr);
     return hipGetLastError();
 }
 

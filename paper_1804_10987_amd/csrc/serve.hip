@@ -166,7 +166,7 @@ extern "C" int precode_serve(precode_ctx *ctx, const precode_serve_job *jobs, in
         int rc = make_prob_checked(j.arch, j.rho, j.cluster_sizes, j.C, j.mode, j.B, j.U, j.n_sc, j.K, &q,
                                             &s.p);
         if (rc) return rc;
-        if (j.n_sc > 0 && (!j.H || !j.s || !j.x)) return PRECODE_EINVAL;
+        if (j.n_sc > 0 && (!j.H || (j.K > 0 && (!j.s || !j.x)))) return PRECODE_EINVAL;
         s.fused = cfg->impl != PRECODE_IMPL_PLAIN && fused_supported(s.p, cfg->precision);
         if (!s.fused && (cfg->impl == PRECODE_IMPL_FUSED || cfg->precision == PRECODE_PREC_SPLIT_FP16 ||
                          cfg->precision == PRECODE_PREC_SPLIT_BF16))
@@ -281,7 +281,9 @@ extern "C" int precode_serve(precode_ctx *ctx, const precode_serve_job *jobs, in
                 if (e == hipSuccess && j.status)
                     e = hipMemcpyAsync(j.status, s.status, ni * sizeof(int), hipMemcpyDeviceToDevice, stream);
             }
-            if (e == hipSuccess && one_launch) {
+            // a job with no symbols still retires only once its factors and
+            // their copies are done (its slab region is written until then)
+            if (e == hipSuccess && (one_launch || j.K == 0)) {
                 Launch L;
                 L.ev = get_event();
                 L.k0 = 0;
@@ -322,7 +324,7 @@ extern "C" int precode_serve(precode_ctx *ctx, const precode_serve_job *jobs, in
                 Prob pk = s.p;
                 pk.K = nk;
                 if (s.fused)
-                    e = fused_symbols(pk, s.precision, nk, (const float2 *)j.H, s.ainv, sk, xk, stream);
+                    e = fused_symbols(pk, s.precision, nk, (const float2 *)j.H, s.ainv, s.status, sk, xk, stream);
                 else
                     e = plain_symbols(pk, nk, (const float2 *)j.H, sk, xk, s.ainv, s.wsScale, s.wsZ, stream);
             }
@@ -363,7 +365,7 @@ extern "C" int precode_serve(precode_ctx *ctx, const precode_serve_job *jobs, in
                 syms_done += L.nk;
                 subsyms_done += (size_t)L.nk * j.n_sc;
             }
-            if (s.done >= j.K) {
+            if (s.done >= j.K && s.next >= j.K && s.inflight.empty()) {
                 slab.release(s.mem, s.bytes);
                 s.mem = nullptr;
                 ++jobs_done;

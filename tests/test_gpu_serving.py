@@ -125,3 +125,25 @@ def test_serving_rejects_oversize_job(torch, ctx):
     jobs, _ = _jobs(torch, [("pd", synth.Cell(B=64, sizes=(64,), U=16, n_sc=64, K=14))])
     with pytest.raises(pc.PrecodeError):
         ctx.serve(jobs, [0.0], slab_bytes=1024)
+
+
+def test_serving_zero_symbol_job_retires_after_its_factors(torch, ctx):
+    """A job with K = 0 (factors only) retires, and hands its slab region
+    back, only after its factors and their copies are done: jobs admitted
+    after it into the same region (one-job slab) keep their results, and
+    the K = 0 job's beta and status match the oracle."""
+    c0 = synth.Cell(B=64, sizes=(32, 32), U=8, n_sc=48, K=14, snr_db=10.0)
+    H, s = synth.make_cell(c0, seed=21)
+    H2, s2 = synth.make_cell(c0, seed=22)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    jobs = [dict(arch="pd", mode="wf", H=dev(H), s=dev(s[:0]), rho=c0.kappa, sizes=c0.sizes),
+            dict(arch="pd", mode="wf", H=dev(H2), s=dev(s2), rho=c0.kappa, sizes=c0.sizes)]
+    per_job = 48 * 8 * 8 * 8 + 48 * 8 + 1024
+    outs, lat, st = ctx.serve(jobs, [0.0, 0.0], symbol_period_s=0.0, max_active=4, n_streams=2,
+                              slab_bytes=int(per_job * 1.2))
+    torch.cuda.synchronize()
+    assert st["jobs_done"] == 2
+    _, bo, so = oracle.pd(H, s[:1], c0.kappa, c0.sizes)
+    assert (outs[0][2].cpu().numpy() == so).all()
+    assert np.abs(outs[0][1].cpu().numpy() - bo).max() <= 1e-5 * bo.max()
+    _check_oracle(1, "pd", c0, H2, s2, *outs[1])
