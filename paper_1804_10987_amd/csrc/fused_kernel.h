@@ -12,21 +12,6 @@ namespace pc {
 namespace {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
-typedef float floatx4 __attribute__((ext_vector_type(4)));
-typedef float floatx2 __attribute__((ext_vector_type(2)));
-
-// Channel tile loads are a row's last read in a launch (register tiles are
-// read once; streamed rows are read by the Gram first, temporally), so they
-// are non-temporal: a 1200-subcarrier frame's loads and stores in a kernel of
-// this shape take 13.8 us instead of 17.0 us with temporal loads.
-__device__ __forceinline__ float4 ld_stream4(const float4 *p) {
-    const floatx4 v = __builtin_nontemporal_load((const floatx4 *)p);
-    return make_float4(v.x, v.y, v.z, v.w);
-}
-__device__ __forceinline__ float2 ld_stream2(const float2 *p) {
-    const floatx2 v = __builtin_nontemporal_load((const floatx2 *)p);
-    return make_float2(v.x, v.y);
-}
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
@@ -204,7 +189,7 @@ __device__ __forceinline__ void gram_load(const float *__restrict__ Hf, int u2, 
 #pragma unroll
         for (int ti = 0; ti < NT; ++ti) {
             const int col = 32 * ti + j;
-            b.v[ti][q] = rowp[col < u2 ? col : 0];  // read again by the precode: temporal
+            b.v[ti][q] = rowp[col < u2 ? col : 0];
         }
     }
 }
@@ -900,7 +885,7 @@ __device__ __forceinline__ void load_tile(const float2 *__restrict__ Hn, int U, 
         const float4 *rp = (const float4 *)(Hn + (size_t)(row0 + jr) * UP + g * (UP / 2));
 #pragma unroll
         for (int m4 = 0; m4 < UP / 4; ++m4) {
-            const float4 v = ld_stream4(rp + m4);
+            const float4 v = rp[m4];
             tl.f[4 * m4] = v.x;
             tl.f[4 * m4 + 1] = v.y;
             tl.f[4 * m4 + 2] = v.z;
@@ -911,10 +896,38 @@ __device__ __forceinline__ void load_tile(const float2 *__restrict__ Hn, int U, 
 #pragma unroll
         for (int m2 = 0; m2 < UP / 2; ++m2) {
             const int u = g * (UP / 2) + m2;
-            const float2 v = ld_stream2(rp + (u < U ? u : U - 1));
+            const float2 v = rp[u < U ? u : U - 1];
             tl.f[2 * m2] = v.x;
             tl.f[2 * m2 + 1] = v.y;
         }
+    }
+}
+
+// Register tiles with U == UP (VEC) load their rows in whole cache lines:
+// instruction m, lane l reads the 16 bytes at m * 1 KiB + 16 l of the tile
+// (rows m * RPI + l / LPR, float4 l % LPR of the row; LPR = UP / 2 lanes
+// per row, RPI = 128 / UP rows per instruction), non-temporally (a register
+// tile is a row's only read in a launch).  tile_to_gram stages this "raw"
+// layout in LDS and reads back both the Gram operands and the precode
+// layout; a row-per-lane load would touch 32 lines per instruction and
+// fetch each line four times through the cache.
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+template <int UP, int PREC>
+__device__ __forceinline__ void load_tile_raw(const float2 *__restrict__ Hn, int row0, int nrows,
+                                              Tile<UP, PREC> &tl) {
+    constexpr int LPR = UP / 2, RPI = 128 / UP;
+    const int lane = lane_id();
+    const int lr = lane / LPR, c4 = lane % LPR;
+#pragma unroll
+    for (int m = 0; m < UP / 4; ++m) {
+        const int row = m * RPI + lr;
+        const int rr = row < nrows ? row : (nrows > 0 ? nrows - 1 : 0);
+        const floatx4 v = __builtin_nontemporal_load((const floatx4 *)(Hn + (size_t)(row0 + rr) * UP) + c4);
+        tl.f[4 * m] = v.x;
+        tl.f[4 * m + 1] = v.y;
+        tl.f[4 * m + 2] = v.z;
+        tl.f[4 * m + 3] = v.w;
     }
 }
 
@@ -999,21 +1012,34 @@ __device__ __forceinline__ floatx16 mfma_apply_packed(const Tile<UP, PREC> &tl, 
 // The Gram operand buffer of a register tile, transposed through the wave's
 // LDS scratch (rows stored row-major with stride RS, read back by column).
 // Rows >= nrows and users >= U are zeroed here (the tile holds copies there).
-template <int UP, int PREC>
-__device__ __forceinline__ void tile_to_gram(const Tile<UP, PREC> &tl, int nrows, int U, float *scr,
-                                             GramBuf<UP> &b) {
+template <int UP, int PREC, bool RAW = false>
+__device__ __forceinline__ void tile_to_gram(Tile<UP, PREC> &tl, int nrows, int U, float *scr, GramBuf<UP> &b) {
     constexpr int NT = Shape<UP>::NT;
     constexpr int RS = Shape<UP>::RS;
     const int lane = lane_id();
     const int j = lane & 31, g = lane >> 5;
-    const bool live = j < nrows;
-    float *rp = scr + j * RS + g * UP;
+    if constexpr (RAW) {
+        // load_tile_raw's layout (U == UP); rows >= nrows are zeroed
+        constexpr int LPR = UP / 2, RPI = 128 / UP;
+        const int lr = lane / LPR, c4 = lane % LPR;
 #pragma unroll
-    for (int m4 = 0; m4 < UP; m4 += 4) {
-        float v[4];
+        for (int m = 0; m < UP / 4; ++m) {
+            const int row = m * RPI + lr;
+            const bool live = row < nrows;
+            *(float4 *)(scr + row * RS + 4 * c4) =
+                live ? make_float4(tl.f[4 * m], tl.f[4 * m + 1], tl.f[4 * m + 2], tl.f[4 * m + 3])
+                     : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    } else {
+        const bool live = j < nrows;
+        float *rp = scr + j * RS + g * UP;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) v[e] = (live && g * (UP / 2) + (m4 + e) / 2 < U) ? tl.f[m4 + e] : 0.f;
-        *(float4 *)(rp + m4) = make_float4(v[0], v[1], v[2], v[3]);
+        for (int m4 = 0; m4 < UP; m4 += 4) {
+            float v[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[e] = (live && g * (UP / 2) + (m4 + e) / 2 < U) ? tl.f[m4 + e] : 0.f;
+            *(float4 *)(rp + m4) = make_float4(v[0], v[1], v[2], v[3]);
+        }
     }
     wave_sync();
 #pragma unroll
@@ -1022,7 +1048,48 @@ __device__ __forceinline__ void tile_to_gram(const Tile<UP, PREC> &tl, int nrows
 #pragma unroll
         for (int ti = 0; ti < NT; ++ti) b.v[ti][q] = scr[row * RS + 32 * ti + j];
     }
+    if constexpr (RAW) {
+        // the precode layout: lane (j, g) holds row j, real columns g UP ..
+        const float *rp = scr + j * RS + g * UP;
+#pragma unroll
+        for (int m4 = 0; m4 < UP; m4 += 4) {
+            const float4 v = *(const float4 *)(rp + m4);
+            tl.f[m4] = v.x;
+            tl.f[m4 + 1] = v.y;
+            tl.f[m4 + 2] = v.z;
+            tl.f[m4 + 3] = v.w;
+        }
+    }
     wave_sync();  // the scratch is rewritten by the next tile
+}
+
+// A raw register tile (load_tile_raw) in the precode layout through the
+// wave's LDS scratch, without a Gram (per-symbol mode); rows >= nrows zero.
+template <int UP, int PREC>
+__device__ __forceinline__ void tile_to_precode(Tile<UP, PREC> &tl, int nrows, float *scr) {
+    constexpr int RS = Shape<UP>::RS;
+    constexpr int LPR = UP / 2, RPI = 128 / UP;
+    const int lane = lane_id();
+    const int j = lane & 31, g = lane >> 5;
+    const int lr = lane / LPR, c4 = lane % LPR;
+#pragma unroll
+    for (int m = 0; m < UP / 4; ++m) {
+        const int row = m * RPI + lr;
+        *(float4 *)(scr + row * RS + 4 * c4) = row < nrows
+                                                   ? make_float4(tl.f[4 * m], tl.f[4 * m + 1], tl.f[4 * m + 2], tl.f[4 * m + 3])
+                                                   : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    wave_sync();
+    const float *rp = scr + j * RS + g * UP;
+#pragma unroll
+    for (int m4 = 0; m4 < UP; m4 += 4) {
+        const float4 v = *(const float4 *)(rp + m4);
+        tl.f[m4] = v.x;
+        tl.f[m4 + 1] = v.y;
+        tl.f[m4 + 2] = v.z;
+        tl.f[m4 + 3] = v.w;
+    }
+    wave_sync();
 }
 
 // Stores the X^T tile of rows [row0, row0 + nrows), symbols k0 .. k0 + kc - 1.
@@ -1168,7 +1235,10 @@ __device__ __forceinline__ void wave_system(const Prob &p, const int *__restrict
         for (int q = 0; q < MAXT; ++q) {
             const int rq = r0 + 32 * q;
             // tiles past the system load (and zero) its first rows: no branch
-            load_tile<UP, PREC, VEC>(Hn, U, q < ntile ? rq : r0, q < ntile ? min(32, r1 - rq) : 0, tiles[q]);
+            if constexpr (VEC)
+                load_tile_raw<UP, PREC>(Hn, q < ntile ? rq : r0, q < ntile ? min(32, r1 - rq) : 0, tiles[q]);
+            else
+                load_tile<UP, PREC, VEC>(Hn, U, q < ntile ? rq : r0, q < ntile ? min(32, r1 - rq) : 0, tiles[q]);
         }
     }
     // the first chunk's symbols: loaded after the Gram, in flight during the
@@ -1195,7 +1265,7 @@ __device__ __forceinline__ void wave_system(const Prob &p, const int *__restrict
             for (int q = 0; q < MAXT; ++q) {
                 if (q < ntile) {
                     GramBuf<UP> b;
-                    tile_to_gram<UP, PREC>(tiles[q], min(32, r1 - (r0 + 32 * q)), U, scr, b);
+                    tile_to_gram<UP, PREC, VEC>(tiles[q], min(32, r1 - (r0 + 32 * q)), U, scr, b);
                     gram_tile<UP, PREC>(b, tiles[q], acc, ew, have_e);
                 }
                 // one tile at a time: keeps the scheduler from overlapping
@@ -1230,7 +1300,11 @@ __device__ __forceinline__ void wave_system(const Prob &p, const int *__restrict
     if constexpr (MAXT > 0) {
         if (mode == kSymbols) {
 #pragma unroll
-            for (int q = 0; q < MAXT; ++q) tiles[q].e = tile_exp<UP, PREC>(tiles[q]);
+            for (int q = 0; q < MAXT; ++q) {
+                if constexpr (VEC) tile_to_precode<UP, PREC>(tiles[q], q < ntile ? min(32, r1 - (r0 + 32 * q)) : 0,
+                                                             (float *)Zw);
+                tiles[q].e = tile_exp<UP, PREC>(tiles[q]);
+            }
         }
 #pragma unroll
         for (int q = 0; q < MAXT; ++q) tile_pack<UP, PREC>(tiles[q], tiles[q].e);
@@ -1344,7 +1418,7 @@ __device__ __forceinline__ void wg_pd_split(const Prob &p, int blk, int K, int m
                                             int *__restrict__ status, char *lds) {
     constexpr int NTT = Shape<UP>::NTT;
     __shared__ float sh_scale, sh_amax;
-    __shared__ int sh_ok, sh_retry;
+    __shared__ int sh_ok;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int mw = blk % NW;
@@ -1362,30 +1436,19 @@ __device__ __forceinline__ void wg_pd_split(const Prob &p, int blk, int K, int m
     for (int q = 0; q < MAXT; ++q) {
         const int tt = wave + NW * q;
         const bool v = tt < ntile;
-        load_tile<UP, PREC, VEC>(Hn, U, v ? 32 * tt : 0, v ? min(32, B - 32 * tt) : 0, tiles[q]);
+        if constexpr (VEC)
+            load_tile_raw<UP, PREC>(Hn, v ? 32 * tt : 0, v ? min(32, B - 32 * tt) : 0, tiles[q]);
+        else
+            load_tile<UP, PREC, VEC>(Hn, U, v ? 32 * tt : 0, v ? min(32, B - 32 * tt) : 0, tiles[q]);
     }
     const float kap = pd_kappa(p);
     // the first chunk's symbols, loaded by the master while it factors
     SymRaw<UP> sym0;
     const bool pre_sym = mode != kPrepare && K > 0;
     const float2 *s0 = s + (size_t)n * U;
-    if (mode == kSymbols) {
-        if (wave == mw) {
-            // an instance prepare moved to the FP64 route is solved again at
-            // the end (no wave stores a precoded row for it before)
-            const bool retry = on_f64_route(status, n);
-            if (!retry) {
-                if (pre_sym) load_sym<UP>(s0, (size_t)n_sc * U, U, min(KC, K), sym0);
-                const float amax = load_factor<UP>(fac, U, Am);
-                if (lane == 0) {
-                    sh_scale = 1.f;
-                    sh_amax = amax;
-                    sh_ok = 1;
-                }
-            }
-            if (lane == 0) sh_retry = retry;
-        }
-    }
+    // the master's subcarrier goes to the FP64 route (the FP32
+    // factorization failed, or prepare found it so)
+    bool retry = false;
     // 16-bit: the Gram runs on a running exponent (gram_tile); the tiles are
     // packed, each with its own exponent, at a single point for every mode
     // (packing in two branches keeps both forms of the tiles live across the
@@ -1404,17 +1467,37 @@ __device__ __forceinline__ void wg_pd_split(const Prob &p, int blk, int K, int m
             const int tt = wave + NW * q;
             if (tt < ntile) {
                 GramBuf<UP> b;
-                tile_to_gram<UP, PREC>(tiles[q], min(32, B - 32 * tt), U, scr, b);
+                tile_to_gram<UP, PREC, VEC>(tiles[q], min(32, B - 32 * tt), U, scr, b);
                 gram_tile<UP, PREC>(b, tiles[q], acc, ew, have_e);
             }
             __builtin_amdgcn_sched_barrier(0);
         }
     } else {
+        float *scr = (float *)zw_of(wave);
 #pragma unroll
-        for (int q = 0; q < MAXT; ++q) tiles[q].e = tile_exp<UP, PREC>(tiles[q]);
+        for (int q = 0; q < MAXT; ++q) {
+            const int tt = wave + NW * q;
+            if constexpr (VEC) tile_to_precode<UP, PREC>(tiles[q], tt < ntile ? min(32, B - 32 * tt) : 0, scr);
+            tiles[q].e = tile_exp<UP, PREC>(tiles[q]);
+        }
     }
 #pragma unroll
     for (int q = 0; q < MAXT; ++q) tile_pack<UP, PREC>(tiles[q], tiles[q].e);
+    if (mode == kSymbols) {
+        if (wave == mw) {
+            // an instance prepare moved to the FP64 route (its stored factor
+            // is zero) is solved again on that route at the end; the factor
+            // is loaded after the tiles' transposes, which overlay the slot
+            retry = on_f64_route(status, n);
+            if (pre_sym) load_sym<UP>(s0, (size_t)n_sc * U, U, min(KC, K), sym0);
+            const float amax = load_factor<UP>(fac, U, Am);
+            if (lane == 0) {
+                sh_scale = 1.f;
+                sh_amax = amax;
+                sh_ok = !retry;
+            }
+        }
+    }
     if (mode != kSymbols) {
         if constexpr (PREC != kF32) {
             const float un = ldexpf(1.f, -2 * ew);
@@ -1469,23 +1552,30 @@ __device__ __forceinline__ void wg_pd_split(const Prob &p, int blk, int K, int m
                     if (status) status[n] = PRECODE_ST_OK;
                 }
                 if (mode == kPrepare) store_factor<UP>(Am, U, 1.f / beta, fac);
-            } else if (mode == kPrepare) {
-                // the FP32 factorization failed: the FP64 route's factors
-                // and status; its symbols are solved at every symbol pass
-                __builtin_amdgcn_s_setprio(0);
-                f64r::instance(f64r::shape_of(p), nullptr, n, 0, true, H, s, x, scale_out, status,
-                               (char *)raw_of(mw));
-                zero_factor(U, fac);
+            } else {
+                if (lane == 0) {
+                    sh_scale = 0.f;
+                    sh_amax = amax;
+                    sh_ok = 0;
+                }
+                retry = true;
+                if (mode == kPrepare) {
+                    // the FP32 factorization failed: the FP64 route's factors
+                    // and status; its symbols are solved at every symbol pass
+                    __builtin_amdgcn_s_setprio(0);
+                    f64r::instance(f64r::shape_of(p), nullptr, n, 0, true, H, s, x, scale_out, status,
+                                   (char *)raw_of(mw));
+                    zero_factor(U, fac);
+                }
             }
-            if (lane == 0) sh_retry = !ok;
         }
         if (mode == kPrepare) return;
     }
     __syncthreads();
-    // a subcarrier on the FP64 route is solved by the master at the end, over
-    // all rows, once no channel tile is live (the other waves store nothing)
-    const bool retry = sh_retry != 0;
-    for (int k0 = 0; k0 < (retry ? 0 : K); k0 += KC) {
+    // a failed subcarrier's chunks are solved to zero (scale 0) and stored;
+    // the master then overwrites them from the FP64 route at the end, once no
+    // channel tile is live (the last barrier of the loop orders the stores)
+    for (int k0 = 0; k0 < K; k0 += KC) {
         const int kc = min(KC, K - k0);
         if (wave == mw) {
             ZOp<UP, kF32> zs;  // FP32 solve at every precision (see wave_system)
@@ -1512,7 +1602,7 @@ __device__ __forceinline__ void wg_pd_split(const Prob &p, int blk, int K, int m
         }
         __syncthreads();  // Zm is rewritten by the next chunk
     }
-    if (retry && wave == mw) {
+    if (retry) {
         __builtin_amdgcn_s_setprio(0);
         f64r::instance(f64r::shape_of(p), nullptr, n, K, mode != kSymbols, H, s, x, scale_out, status,
                        (char *)raw_of(mw));
