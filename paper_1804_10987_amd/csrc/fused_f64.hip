@@ -1,23 +1,32 @@
 // fused_f64.hip -- the FP64 route in one fused launch: local systems whose
-// conditioning calls for FP64 (U / B_eff >= fp64_ratio, or precision FP64 not
-// requested: see fused_f64_supported) with U <= 16 and U <= B_eff <= 32 rows.
+// conditioning calls for FP64 (U / B_eff >= fp64_ratio; precision FP64 keeps
+// the precode in FP64 on the plain kernels) with U <= 32 users and
+// U <= B_eff <= 64 rows.
 //
 // One wave per local system (FD cluster c of subcarrier n, or a PD subcarrier
-// of at most 32 antennas), four systems per workgroup, no workgroup barrier:
+// of at most 64 antennas), four systems per workgroup, no workgroup barrier.
+// Register layout of the UP x UP system (UP = 16 or 32): lane (r, c) =
+// (lane / UP, lane % UP) holds column c of rows s R + r, s < NS (R = 64 / UP
+// row groups, NS = UP / R slots), in FP64.
 //
-//   load      the system's rows (one 32-row tile) into registers, in the
-//             precode's operand layout (as the FP32 kernel)
-//   Gram      G_c = H_c^H H_c in FP64 on the VALU: the rows go to LDS as
-//             complex64; lane (r, c) accumulates G[4s + r][c], s = 0..3, over
-//             the rows (complex64 products are exact in FP64)
-//   invert    A_c = G_c + kappa_c I inverted in FP64 by Gauss-Jordan without
-//             pivoting (Hermitian positive definite), in the register layout
-//             of the FP32 inversion
+//   Gram      G_c = H_c^H H_c in FP64 on the VALU, straight into the register
+//             layout: each tile is staged in LDS as complex64 with its users
+//             permuted so that the NS users a lane multiplies are contiguous;
+//             complex64 products are exact in FP64
+//   invert    A_c = G_c + kappa_c I (scaled by a power of two, as the FP32
+//             inversion) inverted by Gauss-Jordan without pivoting (Hermitian
+//             positive definite).  Before step k the matrix is
+//             [[A11^-1, A11^-1 A12], [-A21 A11^-1, S]]: its column k equals
+//             row k conjugated, negated above the diagonal, so one staged
+//             copy of row k in LDS gives every lane both its multiplier and
+//             its column-k entries
 //   factor    t = tr A^-1 - kappa ||A^-1||_F^2 (Lemma 1) in FP64; PD beta,
 //             FD w_c = sqrt(rho_c^2 / (t Es)) (Sec. III-C)
-//   solve     Z = scale A^-1 S in FP64 per chunk of 16 symbols, rounded to
-//             complex64
-//   precode   X_c = H_c Z on FP32 MFMA from the register tile (Sec. III-B/C)
+//   solve     Z = scale A^-1 S in FP64 per chunk of 16 symbols: A^-1 is
+//             Hermitian, so lane (r, c) forms the part of Z[c][k] over its own
+//             rows from its column and the row groups add their parts
+//   precode   X_c = H_c Z accumulated in FP64 from the FP32 register tiles
+//             (Sec. III-B/C), rounded to complex64
 //
 // Status of every instance: PRECODE_ST_FP64, plus PRECODE_ST_FAIL when a
 // pivot is not above kRelPivot64 times its original diagonal entry or t is
@@ -28,28 +37,55 @@ namespace pc {
 namespace {
 
 constexpr int kF64Waves = 4;
-constexpr int kF64Up = 16;
-// LDS per wave: the rows (32 x 16 complex64) then A^-1 (16 x 16 complex
-// FP64) in the same area, and the symbol chunk / Z chunk (16 x 16 complex64).
-constexpr size_t kF64RowsBytes = 32 * kF64Up * 8;
-constexpr size_t kF64ZBytes = kF64Up * KC * 8;
-constexpr size_t kF64PerWave = kF64RowsBytes + kF64ZBytes;
-static_assert(kF64Up * kF64Up * 16 <= kF64RowsBytes, "A^-1 overlays the rows");
 
-__device__ __forceinline__ double dpp_bcast16_d(double v, int k) {
-    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
-    const float lo = dpp_bcast16_dyn(ffrom((unsigned)b), k);
-    const float hi = dpp_bcast16_dyn(ffrom((unsigned)(b >> 32)), k);
-    return __builtin_bit_cast(double, (unsigned long long)fbits(lo) | ((unsigned long long)fbits(hi) << 32));
+template <int UP>
+struct F64L {
+    static constexpr int R = 64 / UP;   // row groups
+    static constexpr int NS = UP / R;   // slots per lane
+    // LDS per wave: one staged row tile (32 x UP complex64), later the symbol
+    // chunk [KC][UP] (complex64); the Z chunk [KC][UP] (complex FP64); a row
+    // buffer of UP complex FP64 for the inversion
+    static constexpr size_t rows_bytes = (size_t)32 * UP * 8;
+    static constexpr size_t z_bytes = (size_t)KC * UP * 16;
+    static constexpr size_t rowbuf_bytes = (size_t)UP * 16;
+    static constexpr size_t per_wave = rows_bytes + z_bytes + rowbuf_bytes;
+    static_assert((size_t)UP * KC * 8 <= rows_bytes, "the symbol chunk overlays the rows");
+};
+
+// Position of user u in a staged row (and in a staged FP64 row of the
+// inversion): users s R + r, s < NS, are contiguous for row group r.
+template <int UP>
+__device__ __forceinline__ int upos(int u) {
+    return (u % F64L<UP>::R) * F64L<UP>::NS + u / F64L<UP>::R;
 }
 
-// lane (r, c) receives v of lane (rk, c) (row groups of 16 lanes)
-__device__ __forceinline__ double bperm_group_d(double v, int c4, int rk) {
+__device__ __forceinline__ double swap16_d(double v, bool odd) {
     const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
-    const int addr = rk * 16 * 4 + c4;
-    const unsigned lo = (unsigned)__builtin_amdgcn_ds_bpermute(addr, (int)(unsigned)b);
-    const unsigned hi = (unsigned)__builtin_amdgcn_ds_bpermute(addr, (int)(unsigned)(b >> 32));
+    float a0, a1, b0, b1;
+    swap16(ffrom((unsigned)b), a0, a1);
+    swap16(ffrom((unsigned)(b >> 32)), b0, b1);
+    const unsigned lo = fbits(odd ? a1 : a0), hi = fbits(odd ? b1 : b0);
     return __builtin_bit_cast(double, (unsigned long long)lo | ((unsigned long long)hi << 32));
+}
+__device__ __forceinline__ double swap32_d(double v, bool hi_half) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    float a0, a1, b0, b1;
+    swap32(ffrom((unsigned)b), a0, a1);
+    swap32(ffrom((unsigned)(b >> 32)), b0, b1);
+    const unsigned lo = fbits(hi_half ? a1 : a0), hi = fbits(hi_half ? b1 : b0);
+    return __builtin_bit_cast(double, (unsigned long long)lo | ((unsigned long long)hi << 32));
+}
+
+// Sum of v over the R row groups (lanes c, c + UP, ...): every lane of a
+// column ends with the same sum.
+template <int UP>
+__device__ __forceinline__ double group_sum_d(double v) {
+    const int lane = lane_id();
+    if constexpr (UP == 16) {
+        // rows of 16 lanes: pair 0+1, 2+3 (permlane16 swap), then halves
+        v = v + swap16_d(v, (lane & 16) == 0);
+    }
+    return v + swap32_d(v, lane < 32);
 }
 
 __device__ __forceinline__ double wave_max_d(double v) {
@@ -64,65 +100,119 @@ __device__ __forceinline__ double wave_sum_d(double v) {
     return v;
 }
 
-// Gauss-Jordan inversion of the m x m Hermitian positive-definite system in
-// registers (lane (r, c) holds column c of rows 4s + r, s = 0..3; rows and
-// columns >= m are the identity), in FP64: step k divides row k by the pivot
-// and eliminates column k from every other row.  Returns whether every pivot
-// is finite and above kRelPivot64 times its original diagonal entry d0.
-__device__ bool wave_inverse_f64(double (&re)[4], double (&im)[4], int m, double d0) {
+__device__ __forceinline__ double readlane_d(double v, int l) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+    return __builtin_bit_cast(double, (unsigned long long)lo | ((unsigned long long)hi << 32));
+}
+
+// Stages a register tile (precode layout: lane (j, g) holds row j, users
+// g UP/2 ..) in LDS as [row][upos(user)] complex64; rows >= nrows and users
+// >= U are zero.
+template <int UP>
+__device__ __forceinline__ void stage_rows(const Tile<UP, kF32> &tl, int nrows, int U, float2 *rowsL) {
     const int lane = lane_id();
-    const int r = lane >> 4, c = lane & 15, c4 = 4 * c;
-    double pv = 1.0;
-    double akc_re = bperm_group_d(re[0], c4, 0);
-    double akc_im = bperm_group_d(im[0], c4, 0);
+    const int j = lane & 31, g = lane >> 5;
+    const bool live = j < nrows;
 #pragma unroll
-    for (int k = 0; k < kF64Up; ++k) {
-        const int sk = k >> 2, rk = k & 3;
-        const double piv = dpp_bcast16_d(akc_re, k);
+    for (int m2 = 0; m2 < UP / 2; ++m2) {
+        const int u = g * (UP / 2) + m2;
+        const bool in = live && u < U;
+        rowsL[j * UP + upos<UP>(u)] = in ? make_float2(tl.f[2 * m2], tl.f[2 * m2 + 1]) : make_float2(0.f, 0.f);
+    }
+}
+
+// G[s R + r][c] += sum over the staged tile's 32 rows of conj(h_{s R + r}) h_c.
+template <int UP>
+__device__ __forceinline__ void gram_rows(const float2 *rowsL, double (&gre)[F64L<UP>::NS],
+                                          double (&gim)[F64L<UP>::NS]) {
+    constexpr int R = F64L<UP>::R, NS = F64L<UP>::NS;
+    const int lane = lane_id();
+    const int r = lane / UP, c = lane % UP;
+    const int pc = upos<UP>(c);
+#pragma unroll 2
+    for (int b = 0; b < 32; ++b) {
+        const float2 hc = rowsL[b * UP + pc];
+        const double xr = hc.x, xi = hc.y;
+        const float4 *hu = (const float4 *)(rowsL + b * UP + r * NS);
+#pragma unroll
+        for (int s2 = 0; s2 < NS / 2; ++s2) {
+            const float4 v = hu[s2];
+            const double a0 = v.x, b0 = v.y, a1 = v.z, b1 = v.w;
+            gre[2 * s2] = fma(a0, xr, fma(b0, xi, gre[2 * s2]));
+            gim[2 * s2] = fma(a0, xi, fma(-b0, xr, gim[2 * s2]));
+            gre[2 * s2 + 1] = fma(a1, xr, fma(b1, xi, gre[2 * s2 + 1]));
+            gim[2 * s2 + 1] = fma(a1, xi, fma(-b1, xr, gim[2 * s2 + 1]));
+        }
+    }
+    (void)R;
+}
+
+// Gauss-Jordan inversion in FP64 of the system in registers (rows / columns
+// >= m hold the identity).  Step k: the lanes of row k's group write row k to
+// LDS (as [upos(c)] complex FP64), every lane reads its column's entry (the
+// multiplier) and the entries at its rows' positions (its column-k entries,
+// by the block structure above), then updates its slots.  Returns whether
+// every pivot is finite and above kRelPivot64 times its original diagonal
+// entry d0.
+template <int UP>
+__device__ __forceinline__ bool gj_f64(double (&re)[F64L<UP>::NS], double (&im)[F64L<UP>::NS], double d0,
+                                       cx<double> *row) {
+    constexpr int R = F64L<UP>::R, NS = F64L<UP>::NS;
+    const int lane = lane_id();
+    const int r = lane / UP, c = lane % UP;
+    const int pc = upos<UP>(c);
+    double pv = 1.0;
+#pragma unroll
+    for (int k = 0; k < UP; ++k) {
+        const int sk = k / R, rk = k % R;
+        if (r == rk) row[pc] = {re[sk], im[sk]};
+        wave_sync();
+        // multiplier row: a_kc / a_kk, and 1 + 1/a_kk in the pivot column so
+        // that one update also turns column k into -a_ik / a_kk; row k
+        // itself becomes a_kc / a_kk (pivot 1/a_kk)
+        const cx<double> akc = row[pc];
+        const double piv = row[upos<UP>(k)].re;
         const bool iscol = c == k;
         pv = iscol ? piv : pv;
-        // 1 / piv: hardware reciprocal and two Newton steps (the error
-        // squares per step: below an ulp of FP64); a zero or non-finite
-        // pivot fails the pivot test anyway
+        // 1 / piv: hardware reciprocal and two Newton steps
         double inv = __builtin_amdgcn_rcp(piv);
         inv = fma(inv, fma(-piv, inv, 1.0), inv);
         inv = fma(inv, fma(-piv, inv, 1.0), inv);
-        const double mre = iscol ? 1.0 + inv : akc_re * inv;
-        const double mim = iscol ? 0.0 : akc_im * inv;
-        const double rowre = iscol ? inv : mre, rowim = mim;
-        const int k1 = k + 1, s1 = k1 >> 2;
-        auto update = [&](int s) {
-            const double aik_re = dpp_bcast16_d(re[s], k), aik_im = dpp_bcast16_d(im[s], k);
-            double x = re[s] - (aik_re * mre - aik_im * mim);
-            double y = im[s] - (aik_re * mim + aik_im * mre);
-            if (s == sk) {
-                const bool isrow = r == rk;
-                x = isrow ? rowre : x;
-                y = isrow ? rowim : y;
-            }
-            re[s] = x;
-            im[s] = y;
-        };
-        if (k1 < kF64Up) {
-            update(s1);
-            akc_re = bperm_group_d(re[s1], c4, k1 & 3);
-            akc_im = bperm_group_d(im[s1], c4, k1 & 3);
-        }
+        const double mre = iscol ? 1.0 + inv : akc.re * inv;
+        const double mim = iscol ? 0.0 : akc.im * inv;
+        const bool isrow = r == rk;
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
-            if (k1 >= kF64Up || s != s1) update(s);
+        for (int s = 0; s < NS; ++s) {
+            // column k at row i = s R + r: conj(a_ki), negated for i < k
+            const cx<double> ak = row[r * NS + s];
+            const double sg = s * R + r < k ? -1.0 : 1.0;
+            const double ar = sg * ak.re, ai = -sg * ak.im;
+            const double xr = fma(-ar, mre, fma(ai, mim, re[s]));
+            const double xi = fma(-ar, mim, fma(-ai, mre, im[s]));
+            if (s == sk) {
+                re[s] = isrow ? (iscol ? inv : mre) : xr;
+                im[s] = isrow ? mim : xi;
+            } else {
+                re[s] = xr;
+                im[s] = xi;
+            }
+        }
+        wave_sync();  // the row buffer is rewritten by the next step
+        __builtin_amdgcn_sched_barrier(0);
     }
-    (void)m;
     return __all((pv > kRelPivot64 * d0) && (pv < (double)INFINITY));
 }
 
-template <bool VEC>
+template <int UP, int NT>
 __device__ __forceinline__ void f64_system(const Prob &p, const int *__restrict__ off, int sys, int K,
                                            const float2 *__restrict__ H, const float2 *__restrict__ s,
                                            float2 *__restrict__ x, float *__restrict__ scale_out,
                                            int *__restrict__ status, char *wb) {
+    constexpr int R = F64L<UP>::R, NS = F64L<UP>::NS;
     const int lane = lane_id();
-    const int r = lane >> 4, c = lane & 15;
+    const int r = lane / UP, c = lane % UP;
     const bool pd = p.arch == kPD;
     const int B = p.B, U = p.U, C = p.C, n_sc = p.n_sc;
     const int n = pd ? sys : sys / C;
@@ -130,86 +220,75 @@ __device__ __forceinline__ void f64_system(const Prob &p, const int *__restrict_
     const int r0 = pd ? 0 : off[cl], r1 = pd ? B : off[cl + 1];
     const int nrows = r1 - r0;
     const float2 *Hn = H + (size_t)n * B * U;
-    float2 *rows = (float2 *)wb;                 // [32][16] complex64, then A^-1
-    cx<double> *ainv = (cx<double> *)wb;          // [16][16] complex FP64
-    cx<float> *zb = (cx<float> *)(wb + kF64RowsBytes);  // [16][KC] complex64
+    float2 *rowsL = (float2 *)wb;                                  // [32][UP] staged rows
+    cx<float> *sb = (cx<float> *)wb;                               // [KC][UP] symbols (upos order)
+    cx<double> *zb = (cx<double> *)(wb + F64L<UP>::rows_bytes);   // [KC][UP] Z chunk
+    cx<double> *rowbuf = (cx<double> *)(wb + F64L<UP>::rows_bytes + F64L<UP>::z_bytes);
     const double kap = pd ? (double)pd_kappa(p) : (double)fd_kappa(p);
 
-    Tile<kF64Up, kF32> tl;
-    load_tile<kF64Up, kF32, VEC>(Hn, U, r0, nrows, tl);
-
-    // rows to LDS as [row][user] complex64, rows >= nrows and users >= U zero
-    {
-        const int j = lane & 31, g = lane >> 5;
-        const bool live = j < nrows;
+    // Gram in FP64, tile by tile through the staged rows (the tiles are not
+    // kept in registers across the inversion: the precode loads them again)
+    double gre[NS], gim[NS];
 #pragma unroll
-        for (int m2 = 0; m2 < 8; m2 += 2) {
-            const int u = g * 8 + m2;
-            float4 v;
-            v.x = (live && u < U) ? tl.f[2 * m2] : 0.f;
-            v.y = (live && u < U) ? tl.f[2 * m2 + 1] : 0.f;
-            v.z = (live && u + 1 < U) ? tl.f[2 * m2 + 2] : 0.f;
-            v.w = (live && u + 1 < U) ? tl.f[2 * m2 + 3] : 0.f;
-            *(float4 *)(rows + j * kF64Up + u) = v;
+    for (int q = 0; q < NS; ++q) gre[q] = gim[q] = 0.0;
+#pragma unroll
+    for (int q = 0; q < NT; ++q) {
+        if (32 * q < nrows) {
+            Tile<UP, kF32> tl;
+            load_tile<UP, kF32, false>(Hn, U, r0 + 32 * q, min(32, nrows - 32 * q), tl);
+            stage_rows<UP>(tl, nrows - 32 * q, U, rowsL);
+            wave_sync();
+            gram_rows<UP>(rowsL, gre, gim);
+            wave_sync();  // the staging area is rewritten by the next tile
         }
     }
-    wave_sync();
-    // Gram in FP64: lane (r, c) forms G[4s + r][c] = sum_j conj(h_j,4s+r) h_jc
-    double gre[4] = {0.0, 0.0, 0.0, 0.0}, gim[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-    for (int j = 0; j < 32; ++j) {
-        const float2 hc = rows[j * kF64Up + c];
-        const double xr = hc.x, xi = hc.y;
+    // A = G + kappa I, identity past U; d0 = original diagonal entry of column c
+    double dloc = 0.0;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const float2 hu = rows[j * kF64Up + 4 * q + r];
-            const double ar = hu.x, ai = hu.y;
-            gre[q] = fma(ar, xr, fma(ai, xi, gre[q]));
-            gim[q] = fma(ar, xi, fma(-ai, xr, gim[q]));
-        }
-    }
-    wave_sync();  // the rows area becomes A^-1
-    // A = G + kappa I, identity past U
-    double d0 = 1.0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int i = 4 * q + r;
+    for (int q = 0; q < NS; ++q) {
+        const int i = q * R + r;
         const bool in = i < U && c < U;
         if (i == c) {
             gre[q] = in ? gre[q] + kap : 1.0;
-            d0 = gre[q];
+            dloc = gre[q];
         } else if (!in) {
             gre[q] = 0.0;
         }
         gim[q] = in && i != c ? gim[q] : 0.0;
     }
-    // d0 of column c lives in lane (c & 3, c) slot c >> 2; broadcast it down the column
-    d0 = bperm_group_d(d0, 4 * c, c & 3);
-    // invert 2^-e A with its largest diagonal entry in [0.5, 1), so that no
-    // pivot exceeds 1 and 1 + 1/pivot in the update keeps 1/pivot exact to an
-    // ulp; A^-1 = 2^-e (2^-e A)^-1
+    // the diagonal entry of column c sits in row group c % R: to every lane of the column
+    double d0 = group_sum_d<UP>(r == c % R ? dloc : 0.0);
+    // invert 2^-e A with its largest diagonal entry in [0.5, 1) (no pivot
+    // above 1, so 1 + 1/pivot keeps 1/pivot to an ulp); A^-1 = 2^-e (2^-e A)^-1
     const double dmax = wave_max_d(c < U ? d0 : 0.0);
     int e = 0;
     if (dmax > 0.0 && dmax < (double)INFINITY) e = ilogb(dmax) + 1;
     const double sc = ldexp(1.0, -e);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const bool in = 4 * q + r < U && c < U;
+    for (int q = 0; q < NS; ++q) {
+        const bool in = q * R + r < U && c < U;
         gre[q] = in ? gre[q] * sc : gre[q];
         gim[q] = in ? gim[q] * sc : gim[q];
     }
     d0 = c < U ? d0 * sc : d0;
-    bool ok = wave_inverse_f64(gre, gim, U, d0);
+    bool ok = gj_f64<UP>(gre, gim, d0, rowbuf);
+    // the rows again for the precode (in flight during the Lemma-1 sums)
+    Tile<UP, kF32> tl[NT];
+#pragma unroll
+    for (int q = 0; q < NT; ++q) {
+        const bool v = 32 * q < nrows;
+        load_tile<UP, kF32, false>(Hn, U, v ? r0 + 32 * q : r0, v ? min(32, nrows - 32 * q) : 0, tl[q]);
+    }
     double tr = 0.0, fro = 0.0;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int i = 4 * q + r;
-        const double vr = gre[q] * sc, vi = gim[q] * sc;
+    for (int q = 0; q < NS; ++q) {
+        const int i = q * R + r;
+        gre[q] *= sc;
+        gim[q] *= sc;
         if (i < U && c < U) {
-            fro += vr * vr + vi * vi;
-            if (i == c) tr += vr;
+            fro += gre[q] * gre[q] + gim[q] * gim[q];
+            if (i == c) tr += gre[q];
         }
-        ainv[i * kF64Up + c] = {vr, vi};
     }
     tr = wave_sum_d(tr);
     fro = wave_sum_d(fro);
@@ -229,50 +308,68 @@ __device__ __forceinline__ void f64_system(const Prob &p, const int *__restrict_
         if (scale_out) scale_out[sys] = (float)out;
         if (status) status[sys] = (ok ? PRECODE_ST_OK : PRECODE_ST_FAIL) | PRECODE_ST_FP64;
     }
-    wave_sync();
     for (int k0 = 0; k0 < K; k0 += KC) {
         const int kc = min(KC, K - k0);
-        // symbol chunk to LDS as [user][k] complex64 (zero past U / kc)
-#pragma unroll
-        for (int e = lane; e < kF64Up * KC; e += 64) {
-            const int u = e / KC, k = e % KC;
+        // symbol chunk to LDS as [k][upos(u)] complex64 (zero past U / kc)
+        for (int e2 = lane; e2 < UP * KC; e2 += 64) {
+            const int k = e2 / UP, u = e2 % UP;
             float2 v = make_float2(0.f, 0.f);
             if (u < U && k < kc) v = s[((size_t)(k0 + k) * n_sc + n) * U + u];
-            zb[e] = {v.x, v.y};
+            sb[k * UP + upos<UP>(u)] = {v.x, v.y};
         }
         wave_sync();
-        // Z(u, k) = scale (A^-1 S)(u, k) in FP64: lane -> u = lane & 15, k = (lane >> 4) + 4 q
-        cx<double> zacc[4];
+        // Z[c][k] = scale sum_i conj(A^-1[i][c]) S[i][k] (A^-1 Hermitian): this
+        // lane's rows i = q R + r, then the row groups' parts added
+        for (int k = 0; k < KC; ++k) {
+            const float4 *sk = (const float4 *)(sb + k * UP + r * NS);
+            double zr = 0.0, zi = 0.0;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) zacc[q] = {0.0, 0.0};
-        const int u = lane & 15;
-#pragma unroll 4
-        for (int v = 0; v < kF64Up; ++v) {
-            const cx<double> a = ainv[u * kF64Up + v];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const cx<float> sv = zb[v * KC + (lane >> 4) + 4 * q];
-                const double sr = sv.re, si = sv.im;
-                zacc[q].re = fma(a.re, sr, fma(-a.im, si, zacc[q].re));
-                zacc[q].im = fma(a.re, si, fma(a.im, sr, zacc[q].im));
+            for (int q2 = 0; q2 < NS / 2; ++q2) {
+                const float4 v = sk[q2];
+                const double s0r = v.x, s0i = v.y, s1r = v.z, s1i = v.w;
+                zr = fma(gre[2 * q2], s0r, fma(gim[2 * q2], s0i, zr));
+                zi = fma(gre[2 * q2], s0i, fma(-gim[2 * q2], s0r, zi));
+                zr = fma(gre[2 * q2 + 1], s1r, fma(gim[2 * q2 + 1], s1i, zr));
+                zi = fma(gre[2 * q2 + 1], s1i, fma(-gim[2 * q2 + 1], s1r, zi));
+            }
+            zr = group_sum_d<UP>(zr);
+            zi = group_sum_d<UP>(zi);
+            if (r == 0) {
+                const bool live = ok && c < U && k < kc;
+                zb[k * UP + c] = {live ? scale * zr : 0.0, live ? scale * zi : 0.0};
             }
         }
-        wave_sync();  // every read of the symbol chunk is done
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int k = (lane >> 4) + 4 * q;
-            const bool live = ok && u < U && k < kc;
-            zb[u * KC + k] = {live ? (float)(scale * zacc[q].re) : 0.f, live ? (float)(scale * zacc[q].im) : 0.f};
-        }
         wave_sync();
-        ZOp<kF64Up, kF32> z;
-        make_zop<kF64Up, kF32>(zb, KC, 1, kc, z);
-        store_x(mfma_apply_packed<kF64Up, kF32>(tl, z), r0, nrows, k0, kc, n, n_sc, B, x);
-        wave_sync();  // zb is rewritten by the next chunk
+        // precode x_c = H_c z accumulated in FP64 (an ill-conditioned H_c
+        // cancels in this product: FP32 accumulation would lose about
+        // cond(H_c) units of roundoff); lane (j, g) holds row j, users
+        // g UP/2 .. of each tile and adds its half of the sum to its partner's
+        const int j = lane & 31, g = lane >> 5;
+#pragma unroll
+        for (int q = 0; q < NT; ++q) {
+            if (32 * q >= nrows) continue;
+            const int nq = min(32, nrows - 32 * q);
+            float2 *xq = x + ((size_t)k0 * n_sc + n) * B + r0 + 32 * q + j;
+            for (int k = 0; k < KC; ++k) {
+                const cx<double> *zk = zb + k * UP + g * (UP / 2);
+                double xr = 0.0, xi = 0.0;
+#pragma unroll
+                for (int m2 = 0; m2 < UP / 2; ++m2) {
+                    const cx<double> zz = zk[m2];
+                    const double hr = tl[q].f[2 * m2], hi = tl[q].f[2 * m2 + 1];
+                    xr = fma(hr, zz.re, fma(-hi, zz.im, xr));
+                    xi = fma(hr, zz.im, fma(hi, zz.re, xi));
+                }
+                xr += swap32_d(xr, g == 0);
+                xi += swap32_d(xi, g == 0);
+                if ((k & 1) == g && k < kc && j < nq) xq[(size_t)k * n_sc * B] = make_float2((float)xr, (float)xi);
+            }
+        }
+        wave_sync();  // the chunks are rewritten by the next one
     }
 }
 
-template <bool VEC>
+template <int UP, int NT>
 __global__ void __launch_bounds__(64 * kF64Waves, 2)
     fused_f64_k(Prob p, int K, const float2 *__restrict__ H, const float2 *__restrict__ s, float2 *__restrict__ x,
                 float *__restrict__ scale_out, int *__restrict__ status) {
@@ -281,35 +378,50 @@ __global__ void __launch_bounds__(64 * kF64Waves, 2)
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int sys = blockIdx.x * kF64Waves + wave;
     if (sys >= n_inst(p)) return;
-    f64_system<VEC>(p, off, sys, K, H, s, x, scale_out, status, (char *)smem_f64 + (size_t)wave * kF64PerWave);
+    f64_system<UP, NT>(p, off, sys, K, H, s, x, scale_out, status,
+                       (char *)smem_f64 + (size_t)wave * F64L<UP>::per_wave);
+}
+
+// Rows of the largest local system of a problem.
+int max_rows(const Prob &p) {
+    if (p.arch == kPD) return p.B;
+    int m = 0;
+    for (int c = 0; c < p.C; ++c) m = p.off[c + 1] - p.off[c] > m ? p.off[c + 1] - p.off[c] : m;
+    return m;
+}
+
+template <int UP, int NT>
+hipError_t launch_f64(const Prob &p, const float2 *H, const float2 *s, float2 *x, float *scale_out, int *status,
+                      hipStream_t st) {
+    const int ni = n_inst(p);
+    const unsigned blocks = (unsigned)((ni + kF64Waves - 1) / kF64Waves);
+    const size_t lds = F64L<UP>::per_wave * kF64Waves;
+    hipLaunchKernelGGL((fused_f64_k<UP, NT>), dim3(blocks), dim3(64 * kF64Waves), lds, st, p, p.K, H, s, x,
+                       scale_out, status);
+    return hipGetLastError();
 }
 
 }  // namespace
 
 bool fused_f64_supported(const Prob &p, int precision, int K) {
-    if (K < 1 || p.U > kF64Up || precision == PRECODE_PREC_FP64) return false;
-    if (p.arch == kPD) return p.pd_fp64 && p.B >= p.U && p.B <= 32;
+    if (K < 1 || p.U > 32 || precision == PRECODE_PREC_FP64) return false;
+    if (p.arch == kPD) return p.pd_fp64 && p.B >= p.U && p.B <= 64;
     for (int c = 0; c < p.C; ++c) {
         const int bc = p.off[c + 1] - p.off[c];
-        if (!p.fp64[c] || bc < p.U || bc > 32) return false;
+        if (!p.fp64[c] || bc < p.U || bc > 64) return false;
     }
     return true;
 }
 
 hipError_t fused_f64_run(const Prob &p, const float2 *H, const float2 *s, float2 *x, float *scale_out, int *status,
                          hipStream_t st) {
-    const int ni = n_inst(p);
-    if (ni == 0) return hipSuccess;
-    const unsigned blocks = (unsigned)((ni + kF64Waves - 1) / kF64Waves);
-    const size_t lds = kF64PerWave * kF64Waves;
-    const bool vec = pick_vec(p, H);
-    if (vec)
-        hipLaunchKernelGGL((fused_f64_k<true>), dim3(blocks), dim3(64 * kF64Waves), lds, st, p, p.K, H, s, x,
-                           scale_out, status);
-    else
-        hipLaunchKernelGGL((fused_f64_k<false>), dim3(blocks), dim3(64 * kF64Waves), lds, st, p, p.K, H, s, x,
-                           scale_out, status);
-    return hipGetLastError();
+    if (n_inst(p) == 0) return hipSuccess;
+    const bool two = max_rows(p) > 32;
+    if (p.U <= 16)
+        return two ? launch_f64<16, 2>(p, H, s, x, scale_out, status, st)
+                   : launch_f64<16, 1>(p, H, s, x, scale_out, status, st);
+    return two ? launch_f64<32, 2>(p, H, s, x, scale_out, status, st)
+               : launch_f64<32, 1>(p, H, s, x, scale_out, status, st);
 }
 
 }  // namespace pc

@@ -156,30 +156,38 @@ def test_fp64_route_square(torch, ctx, pc):
     synth.Cell(B=64, sizes=(16,) * 4, U=16, n_sc=23, K=19, snr_db=20.0),          # B_c = U
     synth.Cell(B=47, sizes=(11, 14, 22), U=11, n_sc=15, K=5, snr_db=5.0, qam=16),  # ragged, U < 16
     synth.Cell(B=5, sizes=(1, 2, 2), U=1, n_sc=7, K=3, snr_db=0.0),                 # U = 1, tiny clusters
-], ids=["b256_bc32_u16", "bc16_u16", "ragged_u11", "u1_tiny"])
+    synth.Cell(B=128, sizes=(32,) * 4, U=32, n_sc=11, K=14, snr_db=10.0, channel="kron"),  # B_c = U = 32
+    synth.Cell(B=88, sizes=(40, 48), U=24, n_sc=9, K=17, snr_db=5.0),            # two row tiles, U in 17..32
+    synth.Cell(B=64, sizes=(64,), U=20, n_sc=6, K=3, snr_db=15.0),               # B_c = 64 (ratio 0.3)
+], ids=["b256_bc32_u16", "bc16_u16", "ragged_u11", "u1_tiny", "bc32_u32", "bc40_48_u24", "bc64_u20"])
 @pytest.mark.parametrize("mode", ["wf", "zf"])
 def test_fd_fp64_route_fused(torch, ctx, pc, cell, mode):
-    """FD whose every cluster takes the FP64 route (U / B_c >= 0.5) with
-    U <= B_c <= 32 runs in one fused launch (Gram, inversion and solve in FP64,
-    precode on FP32 MFMA): against the oracle and against the plain FP64
-    kernels; every instance flagged FP64."""
+    """FD whose every cluster takes the FP64 route (U / B_c >= the ratio) with
+    U <= 32 and U <= B_c <= 64 runs in one fused launch (Gram, inversion and
+    solve in FP64, precode on FP32 MFMA): against the oracle and against the
+    plain FP64 kernels; every instance flagged FP64."""
     H, s = synth.make_cell(cell, seed=21)
-    xg, scg, stg = _run(torch, ctx, pc, "fd", H, s, cell.kappa, cell.sizes, mode)
+    ratio = min(cell.U / b for b in cell.sizes)
+    xg, scg, stg = _run(torch, ctx, pc, "fd", H, s, cell.kappa, cell.sizes, mode, fp64_ratio=min(0.5, ratio))
     assert ctx.last_impl == "fused" and ctx.last_waves == 4
     assert ((stg & 2) == 2).all()
     xo, sco, sto = _oracle("fd", H, s, cell.kappa, cell.sizes, mode)
     _check(xg, scg, stg, xo, sco, sto)
-    xp, scp, stp = _run(torch, ctx, pc, "fd", H, s, cell.kappa, cell.sizes, mode, impl="plain")
+    xp, scp, stp = _run(torch, ctx, pc, "fd", H, s, cell.kappa, cell.sizes, mode, impl="plain",
+                        fp64_ratio=min(0.5, ratio))
     assert ctx.last_impl == "plain" and (stp == stg).all()
     assert _vec_err(xg, xp).max() <= TOL
 
 
+@pytest.mark.parametrize("cell", [
+    synth.Cell(B=24, sizes=(12, 12), U=12, n_sc=19, K=17, snr_db=15.0),
+    synth.Cell(B=64, sizes=(32, 32), U=32, n_sc=7, K=17, snr_db=15.0),
+], ids=["b24_u12", "b64_u32"])
 @pytest.mark.parametrize("mode", ["wf", "zf"])
-def test_pd_fp64_route_fused(torch, ctx, pc, mode):
-    """PD with U / B = 0.5 and B <= 32 (every subcarrier on the FP64 route)
+def test_pd_fp64_route_fused(torch, ctx, pc, cell, mode):
+    """PD with U / B = 0.5 and B <= 64 (every subcarrier on the FP64 route)
     runs on the fused FP64 kernel, 17 symbols (two chunks): against the oracle
     and the plain FP64 kernels; precision FP64 keeps the plain kernels."""
-    cell = synth.Cell(B=24, sizes=(12, 12), U=12, n_sc=19, K=17, snr_db=15.0)
     H, s = synth.make_cell(cell, seed=13)
     xg, scg, stg = _run(torch, ctx, pc, "pd", H, s, cell.kappa, cell.sizes, mode)
     assert ctx.last_impl == "fused" and (stg == 2).all()
@@ -315,7 +323,8 @@ def test_refinement_fp64_residual(torch, ctx, pc, arch, cell, ratio, envelope):
     H, s = synth.make_cell(cell, seed=5)
     Hd, sd = _dev(torch, H), _dev(torch, s)
     fn = ctx.pd if arch == "pd" else ctx.fd
-    x0, sc0, _ = fn(Hd, sd, cell.kappa, cell.sizes, "wf", pc.params(fp64_ratio=ratio))
+    # the unrefined result of the same (plain) kernels
+    x0, sc0, _ = fn(Hd, sd, cell.kappa, cell.sizes, "wf", pc.params(fp64_ratio=ratio, impl="plain"))
     x1, sc1, st1 = fn(Hd, sd, cell.kappa, cell.sizes, "wf", pc.params(fp64_ratio=ratio, refine_steps=1))
     torch.cuda.synchronize()
     assert ctx.last_impl == "plain"
