@@ -25,8 +25,10 @@
 //   solve     Z = scale A^-1 S in FP64 per chunk of 16 symbols: A^-1 is
 //             Hermitian, so lane (r, c) forms the part of Z[c][k] over its own
 //             rows from its column and the row groups add their parts
-//   precode   X_c = H_c Z accumulated in FP64 from the FP32 register tiles
-//             (Sec. III-B/C), rounded to complex64
+//   precode   X_c = H_c Z (Sec. III-B/C) from register tiles loaded again
+//             after the inversion: accumulated in FP64 for ZF and for local
+//             systems with U / B_eff > 3/4 (precode_in_fp64), otherwise on
+//             FP32 MFMA from Z rounded to complex64
 //
 // Status of every instance: PRECODE_ST_FP64, plus PRECODE_ST_FAIL when a
 // pivot is not above kRelPivot64 times its original diagonal entry or t is
@@ -42,14 +44,18 @@ template <int UP>
 struct F64L {
     static constexpr int R = 64 / UP;   // row groups
     static constexpr int NS = UP / R;   // slots per lane
-    // LDS per wave: one staged row tile (32 x UP complex64), later the symbol
-    // chunk [KC][UP] (complex64); the Z chunk [KC][UP] (complex FP64); a row
-    // buffer of UP complex FP64 for the inversion
+    // LDS per wave: one staged row tile (32 x UP complex64), whose area then
+    // holds the symbol chunk [KC][UP] and the FP32 Z chunk [UP][KC]
+    // (complex64); the FP64 Z chunk [KC][UP] (complex FP64, precode in
+    // FP64 only); a row buffer of UP complex FP64 for the inversion
     static constexpr size_t rows_bytes = (size_t)32 * UP * 8;
-    static constexpr size_t z_bytes = (size_t)KC * UP * 16;
+    static constexpr size_t s_bytes = (size_t)KC * UP * 8;
+    static constexpr size_t z64_bytes = (size_t)KC * UP * 16;
     static constexpr size_t rowbuf_bytes = (size_t)UP * 16;
-    static constexpr size_t per_wave = rows_bytes + z_bytes + rowbuf_bytes;
-    static_assert((size_t)UP * KC * 8 <= rows_bytes, "the symbol chunk overlays the rows");
+    static constexpr size_t per_wave(bool p64) { return rows_bytes + (p64 ? z64_bytes : 0) + rowbuf_bytes; }
+    static_assert(2 * s_bytes <= rows_bytes, "symbol and FP32 Z chunks overlay the rows");
+    // symbols a lane loads per chunk
+    static constexpr int SPL = UP * KC / 64;
 };
 
 // Position of user u in a staged row (and in a staged FP64 row of the
@@ -205,7 +211,33 @@ __device__ __forceinline__ bool gj_f64(double (&re)[F64L<UP>::NS], double (&im)[
     return __all((pv > kRelPivot64 * d0) && (pv < (double)INFINITY));
 }
 
-template <int UP, int NT>
+// The symbols of chunk k0 a lane stages: entry e = lane + 64 i of the
+// [KC][UP] chunk (symbol e / UP, user e % UP), loaded from clamped in-range
+// addresses (masked when staged).
+template <int UP>
+__device__ __forceinline__ void load_syms(const float2 *__restrict__ s, int k0, int kc, int n, int n_sc, int U,
+                                          float2 (&v)[F64L<UP>::SPL]) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int i = 0; i < F64L<UP>::SPL; ++i) {
+        const int e = lane + 64 * i, k = e / UP, u = e % UP;
+        const int kk = k < kc ? k : kc - 1, uu = u < U ? u : U - 1;
+        v[i] = s[((size_t)(k0 + kk) * n_sc + n) * U + uu];
+    }
+}
+
+template <int UP>
+__device__ __forceinline__ void stage_syms(const float2 (&v)[F64L<UP>::SPL], int kc, int U, cx<float> *sb) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int i = 0; i < F64L<UP>::SPL; ++i) {
+        const int e = lane + 64 * i, k = e / UP, u = e % UP;
+        const bool in = k < kc && u < U;
+        sb[k * UP + upos<UP>(u)] = {in ? v[i].x : 0.f, in ? v[i].y : 0.f};
+    }
+}
+
+template <int UP, int NT, int KU, bool P64>
 __device__ __forceinline__ void f64_system(const Prob &p, const int *__restrict__ off, int sys, int K,
                                            const float2 *__restrict__ H, const float2 *__restrict__ s,
                                            float2 *__restrict__ x, float *__restrict__ scale_out,
@@ -220,28 +252,32 @@ __device__ __forceinline__ void f64_system(const Prob &p, const int *__restrict_
     const int r0 = pd ? 0 : off[cl], r1 = pd ? B : off[cl + 1];
     const int nrows = r1 - r0;
     const float2 *Hn = H + (size_t)n * B * U;
-    float2 *rowsL = (float2 *)wb;                                  // [32][UP] staged rows
-    cx<float> *sb = (cx<float> *)wb;                               // [KC][UP] symbols (upos order)
-    cx<double> *zb = (cx<double> *)(wb + F64L<UP>::rows_bytes);   // [KC][UP] Z chunk
-    cx<double> *rowbuf = (cx<double> *)(wb + F64L<UP>::rows_bytes + F64L<UP>::z_bytes);
+    float2 *rowsL = (float2 *)wb;                                         // [32][UP] staged rows
+    cx<float> *sb = (cx<float> *)wb;                                     // [KC][UP] symbols (upos order)
+    cx<float> *zb32 = (cx<float> *)(wb + F64L<UP>::s_bytes);             // [UP][KC] Z chunk (FP32 precode)
+    cx<double> *zb = (cx<double> *)(wb + F64L<UP>::rows_bytes);          // [KC][UP] Z chunk (FP64 precode)
+    cx<double> *rowbuf = (cx<double> *)(wb + F64L<UP>::rows_bytes + (P64 ? F64L<UP>::z64_bytes : 0));
     const double kap = pd ? (double)pd_kappa(p) : (double)fd_kappa(p);
 
-    // Gram in FP64, tile by tile through the staged rows (the tiles are not
-    // kept in registers across the inversion: the precode loads them again)
+    // Gram in FP64, tile by tile through the staged rows (no tile is held in
+    // registers across the inversion: the precode loads the rows again)
     double gre[NS], gim[NS];
 #pragma unroll
     for (int q = 0; q < NS; ++q) gre[q] = gim[q] = 0.0;
 #pragma unroll
     for (int q = 0; q < NT; ++q) {
         if (32 * q < nrows) {
-            Tile<UP, kF32> tl;
-            load_tile<UP, kF32, false>(Hn, U, r0 + 32 * q, min(32, nrows - 32 * q), tl);
-            stage_rows<UP>(tl, nrows - 32 * q, U, rowsL);
+            Tile<UP, kF32> tq;
+            load_tile<UP, kF32, false>(Hn, U, r0 + 32 * q, min(32, nrows - 32 * q), tq);
+            stage_rows<UP>(tq, nrows - 32 * q, U, rowsL);
             wave_sync();
             gram_rows<UP>(rowsL, gre, gim);
-            wave_sync();  // the staging area is rewritten by the next tile
+            wave_sync();  // the staging area is rewritten by the next tile and the symbols
         }
     }
+    // the first symbol chunk, in flight during the inversion
+    float2 sym[F64L<UP>::SPL];
+    if (K > 0) load_syms<UP>(s, 0, min(KC, K), n, n_sc, U, sym);
     // A = G + kappa I, identity past U; d0 = original diagonal entry of column c
     double dloc = 0.0;
 #pragma unroll
@@ -308,69 +344,100 @@ __device__ __forceinline__ void f64_system(const Prob &p, const int *__restrict_
         if (scale_out) scale_out[sys] = (float)out;
         if (status) status[sys] = (ok ? PRECODE_ST_OK : PRECODE_ST_FAIL) | PRECODE_ST_FP64;
     }
+    const int j = lane & 31, g = lane >> 5;
     for (int k0 = 0; k0 < K; k0 += KC) {
         const int kc = min(KC, K - k0);
-        // symbol chunk to LDS as [k][upos(u)] complex64 (zero past U / kc)
-        for (int e2 = lane; e2 < UP * KC; e2 += 64) {
-            const int k = e2 / UP, u = e2 % UP;
-            float2 v = make_float2(0.f, 0.f);
-            if (u < U && k < kc) v = s[((size_t)(k0 + k) * n_sc + n) * U + u];
-            sb[k * UP + upos<UP>(u)] = {v.x, v.y};
-        }
+        if (k0 > 0) load_syms<UP>(s, k0, kc, n, n_sc, U, sym);
+        stage_syms<UP>(sym, kc, U, sb);
         wave_sync();
         // Z[c][k] = scale sum_i conj(A^-1[i][c]) S[i][k] (A^-1 Hermitian): this
-        // lane's rows i = q R + r, then the row groups' parts added
-        for (int k = 0; k < KC; ++k) {
-            const float4 *sk = (const float4 *)(sb + k * UP + r * NS);
-            double zr = 0.0, zi = 0.0;
+        // lane's rows i = q R + r, then the row groups' parts added; KU
+        // symbols per pass (independent accumulation chains)
+        for (int k4 = 0; k4 < KC; k4 += KU) {
+            double zr[KU], zi[KU];
+#pragma unroll
+            for (int u = 0; u < KU; ++u) zr[u] = zi[u] = 0.0;
 #pragma unroll
             for (int q2 = 0; q2 < NS / 2; ++q2) {
-                const float4 v = sk[q2];
-                const double s0r = v.x, s0i = v.y, s1r = v.z, s1i = v.w;
-                zr = fma(gre[2 * q2], s0r, fma(gim[2 * q2], s0i, zr));
-                zi = fma(gre[2 * q2], s0i, fma(-gim[2 * q2], s0r, zi));
-                zr = fma(gre[2 * q2 + 1], s1r, fma(gim[2 * q2 + 1], s1i, zr));
-                zi = fma(gre[2 * q2 + 1], s1i, fma(-gim[2 * q2 + 1], s1r, zi));
+#pragma unroll
+                for (int u = 0; u < KU; ++u) {
+                    const float4 v = ((const float4 *)(sb + (k4 + u) * UP + r * NS))[q2];
+                    const double s0r = v.x, s0i = v.y, s1r = v.z, s1i = v.w;
+                    zr[u] = fma(gre[2 * q2], s0r, fma(gim[2 * q2], s0i, zr[u]));
+                    zi[u] = fma(gre[2 * q2], s0i, fma(-gim[2 * q2], s0r, zi[u]));
+                    zr[u] = fma(gre[2 * q2 + 1], s1r, fma(gim[2 * q2 + 1], s1i, zr[u]));
+                    zi[u] = fma(gre[2 * q2 + 1], s1i, fma(-gim[2 * q2 + 1], s1r, zi[u]));
+                }
             }
-            zr = group_sum_d<UP>(zr);
-            zi = group_sum_d<UP>(zi);
-            if (r == 0) {
-                const bool live = ok && c < U && k < kc;
-                zb[k * UP + c] = {live ? scale * zr : 0.0, live ? scale * zi : 0.0};
+#pragma unroll
+            for (int u = 0; u < KU; ++u) {
+                const double a = group_sum_d<UP>(zr[u]), b = group_sum_d<UP>(zi[u]);
+                if (r == 0) {
+                    const bool live = ok && c < U && k4 + u < kc;
+                    if constexpr (P64)
+                        zb[(k4 + u) * UP + c] = {live ? scale * a : 0.0, live ? scale * b : 0.0};
+                    else
+                        zb32[c * KC + k4 + u] = {live ? (float)(scale * a) : 0.f, live ? (float)(scale * b) : 0.f};
+                }
             }
         }
         wave_sync();
-        // precode x_c = H_c z accumulated in FP64 (an ill-conditioned H_c
-        // cancels in this product: FP32 accumulation would lose about
-        // cond(H_c) units of roundoff); lane (j, g) holds row j, users
-        // g UP/2 .. of each tile and adds its half of the sum to its partner's
-        const int j = lane & 31, g = lane >> 5;
+        if constexpr (!P64) {
+            // precode X_c = H_c Z on FP32 MFMA from the register tiles
+            ZOp<UP, kF32> z;
+            make_zop<UP, kF32>(zb32, KC, 1, kc, z);
 #pragma unroll
-        for (int q = 0; q < NT; ++q) {
-            if (32 * q >= nrows) continue;
-            const int nq = min(32, nrows - 32 * q);
-            float2 *xq = x + ((size_t)k0 * n_sc + n) * B + r0 + 32 * q + j;
-            for (int k = 0; k < KC; ++k) {
-                const cx<double> *zk = zb + k * UP + g * (UP / 2);
-                double xr = 0.0, xi = 0.0;
+            for (int q = 0; q < NT; ++q)
+                if (32 * q < nrows)
+                    store_x(mfma_apply_packed<UP, kF32>(tl[q], z), r0 + 32 * q, min(32, nrows - 32 * q), k0, kc, n,
+                            n_sc, B, x);
+        } else {
+            // precode accumulated in FP64: lane (j, g) takes row j, users
+            // g UP/2 .. of each tile and adds its half of the sum to its
+            // partner's
 #pragma unroll
-                for (int m2 = 0; m2 < UP / 2; ++m2) {
-                    const cx<double> zz = zk[m2];
-                    const double hr = tl[q].f[2 * m2], hi = tl[q].f[2 * m2 + 1];
-                    xr = fma(hr, zz.re, fma(-hi, zz.im, xr));
-                    xi = fma(hr, zz.im, fma(hi, zz.re, xi));
+            for (int q = 0; q < NT; ++q) {
+                if (32 * q >= nrows) continue;
+                const int nq = min(32, nrows - 32 * q);
+                float2 *xq = x + ((size_t)k0 * n_sc + n) * B + r0 + 32 * q + j;
+                for (int k4 = 0; k4 < KC; k4 += KU) {
+                    double xr[KU], xi[KU];
+#pragma unroll
+                    for (int u = 0; u < KU; ++u) xr[u] = xi[u] = 0.0;
+#pragma unroll
+                    for (int m2 = 0; m2 < UP / 2; ++m2) {
+                        const double hr = tl[q].f[2 * m2], hi = tl[q].f[2 * m2 + 1];
+#pragma unroll
+                        for (int u = 0; u < KU; ++u) {
+                            const cx<double> zz = zb[(k4 + u) * UP + g * (UP / 2) + m2];
+                            xr[u] = fma(hr, zz.re, fma(-hi, zz.im, xr[u]));
+                            xi[u] = fma(hr, zz.im, fma(hi, zz.re, xi[u]));
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < KU; ++u) {
+                        const int k = k4 + u;
+                        const double a = xr[u] + swap32_d(xr[u], g == 0), b = xi[u] + swap32_d(xi[u], g == 0);
+                        if ((k & 1) == g && k < kc && j < nq)
+                            xq[(size_t)k * n_sc * B] = make_float2((float)a, (float)b);
+                    }
                 }
-                xr += swap32_d(xr, g == 0);
-                xi += swap32_d(xi, g == 0);
-                if ((k & 1) == g && k < kc && j < nq) xq[(size_t)k * n_sc * B] = make_float2((float)xr, (float)xi);
             }
         }
         wave_sync();  // the chunks are rewritten by the next one
     }
 }
 
+// Symbols per pass of the solve and the precode (independent chains), and
+// the waves per SIMD the register allocation targets.
 template <int UP, int NT>
-__global__ void __launch_bounds__(64 * kF64Waves, 2)
+struct F64Cfg {
+    static constexpr int KU = UP == 16 ? 2 : 1;
+    static constexpr int min_waves = UP == 16 ? 3 : 2;
+};
+
+template <int UP, int NT, bool P64>
+__global__ void __launch_bounds__(64 * kF64Waves, (F64Cfg<UP, NT>::min_waves))
     fused_f64_k(Prob p, int K, const float2 *__restrict__ H, const float2 *__restrict__ s, float2 *__restrict__ x,
                 float *__restrict__ scale_out, int *__restrict__ status) {
     extern __shared__ float4 smem_f64[];
@@ -378,8 +445,8 @@ __global__ void __launch_bounds__(64 * kF64Waves, 2)
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int sys = blockIdx.x * kF64Waves + wave;
     if (sys >= n_inst(p)) return;
-    f64_system<UP, NT>(p, off, sys, K, H, s, x, scale_out, status,
-                       (char *)smem_f64 + (size_t)wave * F64L<UP>::per_wave);
+    f64_system<UP, NT, F64Cfg<UP, NT>::KU, P64>(p, off, sys, K, H, s, x, scale_out, status,
+                                                (char *)smem_f64 + (size_t)wave * F64L<UP>::per_wave(P64));
 }
 
 // Rows of the largest local system of a problem.
@@ -390,15 +457,38 @@ int max_rows(const Prob &p) {
     return m;
 }
 
-template <int UP, int NT>
+template <int UP, int NT, bool P64>
 hipError_t launch_f64(const Prob &p, const float2 *H, const float2 *s, float2 *x, float *scale_out, int *status,
                       hipStream_t st) {
     const int ni = n_inst(p);
     const unsigned blocks = (unsigned)((ni + kF64Waves - 1) / kF64Waves);
-    const size_t lds = F64L<UP>::per_wave * kF64Waves;
-    hipLaunchKernelGGL((fused_f64_k<UP, NT>), dim3(blocks), dim3(64 * kF64Waves), lds, st, p, p.K, H, s, x,
+    const size_t lds = F64L<UP>::per_wave(P64) * kF64Waves;
+    hipLaunchKernelGGL((fused_f64_k<UP, NT, P64>), dim3(blocks), dim3(64 * kF64Waves), lds, st, p, p.K, H, s, x,
                        scale_out, status);
     return hipGetLastError();
+}
+
+template <int UP, int NT>
+hipError_t launch_f64_p(bool p64, const Prob &p, const float2 *H, const float2 *s, float2 *x, float *scale_out,
+                        int *status, hipStream_t st) {
+    return p64 ? launch_f64<UP, NT, true>(p, H, s, x, scale_out, status, st)
+               : launch_f64<UP, NT, false>(p, H, s, x, scale_out, status, st);
+}
+
+// Whether the precode of the FP64 route accumulates in FP64.  Its FP32
+// accumulation errs by about u |H_c| |z| / |x_c| (u = 2^-24), which grows
+// with the condition number of H_c: ZF (no regularization) and local
+// systems with U / B_eff > 3/4 (cond(H_c) of an i.i.d. channel grows
+// without bound as B_eff approaches U; at 3/4 it is about
+// (1 + sqrt(3/4)) / (1 - sqrt(3/4)) = 14) accumulate in FP64, the others
+// take the FP32 MFMA precode of the FP64 solve (a relative error of about
+// 1e-6 at U / B_eff = 1/2).
+bool precode_in_fp64(const Prob &p) {
+    if (p.zf) return true;
+    if (p.arch == kPD) return 4 * p.U > 3 * p.B;
+    for (int c = 0; c < p.C; ++c)
+        if (4 * p.U > 3 * (p.off[c + 1] - p.off[c])) return true;
+    return false;
 }
 
 }  // namespace
@@ -416,12 +506,12 @@ bool fused_f64_supported(const Prob &p, int precision, int K) {
 hipError_t fused_f64_run(const Prob &p, const float2 *H, const float2 *s, float2 *x, float *scale_out, int *status,
                          hipStream_t st) {
     if (n_inst(p) == 0) return hipSuccess;
-    const bool two = max_rows(p) > 32;
+    const bool two = max_rows(p) > 32, p64 = precode_in_fp64(p);
     if (p.U <= 16)
-        return two ? launch_f64<16, 2>(p, H, s, x, scale_out, status, st)
-                   : launch_f64<16, 1>(p, H, s, x, scale_out, status, st);
-    return two ? launch_f64<32, 2>(p, H, s, x, scale_out, status, st)
-               : launch_f64<32, 1>(p, H, s, x, scale_out, status, st);
+        return two ? launch_f64_p<16, 2>(p64, p, H, s, x, scale_out, status, st)
+                   : launch_f64_p<16, 1>(p64, p, H, s, x, scale_out, status, st);
+    return two ? launch_f64_p<32, 2>(p64, p, H, s, x, scale_out, status, st)
+               : launch_f64_p<32, 1>(p64, p, H, s, x, scale_out, status, st);
 }
 
 }  // namespace pc
