@@ -92,8 +92,13 @@ typedef struct precode_params {
     int refine_steps;  /* 0 or 1 steps of iterative refinement of the U x U solve */
                        /* (PD; FD clusters with B_c >= U): residual               */
                        /* s - (kappa y + H^H (H y)) accumulated in FP64 from the  */
-                       /* complex64 channel, y += A^-1 r; runs on the plain       */
-                       /* kernels (a request for it is never fused); 0            */
+                       /* complex64 channel, y += A^-1 r.  Shapes the fused      */
+                       /* kernel takes run the fused factorization at the call's */
+                       /* precision, then one fused refine-and-precode launch    */
+                       /* (the FP64 Gram gives the exact residual); a call whose */
+                       /* systems all take the fused FP64 route runs it (an FP64 */
+                       /* solve needs no refinement); others run the plain       */
+                       /* kernels.  beta / weights are not refined; 0            */
     float fp64_ratio;  /* an instance whose local system has U / B_eff >= ratio is */
                        /* solved on the FP64 route (B_eff = B for PD, B_c for FD); */
                        /* 0.5; a value > 1 disables the route                      */

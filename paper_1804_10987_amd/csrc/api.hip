@@ -41,6 +41,10 @@ struct precode_ctx {
     hipEvent_t wsDone;
     hipStream_t wsStream;
     int wsUsed;
+    // fused refinement workspace (factors, scale, status), ordered as the
+    // plain workspace
+    void *wsRef;
+    size_t capRef;
     precode_frame *frames;
     int last_impl;
     int last_waves;  // waves per workgroup of the last fused launch
@@ -261,12 +265,28 @@ int run(precode_ctx *ctx, int arch, const void *H, const void *s, float rho, con
     if (!aligned8(H) || !aligned8(s) || !aligned8(x)) return PRECODE_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     const bool can_fuse = K > 0 && q.refine_steps == 0 && fused_supported(p, q.precision);
+    // one refinement step after the fused factorization (refine.hip)
+    const bool can_refine = K > 0 && q.refine_steps == 1 && fused_supported(p, q.precision);
     // the FP64 route fused (its Gram, inversion and solve in FP64) when every
-    // local system takes it and fits
-    const bool can_f64 = !can_fuse && q.refine_steps == 0 && fused_f64_supported(p, q.precision, K);
-    if (q.impl == PRECODE_IMPL_FUSED && !can_fuse && !can_f64) return PRECODE_EUNSUPPORTED;
+    // local system takes it and fits; its FP64 solve needs no refinement step
+    const bool can_f64 = !can_fuse && !can_refine && fused_f64_supported(p, q.precision, K);
+    if (q.impl == PRECODE_IMPL_FUSED && !can_fuse && !can_f64 && !can_refine) return PRECODE_EUNSUPPORTED;
     if (q.precision == PRECODE_PREC_SPLIT_FP16 || q.precision == PRECODE_PREC_SPLIT_BF16) {
-        if (!can_fuse && !can_f64) return PRECODE_EUNSUPPORTED;
+        if (!can_fuse && !can_f64 && !can_refine) return PRECODE_EUNSUPPORTED;
+    }
+    if (q.impl != PRECODE_IMPL_PLAIN && can_refine) {
+        rc = grow(ctx, &ctx->wsRef, &ctx->capRef, fused_refine_ws_bytes(p), st);
+        if (!rc) rc = ws_acquire(ctx, st);
+        if (rc) return rc;
+        rc = dev_err(fused_refine_run(p, q.precision, (const float2 *)H, (const float2 *)s, (float2 *)x, scale, status,
+                                      ctx->wsRef, st));
+        const int rr = ws_release(ctx, st);
+        if (!rc) rc = rr;
+        if (rc == PRECODE_OK) {
+            ctx->last_impl = PRECODE_IMPL_FUSED;
+            ctx->last_waves = 0;
+        }
+        return rc;
     }
     if (q.impl != PRECODE_IMPL_PLAIN && can_f64) {
         rc = dev_err(fused_f64_run(p, (const float2 *)H, (const float2 *)s, (float2 *)x, scale, status, st));
@@ -362,6 +382,7 @@ int precode_ctx_destroy(precode_ctx *ctx) {
     ctx_free(ctx, ctx->wsAinv, ctx->capAinv);
     ctx_free(ctx, ctx->wsScale, ctx->capScale);
     ctx_free(ctx, ctx->wsZ, ctx->capZ);
+    ctx_free(ctx, ctx->wsRef, ctx->capRef);
     ctx_free(ctx, ctx->tab, ctx->capTab);
     if (ctx->tabHost) (void)hipHostFree(ctx->tabHost);
     if (ctx->tabCopied) (void)hipEventDestroy(ctx->tabCopied);

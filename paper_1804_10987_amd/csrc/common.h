@@ -131,6 +131,16 @@ hipError_t fused_prepare(const Prob &p, int precision, const float2 *H, float2 *
 hipError_t fused_symbols(const Prob &p, int precision, int nk, const float2 *H, const float2 *ainv,
                          const int *status, const float2 *s, float2 *x, hipStream_t st);
 
+// One step of iterative refinement fused after the factorization
+// (refine.hip): fused_prepare at `precision` into the workspace ws
+// (fused_refine_ws_bytes: factors, scale, status), then one wave per system
+// forms the FP64 Gram, the FP32 solve, the FP64 residual, the corrected solve
+// and the precode.  scale_out / status (may be NULL) receive the prepare
+// pass's outputs.
+size_t fused_refine_ws_bytes(const Prob &p);
+hipError_t fused_refine_run(const Prob &p, int precision, const float2 *H, const float2 *s, float2 *x,
+                            float *scale_out, int *status, void *ws, hipStream_t st);
+
 // Heterogeneous batch of fused problems (batch.hip): every problem must be
 // fused_supported at `precision` with K >= 1.  The problems are grouped by
 // tile width (U <= 16 or U <= 32) and each group -- PD and FD alike -- runs as

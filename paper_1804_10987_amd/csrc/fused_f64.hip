@@ -33,127 +33,12 @@
 // Status of every instance: PRECODE_ST_FP64, plus PRECODE_ST_FAIL when a
 // pivot is not above kRelPivot64 times its original diagonal entry or t is
 // not positive (then x = 0 and the scale output is 0).
-#include "fused_kernel.h"
+#include "f64_common.h"
 
 namespace pc {
 namespace {
 
 constexpr int kF64Waves = 4;
-
-template <int UP>
-struct F64L {
-    static constexpr int R = 64 / UP;   // row groups
-    static constexpr int NS = UP / R;   // slots per lane
-    // LDS per wave: one staged row tile (32 x UP complex64), whose area then
-    // holds the symbol chunk [KC][UP] and the FP32 Z chunk [UP][KC]
-    // (complex64); the FP64 Z chunk [KC][UP] (complex FP64, precode in
-    // FP64 only); a row buffer of UP complex FP64 for the inversion
-    static constexpr size_t rows_bytes = (size_t)32 * UP * 8;
-    static constexpr size_t s_bytes = (size_t)KC * UP * 8;
-    static constexpr size_t z64_bytes = (size_t)KC * UP * 16;
-    static constexpr size_t rowbuf_bytes = (size_t)UP * 16;
-    static constexpr size_t per_wave(bool p64) { return rows_bytes + (p64 ? z64_bytes : 0) + rowbuf_bytes; }
-    static_assert(2 * s_bytes <= rows_bytes, "symbol and FP32 Z chunks overlay the rows");
-    // symbols a lane loads per chunk
-    static constexpr int SPL = UP * KC / 64;
-};
-
-// Position of user u in a staged row (and in a staged FP64 row of the
-// inversion): users s R + r, s < NS, are contiguous for row group r.
-template <int UP>
-__device__ __forceinline__ int upos(int u) {
-    return (u % F64L<UP>::R) * F64L<UP>::NS + u / F64L<UP>::R;
-}
-
-__device__ __forceinline__ double swap16_d(double v, bool odd) {
-    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
-    float a0, a1, b0, b1;
-    swap16(ffrom((unsigned)b), a0, a1);
-    swap16(ffrom((unsigned)(b >> 32)), b0, b1);
-    const unsigned lo = fbits(odd ? a1 : a0), hi = fbits(odd ? b1 : b0);
-    return __builtin_bit_cast(double, (unsigned long long)lo | ((unsigned long long)hi << 32));
-}
-__device__ __forceinline__ double swap32_d(double v, bool hi_half) {
-    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
-    float a0, a1, b0, b1;
-    swap32(ffrom((unsigned)b), a0, a1);
-    swap32(ffrom((unsigned)(b >> 32)), b0, b1);
-    const unsigned lo = fbits(hi_half ? a1 : a0), hi = fbits(hi_half ? b1 : b0);
-    return __builtin_bit_cast(double, (unsigned long long)lo | ((unsigned long long)hi << 32));
-}
-
-// Sum of v over the R row groups (lanes c, c + UP, ...): every lane of a
-// column ends with the same sum.
-template <int UP>
-__device__ __forceinline__ double group_sum_d(double v) {
-    const int lane = lane_id();
-    if constexpr (UP == 16) {
-        // rows of 16 lanes: pair 0+1, 2+3 (permlane16 swap), then halves
-        v = v + swap16_d(v, (lane & 16) == 0);
-    }
-    return v + swap32_d(v, lane < 32);
-}
-
-__device__ __forceinline__ double wave_max_d(double v) {
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) v = fmax(v, __shfl_xor(v, o));
-    return v;
-}
-
-__device__ __forceinline__ double wave_sum_d(double v) {
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) v += __shfl_xor(v, o);
-    return v;
-}
-
-__device__ __forceinline__ double readlane_d(double v, int l) {
-    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
-    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
-    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
-    return __builtin_bit_cast(double, (unsigned long long)lo | ((unsigned long long)hi << 32));
-}
-
-// Stages a register tile (precode layout: lane (j, g) holds row j, users
-// g UP/2 ..) in LDS as [row][upos(user)] complex64; rows >= nrows and users
-// >= U are zero.
-template <int UP>
-__device__ __forceinline__ void stage_rows(const Tile<UP, kF32> &tl, int nrows, int U, float2 *rowsL) {
-    const int lane = lane_id();
-    const int j = lane & 31, g = lane >> 5;
-    const bool live = j < nrows;
-#pragma unroll
-    for (int m2 = 0; m2 < UP / 2; ++m2) {
-        const int u = g * (UP / 2) + m2;
-        const bool in = live && u < U;
-        rowsL[j * UP + upos<UP>(u)] = in ? make_float2(tl.f[2 * m2], tl.f[2 * m2 + 1]) : make_float2(0.f, 0.f);
-    }
-}
-
-// G[s R + r][c] += sum over the staged tile's 32 rows of conj(h_{s R + r}) h_c.
-template <int UP>
-__device__ __forceinline__ void gram_rows(const float2 *rowsL, double (&gre)[F64L<UP>::NS],
-                                          double (&gim)[F64L<UP>::NS]) {
-    constexpr int R = F64L<UP>::R, NS = F64L<UP>::NS;
-    const int lane = lane_id();
-    const int r = lane / UP, c = lane % UP;
-    const int pc = upos<UP>(c);
-#pragma unroll 2
-    for (int b = 0; b < 32; ++b) {
-        const float2 hc = rowsL[b * UP + pc];
-        const double xr = hc.x, xi = hc.y;
-        const float4 *hu = (const float4 *)(rowsL + b * UP + r * NS);
-#pragma unroll
-        for (int s2 = 0; s2 < NS / 2; ++s2) {
-            const float4 v = hu[s2];
-            const double a0 = v.x, b0 = v.y, a1 = v.z, b1 = v.w;
-            gre[2 * s2] = fma(a0, xr, fma(b0, xi, gre[2 * s2]));
-            gim[2 * s2] = fma(a0, xi, fma(-b0, xr, gim[2 * s2]));
-            gre[2 * s2 + 1] = fma(a1, xr, fma(b1, xi, gre[2 * s2 + 1]));
-            gim[2 * s2 + 1] = fma(a1, xi, fma(-b1, xr, gim[2 * s2 + 1]));
-        }
-    }
-    (void)R;
-}
 
 // Gauss-Jordan inversion in FP64 of the system in registers (rows / columns
 // >= m hold the identity).  Step k: the lanes of row k's group write row k to
@@ -209,32 +94,6 @@ __device__ __forceinline__ bool gj_f64(double (&re)[F64L<UP>::NS], double (&im)[
         __builtin_amdgcn_sched_barrier(0);
     }
     return __all((pv > kRelPivot64 * d0) && (pv < (double)INFINITY));
-}
-
-// The symbols of chunk k0 a lane stages: entry e = lane + 64 i of the
-// [KC][UP] chunk (symbol e / UP, user e % UP), loaded from clamped in-range
-// addresses (masked when staged).
-template <int UP>
-__device__ __forceinline__ void load_syms(const float2 *__restrict__ s, int k0, int kc, int n, int n_sc, int U,
-                                          float2 (&v)[F64L<UP>::SPL]) {
-    const int lane = lane_id();
-#pragma unroll
-    for (int i = 0; i < F64L<UP>::SPL; ++i) {
-        const int e = lane + 64 * i, k = e / UP, u = e % UP;
-        const int kk = k < kc ? k : kc - 1, uu = u < U ? u : U - 1;
-        v[i] = s[((size_t)(k0 + kk) * n_sc + n) * U + uu];
-    }
-}
-
-template <int UP>
-__device__ __forceinline__ void stage_syms(const float2 (&v)[F64L<UP>::SPL], int kc, int U, cx<float> *sb) {
-    const int lane = lane_id();
-#pragma unroll
-    for (int i = 0; i < F64L<UP>::SPL; ++i) {
-        const int e = lane + 64 * i, k = e / UP, u = e % UP;
-        const bool in = k < kc && u < U;
-        sb[k * UP + upos<UP>(u)] = {in ? v[i].x : 0.f, in ? v[i].y : 0.f};
-    }
 }
 
 template <int UP, int NT, int KU, bool P64>

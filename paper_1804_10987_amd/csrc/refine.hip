@@ -1,0 +1,226 @@
+// refine.hip -- one step of iterative refinement after the fused
+// factorization, with the residual in FP64 from the complex64 channel.
+//
+// A refined call runs the fused kernel's per-frame part (Gram on MFMA at the
+// call's precision -- FP32 or split FP16 / BF16 --, inversion, Lemma-1 factor
+// and status) into a workspace of factors F = scale A^-1 (scale 1/beta for
+// PD, w_c for FD), then this kernel, one wave per local system:
+//
+//   Gram      G = H^H H accumulated in FP64 over all the system's rows (32-row
+//             tiles staged in LDS, f64_common.h); complex64 products are
+//             exact in FP64, so A = G + kappa I is the exact regularized
+//             system the factorization rounded
+//   solve     Z = F S per chunk of 16 symbols, in FP64 from the FP32 factor
+//   residual  r = S - A Z / scale in FP64: with y = Z / scale the solution of
+//             A y = S as solved, r = s - (kappa y + H^H (H y)) up to FP64
+//             rounding (A is exactly Hermitian in FP64, so lane (r, c) forms
+//             (A Z)[c] from its column of A)
+//   update    Z += F r (one refinement step of the FP32 solve)
+//   precode   X_c = H_c Z on FP32 MFMA from the rows loaded again, tile by tile
+//
+// Beta (PD) and the weights (FD) come from the factorization and are not
+// refined.  An instance the prepare pass moved to the FP64 route (status
+// PRECODE_ST_FP64) is solved on that route here (retry_f64.h).
+#include "f64_common.h"
+
+namespace pc {
+namespace {
+
+// Waves per workgroup and LDS per wave: the rows area (staged rows, then the
+// symbol chunk [KC][UP] and the complex64 Z chunk [UP][KC]) and two FP64
+// chunks [KC][UP] (Z, then the residual).
+template <int UP>
+struct RefL {
+    static constexpr int waves = UP == 16 ? 4 : 2;
+    static constexpr size_t per_wave = F64L<UP>::rows_bytes + 2 * F64L<UP>::z64_bytes;
+    static_assert(per_wave >= f64r::lds_bytes(UP), "FP64 retry area");
+};
+
+// v = M w over one chunk: lane (r, c) holds M[c][q R + r] (mre / mim, q < NS);
+// w is read as [k][upos(i)] complex FP64 (or complex64 when W32); the sum for
+// row c of symbol k ends in every lane of column c.  conj_m: use conj(M[i][c])
+// held as column c instead (M Hermitian).
+template <int UP, bool W32>
+__device__ __forceinline__ void apply_rows(const double (&mre)[F64L<UP>::NS], const double (&mim)[F64L<UP>::NS],
+                                           const void *w, int k, double &vr, double &vi) {
+    constexpr int NS = F64L<UP>::NS;
+    const int r = lane_id() / UP;
+    vr = 0.0;
+    vi = 0.0;
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        double wr, wi;
+        if constexpr (W32) {
+            const cx<float> v = ((const cx<float> *)w)[k * UP + r * NS + q];
+            wr = v.re;
+            wi = v.im;
+        } else {
+            const cx<double> v = ((const cx<double> *)w)[k * UP + r * NS + q];
+            wr = v.re;
+            wi = v.im;
+        }
+        vr = fma(mre[q], wr, fma(-mim[q], wi, vr));
+        vi = fma(mre[q], wi, fma(mim[q], wr, vi));
+    }
+    vr = group_sum_d<UP>(vr);
+    vi = group_sum_d<UP>(vi);
+}
+
+template <int UP>
+__device__ __forceinline__ void refine_system(const Prob &p, const int *__restrict__ off, int sys, int K,
+                                              const float2 *__restrict__ H, const float2 *__restrict__ s,
+                                              float2 *__restrict__ x, const cx<float> *__restrict__ fac,
+                                              const float *__restrict__ scale_in, const int *__restrict__ status,
+                                              char *wb) {
+    constexpr int R = F64L<UP>::R, NS = F64L<UP>::NS;
+    const int lane = lane_id();
+    const int r = lane / UP, c = lane % UP;
+    const bool pd = p.arch == kPD;
+    const int B = p.B, U = p.U, C = p.C, n_sc = p.n_sc;
+    const int n = pd ? sys : sys / C;
+    const int cl = pd ? 0 : sys - n * C;
+    const int r0 = pd ? 0 : off[cl], r1 = pd ? B : off[cl + 1];
+    const int nrows = r1 - r0, ntile = (nrows + 31) >> 5;
+    if (on_f64_route(status, sys)) {
+        f64r::instance(f64r::shape_of(p), off, sys, K, false, H, s, x, nullptr, nullptr, wb);
+        return;
+    }
+    const float2 *Hn = H + (size_t)n * B * U;
+    float2 *rowsL = (float2 *)wb;                                              // [32][UP] staged rows
+    cx<float> *sb = (cx<float> *)wb;                                          // [KC][UP] symbols (upos order)
+    cx<float> *zb32 = (cx<float> *)(wb + F64L<UP>::s_bytes);                  // [UP][KC] refined Z (complex64)
+    cx<double> *zb = (cx<double> *)(wb + F64L<UP>::rows_bytes);               // [KC][UP] Z (upos order)
+    cx<double> *rb = (cx<double> *)(wb + F64L<UP>::rows_bytes + F64L<UP>::z64_bytes);  // [KC][UP] residual
+    const double kap = pd ? (double)pd_kappa(p) : (double)fd_kappa(p);
+    const float sv = scale_in[sys];
+    // F = scale A^-1: scale = 1 / beta (PD) or w_c (FD); 0 for a failed instance
+    const double scale = pd ? (sv > 0.f ? 1.0 / (double)sv : 0.0) : (double)sv;
+
+    // A = G + kappa I in FP64 (column layout)
+    double are[NS], aim[NS];
+#pragma unroll
+    for (int q = 0; q < NS; ++q) are[q] = aim[q] = 0.0;
+    for (int t = 0; t < ntile; ++t) {
+        Tile<UP, kF32> tq;
+        load_tile<UP, kF32, false>(Hn, U, r0 + 32 * t, min(32, nrows - 32 * t), tq);
+        stage_rows<UP>(tq, nrows - 32 * t, U, rowsL);
+        wave_sync();
+        gram_rows<UP>(rowsL, are, aim);
+        wave_sync();
+    }
+#pragma unroll
+    for (int q = 0; q < NS; ++q)
+        if (q * R + r == c) are[q] += kap;
+    // F in row layout: lane (r, c) holds F[c][q R + r]
+    double fre[NS], fim[NS];
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        const int i = q * R + r;
+        const bool in = c < U && i < U;
+        const cx<float> v = fac[(size_t)sys * U * U + (in ? c * U + i : 0)];
+        fre[q] = in ? v.re : 0.0;
+        fim[q] = in ? v.im : 0.0;
+    }
+    // (A Z)[c] = sum_i conj(A[i][c]) Z[i]: the column layout of A, conjugated
+#pragma unroll
+    for (int q = 0; q < NS; ++q) aim[q] = -aim[q];
+    const bool ok = scale > 0.0;
+    const double inv_scale = ok ? 1.0 / scale : 0.0;
+    float2 sym[F64L<UP>::SPL];
+    for (int k0 = 0; k0 < K; k0 += KC) {
+        const int kc = min(KC, K - k0);
+        load_syms<UP>(s, k0, kc, n, n_sc, U, sym);
+        stage_syms<UP>(sym, kc, U, sb);
+        wave_sync();
+        // Z = F S
+        for (int k = 0; k < KC; ++k) {
+            double vr, vi;
+            apply_rows<UP, true>(fre, fim, sb, k, vr, vi);
+            if (r == 0) zb[k * UP + upos<UP>(c)] = {vr, vi};
+        }
+        wave_sync();
+        // r = S - A Z / scale
+        for (int k = 0; k < KC; ++k) {
+            double vr, vi;
+            apply_rows<UP, false>(are, aim, zb, k, vr, vi);
+            if (r == 0) {
+                const cx<float> sk = sb[k * UP + upos<UP>(c)];
+                const bool live = ok && c < U && k < kc;
+                rb[k * UP + upos<UP>(c)] = {live ? (double)sk.re - vr * inv_scale : 0.0,
+                                            live ? (double)sk.im - vi * inv_scale : 0.0};
+            }
+        }
+        wave_sync();
+        // Z += F r, rounded to complex64 for the precode
+        for (int k = 0; k < KC; ++k) {
+            double vr, vi;
+            apply_rows<UP, false>(fre, fim, rb, k, vr, vi);
+            if (r == 0) {
+                const cx<double> z = zb[k * UP + upos<UP>(c)];
+                const bool live = ok && c < U && k < kc;
+                zb32[c * KC + k] = {live ? (float)(z.re + vr) : 0.f, live ? (float)(z.im + vi) : 0.f};
+            }
+        }
+        wave_sync();
+        ZOp<UP, kF32> z;
+        make_zop<UP, kF32>(zb32, KC, 1, kc, z);
+        for (int t = 0; t < ntile; ++t) {
+            Tile<UP, kF32> tq;
+            const int nt = min(32, nrows - 32 * t);
+            load_tile<UP, kF32, false>(Hn, U, r0 + 32 * t, nt, tq);
+            store_x(mfma_apply_packed<UP, kF32>(tq, z), r0 + 32 * t, nt, k0, kc, n, n_sc, B, x);
+        }
+        wave_sync();  // the chunks are rewritten by the next one
+    }
+}
+
+template <int UP>
+__global__ void __launch_bounds__(64 * RefL<UP>::waves, 2)
+    refine_k(Prob p, int K, const float2 *__restrict__ H, const float2 *__restrict__ s, float2 *__restrict__ x,
+             const cx<float> *__restrict__ fac, const float *__restrict__ scale_in, const int *__restrict__ status) {
+    extern __shared__ float4 smem_ref[];
+    const int *off = (const int *)((const char *)__builtin_amdgcn_kernarg_segment_ptr() + offsetof(Prob, off));
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int sys = blockIdx.x * RefL<UP>::waves + wave;
+    if (sys >= n_inst(p)) return;
+    refine_system<UP>(p, off, sys, K, H, s, x, fac, scale_in, status,
+                      (char *)smem_ref + (size_t)wave * RefL<UP>::per_wave);
+}
+
+template <int UP>
+hipError_t launch_refine(const Prob &p, const float2 *H, const float2 *s, float2 *x, const void *fac,
+                         const float *scale_in, const int *status, hipStream_t st) {
+    constexpr int W = RefL<UP>::waves;
+    const unsigned blocks = (unsigned)((n_inst(p) + W - 1) / W);
+    const size_t lds = RefL<UP>::per_wave * W;
+    hipLaunchKernelGGL((refine_k<UP>), dim3(blocks), dim3(64 * W), lds, st, p, p.K, H, s, x,
+                       (const cx<float> *)fac, scale_in, status);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+size_t fused_refine_ws_bytes(const Prob &p) {
+    const size_t ni = (size_t)n_inst(p);
+    return ((ni * p.U * p.U * sizeof(float2) + 255) & ~(size_t)255) + ((ni * sizeof(float) + 255) & ~(size_t)255) +
+           ni * sizeof(int);
+}
+
+hipError_t fused_refine_run(const Prob &p, int precision, const float2 *H, const float2 *s, float2 *x,
+                            float *scale_out, int *status, void *ws, hipStream_t st) {
+    if (!fused_supported(p, precision)) return hipErrorNotSupported;
+    const size_t ni = (size_t)n_inst(p);
+    if (ni == 0) return hipSuccess;
+    char *w = (char *)ws;
+    float2 *fac = (float2 *)w;
+    float *sc = (float *)(w + ((ni * p.U * p.U * sizeof(float2) + 255) & ~(size_t)255));
+    int *stt = (int *)((char *)sc + ((ni * sizeof(float) + 255) & ~(size_t)255));
+    hipError_t e = fused_prepare(p, precision, H, fac, sc, stt, st);
+    if (e == hipSuccess && p.K > 0)
+        e = p.U <= 16 ? launch_refine<16>(p, H, s, x, fac, sc, stt, st) : launch_refine<32>(p, H, s, x, fac, sc, stt, st);
+    if (e == hipSuccess && scale_out) e = hipMemcpyAsync(scale_out, sc, ni * sizeof(float), hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess && status) e = hipMemcpyAsync(status, stt, ni * sizeof(int), hipMemcpyDeviceToDevice, st);
+    return e;
+}
+
+}  // namespace pc

@@ -314,20 +314,26 @@ def _rescaled_err(arch, cell, xg, scg, xo, sco):
     ("fd", synth.Cell(B=64, sizes=(16, 16, 32), U=16, n_sc=24, K=14, snr_db=20.0), 2.0, False),  # forced FP32, B_c = U
     ("pd", synth.Cell(B=24, sizes=(24,), U=16, n_sc=12, K=6, snr_db=20.0), 2.0, False),           # forced FP32, U/B = 0.67
 ])
-def test_refinement_fp64_residual(torch, ctx, pc, arch, cell, ratio, envelope):
+@pytest.mark.parametrize("impl", ["auto", "plain"])
+def test_refinement_fp64_residual(torch, ctx, pc, arch, cell, ratio, envelope, impl):
     """One refinement step with the residual in FP64 from the complex64
-    channel.  It refines the solve, not the Lemma-1 factor: with the factor
-    replaced by the oracle's the error never grows and meets the FP32 bound;
-    inside the routing envelope (FP64 for U / B_eff >= 0.5) the full result
-    meets it too."""
+    channel, fused (factorization, then the refine-and-precode kernel) where
+    the fused kernel takes the shape, else on the plain kernels.  It refines
+    the solve, not the Lemma-1 factor: with the factor replaced by the
+    oracle's the error never grows and meets the FP32 bound; inside the
+    routing envelope (FP64 for U / B_eff >= 0.5) the full result meets it
+    too."""
     H, s = synth.make_cell(cell, seed=5)
     Hd, sd = _dev(torch, H), _dev(torch, s)
     fn = ctx.pd if arch == "pd" else ctx.fd
-    # the unrefined result of the same (plain) kernels
-    x0, sc0, _ = fn(Hd, sd, cell.kappa, cell.sizes, "wf", pc.params(fp64_ratio=ratio, impl="plain"))
-    x1, sc1, st1 = fn(Hd, sd, cell.kappa, cell.sizes, "wf", pc.params(fp64_ratio=ratio, refine_steps=1))
+    # the unrefined result of the same kernels
+    x0, sc0, _ = fn(Hd, sd, cell.kappa, cell.sizes, "wf", pc.params(fp64_ratio=ratio, impl=impl))
+    impl0 = ctx.last_impl
+    x1, sc1, st1 = fn(Hd, sd, cell.kappa, cell.sizes, "wf", pc.params(fp64_ratio=ratio, refine_steps=1, impl=impl))
     torch.cuda.synchronize()
-    assert ctx.last_impl == "plain"
+    # fused unless forced plain (the FP64 route, ratio 0.5 here, runs its
+    # fused FP64 solve)
+    assert ctx.last_impl == ("plain" if impl == "plain" else "fused") and impl0 == ctx.last_impl
     xo, sco, sto = _oracle(arch, H, s, cell.kappa, cell.sizes, "wf")
     assert (st1.cpu().numpy().reshape(sto.shape) & 1 == sto).all()
     scg0, scg1 = (v.cpu().numpy().reshape(sco.shape).astype(np.float64) for v in (sc0, sc1))
@@ -335,7 +341,8 @@ def test_refinement_fp64_residual(torch, ctx, pc, arch, cell, ratio, envelope):
     d1 = _rescaled_err(arch, cell, x1.cpu().numpy(), scg1, xo, sco)
     e0 = _vec_err(x0.cpu().numpy(), xo).max()
     e1 = _vec_err(x1.cpu().numpy(), xo).max()
-    print("refinement: solve err %.3e -> %.3e, full err %.3e -> %.3e" % (d0, d1, e0, e1), flush=True)
+    print("refinement (%s): solve err %.3e -> %.3e, full err %.3e -> %.3e" % (ctx.last_impl, d0, d1, e0, e1),
+          flush=True)
     assert d1 <= max(d0, 2e-7) and d1 <= TOL
     if envelope:
         _check(x1.cpu().numpy(), scg1, st1.cpu().numpy().reshape(sto.shape), xo, sco, sto)
@@ -579,3 +586,43 @@ def test_channel_scale(torch, ctx, pc, arch, U, prec, scale):
     xo, sco, sto = _oracle(arch, H, s, kappa, cell.sizes, "wf")
     e = _check(x, sc.reshape(sco.shape), st.reshape(sto.shape), xo, sco, sto, tol=tol)
     print("%s U=%d %s scale %g max rel err %.3e" % (arch, U, prec, scale, e), flush=True)
+
+
+@pytest.mark.parametrize("prec", ["split_fp16", "split_bf16", "fp32"])
+@pytest.mark.parametrize("arch", ["pd", "fd"])
+def test_refinement_fused_full_frame(torch, ctx, pc, arch, prec):
+    """The fused refinement at 256 antennas (8 x 32), 16 users, 1200
+    subcarriers x 14 symbols: runs fused, never increases the solve error,
+    and the full result meets the FP32 bound at every precision."""
+    cell = synth.config(2)
+    H, s = synth.make_cell(cell, seed=6)
+    Hd, sd = _dev(torch, H), _dev(torch, s)
+    fn = ctx.pd if arch == "pd" else ctx.fd
+    x0, sc0, _ = fn(Hd, sd, cell.kappa, cell.sizes, "wf", pc.params(fp64_ratio=2.0, precision=prec))
+    x1, sc1, st1 = fn(Hd, sd, cell.kappa, cell.sizes, "wf", pc.params(fp64_ratio=2.0, precision=prec, refine_steps=1))
+    torch.cuda.synchronize()
+    assert ctx.last_impl == "fused"
+    xo, sco, sto = _oracle(arch, H, s, cell.kappa, cell.sizes, "wf")
+    scg0, scg1 = (v.cpu().numpy().reshape(sco.shape).astype(np.float64) for v in (sc0, sc1))
+    # the factor is not refined (the prepare pass may sum the clusters in
+    # another launch shape's order)
+    assert np.abs(scg1 - scg0).max() <= 1e-6 * np.abs(scg0).max()
+    d0 = _rescaled_err(arch, cell, x0.cpu().numpy(), scg0, xo, sco)
+    d1 = _rescaled_err(arch, cell, x1.cpu().numpy(), scg1, xo, sco)
+    e1 = _check(x1.cpu().numpy(), scg1, st1.cpu().numpy().reshape(sto.shape), xo, sco, sto)
+    print("%s %s refinement: solve err %.3e -> %.3e, full %.3e" % (arch, prec, d0, d1, e1), flush=True)
+    assert d1 <= max(d0, 2e-7)
+
+
+@pytest.mark.parametrize("prec", ["split_fp16", "split_bf16", "fp32"])
+def test_refinement_fused_u32_sampled(torch, ctx, pc, cell_u32, prec):
+    """The fused refinement at the 32-user workload (512 antennas as 16 x 32,
+    3300 subcarriers, correlated channel), PD: the sampled subcarriers meet
+    the FP32 bound against the oracle at every precision."""
+    cell, Hs, ss, Hd, sd, idx = cell_u32
+    x, sc, st = ctx.pd(Hd, sd, cell.kappa, cell.sizes, "wf", pc.params(precision=prec, refine_steps=1))
+    torch.cuda.synchronize()
+    assert ctx.last_impl == "fused"
+    xo, sco, sto = _oracle("pd", Hs, ss, cell.kappa, cell.sizes, "wf")
+    e = _check(x.cpu().numpy()[:, idx], sc.cpu().numpy()[idx], st.cpu().numpy()[idx], xo, sco, sto)
+    print("u32 %s refined max rel err %.3e" % (prec, e), flush=True)
