@@ -171,6 +171,23 @@ int precode_pd(precode_ctx *ctx, const void *H, const void *s, float rho,
                int *status, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * precode_pd without any device allocation, for callers that cannot
+ * allocate: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Arguments, outputs and routing as precode_pd.  The
+ * workspace a call needs (the fused refinement's factors, or the plain
+ * kernels' workspace) comes from a fixed 64 MiB device array of the library,
+ * one per GPU, held until the process ends; a call needing more returns
+ * PRECODE_ENOMEM before anything is enqueued.  The call allocates nothing,
+ * creates no event and times no launch shape (an untuned shape uses the
+ * default launch shape).  All calls on one GPU share that array: calls that
+ * overlap on one GPU race.
+ * ------------------------------------------------------------------------- */
+int precode_pd_noalloc(precode_ctx *ctx, const void *H, const void *s, float rho,
+                       const int *cluster_sizes, int C, int mode, int B, int U, int n_sc,
+                       int K, const precode_params *params, void *x, float *beta,
+                       int *status, void *stream);
+
+/* ---------------------------------------------------------------------------
  * FD precoding of a frame (Sec. III-C).  Per subcarrier and cluster c, with
  * rho_c^2 = power / C and kappa_c = tau C kappa (eq. regularization):
  *     B_c >= U:  A_c = H_c^H H_c + kappa_c I_U,   x_c = w_c H_c A_c^-1 s

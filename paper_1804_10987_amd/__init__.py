@@ -140,7 +140,7 @@ class Context:
         """Waves per workgroup (1, 2 or 4) of the last fused launch (autotuned shape)."""
         return _lib.load().precode_ctx_last_waves(self.handle)
 
-    def _run(self, arch, H, s, rho, sizes, mode, prm, x, scale, status, stream):
+    def _run(self, arch, H, s, rho, sizes, mode, prm, x, scale, status, stream, noalloc=False):
         torch = _torch()
         n_sc, B, U = H.shape
         K = s.shape[0]
@@ -157,10 +157,10 @@ class Context:
             status = torch.empty(n_scale, dtype=torch.int32, device=H.device)
         arr, C = _sizes(sizes)
         prm = prm if prm is not None else params()
-        fn = _lib.load().precode_pd if arch == ARCH_PD else _lib.load().precode_fd
+        name = "precode_pd_noalloc" if noalloc else ("precode_pd" if arch == ARCH_PD else "precode_fd")
+        fn = getattr(_lib.load(), name)
         _lib.check(fn(self.handle, _ptr(H), _ptr(s), float(rho), arr, C, _mode(mode), B, U, n_sc, K,
-                      ctypes.byref(prm), _ptr(x), _ptr(scale), _ptr(status), _stream(stream)),
-                   "precode_pd" if arch == ARCH_PD else "precode_fd")
+                      ctypes.byref(prm), _ptr(x), _ptr(scale), _ptr(status), _stream(stream)), name)
         if arch == ARCH_FD:
             scale, status = scale.view(n_sc, C), status.view(n_sc, C)
         return x, scale, status
@@ -168,6 +168,11 @@ class Context:
     def pd(self, H, s, rho, sizes, mode="wf", prm=None, x=None, beta=None, status=None, stream=None):
         """PD precoding (Sec. III-B).  Returns (x, beta [n_sc], status [n_sc])."""
         return self._run(ARCH_PD, H, s, rho, sizes, mode, prm, x, beta, status, stream)
+
+    def pd_noalloc(self, H, s, rho, sizes, mode="wf", prm=None, x=None, beta=None, status=None, stream=None):
+        """precode_pd_noalloc: PD precoding whose workspace comes from the
+        library's fixed per-GPU array (no device allocation by the call)."""
+        return self._run(ARCH_PD, H, s, rho, sizes, mode, prm, x, beta, status, stream, noalloc=True)
 
     def fd(self, H, s, rho, sizes, mode="wf", prm=None, x=None, weights=None, status=None, stream=None):
         """FD precoding (Sec. III-C).  Returns (x, weights [n_sc, C], status [n_sc, C])."""

@@ -86,6 +86,7 @@ SIGNATURES = {
     "precode_ctx_last_waves": (I, [VP]),
     "precode_pd": (I, [VP, VP, VP, F, IP, I, I, I, I, I, I, ctypes.POINTER(Params), VP, VP, VP, VP]),
     "precode_fd": (I, [VP, VP, VP, F, IP, I, I, I, I, I, I, ctypes.POINTER(Params), VP, VP, VP, VP]),
+    "precode_pd_noalloc": (I, [VP, VP, VP, F, IP, I, I, I, I, I, I, ctypes.POINTER(Params), VP, VP, VP, VP]),
     "precode_frame_prepare": (I, [VP, I, VP, F, IP, I, I, I, I, I, ctypes.POINTER(Params),
                                   ctypes.POINTER(VP), VP]),
     "precode_frame_symbols": (I, [VP, VP, VP, I, VP, VP]),

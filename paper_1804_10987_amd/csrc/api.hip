@@ -252,9 +252,15 @@ int run_plain(const Prob &p, const precode_job &j, void *wsA, void *wsAinv, void
     return rc;
 }
 
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// One PD / FD call.  Workspace: the context's (grown on demand, its uses
+// ordered across streams) or, with fixed_ws, the fixed_cap bytes there (no
+// allocation, no event, no launch-shape timing: PRECODE_ENOMEM when the call
+// needs more).
 int run(precode_ctx *ctx, int arch, const void *H, const void *s, float rho, const int *sizes, int C, int mode,
         int B, int U, int n_sc, int K, const precode_params *params, void *x, float *scale, int *status,
-        void *stream) {
+        void *stream, void *fixed_ws = nullptr, size_t fixed_cap = 0) {
     if (!ctx) return PRECODE_EINVAL;
     const precode_params q = params ? *params : defaults();
     Prob p;
@@ -274,13 +280,30 @@ int run(precode_ctx *ctx, int arch, const void *H, const void *s, float rho, con
     if (q.precision == PRECODE_PREC_SPLIT_FP16 || q.precision == PRECODE_PREC_SPLIT_BF16) {
         if (!can_fuse && !can_f64 && !can_refine) return PRECODE_EUNSUPPORTED;
     }
+    const bool fixed = fixed_ws != nullptr;
+    // no launch-shape timing on a fixed workspace (it would create events)
+    struct Tune {
+        bool off;
+        explicit Tune(bool o) : off(o) {
+            if (off) fused_set_autotune(false);
+        }
+        ~Tune() {
+            if (off) fused_set_autotune(true);
+        }
+    } tune(fixed);
     if (q.impl != PRECODE_IMPL_PLAIN && can_refine) {
-        rc = grow(ctx, &ctx->wsRef, &ctx->capRef, fused_refine_ws_bytes(p), st);
-        if (!rc) rc = ws_acquire(ctx, st);
-        if (rc) return rc;
+        void *ws = fixed_ws;
+        if (fixed) {
+            if (fused_refine_ws_bytes(p) > fixed_cap) return PRECODE_ENOMEM;
+        } else {
+            rc = grow(ctx, &ctx->wsRef, &ctx->capRef, fused_refine_ws_bytes(p), st);
+            if (!rc) rc = ws_acquire(ctx, st);
+            if (rc) return rc;
+            ws = ctx->wsRef;
+        }
         rc = dev_err(fused_refine_run(p, q.precision, (const float2 *)H, (const float2 *)s, (float2 *)x, scale, status,
-                                      ctx->wsRef, st));
-        const int rr = ws_release(ctx, st);
+                                      ws, st));
+        const int rr = fixed ? PRECODE_OK : ws_release(ctx, st);
         if (!rc) rc = rr;
         if (rc == PRECODE_OK) {
             ctx->last_impl = PRECODE_IMPL_FUSED;
@@ -306,17 +329,34 @@ int run(precode_ctx *ctx, int arch, const void *H, const void *s, float rho, con
         }
         return rc;
     }
-    rc = grow(ctx, &ctx->wsA, &ctx->capA, plain_ws_bytes_A(p), st);
-    if (!rc) rc = grow(ctx, &ctx->wsAinv, &ctx->capAinv, plain_ws_bytes_A(p), st);
-    if (!rc) rc = grow(ctx, &ctx->wsScale, &ctx->capScale, plain_ws_bytes_scale(p), st);
-    if (!rc) rc = grow(ctx, &ctx->wsZ, &ctx->capZ, plain_ws_bytes_z(p, K > 0 ? K : 1), st);
-    if (!rc) rc = ws_acquire(ctx, st);
-    if (rc) return rc;
-    rc = dev_err(plain_prepare(p, (const float2 *)H, scale, status, ctx->wsA, ctx->wsAinv, ctx->wsScale, st));
+    void *wA, *wAinv, *wScale, *wZ;
+    if (fixed) {
+        // the four plain workspaces carved from the fixed area
+        const size_t bA = align256(plain_ws_bytes_A(p)), bS = align256(plain_ws_bytes_scale(p));
+        const size_t bZ = align256(plain_ws_bytes_z(p, K > 0 ? K : 1));
+        if (2 * bA + bS + bZ > fixed_cap) return PRECODE_ENOMEM;
+        char *w = (char *)fixed_ws;
+        wA = w;
+        wAinv = w + bA;
+        wScale = w + 2 * bA;
+        wZ = w + 2 * bA + bS;
+    } else {
+        rc = grow(ctx, &ctx->wsA, &ctx->capA, plain_ws_bytes_A(p), st);
+        if (!rc) rc = grow(ctx, &ctx->wsAinv, &ctx->capAinv, plain_ws_bytes_A(p), st);
+        if (!rc) rc = grow(ctx, &ctx->wsScale, &ctx->capScale, plain_ws_bytes_scale(p), st);
+        if (!rc) rc = grow(ctx, &ctx->wsZ, &ctx->capZ, plain_ws_bytes_z(p, K > 0 ? K : 1), st);
+        if (!rc) rc = ws_acquire(ctx, st);
+        if (rc) return rc;
+        wA = ctx->wsA;
+        wAinv = ctx->wsAinv;
+        wScale = ctx->wsScale;
+        wZ = ctx->wsZ;
+    }
+    rc = dev_err(plain_prepare(p, (const float2 *)H, scale, status, wA, wAinv, wScale, st));
     if (!rc && K > 0)
-        rc = dev_err(plain_symbols(p, K, (const float2 *)H, (const float2 *)s, (float2 *)x, ctx->wsAinv,
-                                   ctx->wsScale, ctx->wsZ, st, q.refine_steps));
-    const int rr = ws_release(ctx, st);
+        rc = dev_err(plain_symbols(p, K, (const float2 *)H, (const float2 *)s, (float2 *)x, wAinv, wScale, wZ, st,
+                                   q.refine_steps));
+    const int rr = fixed ? PRECODE_OK : ws_release(ctx, st);
     if (!rc) rc = rr;
     if (rc == PRECODE_OK) ctx->last_impl = PRECODE_IMPL_PLAIN;
     return rc;
@@ -331,6 +371,12 @@ int make_prob_checked(int arch, float rho, const int *sizes, int C, int mode, in
     return make_prob(arch, rho, sizes, C, mode, B, U, n_sc, K, qq, out);
 }
 int ctx_device(const precode_ctx *ctx) { return ctx->device; }
+int pd_fixed_ws(precode_ctx *ctx, const void *H, const void *s, float rho, const int *sizes, int C, int mode, int B,
+                int U, int n_sc, int K, const precode_params *params, void *x, float *beta, int *status, void *stream,
+                void *ws, size_t cap) {
+    if (!ws) return PRECODE_EINVAL;
+    return run(ctx, kPD, H, s, rho, sizes, C, mode, B, U, n_sc, K, params, x, beta, status, stream, ws, cap);
+}
 }  // namespace pc
 
 extern "C" {

@@ -89,6 +89,12 @@ int make_prob_checked(int arch, float rho, const int *sizes, int C, int mode, in
                       const precode_params *q, Prob *out);
 // Device of a context (api.hip).
 int ctx_device(const precode_ctx *ctx);
+// precode_pd with every workspace the call needs carved from ws (cap bytes):
+// no allocation, no event, no launch-shape timing; PRECODE_ENOMEM when the
+// call needs more than cap (api.hip).
+int pd_fixed_ws(precode_ctx *ctx, const void *H, const void *s, float rho, const int *sizes, int C, int mode, int B,
+                int U, int n_sc, int K, const precode_params *params, void *x, float *beta, int *status, void *stream,
+                void *ws, size_t cap);
 
 // Plain kernels (plain.hip).  Workspace: A and Ainv hold n_inst U x U
 // complex<double>-sized slots, scale n_inst doubles, z K * n_inst * U complex64.
