@@ -49,8 +49,16 @@ def _load():
         lib.oracle_pd.restype = ctypes.c_int
         lib.oracle_fd.argtypes = [dp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                   ip, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double,
-                                  ctypes.c_double, ctypes.c_double, ctypes.c_int, dp, dp, ip]
+                                  ctypes.c_double, ctypes.c_double, ctypes.c_int, dp, dp, ip, dp, dp]
         lib.oracle_fd.restype = ctypes.c_int
+        lib.oracle_central.argtypes = [dp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                       ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                       dp, dp, ip]
+        lib.oracle_central.restype = ctypes.c_int
+        lib.oracle_mrt.argtypes = [dp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                   ip, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                   dp, dp, ip, dp]
+        lib.oracle_mrt.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -104,20 +112,71 @@ def pd(H, s, kappa, sizes=None, zf=False, power=1.0, Es=1.0, threads=None, inter
     return x, beta, status
 
 
-def fd(H, s, kappa, sizes, zf=False, tau=0.125, power=1.0, Es=1.0, threads=None):
+def _per_cluster(v, C, what):
+    if v is None:
+        return None
+    a = np.ascontiguousarray(np.asarray(v, dtype=np.float64))
+    if a.shape != (C,):
+        raise ValueError("%s: one value per cluster expected" % what)
+    return a
+
+
+def fd(H, s, kappa, sizes, zf=False, tau=0.125, power=1.0, Es=1.0, threads=None, tau_c=None, power_c=None):
     """FD-WF (zf=False) or FD-ZF precoding in FP64 (Sec. III-C).
 
+    tau_c / power_c: optional per-cluster tau_c and budgets rho_c^2 (sum rho^2).
     Returns (x [K][n_sc][B] complex128, weights [n_sc][C], status [n_sc][C]).
     """
     H, s, sizes, n_sc, B, U, K = _prep(H, s, sizes)
     C = len(sizes)
+    tc = _per_cluster(tau_c, C, "tau_c")
+    pc = _per_cluster(power_c, C, "power_c")
+    if pc is not None and (not (pc > 0).all() or abs(pc.sum() - power) > 1e-9 * power):
+        raise ValueError("power_c: positive budgets summing to power expected")
     x = np.zeros((K, n_sc, B), np.complex128)
     w = np.zeros((n_sc, C), np.float64)
     status = np.zeros((n_sc, C), np.int32)
     rc = _load().oracle_fd(_dptr(H.view(np.float64)), _dptr(s.view(np.float64)), B, U, n_sc, K,
                            _iptr(sizes), C, float(kappa), int(bool(zf)), float(tau), float(power),
                            float(Es), int(threads or os.cpu_count() or 1),
-                           _dptr(x.view(np.float64)), _dptr(w), _iptr(status))
+                           _dptr(x.view(np.float64)), _dptr(w), _iptr(status), _dptr(tc), _dptr(pc))
     if rc != 0:
         raise ValueError("oracle_fd: cluster sizes do not sum to B")
+    return x, w, status
+
+
+def central(H, s, kappa, power=1.0, Es=1.0, threads=None):
+    """Centralized WF precoding in the B x B form of Theorem 1 (eq.
+    originalQmatrix, eq. precodingfactor), FP64.  kappa > 0.
+
+    Returns (x [K][n_sc][B] complex128, beta [n_sc], status [n_sc]).
+    """
+    H, s, _, n_sc, B, U, K = _prep(H, s, None)
+    x = np.zeros((K, n_sc, B), np.complex128)
+    beta = np.zeros(n_sc, np.float64)
+    status = np.zeros(n_sc, np.int32)
+    rc = _load().oracle_central(_dptr(H.view(np.float64)), _dptr(s.view(np.float64)), B, U, n_sc, K,
+                                float(kappa), float(power), float(Es), int(threads or os.cpu_count() or 1),
+                                _dptr(x.view(np.float64)), _dptr(beta), _iptr(status))
+    if rc != 0:
+        raise ValueError("oracle_central: kappa must be positive")
+    return x, beta, status
+
+
+def mrt(H, s, sizes=None, power=1.0, Es=1.0, threads=None, power_c=None):
+    """MRT with per-cluster power normalization (C = 1: centralized), FP64.
+
+    Returns (x [K][n_sc][B] complex128, weights [n_sc][C], status [n_sc][C]).
+    """
+    H, s, sizes, n_sc, B, U, K = _prep(H, s, sizes)
+    C = len(sizes)
+    pc = _per_cluster(power_c, C, "power_c")
+    x = np.zeros((K, n_sc, B), np.complex128)
+    w = np.zeros((n_sc, C), np.float64)
+    status = np.zeros((n_sc, C), np.int32)
+    rc = _load().oracle_mrt(_dptr(H.view(np.float64)), _dptr(s.view(np.float64)), B, U, n_sc, K,
+                            _iptr(sizes), C, float(power), float(Es), int(threads or os.cpu_count() or 1),
+                            _dptr(x.view(np.float64)), _dptr(w), _iptr(status), _dptr(pc))
+    if rc != 0:
+        raise ValueError("oracle_mrt: cluster sizes do not sum to B")
     return x, w, status

@@ -192,21 +192,29 @@ int oracle_pd(const double *H, const double *s, int B, int U, int n_sc, int K,
  *   x_c = sqrt(rho_c^2 / (tr(Q_c^H Q_c) Es)) Q_c s
  *
  * The weight sqrt(rho_c^2 / (tr(Q_c^H Q_c) Es)) is returned in wgt.
+ *
+ * Variants of Sec. III-C: tau_c (optional, [C]) gives every cluster its own
+ * tau_c of eq. regularization; power_c (optional, [C]) replaces the equal
+ * split by per-cluster budgets rho_c^2 with sum_c rho_c^2 = rho^2 (the
+ * allocation strategies the power footnote of Sec. III-C mentions); then
+ * kappa_c = tau_c U N0 / rho_c^2 = tau_c kappa rho^2 / rho_c^2.
  * ------------------------------------------------------------------------- */
 int oracle_fd(const double *H, const double *s, int B, int U, int n_sc, int K,
               const int *sizes, int C, double kappa, int zf, double tau,
               double power, double Es, int threads, double *x, double *wgt,
-              int *status) {
+              int *status, const double *tau_c, const double *power_c) {
     int sum = 0;
     for (int c = 0; c < C; ++c) sum += sizes[c];
     if (sum != B) return -1;
-    const double rho_c2 = power / C;
-    const double kappa_c = zf ? 0.0 : tau * C * kappa;
 #pragma omp parallel for schedule(dynamic) num_threads(threads)
     for (int n = 0; n < n_sc; ++n) {
         const double *Hn = H + (size_t)n * B * U * 2;
         int row0 = 0;
         for (int c = 0; c < C; ++c) {
+            /* rho_c^2 (equal split unless given) and kappa_c = tau_c U N0 /
+             * rho_c^2 = tau_c kappa rho^2 / rho_c^2 (eq. regularization) */
+            const double rho_c2 = power_c ? power_c[c] : power / C;
+            const double kappa_c = zf ? 0.0 : (tau_c ? tau_c[c] : tau) * kappa * power / rho_c2;
             const int Bc = sizes[c];
             const double *Hc = Hn + (size_t)row0 * U * 2;
             const int m = (Bc < U) ? Bc : U; /* order of the local system */
@@ -267,6 +275,127 @@ int oracle_fd(const double *H, const double *s, int B, int U, int n_sc, int K,
             free(A);
             free(Ai);
             free(Q);
+            row0 += Bc;
+        }
+    }
+    return 0;
+}
+
+/* ---------------------------------------------------------------------------
+ * Centralized WF precoding in the B x B form of Theorem 1 (Sec. II-B).
+ *
+ * In the paper's U x B downlink channel H_dl, Q = (H_dl^H H_dl + kappa I_B)^-1
+ * H_dl^H (eq. originalQmatrix); with this file's H = H_dl^H (B x U):
+ *
+ *   M    = H H^H + kappa I_B                    (B x B, Hermitian PD for kappa > 0)
+ *   Q    = M^-1 H                               (B x U; Cholesky of M, one
+ *                                                forward and one back substitution
+ *                                                per user column)
+ *   beta = sqrt(tr(Q^H Q) Es / rho^2)           (eq. precodingfactor)
+ *   x    = Q s / beta
+ *
+ * This is the form Lemma 1 avoids; it serves as the reference the PD
+ * architecture must equal.  kappa must be positive (for B > U the matrix
+ * H H^H is singular, so ZF has no B x B form).  Returns -2 for kappa <= 0.
+ * ------------------------------------------------------------------------- */
+int oracle_central(const double *H, const double *s, int B, int U, int n_sc, int K,
+                   double kappa, double power, double Es, int threads, double *x,
+                   double *beta, int *status) {
+    if (!(kappa > 0.0)) return -2;
+#pragma omp parallel for schedule(dynamic) num_threads(threads)
+    for (int n = 0; n < n_sc; ++n) {
+        const double *Hn = H + (size_t)n * B * U * 2;
+        cplx *M = malloc(sizeof(cplx) * B * B);
+        cplx *Q = malloc(sizeof(cplx) * B * U);
+        cplx *y = malloc(sizeof(cplx) * B);
+        for (int a = 0; a < B; ++a)
+            for (int b = 0; b < B; ++b) {
+                cplx g = 0.0;
+                for (int u = 0; u < U; ++u)
+                    g += ld(Hn + ((size_t)a * U + u) * 2) * conj(ld(Hn + ((size_t)b * U + u) * 2));
+                M[a * B + b] = g + ((a == b) ? kappa : 0.0);
+            }
+        int bad = cholesky(M, B);
+        double t = 0.0;
+        for (int u = 0; u < U && !bad; ++u) {
+            for (int i = 0; i < B; ++i) {
+                cplx acc = ld(Hn + ((size_t)i * U + u) * 2);
+                for (int k = 0; k < i; ++k) acc -= M[i * B + k] * y[k];
+                y[i] = acc / M[i * B + i];
+            }
+            for (int i = B - 1; i >= 0; --i) {
+                cplx acc = y[i];
+                for (int k = i + 1; k < B; ++k) acc -= conj(M[k * B + i]) * Q[k * U + u];
+                Q[i * U + u] = acc / creal(M[i * B + i]);
+            }
+            for (int i = 0; i < B; ++i) t += creal(Q[i * U + u] * conj(Q[i * U + u]));
+        }
+        if (!bad && (!(t > 0.0) || !isfinite(t))) bad = 1;
+        const double b_wf = bad ? 0.0 : sqrt(t * Es / power);
+        beta[n] = b_wf;
+        if (status) status[n] = bad;
+        for (int k = 0; k < K; ++k) {
+            const double *sk = s + ((size_t)k * n_sc + n) * U * 2;
+            double *xk = x + ((size_t)k * n_sc + n) * B * 2;
+            for (int b = 0; b < B; ++b) {
+                cplx acc = 0.0;
+                if (!bad)
+                    for (int u = 0; u < U; ++u) acc += Q[b * U + u] * ld(sk + u * 2);
+                st(xk + b * 2, bad ? 0.0 : acc / b_wf);
+            }
+        }
+        free(M);
+        free(Q);
+        free(y);
+    }
+    return 0;
+}
+
+/* ---------------------------------------------------------------------------
+ * Maximum ratio transmission (MRT; named as the fully distributed comparison
+ * precoder in Sec. I and Sec. III-D).  The matched filter Q_c = H_c (this
+ * file's convention; the paper's H_dl,c^H) with the per-cluster power
+ * normalization of Sec. III-C:
+ *
+ *   x_c = sqrt(rho_c^2 / (||H_c||_F^2 Es)) H_c s,   rho_c^2 = rho^2 / C
+ *
+ * (power_c, optional [C], gives per-cluster budgets instead).  C = 1 is
+ * centralized MRT, whose factor is the beta of eq. precodingfactor with
+ * Q = H.  The weight is returned in wgt [n_sc][C]; a cluster with a zero
+ * channel has status 1 and weight 0.
+ * ------------------------------------------------------------------------- */
+int oracle_mrt(const double *H, const double *s, int B, int U, int n_sc, int K,
+               const int *sizes, int C, double power, double Es, int threads,
+               double *x, double *wgt, int *status, const double *power_c) {
+    int sum = 0;
+    for (int c = 0; c < C; ++c) sum += sizes[c];
+    if (sum != B) return -1;
+#pragma omp parallel for schedule(dynamic) num_threads(threads)
+    for (int n = 0; n < n_sc; ++n) {
+        const double *Hn = H + (size_t)n * B * U * 2;
+        int row0 = 0;
+        for (int c = 0; c < C; ++c) {
+            const int Bc = sizes[c];
+            const double rho_c2 = power_c ? power_c[c] : power / C;
+            double f = 0.0;
+            for (int b = row0; b < row0 + Bc; ++b)
+                for (int u = 0; u < U; ++u) {
+                    cplx h = ld(Hn + ((size_t)b * U + u) * 2);
+                    f += creal(h * conj(h));
+                }
+            const int bad = !(f > 0.0) || !isfinite(f);
+            const double w = bad ? 0.0 : sqrt(rho_c2 / (f * Es));
+            wgt[(size_t)n * C + c] = w;
+            if (status) status[(size_t)n * C + c] = bad;
+            for (int k = 0; k < K; ++k) {
+                const double *sk = s + ((size_t)k * n_sc + n) * U * 2;
+                double *xk = x + ((size_t)k * n_sc + n) * B * 2;
+                for (int b = row0; b < row0 + Bc; ++b) {
+                    cplx acc = 0.0;
+                    for (int u = 0; u < U; ++u) acc += ld(Hn + ((size_t)b * U + u) * 2) * ld(sk + u * 2);
+                    st(xk + b * 2, w * acc);
+                }
+            }
             row0 += Bc;
         }
     }
