@@ -103,6 +103,17 @@ typedef struct precode_params {
                        /* solved on the FP64 route (B_eff = B for PD, B_c for FD); */
                        /* 0.5; a value > 1 disables the route                      */
     int impl;          /* enum precode_impl; PRECODE_IMPL_AUTO                     */
+    /* FD and MRT only (PD ignores them); HOST arrays of C values read during  */
+    /* the call, or NULL; either one needs C <= 64:                             */
+    const float *cluster_tau;    /* tau_c >= 0 per cluster (eq. regularization); */
+                                 /* NULL: tau for every cluster                  */
+    const float *cluster_power;  /* budgets rho_c^2 > 0 summing to power       */
+                                 /* (relative 1e-5), the unequal allocations the */
+                                 /* power footnote of Sec. III-C considers;      */
+                                 /* NULL: rho^2 / C each.  Then                  */
+                                 /* kappa_c = tau_c U N0 / rho_c^2               */
+                                 /*         = tau_c kappa rho^2 / rho_c^2 and    */
+                                 /* w_c = sqrt(rho_c^2 / (t_c Es))               */
 } precode_params;
 
 typedef struct precode_ctx precode_ctx;
@@ -186,6 +197,75 @@ int precode_pd_noalloc(precode_ctx *ctx, const void *H, const void *s, float rho
                        const int *cluster_sizes, int C, int mode, int B, int U, int n_sc,
                        int K, const precode_params *params, void *x, float *beta,
                        int *status, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Centralized WF precoding in the B x B form of Theorem 1 (Sec. II-B), the
+ * reference the PD architecture must equal (Sec. III-D):
+ *     M = H H^H + kappa I_B,  Q = M^-1 H  (eq. originalQmatrix),
+ *     beta = sqrt(tr(Q^H Q) Es / rho^2)  (eq. precodingfactor),  x = Q s / beta,
+ * with H = H_dl^H as everywhere in this library and kappa = rho (> 0: the
+ * B x B form has no ZF case for B > U).  FP32 Cholesky of M by 32 x 32
+ * tiles, one workgroup per subcarrier; the context holds the factor tiles
+ * (up to 256 MiB, launches chunked).  Layouts, beta and status as precode_pd
+ * (PRECODE_ST_FAIL with x = 0 on a pivot not above 2^-20 of its diagonal
+ * entry; no FP64 route).  params: power and Es; precision must be FP32.
+ * PRECODE_EUNSUPPORTED for kappa = 0 or shapes whose factor tiles and Q do
+ * not fit (about (B + 32) (U + 1) <= 18000).
+ * ------------------------------------------------------------------------- */
+int precode_central(precode_ctx *ctx, const void *H, const void *s, float rho, int B, int U,
+                    int n_sc, int K, const precode_params *params, void *x, float *beta,
+                    int *status, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Maximum ratio transmission, the fully distributed comparison precoder of
+ * Sec. I and Sec. III-D: the matched filter Q_c = H_c with the per-cluster
+ * power normalization of Sec. III-C,
+ *     x_c = sqrt(rho_c^2 / (||H_c||_F^2 Es)) H_c s,   rho_c^2 = rho^2 / C
+ * (C = 1: centralized MRT).  weights [n_sc][C] receive the factors; a
+ * cluster with a zero channel gets status PRECODE_ST_FAIL, weight 0, x_c = 0.
+ * params: power and Es; precision must be FP32.
+ * ------------------------------------------------------------------------- */
+int precode_mrt(precode_ctx *ctx, const void *H, const void *s, const int *cluster_sizes,
+                int C, int B, int U, int n_sc, int K, const precode_params *params, void *x,
+                float *weights, int *status, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * The UE side of the uncoded-BER link (Sec. III-D; downlink model of
+ * Sec. II-A, UE scaling of Sec. II-B).  Device pointers, asynchronous on
+ * `stream`, no context.
+ *
+ * precode_qam_map: labels [n] (int32 in [0, order); higher bits ignored) to
+ * unit-energy square QAM points s [n] (complex64).  The upper half of a
+ * label's log2(order) bits is the binary-reflected Gray code of the in-phase
+ * level, the lower half that of the quadrature level; level i of
+ * m = sqrt(order) sits at (2 i - (m - 1)) d, d = sqrt(3 / (2 (order - 1))).
+ * order = 4, 16, 64, ..., 65536.
+ *
+ * precode_ue_receive: s_hat[k][n][u] = scale[n] (sum_b conj(H[n][b][u])
+ * x[k][n][b] + sqrt(N0) noise[k][n][u]), i.e. y = H_dl x + n scaled by the
+ * UE factor.  noise [K][n_sc][U] complex64 of unit variance per complex
+ * entry, or NULL (noise-free); scale [n_sc] float or NULL (1).
+ *
+ * precode_ue_gain: the joint UE factor minimizing the MSE of Sec. II-B for
+ * the precoder in use, from its noise-free responses to the U pilots
+ * s = e_v: y_pilot [U][n_sc][U] = precode_ue_receive output for those
+ * pilots (scale NULL), E[n][u][v] = y_pilot[v][n][u] = (H_dl P)[u][v],
+ * beta[n] = Es Re(tr E) / (Es ||E||_F^2 + U N0).  For the WF precoder this
+ * is beta_WF.
+ *
+ * precode_qam_errors: nearest-point decision of every s_hat (per axis,
+ * clamped to the outer levels), its Gray label to labels_out [n] (or NULL),
+ * and the number of bits that differ from labels [n] added to the 64-bit
+ * device counter *bit_errors (or NULL); the caller clears the counter.
+ * ------------------------------------------------------------------------- */
+int precode_qam_map(const int *labels, long long n, int order, void *s, void *stream);
+int precode_ue_receive(const void *H, const void *x, const void *noise, float N0,
+                       const float *scale, int B, int U, int n_sc, int K, void *s_hat,
+                       void *stream);
+int precode_ue_gain(const void *y_pilot, float N0, float Es, int U, int n_sc, float *beta,
+                    void *stream);
+int precode_qam_errors(const void *s_hat, const int *labels, long long n, int order,
+                       int *labels_out, unsigned long long *bit_errors, void *stream);
 
 /* ---------------------------------------------------------------------------
  * FD precoding of a frame (Sec. III-C).  Per subcarrier and cluster c, with

@@ -25,7 +25,9 @@ _IMPL = {"auto": IMPL_AUTO, "fused": IMPL_FUSED, "plain": IMPL_PLAIN}
 
 
 def params(power: float = 1.0, Es: float = 1.0, tau: float = 0.125, precision="fp32", refine_steps: int = 0,
-           fp64_ratio: float = 0.5, impl="auto") -> _lib.Params:
+           fp64_ratio: float = 0.5, impl="auto", tau_c=None, power_c=None) -> _lib.Params:
+    """Call parameters.  tau_c / power_c: optional per-cluster tau_c and
+    budgets rho_c^2 (summing to power) for FD and MRT (Sec. III-C)."""
     p = _lib.Params()
     _lib.load().precode_params_init(ctypes.byref(p))
     p.power, p.Es, p.tau = power, Es, tau
@@ -33,6 +35,13 @@ def params(power: float = 1.0, Es: float = 1.0, tau: float = 0.125, precision="f
     p.refine_steps = refine_steps
     p.fp64_ratio = fp64_ratio
     p.impl = _IMPL[impl] if isinstance(impl, str) else int(impl)
+    keep = []
+    for name, vals in (("cluster_tau", tau_c), ("cluster_power", power_c)):
+        if vals is not None:
+            arr = (ctypes.c_float * len(vals))(*[float(v) for v in vals])
+            keep.append(arr)
+            setattr(p, name, ctypes.cast(arr, ctypes.POINTER(ctypes.c_float)))
+    p._keep = keep  # the host arrays live as long as the parameters
     return p
 
 
@@ -177,6 +186,43 @@ class Context:
     def fd(self, H, s, rho, sizes, mode="wf", prm=None, x=None, weights=None, status=None, stream=None):
         """FD precoding (Sec. III-C).  Returns (x, weights [n_sc, C], status [n_sc, C])."""
         return self._run(ARCH_FD, H, s, rho, sizes, mode, prm, x, weights, status, stream)
+
+    def central(self, H, s, rho, prm=None, x=None, beta=None, status=None, stream=None):
+        """Centralized WF in the B x B form of Theorem 1 (rho = kappa > 0).
+        Returns (x, beta [n_sc], status [n_sc])."""
+        torch = _torch()
+        n_sc, B, U = H.shape
+        K = s.shape[0]
+        _check_tensor(H, "H", (n_sc, B, U))
+        _check_tensor(s, "s", (K, n_sc, U))
+        x = torch.empty((K, n_sc, B), dtype=torch.complex64, device=H.device) if x is None else x
+        _check_tensor(x, "x", (K, n_sc, B))
+        beta = torch.empty(n_sc, dtype=torch.float32, device=H.device) if beta is None else beta
+        status = torch.empty(n_sc, dtype=torch.int32, device=H.device) if status is None else status
+        prm = prm if prm is not None else params()
+        _lib.check(_lib.load().precode_central(self.handle, _ptr(H), _ptr(s), float(rho), B, U, n_sc, K,
+                                               ctypes.byref(prm), _ptr(x), _ptr(beta), _ptr(status),
+                                               _stream(stream)), "precode_central")
+        return x, beta, status
+
+    def mrt(self, H, s, sizes, prm=None, x=None, weights=None, status=None, stream=None):
+        """MRT with per-cluster power normalization (one cluster: centralized).
+        Returns (x, weights [n_sc, C], status [n_sc, C])."""
+        torch = _torch()
+        n_sc, B, U = H.shape
+        K = s.shape[0]
+        _check_tensor(H, "H", (n_sc, B, U))
+        _check_tensor(s, "s", (K, n_sc, U))
+        arr, C = _sizes(sizes)
+        x = torch.empty((K, n_sc, B), dtype=torch.complex64, device=H.device) if x is None else x
+        _check_tensor(x, "x", (K, n_sc, B))
+        weights = torch.empty(n_sc * C, dtype=torch.float32, device=H.device) if weights is None else weights
+        status = torch.empty(n_sc * C, dtype=torch.int32, device=H.device) if status is None else status
+        prm = prm if prm is not None else params()
+        _lib.check(_lib.load().precode_mrt(self.handle, _ptr(H), _ptr(s), arr, C, B, U, n_sc, K,
+                                           ctypes.byref(prm), _ptr(x), _ptr(weights), _ptr(status),
+                                           _stream(stream)), "precode_mrt")
+        return x, weights.view(n_sc, C), status.view(n_sc, C)
 
     def frame(self, arch, H, rho, sizes, mode="wf", prm=None, stream=None) -> Frame:
         """Per-frame part (Gram, factorization, beta / weights) kept resident."""
@@ -334,3 +380,69 @@ def fd(H, s, rho, sizes, mode="wf", **kw):
     if prm is None and kw:
         prm = params(**{k: kw.pop(k) for k in list(kw) if k in params.__code__.co_varnames})
     return default_context(H.device.index or 0).fd(H, s, rho, sizes, mode, prm, **kw)
+
+
+# ---------------------------------------------------------------------------
+# The UE side of the uncoded-BER link (precode_qam_map, precode_ue_receive,
+# precode_ue_gain, precode_qam_errors)
+# ---------------------------------------------------------------------------
+def _check_labels(t, name):
+    torch = _torch()
+    if t.dtype != torch.int32 or not t.is_cuda or not t.is_contiguous():
+        raise ValueError("%s must be a contiguous int32 CUDA tensor" % name)
+
+
+def qam_map(labels, order: int, s=None, stream=None):
+    """Gray-labelled unit-energy square QAM points of int32 labels (any shape)."""
+    torch = _torch()
+    _check_labels(labels, "labels")
+    s = torch.empty(labels.shape, dtype=torch.complex64, device=labels.device) if s is None else s
+    _check_tensor(s, "s", tuple(labels.shape))
+    _lib.check(_lib.load().precode_qam_map(_ptr(labels), labels.numel(), int(order), _ptr(s), _stream(stream)),
+               "precode_qam_map")
+    return s
+
+
+def ue_receive(H, x, noise=None, N0: float = 0.0, scale=None, s_hat=None, stream=None):
+    """s_hat [K, n_sc, U] = scale[n] (H_dl x + sqrt(N0) noise), H_dl = H^H."""
+    torch = _torch()
+    n_sc, B, U = H.shape
+    K = x.shape[0]
+    _check_tensor(H, "H", (n_sc, B, U))
+    _check_tensor(x, "x", (K, n_sc, B))
+    if noise is not None:
+        _check_tensor(noise, "noise", (K, n_sc, U))
+    if scale is not None and (scale.dtype != torch.float32 or tuple(scale.shape) != (n_sc,) or not scale.is_cuda):
+        raise ValueError("scale must be a float32 CUDA tensor [n_sc]")
+    s_hat = torch.empty((K, n_sc, U), dtype=torch.complex64, device=H.device) if s_hat is None else s_hat
+    _check_tensor(s_hat, "s_hat", (K, n_sc, U))
+    _lib.check(_lib.load().precode_ue_receive(_ptr(H), _ptr(x), _ptr(noise), float(N0), _ptr(scale), B, U, n_sc,
+                                              K, _ptr(s_hat), _stream(stream)), "precode_ue_receive")
+    return s_hat
+
+
+def ue_gain(y_pilot, N0: float, Es: float = 1.0, beta=None, stream=None):
+    """Joint MSE-optimal UE factor [n_sc] from noise-free pilot responses [U, n_sc, U]."""
+    torch = _torch()
+    U, n_sc, U2 = y_pilot.shape
+    _check_tensor(y_pilot, "y_pilot", (U, n_sc, U))
+    beta = torch.empty(n_sc, dtype=torch.float32, device=y_pilot.device) if beta is None else beta
+    _lib.check(_lib.load().precode_ue_gain(_ptr(y_pilot), float(N0), float(Es), U, n_sc, _ptr(beta),
+                                           _stream(stream)), "precode_ue_gain")
+    return beta
+
+
+def qam_errors(s_hat, labels, order: int, count=None, labels_out=None, stream=None):
+    """Adds the bit errors of the nearest-point decisions of s_hat against
+    labels to the int64 device counter `count` (created zeroed if None);
+    returns (count, labels_out)."""
+    torch = _torch()
+    _check_labels(labels, "labels")
+    _check_tensor(s_hat, "s_hat", tuple(labels.shape))
+    if count is None:
+        count = torch.zeros(1, dtype=torch.int64, device=labels.device)
+    if labels_out is not None:
+        _check_labels(labels_out, "labels_out")
+    _lib.check(_lib.load().precode_qam_errors(_ptr(s_hat), _ptr(labels), labels.numel(), int(order),
+                                              _ptr(labels_out), _ptr(count), _stream(stream)), "precode_qam_errors")
+    return count, labels_out

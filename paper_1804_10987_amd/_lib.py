@@ -27,6 +27,8 @@ class Params(ctypes.Structure):
         ("refine_steps", ctypes.c_int),
         ("fp64_ratio", ctypes.c_float),
         ("impl", ctypes.c_int),
+        ("cluster_tau", ctypes.POINTER(ctypes.c_float)),
+        ("cluster_power", ctypes.POINTER(ctypes.c_float)),
     ]
 
 
@@ -87,6 +89,12 @@ SIGNATURES = {
     "precode_pd": (I, [VP, VP, VP, F, IP, I, I, I, I, I, I, ctypes.POINTER(Params), VP, VP, VP, VP]),
     "precode_fd": (I, [VP, VP, VP, F, IP, I, I, I, I, I, I, ctypes.POINTER(Params), VP, VP, VP, VP]),
     "precode_pd_noalloc": (I, [VP, VP, VP, F, IP, I, I, I, I, I, I, ctypes.POINTER(Params), VP, VP, VP, VP]),
+    "precode_central": (I, [VP, VP, VP, F, I, I, I, I, ctypes.POINTER(Params), VP, VP, VP, VP]),
+    "precode_mrt": (I, [VP, VP, VP, IP, I, I, I, I, I, ctypes.POINTER(Params), VP, VP, VP, VP]),
+    "precode_qam_map": (I, [VP, ctypes.c_longlong, I, VP, VP]),
+    "precode_ue_receive": (I, [VP, VP, VP, F, VP, I, I, I, I, VP, VP]),
+    "precode_ue_gain": (I, [VP, F, F, I, I, VP, VP]),
+    "precode_qam_errors": (I, [VP, VP, ctypes.c_longlong, I, VP, VP, VP]),
     "precode_frame_prepare": (I, [VP, I, VP, F, IP, I, I, I, I, I, ctypes.POINTER(Params),
                                   ctypes.POINTER(VP), VP]),
     "precode_frame_symbols": (I, [VP, VP, VP, I, VP, VP]),

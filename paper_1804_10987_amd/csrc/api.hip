@@ -45,6 +45,9 @@ struct precode_ctx {
     // plain workspace
     void *wsRef;
     size_t capRef;
+    // centralized B x B WF factor tiles, ordered as the plain workspace
+    void *wsCen;
+    size_t capCen;
     precode_frame *frames;
     int last_impl;
     int last_waves;  // waves per workgroup of the last fused launch
@@ -150,6 +153,8 @@ precode_params defaults() {
     d.refine_steps = 0;
     d.fp64_ratio = 0.5f;
     d.impl = PRECODE_IMPL_AUTO;
+    d.cluster_tau = nullptr;
+    d.cluster_power = nullptr;
     return d;
 }
 
@@ -198,6 +203,21 @@ int make_prob(int arch, float rho, const int *sizes, int C, int mode, int B, int
         p.off[c + 1] = (int)sum;
     }
     if (sum != B) return PRECODE_EINVAL;
+    if (arch == kFD && (q.cluster_tau || q.cluster_power)) {
+        // per-cluster tau_c / rho_c^2 (eq. regularization, Sec. III-C)
+        if (C > kMaxCv) return PRECODE_EUNSUPPORTED;
+        double total = 0.0;
+        for (int c = 0; c < C; ++c) {
+            const float pw = q.cluster_power ? q.cluster_power[c] : q.power / (float)C;
+            const float tc = q.cluster_tau ? q.cluster_tau[c] : q.tau;
+            if (!(isfinite(pw) && pw > 0.f) || !finite_nonneg(tc)) return PRECODE_EINVAL;
+            total += pw;
+            p.clp[c] = pw;
+            p.clk[c] = p.zf ? 0.f : (float)((double)tc * (double)rho * (double)q.power / (double)pw);
+        }
+        if (q.cluster_power && fabs(total - (double)q.power) > 1e-5 * (double)q.power) return PRECODE_EINVAL;
+        p.clvar = 1;
+    }
     const bool all64 = q.precision == PRECODE_PREC_FP64;
     p.pd_fp64 = all64 || (double)U / (double)B >= (double)q.fp64_ratio;
     for (int c = 0; c < C; ++c)
@@ -429,6 +449,7 @@ int precode_ctx_destroy(precode_ctx *ctx) {
     ctx_free(ctx, ctx->wsScale, ctx->capScale);
     ctx_free(ctx, ctx->wsZ, ctx->capZ);
     ctx_free(ctx, ctx->wsRef, ctx->capRef);
+    ctx_free(ctx, ctx->wsCen, ctx->capCen);
     ctx_free(ctx, ctx->tab, ctx->capTab);
     if (ctx->tabHost) (void)hipHostFree(ctx->tabHost);
     if (ctx->tabCopied) (void)hipEventDestroy(ctx->tabCopied);
@@ -461,6 +482,86 @@ int precode_fd(precode_ctx *ctx, const void *H, const void *s, float rho, const 
                int B, int U, int n_sc, int K, const precode_params *params, void *x, float *weights, int *status,
                void *stream) {
     return run(ctx, kFD, H, s, rho, cluster_sizes, C, mode, B, U, n_sc, K, params, x, weights, status, stream);
+}
+
+int precode_central(precode_ctx *ctx, const void *H, const void *s, float rho, int B, int U, int n_sc, int K,
+                    const precode_params *params, void *x, float *beta, int *status, void *stream) {
+    if (!ctx) return PRECODE_EINVAL;
+    const precode_params q = params ? *params : defaults();
+    int rc = check_params(q);
+    if (rc) return rc;
+    if (U < 1 || B < 1 || n_sc < 0 || K < 0) return PRECODE_EINVAL;
+    if (!isfinite(rho) || rho < 0.f) return PRECODE_EINVAL;
+    // the B x B form needs kappa > 0 (H H^H is singular for B > U); FP32 only
+    if (!(rho > 0.f) || q.precision != PRECODE_PREC_FP32) return PRECODE_EUNSUPPORTED;
+    if (B > kMaxB || U > kMaxU || K > kMaxK || !central_supported(B, U)) return PRECODE_EUNSUPPORTED;
+    if (n_sc == 0) return PRECODE_OK;
+    if (!H || (K > 0 && (!s || !x))) return PRECODE_EINVAL;
+    if (!aligned8(H) || !aligned8(s) || !aligned8(x)) return PRECODE_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    // factor tiles for up to 256 MiB of subcarriers per launch
+    const size_t per = central_ws_bytes(B, 1);
+    const size_t chunk = std::max<size_t>(1, std::min<size_t>((size_t)n_sc, (size_t(256) << 20) / per));
+    rc = grow(ctx, &ctx->wsCen, &ctx->capCen, chunk * per, st);
+    if (!rc) rc = ws_acquire(ctx, st);
+    if (rc) return rc;
+    rc = dev_err(central_run(B, U, n_sc, K, rho, q.Es, q.power, (const float2 *)H, (const float2 *)s, (float2 *)x,
+                             beta, status, ctx->wsCen, chunk * per, st));
+    const int rr = ws_release(ctx, st);
+    return rc ? rc : rr;
+}
+
+int precode_mrt(precode_ctx *ctx, const void *H, const void *s, const int *cluster_sizes, int C, int B, int U,
+                int n_sc, int K, const precode_params *params, void *x, float *weights, int *status, void *stream) {
+    if (!ctx) return PRECODE_EINVAL;
+    const precode_params q = params ? *params : defaults();
+    Prob p;
+    int rc = make_prob(kFD, 0.f, cluster_sizes, C, PRECODE_ZF, B, U, n_sc, K, q, &p);
+    if (rc) return rc;
+    if (q.precision != PRECODE_PREC_FP32) return PRECODE_EUNSUPPORTED;
+    if (n_sc == 0) return PRECODE_OK;
+    if (!H || (K > 0 && (!s || !x))) return PRECODE_EINVAL;
+    if (!aligned8(H) || !aligned8(s) || !aligned8(x)) return PRECODE_EINVAL;
+    return dev_err(mrt_run(p, (const float2 *)H, (const float2 *)s, (float2 *)x, weights, status, (hipStream_t)stream));
+}
+
+static int qam_half_bits(int order) {
+    for (int hb = 1; hb <= 8; ++hb)
+        if (order == 1 << (2 * hb)) return hb;
+    return 0;
+}
+
+int precode_qam_map(const int *labels, long long n, int order, void *s, void *stream) {
+    const int hb = qam_half_bits(order);
+    if (!hb || n < 0) return PRECODE_EINVAL;
+    if (n > 0 && (!labels || !s || !aligned8(s))) return PRECODE_EINVAL;
+    return dev_err(qam_map_run(labels, n, hb, (float2 *)s, (hipStream_t)stream));
+}
+
+int precode_ue_receive(const void *H, const void *x, const void *noise, float N0, const float *scale, int B, int U,
+                       int n_sc, int K, void *s_hat, void *stream) {
+    if (B < 1 || U < 1 || U > kMaxU || n_sc < 0 || K < 0) return PRECODE_EINVAL;
+    if (!isfinite(N0) || N0 < 0.f) return PRECODE_EINVAL;
+    if (n_sc == 0 || K == 0) return PRECODE_OK;
+    if (!H || !x || !s_hat) return PRECODE_EINVAL;
+    if (!aligned8(H) || !aligned8(x) || !aligned8(noise) || !aligned8(s_hat)) return PRECODE_EINVAL;
+    return dev_err(ue_receive_run((const float2 *)H, (const float2 *)x, (const float2 *)noise, N0, scale, B, U, n_sc,
+                                  K, (float2 *)s_hat, (hipStream_t)stream));
+}
+
+int precode_ue_gain(const void *y_pilot, float N0, float Es, int U, int n_sc, float *beta, void *stream) {
+    if (U < 1 || n_sc < 0 || !isfinite(N0) || N0 < 0.f || !isfinite(Es) || !(Es > 0.f)) return PRECODE_EINVAL;
+    if (n_sc == 0) return PRECODE_OK;
+    if (!y_pilot || !beta || !aligned8(y_pilot)) return PRECODE_EINVAL;
+    return dev_err(ue_gain_run((const float2 *)y_pilot, N0, Es, U, n_sc, beta, (hipStream_t)stream));
+}
+
+int precode_qam_errors(const void *s_hat, const int *labels, long long n, int order, int *labels_out,
+                       unsigned long long *bit_errors, void *stream) {
+    const int hb = qam_half_bits(order);
+    if (!hb || n < 0) return PRECODE_EINVAL;
+    if (n > 0 && (!s_hat || !labels || !aligned8(s_hat))) return PRECODE_EINVAL;
+    return dev_err(qam_errors_run((const float2 *)s_hat, labels, n, hb, labels_out, bit_errors, (hipStream_t)stream));
 }
 
 int precode_frame_prepare(precode_ctx *ctx, int arch, const void *H, float rho, const int *cluster_sizes, int C,

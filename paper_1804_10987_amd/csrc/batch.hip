@@ -93,7 +93,7 @@ __global__ void __launch_bounds__(64 * NW, (min_waves<UP, MAXT, PREC>()))
         else hi = mid - 1;
     }
     const Entry &E = tab[lo];
-    fused_body<UP, PREC, NW, MAXT, VEC, false>(E.p, E.p.off, b - E.block0, E.K, kFull, E.H, E.s, E.x, nullptr, E.scale_out,
+    fused_body<UP, PREC, NW, MAXT, VEC, false>(E.p, &E.p, b - E.block0, E.K, kFull, E.H, E.s, E.x, nullptr, E.scale_out,
                                    E.status);
 }
 

@@ -17,6 +17,7 @@ constexpr int kMaxC = 256;   // clusters per cell
 constexpr int kMaxU = 64;    // users
 constexpr int kMaxB = 4096;  // antennas
 constexpr int kMaxK = 4096;  // symbols per call
+constexpr int kMaxCv = 64;   // clusters of a call with per-cluster tau_c / rho_c^2
 
 enum Arch { kPD = 0, kFD = 1 };
 
@@ -38,14 +39,30 @@ struct Prob {
     int off[kMaxC + 1];          // cluster row offsets, off[C] = B
     unsigned char fp64[kMaxC];   // FD: cluster solved on the FP64 route
     int pd_fp64;                 // PD: every subcarrier on the FP64 route
+    int clvar;                   // FD: the call's per-cluster kappa_c / rho_c^2 below
+    float clk[kMaxCv];           // kappa_c = tau_c U N0 / rho_c^2 (clvar)
+    float clp[kMaxCv];           // rho_c^2 (clvar)
 };
 
 __host__ __device__ inline int n_inst(const Prob &p) { return p.arch == kPD ? p.n_sc : p.n_sc * p.C; }
 
-// Regularizer of the local system of cluster c (FD, eq. regularization):
-// kappa_c = tau_c U N0 / rho_c^2 = tau_c C kappa with rho_c^2 = rho^2 / C.
-__host__ __device__ inline float fd_kappa(const Prob &p) { return p.zf ? 0.f : p.tau * (float)p.C * p.kappa; }
 __host__ __device__ inline float pd_kappa(const Prob &p) { return p.zf ? 0.f : p.kappa; }
+
+// Regularizer and power budget of FD cluster c (eq. regularization and the
+// power-allocation footnote of Sec. III-C): the call's per-cluster values when
+// given, else kappa_c = tau_c U N0 / rho_c^2 = tau C kappa and rho_c^2 =
+// rho^2 / C.  pk: the problem in memory a kernel can index (the
+// kernarg segment or a table in device memory).
+__host__ __device__ inline float fd_kappa_c(const Prob *pk, int c) {
+    if (pk->zf) return 0.f;
+    return pk->clvar ? pk->clk[c] : pk->tau * (float)pk->C * pk->kappa;
+}
+__host__ __device__ inline float fd_power_c(const Prob *pk, int c) {
+    return pk->clvar ? pk->clp[c] : pk->power / (float)pk->C;
+}
+__host__ __device__ inline double fd_power_c_d(const Prob *pk, int c) {
+    return pk->clvar ? (double)pk->clp[c] : (double)pk->power / (double)pk->C;
+}
 
 template <typename T>
 struct cx {
@@ -167,5 +184,26 @@ void fused_batch_fill(const BatchProblem *bp, int n, void *host);
 // what fused_batch_fill wrote); *launches receives the number of launches.
 hipError_t fused_batch_launch(const BatchProblem *bp, int n, int precision, const void *dev, hipStream_t st,
                               int *launches);
+
+// Comparison precoders (compare.hip).  Centralized WF in the B x B form of
+// Theorem 1: FP32, one workgroup per subcarrier, ws holds ws_bytes of
+// per-subcarrier factor tiles (central_ws_bytes(B, 1) each; launches are
+// chunked to fit).  MRT with the per-cluster normalization of Sec. III-C.
+bool central_supported(int B, int U);
+size_t central_ws_bytes(int B, int n_chunk);
+hipError_t central_run(int B, int U, int n_sc, int K, float kappa, float Es, float power, const float2 *H,
+                       const float2 *s, float2 *x, float *beta, int *status, void *ws, size_t ws_bytes,
+                       hipStream_t st);
+hipError_t mrt_run(const Prob &p, const float2 *H, const float2 *s, float2 *x, float *wgt, int *status,
+                   hipStream_t st);
+
+// The UE side of the uncoded-BER link (ue.hip); half_bits = log2(order) / 2.
+float qam_spacing(int order);
+hipError_t qam_map_run(const int *labels, long long n, int half_bits, float2 *s, hipStream_t st);
+hipError_t ue_receive_run(const float2 *H, const float2 *x, const float2 *noise, float N0, const float *scale, int B,
+                          int U, int n_sc, int K, float2 *y, hipStream_t st);
+hipError_t ue_gain_run(const float2 *y_pilot, float N0, float Es, int U, int n_sc, float *beta, hipStream_t st);
+hipError_t qam_errors_run(const float2 *s_hat, const int *labels, long long n, int half_bits, int *out,
+                          unsigned long long *count, hipStream_t st);
 
 }  // namespace pc

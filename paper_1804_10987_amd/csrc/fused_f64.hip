@@ -97,7 +97,7 @@ __device__ __forceinline__ bool gj_f64(double (&re)[F64L<UP>::NS], double (&im)[
 }
 
 template <int UP, int NT, int KU, bool P64>
-__device__ __forceinline__ void f64_system(const Prob &p, const int *__restrict__ off, int sys, int K,
+__device__ __forceinline__ void f64_system(const Prob &p, const Prob *__restrict__ pk, int sys, int K,
                                            const float2 *__restrict__ H, const float2 *__restrict__ s,
                                            float2 *__restrict__ x, float *__restrict__ scale_out,
                                            int *__restrict__ status, char *wb) {
@@ -108,7 +108,7 @@ __device__ __forceinline__ void f64_system(const Prob &p, const int *__restrict_
     const int B = p.B, U = p.U, C = p.C, n_sc = p.n_sc;
     const int n = pd ? sys : sys / C;
     const int cl = pd ? 0 : sys - n * C;
-    const int r0 = pd ? 0 : off[cl], r1 = pd ? B : off[cl + 1];
+    const int r0 = pd ? 0 : pk->off[cl], r1 = pd ? B : pk->off[cl + 1];
     const int nrows = r1 - r0;
     const float2 *Hn = H + (size_t)n * B * U;
     float2 *rowsL = (float2 *)wb;                                         // [32][UP] staged rows
@@ -116,7 +116,7 @@ __device__ __forceinline__ void f64_system(const Prob &p, const int *__restrict_
     cx<float> *zb32 = (cx<float> *)(wb + F64L<UP>::s_bytes);             // [UP][KC] Z chunk (FP32 precode)
     cx<double> *zb = (cx<double> *)(wb + F64L<UP>::rows_bytes);          // [KC][UP] Z chunk (FP64 precode)
     cx<double> *rowbuf = (cx<double> *)(wb + F64L<UP>::rows_bytes + (P64 ? F64L<UP>::z64_bytes : 0));
-    const double kap = pd ? (double)pd_kappa(p) : (double)fd_kappa(p);
+    const double kap = pd ? (double)pd_kappa(p) : (double)fd_kappa_c(pk, cl);
 
     // Gram in FP64, tile by tile through the staged rows (no tile is held in
     // registers across the inversion: the precode loads the rows again)
@@ -195,7 +195,7 @@ __device__ __forceinline__ void f64_system(const Prob &p, const int *__restrict_
             out = sqrt((double)p.Es / (double)p.power * t);  // beta
             scale = 1.0 / out;
         } else {
-            out = sqrt((double)p.power / (double)C / (t * (double)p.Es));  // w_c
+            out = sqrt(fd_power_c_d(pk, cl) / (t * (double)p.Es));  // w_c
             scale = out;
         }
     }
@@ -300,11 +300,11 @@ __global__ void __launch_bounds__(64 * kF64Waves, (F64Cfg<UP, NT>::min_waves))
     fused_f64_k(Prob p, int K, const float2 *__restrict__ H, const float2 *__restrict__ s, float2 *__restrict__ x,
                 float *__restrict__ scale_out, int *__restrict__ status) {
     extern __shared__ float4 smem_f64[];
-    const int *off = (const int *)((const char *)__builtin_amdgcn_kernarg_segment_ptr() + offsetof(Prob, off));
+    const Prob *pk = (const Prob *)__builtin_amdgcn_kernarg_segment_ptr();  // p: the first argument
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int sys = blockIdx.x * kF64Waves + wave;
     if (sys >= n_inst(p)) return;
-    f64_system<UP, NT, F64Cfg<UP, NT>::KU, P64>(p, off, sys, K, H, s, x, scale_out, status,
+    f64_system<UP, NT, F64Cfg<UP, NT>::KU, P64>(p, pk, sys, K, H, s, x, scale_out, status,
                                                 (char *)smem_f64 + (size_t)wave * F64L<UP>::per_wave(P64));
 }
 

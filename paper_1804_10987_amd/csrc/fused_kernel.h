@@ -1206,7 +1206,7 @@ constexpr int min_waves() {
 //             X_c = H_c Z and stored
 // Modes kPrepare / kSymbols store / load scale * A^-1 per system instead.
 template <int UP, int PREC, int MAXT, bool VEC>
-__device__ __forceinline__ void wave_system(const Prob &p, const int *__restrict__ off, int sys, int K, int mode,
+__device__ __forceinline__ void wave_system(const Prob &p, const Prob *__restrict__ pk, int sys, int K, int mode,
                                             const float2 *__restrict__ H, const float2 *__restrict__ s,
                                             float2 *__restrict__ x, cx<float> *__restrict__ ainv_g,
                                             float *__restrict__ scale_out, int *__restrict__ status, cx<float> *Zw,
@@ -1218,11 +1218,11 @@ __device__ __forceinline__ void wave_system(const Prob &p, const int *__restrict
     const int B = p.B, U = p.U, C = p.C, n_sc = p.n_sc;
     const int n = pd ? sys : sys / C;
     const int c = pd ? 0 : sys - n * C;
-    const int r0 = pd ? 0 : off[c], r1 = pd ? B : off[c + 1];
+    const int r0 = pd ? 0 : pk->off[c], r1 = pd ? B : pk->off[c + 1];
     const int ntile = (r1 - r0 + 31) >> 5;
     const float2 *Hn = H + (size_t)n * B * U;
     const float *Hf = (const float *)Hn;
-    const float kap = pd ? pd_kappa(p) : fd_kappa(p);
+    const float kap = pd ? pd_kappa(p) : fd_kappa_c(pk, c);
     cx<float> *fac = ainv_g ? ainv_g + (size_t)sys * U * U : nullptr;
     float scale = 1.f, amax = 0.f;
     bool ok = true;
@@ -1311,7 +1311,7 @@ __device__ __forceinline__ void wave_system(const Prob &p, const int *__restrict
     }
     if (mode == kSymbols) {
         if (on_f64_route(status, sys)) {
-            f64r::instance(f64r::shape_of(p), off, sys, K, false, H, s, x, nullptr, nullptr, (char *)Zw);
+            f64r::instance(f64r::shape_of(p), pk, sys, K, false, H, s, x, nullptr, nullptr, (char *)Zw);
             return;
         }
         if (pre_sym) load_sym<UP>(s + (size_t)n * U, (size_t)n_sc * U, U, min(KC, K), sym0);
@@ -1332,7 +1332,7 @@ __device__ __forceinline__ void wave_system(const Prob &p, const int *__restrict
         if (!ok) {
             // the FP32 factorization failed: the FP64 route solves the
             // instance (factors, status and every symbol) in this wave
-            f64r::instance(f64r::shape_of(p), off, sys, mode == kPrepare ? 0 : K, true, H, s, x, scale_out, status, (char *)Zw);
+            f64r::instance(f64r::shape_of(p), pk, sys, mode == kPrepare ? 0 : K, true, H, s, x, scale_out, status, (char *)Zw);
             if (mode == kPrepare) zero_factor(U, fac);
             return;
         }
@@ -1341,7 +1341,7 @@ __device__ __forceinline__ void wave_system(const Prob &p, const int *__restrict
             out = sqrtf(p.Es / p.power * tr);  // beta
             scale = 1.f / out;
         } else {
-            out = sqrtf(p.power / (float)C / (tr * p.Es));  // w_c
+            out = sqrtf(fd_power_c(pk, c) / (tr * p.Es));  // w_c
             scale = out;
         }
         if (lane == 0) {
@@ -1612,14 +1612,15 @@ __device__ __forceinline__ void wg_pd_split(const Prob &p, int blk, int K, int m
 // ---- the kernel body -----------------------------------------------------------
 // Workgroups of NW waves; wave w of block blk runs system blk * NW + w (PD:
 // consecutive subcarriers; FD: consecutive clusters of a subcarrier).
-// off: the problem's cluster offsets (p.off) in memory the kernel can index.
+// pk: the problem (p) in memory the kernel can index (cluster offsets and
+// per-cluster regularizers / budgets).
 // MAXT: channel tiles (32 rows) of the largest system that a wave keeps in
 // registers (0: the precode streams the rows a second time).  VEC: U == UP
 // and a 16-byte aligned channel (wider loads).
 // SPLIT (PD only): one subcarrier per workgroup, MAXT tiles per wave
 // (wg_pd_split); otherwise one system per wave.
 template <int UP, int PREC, int NW, int MAXT, bool VEC, bool SPLIT>
-__device__ __forceinline__ void fused_body(const Prob &p, const int *__restrict__ off, int blk, int K, int mode,
+__device__ __forceinline__ void fused_body(const Prob &p, const Prob *__restrict__ pk, int blk, int K, int mode,
                                            const float2 *__restrict__ H,
                                            const float2 *__restrict__ s, float2 *__restrict__ x,
                                            cx<float> *__restrict__ ainv_g, float *__restrict__ scale_out,
@@ -1637,7 +1638,7 @@ __device__ __forceinline__ void fused_body(const Prob &p, const int *__restrict_
     const int sys = blk * NW + wave;
     if (sys >= n_sys) return;
     char *wb = (char *)smem4 + (size_t)wave * Lds<UP>::per_wave;
-    wave_system<UP, PREC, MAXT, VEC>(p, off, sys, K, mode, H, s, x, ainv_g, scale_out, status, (cx<float> *)wb,
+    wave_system<UP, PREC, MAXT, VEC>(p, pk, sys, K, mode, H, s, x, ainv_g, scale_out, status, (cx<float> *)wb,
                                 (cx<float> *)(wb + Lds<UP>::zbytes));
 }
 

@@ -62,7 +62,7 @@ __device__ inline InstInfo inst_info(const Prob &p, int inst) {
         q.big = q.rows >= p.U;
         q.m = q.big ? p.U : q.rows;
         q.r64 = p.fp64[q.c] != 0;
-        q.kap = fd_kappa(p);
+        q.kap = fd_kappa_c(&p, q.c);
     }
     return q;
 }
@@ -201,7 +201,8 @@ __global__ void __launch_bounds__(64) plain_factor_k(Prob p, cx<T> *__restrict__
                 sc = (T)1 / beta;
                 out = beta;
             } else {
-                const T w = sqrt(((T)p.power / (T)p.C) / (t * (T)p.Es));
+                const T rho_c2 = sizeof(T) == sizeof(double) ? (T)fd_power_c_d(&p, q.c) : (T)fd_power_c(&p, q.c);
+                const T w = sqrt(rho_c2 / (t * (T)p.Es));
                 sc = w;
                 out = w;
             }
@@ -380,9 +381,9 @@ __global__ void __launch_bounds__(64) plain_retry_k(Prob p, int K, int factors, 
     float *sc = scale_ws + (size_t)inst * kW<float>();
     const float v = *sc;
     if (factors ? v != 0.f : v >= 0.f) return;
-    // the cluster offsets read in place from the kernel arguments (p first)
-    const int *off = (const int *)((const char *)__builtin_amdgcn_kernarg_segment_ptr() + offsetof(Prob, off));
-    f64r::instance(f64r::shape_of(p), off, inst, K, factors != 0, H, s, x, scale_out, status, (char *)retry_lds);
+    // the problem read in place from the kernel arguments (p first)
+    const Prob *pk = (const Prob *)__builtin_amdgcn_kernarg_segment_ptr();
+    f64r::instance(f64r::shape_of(p), pk, inst, K, factors != 0, H, s, x, scale_out, status, (char *)retry_lds);
     if (factors && threadIdx.x == 0) *sc = -1.f;
 }
 

@@ -67,7 +67,7 @@ __device__ __forceinline__ void apply_rows(const double (&mre)[F64L<UP>::NS], co
 }
 
 template <int UP>
-__device__ __forceinline__ void refine_system(const Prob &p, const int *__restrict__ off, int sys, int K,
+__device__ __forceinline__ void refine_system(const Prob &p, const Prob *__restrict__ pk, int sys, int K,
                                               const float2 *__restrict__ H, const float2 *__restrict__ s,
                                               float2 *__restrict__ x, const cx<float> *__restrict__ fac,
                                               const float *__restrict__ scale_in, const int *__restrict__ status,
@@ -79,10 +79,10 @@ __device__ __forceinline__ void refine_system(const Prob &p, const int *__restri
     const int B = p.B, U = p.U, C = p.C, n_sc = p.n_sc;
     const int n = pd ? sys : sys / C;
     const int cl = pd ? 0 : sys - n * C;
-    const int r0 = pd ? 0 : off[cl], r1 = pd ? B : off[cl + 1];
+    const int r0 = pd ? 0 : pk->off[cl], r1 = pd ? B : pk->off[cl + 1];
     const int nrows = r1 - r0, ntile = (nrows + 31) >> 5;
     if (on_f64_route(status, sys)) {
-        f64r::instance(f64r::shape_of(p), off, sys, K, false, H, s, x, nullptr, nullptr, wb);
+        f64r::instance(f64r::shape_of(p), pk, sys, K, false, H, s, x, nullptr, nullptr, wb);
         return;
     }
     const float2 *Hn = H + (size_t)n * B * U;
@@ -91,7 +91,7 @@ __device__ __forceinline__ void refine_system(const Prob &p, const int *__restri
     cx<float> *zb32 = (cx<float> *)(wb + F64L<UP>::s_bytes);                  // [UP][KC] refined Z (complex64)
     cx<double> *zb = (cx<double> *)(wb + F64L<UP>::rows_bytes);               // [KC][UP] Z (upos order)
     cx<double> *rb = (cx<double> *)(wb + F64L<UP>::rows_bytes + F64L<UP>::z64_bytes);  // [KC][UP] residual
-    const double kap = pd ? (double)pd_kappa(p) : (double)fd_kappa(p);
+    const double kap = pd ? (double)pd_kappa(p) : (double)fd_kappa_c(pk, cl);
     const float sv = scale_in[sys];
     // F = scale A^-1: scale = 1 / beta (PD) or w_c (FD); 0 for a failed instance
     const double scale = pd ? (sv > 0.f ? 1.0 / (double)sv : 0.0) : (double)sv;
@@ -179,11 +179,11 @@ __global__ void __launch_bounds__(64 * RefL<UP>::waves, 2)
     refine_k(Prob p, int K, const float2 *__restrict__ H, const float2 *__restrict__ s, float2 *__restrict__ x,
              const cx<float> *__restrict__ fac, const float *__restrict__ scale_in, const int *__restrict__ status) {
     extern __shared__ float4 smem_ref[];
-    const int *off = (const int *)((const char *)__builtin_amdgcn_kernarg_segment_ptr() + offsetof(Prob, off));
+    const Prob *pk = (const Prob *)__builtin_amdgcn_kernarg_segment_ptr();  // p: the first argument
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int sys = blockIdx.x * RefL<UP>::waves + wave;
     if (sys >= n_inst(p)) return;
-    refine_system<UP>(p, off, sys, K, H, s, x, fac, scale_in, status,
+    refine_system<UP>(p, pk, sys, K, H, s, x, fac, scale_in, status,
                       (char *)smem_ref + (size_t)wave * RefL<UP>::per_wave);
 }
 

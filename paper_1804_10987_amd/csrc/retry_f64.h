@@ -81,20 +81,20 @@ __device__ __forceinline__ Shape64 shape_of(const Prob &p) {
     q.B = p.B;
     q.C = p.C;
     q.n_sc = p.n_sc;
-    q.kap = q.pd ? pd_kappa(p) : fd_kappa(p);
+    q.kap = q.pd ? pd_kappa(p) : 0.f;  // FD: per cluster (fd_kappa_c)
     q.Es = p.Es;
     q.power = p.power;
     return q;
 }
 
 // Local system `sys` of problem p (PD: subcarrier sys over all rows; FD:
-// cluster sys % C of subcarrier sys / C).  off: the cluster offsets (read for
-// FD only).  K symbols s[k][n_sc][U] -> x[k][n_sc][B], k < K (K = 0: the
+// cluster sys % C of subcarrier sys / C).  pk: the problem in memory the
+// kernel can index (cluster offsets, kappa_c and rho_c^2; read for FD only).  K symbols s[k][n_sc][U] -> x[k][n_sc][B], k < K (K = 0: the
 // factorization only).  factors: write scale_out[sys] (beta for PD, w_c for
 // FD; 0 on failure) and status[sys] (PRECODE_ST_FP64, plus PRECODE_ST_FAIL
 // when the FP64 factorization fails too); either pointer may be NULL.
 // lds: lds_bytes(m) bytes of this wave's LDS, m = U (big) or B_c (small).
-__device__ __forceinline__ void instance(Shape64 p, const int *__restrict__ off, int sys, int K, bool factors,
+__device__ __forceinline__ void instance(Shape64 p, const Prob *__restrict__ pk, int sys, int K, bool factors,
                                              const float2 *__restrict__ H, const float2 *__restrict__ s,
                                              float2 *__restrict__ x, float *__restrict__ scale_out,
                                              int *__restrict__ status, char *lds) {
@@ -103,12 +103,12 @@ __device__ __forceinline__ void instance(Shape64 p, const int *__restrict__ off,
     const int U = p.U, B = p.B, C = p.C, n_sc = p.n_sc;
     const int n = pd ? sys : sys / C;
     const int c = pd ? 0 : sys - n * C;
-    const int r0 = pd ? 0 : off[c];
-    const int rows = pd ? B : off[c + 1] - r0;
+    const int r0 = pd ? 0 : pk->off[c];
+    const int rows = pd ? B : pk->off[c + 1] - r0;
     const bool big = rows >= U;
     const int m = big ? U : rows;
     const int nt = tri(m, 0);
-    const double kap = (double)p.kap;
+    const double kap = pd ? (double)p.kap : (double)fd_kappa_c(pk, c);
     const float2 *Hn = H + (size_t)n * B * U;
     cx<double> *L = (cx<double> *)lds;
     double *d0 = (double *)(L + nt);
@@ -191,7 +191,7 @@ __device__ __forceinline__ void instance(Shape64 p, const int *__restrict__ off,
             out = sqrt((double)p.Es / (double)p.power * t);  // beta
             scale = 1.0 / out;
         } else {
-            out = sqrt((double)p.power / (double)C / (t * (double)p.Es));  // w_c
+            out = sqrt(fd_power_c_d(pk, c) / (t * (double)p.Es));  // w_c
             scale = out;
         }
     }

@@ -164,3 +164,40 @@ def device_cell(cell: Cell, device, seed: int = 0, cell_id: int = 0):
     lv = torch.randint(0, m, (cell.K, cell.n_sc, cell.U, 2), generator=g, device=device).float() * 2 - (m - 1)
     lv = lv / math.sqrt(2.0 * (m * m - 1) / 3.0)
     return torch.view_as_complex(H.contiguous()), torch.view_as_complex(lv.contiguous())
+
+
+# ---------------------------------------------------------------------------
+# uncoded-BER link inputs (Sec. III-D): random labels and receiver noise only
+# ---------------------------------------------------------------------------
+def labels(shape, order: int, rng: np.random.Generator) -> np.ndarray:
+    """Uniform QAM labels in [0, order) (the information bits), int32."""
+    return rng.integers(0, order, size=shape, dtype=np.int64).astype(np.int32)
+
+
+def cn_noise(shape, rng: np.random.Generator) -> np.ndarray:
+    """i.i.d. CN(0, 1) samples (unit variance per complex entry), complex64."""
+    re = rng.standard_normal(shape)
+    im = rng.standard_normal(shape)
+    return ((re + 1j * im) / math.sqrt(2.0)).astype(np.complex64)
+
+
+def link_frame(cell: Cell, seed: int = 0, frame: int = 0):
+    """(H [n_sc][B][U], labels [K][n_sc][U] int32, noise [K][n_sc][U]) for one
+    frame of an uncoded-BER run on the cell (labels in [0, cell.qam))."""
+    H = channel(cell, seed, 0, frame)
+    rng = _rng(6, seed, frame)
+    return H, labels((cell.K, cell.n_sc, cell.U), cell.qam, rng), cn_noise((cell.K, cell.n_sc, cell.U), rng)
+
+
+def device_link_frame(cell: Cell, device, seed: int = 0, frame: int = 0):
+    """link_frame drawn in device memory with a seeded torch generator
+    (i.i.d. CN(0,1) channel): for long Monte Carlo runs.  Not bit-identical
+    to link_frame."""
+    import torch
+
+    g = torch.Generator(device=device)
+    g.manual_seed((seed * 1_000_003 + frame * 7919 + 17) & 0x7FFFFFFF)
+    H = torch.randn((cell.n_sc, cell.B, cell.U, 2), generator=g, device=device) * math.sqrt(0.5)
+    lab = torch.randint(0, cell.qam, (cell.K, cell.n_sc, cell.U), generator=g, device=device, dtype=torch.int32)
+    w = torch.randn((cell.K, cell.n_sc, cell.U, 2), generator=g, device=device) * math.sqrt(0.5)
+    return torch.view_as_complex(H.contiguous()), lab, torch.view_as_complex(w.contiguous())

@@ -1,0 +1,149 @@
+"""GPU: FD and MRT with per-cluster tau_c and power budgets rho_c^2 (eq.
+regularization and the power-allocation footnote of Sec. III-C) through the
+C ABI, against the FP64 oracle, on every route an FD call can take: the
+fused FP32 / split kernels, the fused FP64 route, the fused refinement, the
+plain kernels (both Q_c forms), the frame API and MRT.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+
+    if not _t.cuda.is_available():
+        pytest.skip("no GPU")
+    return _t
+
+
+@pytest.fixture(scope="module")
+def pc(torch):
+    import paper_1804_10987_amd as m
+
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(pc):
+    return pc.Context(0)
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _vec_err(xg, xo):
+    num = np.linalg.norm(xg - xo, axis=-1)
+    den = np.linalg.norm(xo, axis=-1)
+    return num / np.where(den > 0, den, 1.0)
+
+
+def _variants(C, seed, power=1.0):
+    rng = np.random.default_rng(seed)
+    tau_c = rng.uniform(0.05, 1.0, C)
+    share = rng.uniform(0.5, 2.0, C)
+    # float32 budgets whose float64 sum is power to well within 1e-5
+    power_c = (power * share / share.sum()).astype(np.float32)
+    return tau_c.astype(np.float32), power_c
+
+
+def _budget(power_c, power=1.0):
+    """rho^2 for the oracle: the FP64 sum of the float32 budgets (within 1e-7
+    of the call's rho^2, which the library accepts to 1e-5)."""
+    return power if power_c is None else float(np.sum(power_c.astype(np.float64)))
+
+
+# (name, cell, params, expected route)
+ROUTES = [
+    ("fused_fp32", synth.Cell(B=128, sizes=(32, 32, 64), U=8, n_sc=24, K=14, snr_db=8.0), dict(), "fused"),
+    ("fused_split_fp16", synth.Cell(B=128, sizes=(32, 32, 64), U=8, n_sc=24, K=14, snr_db=8.0),
+     dict(precision="split_fp16"), "fused"),
+    ("fused_fp64_route", synth.Cell(B=256, sizes=(32,) * 8, U=16, n_sc=12, K=14, snr_db=10.0), dict(), "fused"),
+    ("fused_refine", synth.Cell(B=128, sizes=(32, 32, 64), U=8, n_sc=16, K=14, snr_db=8.0),
+     dict(refine_steps=1, precision="split_bf16"), "fused"),
+    ("plain_small_clusters", synth.Cell(B=44, sizes=(4, 12, 8, 20), U=8, n_sc=9, K=6, snr_db=5.0), dict(), "plain"),
+    ("plain_forced", synth.Cell(B=96, sizes=(40, 56), U=12, n_sc=7, K=5, snr_db=5.0), dict(impl="plain"), "plain"),
+    ("plain_u40", synth.Cell(B=160, sizes=(80, 80), U=40, n_sc=5, K=3, snr_db=10.0), dict(), "plain"),
+]
+
+
+@pytest.mark.parametrize("which", ["tau", "power", "both"])
+@pytest.mark.parametrize("name,cell,prm,route", ROUTES, ids=[r[0] for r in ROUTES])
+def test_fd_per_cluster(torch, ctx, pc, name, cell, prm, route, which):
+    H, s = synth.make_cell(cell, seed=50)
+    tau_c, power_c = _variants(cell.C, 51)
+    kw = dict(tau_c=tau_c if which != "power" else None, power_c=power_c if which != "tau" else None)
+    print("fd per-cluster", name, which, flush=True)
+    x, w, st = ctx.fd(_dev(torch, H), _dev(torch, s), cell.kappa, cell.sizes, "wf", pc.params(**prm, **kw))
+    torch.cuda.synchronize()
+    assert ctx.last_impl == route
+    xo, wo, so = oracle.fd(H, s, cell.kappa, cell.sizes, power=_budget(kw["power_c"]),
+                           **{k: (None if v is None else v.astype(np.float64)) for k, v in kw.items()})
+    assert ((st.cpu().numpy() & 1) == so).all()
+    assert _vec_err(x.cpu().numpy(), xo).max() <= TOL
+    assert (np.abs(w.cpu().numpy() - wo) <= TOL * wo).all()
+
+
+def test_fd_frame_api_per_cluster(torch, ctx, pc):
+    cell = synth.Cell(B=128, sizes=(32, 32, 64), U=8, n_sc=10, K=6, snr_db=8.0)
+    H, s = synth.make_cell(cell, seed=52)
+    tau_c, power_c = _variants(cell.C, 53)
+    Hd, sd = _dev(torch, H), _dev(torch, s)
+    fr = ctx.frame("fd", Hd, cell.kappa, cell.sizes, "wf", pc.params(tau_c=tau_c, power_c=power_c))
+    xs = [fr.symbols(sd[k0:k0 + 3].contiguous()) for k0 in (0, 3)]
+    w, st = fr.factors()
+    torch.cuda.synchronize()
+    x = torch.cat(xs, 0).cpu().numpy()
+    fr.release()
+    xo, wo, so = oracle.fd(H, s, cell.kappa, cell.sizes, tau_c=tau_c.astype(np.float64),
+                           power_c=power_c.astype(np.float64), power=_budget(power_c))
+    assert _vec_err(x, xo).max() <= TOL
+    assert (np.abs(w.cpu().numpy().reshape(wo.shape) - wo) <= TOL * wo).all()
+
+
+def test_uniform_variants_are_bitwise_default(torch, ctx, pc):
+    """tau_c = tau and rho_c^2 = rho^2 / C for every cluster (C = 8, where
+    both are exact) reproduce the default call bit for bit."""
+    cell = synth.Cell(B=256, sizes=(32,) * 8, U=8, n_sc=20, K=14, snr_db=10.0)
+    H, s = synth.make_cell(cell, seed=54)
+    Hd, sd = _dev(torch, H), _dev(torch, s)
+    x0, w0, s0 = ctx.fd(Hd, sd, cell.kappa, cell.sizes, "wf", pc.params())
+    x1, w1, s1 = ctx.fd(Hd, sd, cell.kappa, cell.sizes, "wf",
+                        pc.params(tau_c=[0.125] * 8, power_c=[0.125] * 8))
+    torch.cuda.synchronize()
+    assert torch.equal(x0, x1) and torch.equal(w0, w1) and torch.equal(s0, s1)
+
+
+@pytest.mark.parametrize("sizes", [(32, 32), (37, 63), (256,)])
+def test_mrt_per_cluster_power(torch, ctx, pc, sizes):
+    cell = synth.Cell(B=sum(sizes), sizes=sizes, U=16, n_sc=9, K=5)
+    H, s = synth.make_cell(cell, seed=55)
+    _, power_c = _variants(cell.C, 56, power=1.5)
+    x, w, st = ctx.mrt(_dev(torch, H), _dev(torch, s), sizes, pc.params(power=1.5, power_c=power_c))
+    torch.cuda.synchronize()
+    xo, wo, so = oracle.mrt(H, s, sizes, power=1.5, power_c=power_c.astype(np.float64))
+    assert _vec_err(x.cpu().numpy(), xo).max() <= TOL
+    assert (np.abs(w.cpu().numpy() - wo) <= TOL * wo).all()
+
+
+def test_per_cluster_validation(torch, ctx, pc):
+    cell = synth.Cell(B=64, sizes=(32, 32), U=8, n_sc=2, K=1)
+    H, s = synth.make_cell(cell, seed=57)
+    Hd, sd = _dev(torch, H), _dev(torch, s)
+    for bad in (dict(power_c=[0.5, 0.6]), dict(power_c=[1.0, 0.0]), dict(tau_c=[0.1, -1.0])):
+        with pytest.raises(pc.PrecodeError) as ei:
+            ctx.fd(Hd, sd, cell.kappa, cell.sizes, "wf", pc.params(**bad))
+        assert ei.value.code == -1
+    big = synth.Cell(B=130, sizes=(2,) * 65, U=1, n_sc=1, K=1)
+    Hb, sb = synth.make_cell(big, seed=58)
+    with pytest.raises(pc.PrecodeError) as ei:
+        ctx.fd(_dev(torch, Hb), _dev(torch, sb), big.kappa, big.sizes, "wf", pc.params(tau_c=[0.1] * 65))
+    assert ei.value.code == -2
