@@ -303,12 +303,92 @@ def main():
             "default_route_value": n_sc * K / (ms_fd * 1e-3),
             "plain_fp64_route_ms_per_step": ms_fd_plain64, "fp64_route_speedup_vs_plain": ms_fd_plain64 / ms_fd,
         }
+    if not args.quick:
+        out["comparison"] = comparison_leg(ctx, pc, Hs, Ss, Xs, cell, dev, time_graph, args)
     if not args.quick and not args.no_serving:
         out["serving"] = serving_leg(ctx, pc, Hs, Ss, cell, dev, args)
     if not args.no_cpu:
         out["cpu_baseline"], out["rel_err"] = cpu_baseline(cell, Hs[0], Ss[0], Xs[0], betas[0], ctx, pc, stream,
                                                            (HEAD_PREC, "fp32", "split_bf16"))
     print(json.dumps(out), flush=True)
+
+
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+
+
+def central_flops(B, U, K):
+    """Real flops per subcarrier of centralized WF in the B x B form: the
+    lower triangle of M = H H^H (4 B^2 U), its Cholesky (4 B^3 / 3), the
+    forward and back substitution with U right-hand sides (8 B^2 U) and the
+    precode Q s (8 K B U); one complex multiply-add counts 8."""
+    return 4 * B * B * U + 4 * B ** 3 / 3 + 8 * B * B * U + 8 * K * B * U
+
+
+def comparison_leg(ctx, pc, Hs, Ss, Xs, cell, dev, time_graph, args):
+    """The comparison precoders and the UE side of the BER link at the
+    headline shape, each on graph replay over the rotating frames."""
+    import torch
+
+    import synth
+    from paper_1804_10987_amd import ber
+
+    n_sc, B, U, K, sizes = cell.n_sc, cell.B, cell.U, cell.K, list(cell.sizes)
+    nf = len(Hs)
+    steps = max(8, args.steps // 8)
+    beta = torch.empty(n_sc, dtype=torch.float32, device=dev)
+    st = torch.empty(n_sc, dtype=torch.int32, device=dev)
+    w = torch.empty(n_sc * len(sizes), dtype=torch.float32, device=dev)
+    wst = torch.empty(n_sc * len(sizes), dtype=torch.int32, device=dev)
+    cur = torch.cuda.current_stream
+
+    def central(f):
+        ctx.central(Hs[f], Ss[f], cell.kappa, x=Xs[f], beta=beta, status=st, stream=cur())
+
+    def mrt(f):
+        ctx.mrt(Hs[f], Ss[f], sizes, x=Xs[f], weights=w, status=wst, stream=cur())
+
+    noise = torch.zeros((K, n_sc, U), dtype=torch.complex64, device=dev)
+    y = torch.empty((K, n_sc, U), dtype=torch.complex64, device=dev)
+
+    def receive(f):
+        pc.ue_receive(Hs[f], Xs[f], noise, 0.1, beta, s_hat=y, stream=cur())
+
+    out = {}
+    ms_c, _ = time_graph(central, max(4, steps // 4), 2)
+    fl = central_flops(B, U, K) * n_sc
+    out["central_wf_bxb"] = {
+        "ms_per_frame": ms_c, "value": n_sc * K / (ms_c * 1e-3),
+        "roofline": {"bound": "alu", "achieved": fl / (ms_c * 1e-3) / 1e12, "peak": FP32_VECTOR_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": fl / (ms_c * 1e-3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS,
+                     "flops_per_frame": fl},
+        "note": "Theorem 1's B x B form: FP32 tiled Cholesky of M = H H^H + kappa I_B per subcarrier"}
+    ms_m, _ = time_graph(mrt, steps, 3)
+    by = algorithmic_bytes(B, U, K, n_sc)
+    out["mrt"] = {"ms_per_frame": ms_m, "value": n_sc * K / (ms_m * 1e-3),
+                  "roofline": {"bound": "hbm", "achieved": by / (ms_m * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                               "unit": "GB/s", "frac": by / (ms_m * 1e-3) / 1e9 / HBM_PEAK_GBS}}
+    ms_r, _ = time_graph(receive, steps, 3)
+    by_r = 8 * n_sc * (B * U + K * B + 2 * K * U)
+    out["ue_receive"] = {"ms_per_frame": ms_r,
+                         "roofline": {"bound": "hbm", "achieved": by_r / (ms_r * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                                      "unit": "GB/s", "frac": by_r / (ms_r * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                      "bytes_per_frame": by_r}}
+    # one whole PD link frame (QAM map, precode, receive, decisions, count), eager
+    lcell = cell.with_(qam=64, snr_db=0.0)
+    H, lab, wn = synth.device_link_frame(lcell, dev, seed=7, frame=0)
+    count = torch.zeros(1, dtype=torch.int64, device=dev)
+    for _ in range(2):
+        ber.frame_errors(ctx, "pd", H, lab, wn, lcell.snr_db, lcell.qam, sizes, count=count)
+    torch.cuda.synchronize()
+    reps = 10
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ber.frame_errors(ctx, "pd", H, lab, wn, lcell.snr_db, lcell.qam, sizes, count=count)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    out["ber_link_pd"] = {"ms_per_frame": dt * 1e3, "bits_per_s": n_sc * K * U * 6 / dt,
+                          "note": "64-QAM, eager host calls (map, precode, receive, count) per frame"}
+    return out
 
 
 SYMBOL_PERIOD_S = 1e-3 / 14  # LTE: 14 OFDM symbols per 1 ms subframe

@@ -126,6 +126,11 @@ def load() -> ctypes.CDLL:
         if not os.path.exists(LIB_PATH):
             raise ImportError("libprecode.so is not built; run `python -m paper_1804_10987_amd.build` "
                               "(the HIP library is required: there is no fallback)")
+        # torch ships its own HIP runtime: load it first, so that this library
+        # binds to the same runtime as the tensors it is handed (whichever
+        # libamdhip64 a process loads first serves both)
+        import torch  # noqa: F401
+
         lib = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(lib, name)

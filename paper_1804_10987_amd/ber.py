@@ -30,9 +30,10 @@ def _pilots(torch, n_sc, U, device):
 
 
 def precode(ctx: Context, scheme: str, H, s, kappa: float, sizes, mode="wf", tau=0.125, power=1.0, Es=1.0,
-            precision="fp32", stream=None):
-    """x of one precoder, with its own factor (beta, or None for FD / MRT)."""
-    prm = params(power=power, Es=Es, tau=tau, precision=precision)
+            precision="fp32", stream=None, tau_c=None, power_c=None):
+    """x of one precoder, with its own factor (beta, or None for FD / MRT).
+    tau_c / power_c: per-cluster tau_c and budgets rho_c^2 (FD, MRT)."""
+    prm = params(power=power, Es=Es, tau=tau, precision=precision, tau_c=tau_c, power_c=power_c)
     if scheme == "pd":
         x, beta, _ = ctx.pd(H, s, kappa, sizes, mode, prm, stream=stream)
         return x, beta
@@ -43,14 +44,14 @@ def precode(ctx: Context, scheme: str, H, s, kappa: float, sizes, mode="wf", tau
         x, beta, _ = ctx.central(H, s, kappa, params(power=power, Es=Es), stream=stream)
         return x, beta
     if scheme == "mrt":
-        x, _, _ = ctx.mrt(H, s, sizes, params(power=power, Es=Es), stream=stream)
+        x, _, _ = ctx.mrt(H, s, sizes, params(power=power, Es=Es, power_c=power_c), stream=stream)
         return x, None
     raise ValueError("scheme must be one of %s" % (SCHEMES,))
 
 
 def frame_errors(ctx: Context, scheme: str, H, labels, noise, snr_db: float, order: int, sizes, mode="wf",
                  tau=0.125, power=1.0, Es=1.0, precision="fp32", joint=False, count=None, labels_out=None,
-                 stream=None):
+                 stream=None, tau_c=None, power_c=None):
     """Bit errors of one frame, added to the device counter `count` (created if
     None).  joint=True uses the pilot-measured joint factor for every scheme.
     Returns (count, s_hat, ue_scale)."""
@@ -60,10 +61,10 @@ def frame_errors(ctx: Context, scheme: str, H, labels, noise, snr_db: float, ord
     N0 = noise_var(snr_db, power)
     kappa = U * N0 / power
     s = qam_map(labels, order, stream=stream)
-    x, scale = precode(ctx, scheme, H, s, kappa, sizes, mode, tau, power, Es, precision, stream)
+    x, scale = precode(ctx, scheme, H, s, kappa, sizes, mode, tau, power, Es, precision, stream, tau_c, power_c)
     if scale is None or joint:
         xp, _ = precode(ctx, scheme, H, _pilots(torch, n_sc, U, H.device), kappa, sizes, mode, tau, power, Es,
-                        precision, stream)
+                        precision, stream, tau_c, power_c)
         scale = ue_gain(ue_receive(H, xp, stream=stream), N0, Es, stream=stream)
     s_hat = ue_receive(H, x, noise, N0, scale, stream=stream)
     count, _ = qam_errors(s_hat, labels, order, count=count, labels_out=labels_out, stream=stream)
@@ -71,9 +72,10 @@ def frame_errors(ctx: Context, scheme: str, H, labels, noise, snr_db: float, ord
 
 
 def ber(ctx: Context, scheme: str, cell, snr_db: float, frames: int, seed: int = 0, tau=0.125, power=1.0,
-        precision="fp32", joint=False) -> float:
+        precision="fp32", joint=False, tau_c=None, power_c=None) -> float:
     """Uncoded BER of a scheme on `frames` seeded device-drawn frames of a cell
-    (synth.device_link_frame), counted on the device."""
+    (synth.device_link_frame), counted on the device.  The same seed gives
+    every scheme the same channels, symbols and noise."""
     import torch
 
     import synth
@@ -82,6 +84,80 @@ def ber(ctx: Context, scheme: str, cell, snr_db: float, frames: int, seed: int =
     for f in range(frames):
         H, lab, w = synth.device_link_frame(cell, "cuda", seed, f)
         frame_errors(ctx, scheme, H, lab, w, snr_db, cell.qam, cell.sizes, "wf", tau, power, 1.0, precision, joint,
-                     count=count)
+                     count=count, tau_c=tau_c, power_c=power_c)
     bits = frames * cell.K * cell.n_sc * cell.U * int(math.log2(cell.qam))
     return int(count.item()) / bits
+
+
+# The antenna configurations of the paper's BER figures (Sec. III-D): B = 256
+# as C = 2, 4, 8 clusters, and clusters of 32 with B = 64, 128, 256; U = 16,
+# 64-QAM, i.i.d. Rayleigh.
+FIGURE_CONFIGS = [(256, (128, 128)), (256, (64,) * 4), (256, (32,) * 8), (64, (32, 32)), (128, (32,) * 4)]
+
+
+def _cell(B, sizes, n_sc, U=16, qam=64):
+    import synth
+
+    return synth.Cell(B=B, sizes=tuple(sizes), U=U, n_sc=n_sc, K=14, qam=qam)
+
+
+def main(argv=None):
+    """Uncoded-BER experiments on the GPU; prints one JSON line per point.
+
+    --sweep snr    every scheme on FIGURE_CONFIGS over an SNR range
+    --sweep tau    FD over tau_c (the same for every cluster) at one SNR
+    --sweep power  FD and MRT with uneven clusters under per-cluster budgets:
+                   equal (rho^2 / C), proportional to B_c, and to sqrt(B_c)
+    """
+    import argparse
+    import json
+    import time
+
+    ap = argparse.ArgumentParser(prog="python -m paper_1804_10987_amd.ber")
+    ap.add_argument("--sweep", choices=("snr", "tau", "power"), default="snr")
+    ap.add_argument("--snr", type=float, nargs="*", default=None)
+    ap.add_argument("--frames", type=int, default=4)
+    ap.add_argument("--n-sc", type=int, default=300)
+    ap.add_argument("--seed", type=int, default=1)
+    a = ap.parse_args(argv)
+    ctx = Context(0)
+    t0 = time.time()
+
+    def emit(**kw):
+        kw["elapsed_s"] = round(time.time() - t0, 2)
+        print(json.dumps(kw), flush=True)
+
+    bits = lambda c: a.frames * c.K * c.n_sc * c.U * 6  # noqa: E731
+    if a.sweep == "snr":
+        snrs = a.snr if a.snr else [-4.0, -2.0, 0.0, 2.0, 4.0, 6.0, 8.0, 10.0, 12.0]
+        for B, sizes in FIGURE_CONFIGS:
+            c = _cell(B, sizes, a.n_sc)
+            for snr in snrs:
+                row = {s_: ber(ctx, s_, c, snr, a.frames, a.seed) for s_ in SCHEMES}
+                emit(sweep="snr", B=B, C=len(sizes), Bc=sizes[0], U=c.U, qam=64, snr_db=snr, bits=bits(c), ber=row)
+    elif a.sweep == "tau":
+        snr = a.snr[0] if a.snr else 0.0
+        for B, sizes in FIGURE_CONFIGS:
+            c = _cell(B, sizes, a.n_sc)
+            ref = ber(ctx, "pd", c, snr, a.frames, a.seed)
+            row = {str(t): ber(ctx, "fd", c, snr, a.frames, a.seed, tau=t)
+                   for t in (1 / 64, 1 / 32, 1 / 16, 1 / 8, 1 / 4, 1 / 2, 1.0)}
+            emit(sweep="tau", B=B, C=len(sizes), Bc=sizes[0], snr_db=snr, bits=bits(c), pd=ref, fd_by_tau=row)
+    else:
+        snr = a.snr[0] if a.snr else 0.0
+        for sizes in ((16, 48, 64, 128), (32, 32, 64, 128), (8, 24, 96, 128)):
+            B = sum(sizes)
+            c = _cell(B, sizes, a.n_sc)
+            bc = [float(v) for v in sizes]
+            shares = {"equal": [1.0] * len(sizes), "prop_Bc": bc, "prop_sqrt_Bc": [v ** 0.5 for v in bc]}
+            row = {}
+            for name, sh in shares.items():
+                pw = [v / sum(sh) for v in sh]
+                row[name] = {"fd": ber(ctx, "fd", c, snr, a.frames, a.seed, power_c=pw),
+                             "mrt": ber(ctx, "mrt", c, snr, a.frames, a.seed, power_c=pw)}
+            emit(sweep="power", B=B, sizes=list(sizes), snr_db=snr, bits=bits(c),
+                 pd=ber(ctx, "pd", c, snr, a.frames, a.seed), by_allocation=row)
+
+
+if __name__ == "__main__":
+    main()

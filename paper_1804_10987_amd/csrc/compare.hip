@@ -361,33 +361,52 @@ __global__ void __launch_bounds__(kCenThreads) central_k(Cen c, const float2 *__
     }
 }
 
-// MRT: row norms, per-cluster weights, then x = w_c H_c s per row.
+// MRT, one workgroup per subcarrier: row norms, per-cluster weights, then
+// thread b forms x_k[b] = w_c sum_u H[b][u] s_k[u] for every symbol.  STAGE:
+// the subcarrier's channel is copied to LDS once with coalesced loads (rows
+// padded to U + 1 entries against bank conflicts), so HBM sees it once;
+// otherwise each thread reads its rows from global memory twice.
+constexpr size_t kMrtStageLds = 64 * 1024;
+
+__host__ __device__ inline size_t mrt_lds(int B, int U, int C, bool stage) {
+    const size_t head = ((size_t)(B + C) * sizeof(float) + 15) & ~(size_t)15;
+    return head + (stage ? (size_t)B * (U + 1) * sizeof(float2) : 0);
+}
+
+template <bool STAGE>
 __global__ void __launch_bounds__(256) mrt_k(Prob p, const float2 *__restrict__ H, const float2 *__restrict__ s,
                                             float2 *__restrict__ x, float *__restrict__ wgt,
                                             int *__restrict__ status) {
-    extern __shared__ float smem_mrt[];
-    const int *off = (const int *)((const char *)__builtin_amdgcn_kernarg_segment_ptr() + offsetof(Prob, off));
-    float *rn = smem_mrt;          // [B] row norms
-    float *cw = smem_mrt + p.B;    // [C] cluster weights
+    extern __shared__ float4 smem_mrt[];
+    const Prob *pk = (const Prob *)__builtin_amdgcn_kernarg_segment_ptr();  // p: the first argument
     const int n = blockIdx.x, tid = threadIdx.x;
-    const int B = p.B, U = p.U, C = p.C;
+    const int B = p.B, U = p.U, C = p.C, ru = STAGE ? U + 1 : U;
+    float *rn = (float *)smem_mrt;  // [B] row norms
+    float *cw = rn + B;             // [C] cluster weights
+    float2 *Hl = (float2 *)((char *)smem_mrt + mrt_lds(B, U, C, false));  // [B][U + 1]
     const float2 *Hn = H + (size_t)n * B * U;
+    if constexpr (STAGE) {
+        for (int e = tid; e < B * U; e += 256) {
+            const int b = e / U;
+            Hl[b * ru + (e - b * U)] = Hn[e];
+        }
+        __syncthreads();
+    }
+    const float2 *rows = STAGE ? Hl : Hn;
     for (int b = tid; b < B; b += 256) {
         float f = 0.f;
         for (int u = 0; u < U; ++u) {
-            const float2 h = Hn[(size_t)b * U + u];
+            const float2 h = rows[(size_t)b * ru + u];
             f = fmaf(h.x, h.x, fmaf(h.y, h.y, f));
         }
         rn[b] = f;
     }
     __syncthreads();
-    const Prob *pk = (const Prob *)__builtin_amdgcn_kernarg_segment_ptr();  // p: the first argument
     for (int cl = tid; cl < C; cl += 256) {
-        const float rho_c2 = fd_power_c(pk, cl);
         float f = 0.f;
-        for (int b = off[cl]; b < off[cl + 1]; ++b) f += rn[b];
+        for (int b = pk->off[cl]; b < pk->off[cl + 1]; ++b) f += rn[b];
         const bool bad = !(f > 0.f) || !(f - f == 0.f);
-        const float w = bad ? 0.f : sqrtf(rho_c2 / (f * p.Es));
+        const float w = bad ? 0.f : sqrtf(fd_power_c(pk, cl) / (f * p.Es));
         cw[cl] = w;
         if (wgt) wgt[(size_t)n * C + cl] = w;
         if (status) status[(size_t)n * C + cl] = bad ? PRECODE_ST_FAIL : PRECODE_ST_OK;
@@ -397,10 +416,10 @@ __global__ void __launch_bounds__(256) mrt_k(Prob p, const float2 *__restrict__ 
         int lo = 0, hi = C - 1;  // cluster of row b: off[lo] <= b < off[lo + 1]
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if (off[mid] <= b) lo = mid; else hi = mid - 1;
+            if (pk->off[mid] <= b) lo = mid; else hi = mid - 1;
         }
         const float w = cw[lo];
-        const float2 *hb = Hn + (size_t)b * U;
+        const float2 *hb = rows + (size_t)b * ru;
         for (int k = 0; k < p.K; ++k) {
             const float2 *sk = s + ((size_t)k * p.n_sc + n) * U;
             float2 acc = make_float2(0.f, 0.f);
@@ -450,8 +469,12 @@ hipError_t central_run(int B, int U, int n_sc, int K, float kappa, float Es, flo
 hipError_t mrt_run(const Prob &p, const float2 *H, const float2 *s, float2 *x, float *wgt, int *status,
                    hipStream_t st) {
     if (p.n_sc == 0) return hipSuccess;
-    const size_t lds = (size_t)(p.B + p.C) * sizeof(float);
-    hipLaunchKernelGGL(mrt_k, dim3(p.n_sc), dim3(256), lds, st, p, H, s, x, wgt, status);
+    const bool stage = mrt_lds(p.B, p.U, p.C, true) <= kMrtStageLds;
+    const size_t lds = mrt_lds(p.B, p.U, p.C, stage);
+    if (stage)
+        hipLaunchKernelGGL(mrt_k<true>, dim3(p.n_sc), dim3(256), lds, st, p, H, s, x, wgt, status);
+    else
+        hipLaunchKernelGGL(mrt_k<false>, dim3(p.n_sc), dim3(256), lds, st, p, H, s, x, wgt, status);
     return hipGetLastError();
 }
 
