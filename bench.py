@@ -73,7 +73,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--quick", action="store_true", help="headline path only (for profiling)")
+    ap.add_argument("--quick", action="store_true", help="headline launches only (for profiling)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--cell", type=int, default=2, choices=(2, 3),
                     help="2: the headline cell (B=256 as 8x32, U=16, 1200 subcarriers); 3: B=512 as 16x32, U=32, "
@@ -260,7 +260,7 @@ def main():
                     "note": "one host call per frame; includes host enqueue time"},
     }
     variants = {}
-    for prec in ("fp32", "split_bf16"):
+    for prec in (() if args.quick else ("fp32", "split_bf16")):
         ms_v, _ = time_graph(lambda f, prec=prec: pd_fused(f, prec), args.steps, args.warmup)
         variants[prec] = {"ms_per_step": ms_v, "value": n_sc * K / (ms_v * 1e-3),
                           "achieved_gbs": frame_bytes / (ms_v * 1e-3) / 1e9, "waves_per_workgroup": ctx.last_waves}
@@ -277,11 +277,11 @@ def main():
                                          "throughput over the timed region"}
     # every launch shape the autotuner chooses from, forced
     shapes = {}
-    for nw in (1, 2, 4):
+    for nw in (() if args.quick else (1, 2, 4)):
         os.environ["PRECODE_FUSED_WAVES"] = str(nw)
         ms_s, _ = time_graph(pd_fused, max(16, args.steps // 4), 3)
         shapes[str(nw)] = {"ms_per_step": ms_s, "used": ctx.last_waves}
-    del os.environ["PRECODE_FUSED_WAVES"]
+    os.environ.pop("PRECODE_FUSED_WAVES", None)
     out["pd_launch_shapes"] = shapes
     if not args.quick:
         steps2 = max(10, args.steps // 4)
