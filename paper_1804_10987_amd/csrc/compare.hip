@@ -361,45 +361,53 @@ __global__ void __launch_bounds__(kCenThreads) central_k(Cen c, const float2 *__
     }
 }
 
-// MRT, one workgroup per subcarrier: row norms, per-cluster weights, then
-// thread b forms x_k[b] = w_c sum_u H[b][u] s_k[u] for every symbol.  STAGE:
-// the subcarrier's channel is copied to LDS once with coalesced loads (rows
-// padded to U + 1 entries against bank conflicts), so HBM sees it once;
-// otherwise each thread reads its rows from global memory twice.
-constexpr size_t kMrtStageLds = 64 * 1024;
+// MRT, one workgroup per subcarrier, in two passes over chunks of antenna
+// rows staged in LDS with coalesced loads (rows padded to U + 1 entries
+// against bank conflicts): row norms, then per-cluster weights, then the
+// outputs x_k[b] = w_c sum_u H[b][u] s_k[u] with consecutive threads on
+// consecutive rows of one symbol (coalesced stores).  ONE: the subcarrier's
+// channel fits one chunk, staged once for both passes (HBM sees it once);
+// otherwise each chunk is staged again for the second pass.
+constexpr size_t kMrtChunkLds = 48 * 1024;
 
-__host__ __device__ inline size_t mrt_lds(int B, int U, int C, bool stage) {
-    const size_t head = ((size_t)(B + C) * sizeof(float) + 15) & ~(size_t)15;
-    return head + (stage ? (size_t)B * (U + 1) * sizeof(float2) : 0);
+__host__ __device__ inline int mrt_chunk_rows(int B, int U) {
+    const int r = (int)(kMrtChunkLds / ((size_t)(U + 1) * sizeof(float2)));
+    return r < B ? r : B;
 }
+__host__ __device__ inline size_t mrt_head(int B, int C) { return ((size_t)(B + C) * sizeof(float) + 15) & ~(size_t)15; }
 
-template <bool STAGE>
+template <bool ONE>
 __global__ void __launch_bounds__(256) mrt_k(Prob p, const float2 *__restrict__ H, const float2 *__restrict__ s,
                                             float2 *__restrict__ x, float *__restrict__ wgt,
                                             int *__restrict__ status) {
     extern __shared__ float4 smem_mrt[];
     const Prob *pk = (const Prob *)__builtin_amdgcn_kernarg_segment_ptr();  // p: the first argument
     const int n = blockIdx.x, tid = threadIdx.x;
-    const int B = p.B, U = p.U, C = p.C, ru = STAGE ? U + 1 : U;
+    const int B = p.B, U = p.U, C = p.C, K = p.K, ru = U + 1;
+    const int R = mrt_chunk_rows(B, U);
     float *rn = (float *)smem_mrt;  // [B] row norms
     float *cw = rn + B;             // [C] cluster weights
-    float2 *Hl = (float2 *)((char *)smem_mrt + mrt_lds(B, U, C, false));  // [B][U + 1]
+    float2 *Hl = (float2 *)((char *)smem_mrt + mrt_head(B, C));  // [R][U + 1]
     const float2 *Hn = H + (size_t)n * B * U;
-    if constexpr (STAGE) {
-        for (int e = tid; e < B * U; e += 256) {
+    auto stage = [&](int b0, int nb) {
+        __syncthreads();  // the previous chunk is consumed
+        for (int e = tid; e < nb * U; e += 256) {
             const int b = e / U;
-            Hl[b * ru + (e - b * U)] = Hn[e];
+            Hl[b * ru + (e - b * U)] = Hn[(size_t)b0 * U + e];
         }
         __syncthreads();
-    }
-    const float2 *rows = STAGE ? Hl : Hn;
-    for (int b = tid; b < B; b += 256) {
-        float f = 0.f;
-        for (int u = 0; u < U; ++u) {
-            const float2 h = rows[(size_t)b * ru + u];
-            f = fmaf(h.x, h.x, fmaf(h.y, h.y, f));
+    };
+    for (int b0 = 0; b0 < B; b0 += R) {
+        const int nb = min(R, B - b0);
+        if (!ONE || b0 == 0) stage(b0, nb);
+        for (int b = tid; b < nb; b += 256) {
+            float f = 0.f;
+            for (int u = 0; u < U; ++u) {
+                const float2 h = Hl[b * ru + u];
+                f = fmaf(h.x, h.x, fmaf(h.y, h.y, f));
+            }
+            rn[b0 + b] = f;
         }
-        rn[b] = f;
     }
     __syncthreads();
     for (int cl = tid; cl < C; cl += 256) {
@@ -412,19 +420,22 @@ __global__ void __launch_bounds__(256) mrt_k(Prob p, const float2 *__restrict__ 
         if (status) status[(size_t)n * C + cl] = bad ? PRECODE_ST_FAIL : PRECODE_ST_OK;
     }
     __syncthreads();
-    for (int b = tid; b < B; b += 256) {
-        int lo = 0, hi = C - 1;  // cluster of row b: off[lo] <= b < off[lo + 1]
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (pk->off[mid] <= b) lo = mid; else hi = mid - 1;
-        }
-        const float w = cw[lo];
-        const float2 *hb = rows + (size_t)b * ru;
-        for (int k = 0; k < p.K; ++k) {
+    for (int b0 = 0; b0 < B; b0 += R) {
+        const int nb = min(R, B - b0);
+        if (!ONE) stage(b0, nb);
+        for (int o = tid; o < nb * K; o += 256) {
+            const int k = o / nb, b = o - k * nb;
+            int lo = 0, hi = C - 1;  // cluster of row b0 + b: off[lo] <= b0 + b < off[lo + 1]
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (pk->off[mid] <= b0 + b) lo = mid; else hi = mid - 1;
+            }
             const float2 *sk = s + ((size_t)k * p.n_sc + n) * U;
+            const float2 *hb = Hl + b * ru;
             float2 acc = make_float2(0.f, 0.f);
             for (int u = 0; u < U; ++u) acc = mac(acc, hb[u], sk[u]);
-            x[((size_t)k * p.n_sc + n) * B + b] = make_float2(acc.x * w, acc.y * w);
+            const float w = cw[lo];
+            x[((size_t)k * p.n_sc + n) * B + b0 + b] = make_float2(acc.x * w, acc.y * w);
         }
     }
 }
@@ -469,9 +480,14 @@ hipError_t central_run(int B, int U, int n_sc, int K, float kappa, float Es, flo
 hipError_t mrt_run(const Prob &p, const float2 *H, const float2 *s, float2 *x, float *wgt, int *status,
                    hipStream_t st) {
     if (p.n_sc == 0) return hipSuccess;
-    const bool stage = mrt_lds(p.B, p.U, p.C, true) <= kMrtStageLds;
-    const size_t lds = mrt_lds(p.B, p.U, p.C, stage);
-    if (stage)
+    const int R = mrt_chunk_rows(p.B, p.U);
+    const size_t lds = mrt_head(p.B, p.C) + (size_t)R * (p.U + 1) * sizeof(float2);
+    if (lds > 64 * 1024) {
+        const void *fn = R == p.B ? (const void *)mrt_k<true> : (const void *)mrt_k<false>;
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    if (R == p.B)
         hipLaunchKernelGGL(mrt_k<true>, dim3(p.n_sc), dim3(256), lds, st, p, H, s, x, wgt, status);
     else
         hipLaunchKernelGGL(mrt_k<false>, dim3(p.n_sc), dim3(256), lds, st, p, H, s, x, wgt, status);

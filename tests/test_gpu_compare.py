@@ -162,6 +162,7 @@ MRT = [
     ("eight", synth.Cell(B=256, sizes=(32,) * 8, U=16, n_sc=20, K=14)),
     ("central", synth.Cell(B=256, sizes=(256,), U=16, n_sc=7, K=3)),
     ("u64", synth.Cell(B=128, sizes=(64, 64), U=64, n_sc=5, K=2)),
+    ("b300u40_chunks", synth.Cell(B=300, sizes=(100, 200), U=40, n_sc=4, K=3)),  # 3 row chunks, ragged tail
 ]
 
 
