@@ -83,19 +83,31 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
     return __builtin_bit_cast(double, (unsigned long long)lo | ((unsigned long long)hi << 32));
 }
 
-// Stages a register tile (precode layout: lane (j, g) holds row j, users
-// g UP/2 ..) in LDS as [row][upos(user)] complex64; rows >= nrows and users
-// >= U are zero.
+// Stages rows [row0, row0 + nr) of a local system (U users; its rows are one
+// contiguous block of complex64 in HBM) in LDS as [row][upos(user)], rows
+// >= nr and users >= U zero: entry e = lane + 64 i of the 32 x UP tile is
+// loaded by lane e % 64, so each load instruction reads consecutive
+// addresses; every load is issued (from a clamped in-range address) before
+// the first LDS write.
 template <int UP>
-__device__ __forceinline__ void stage_rows(const Tile<UP, kF32> &tl, int nrows, int U, float2 *rowsL) {
+__device__ __forceinline__ void stage_rows_direct(const float2 *__restrict__ Hn, int U, int row0, int nr,
+                                                  float2 *rowsL) {
+    constexpr int PER = 32 * UP / 64;
     const int lane = lane_id();
-    const int j = lane & 31, g = lane >> 5;
-    const bool live = j < nrows;
+    const float2 *src = Hn + (size_t)row0 * U;
+    const int last = nr * U - 1;
+    float2 v[PER];
 #pragma unroll
-    for (int m2 = 0; m2 < UP / 2; ++m2) {
-        const int u = g * (UP / 2) + m2;
-        const bool in = live && u < U;
-        rowsL[j * UP + upos<UP>(u)] = in ? make_float2(tl.f[2 * m2], tl.f[2 * m2 + 1]) : make_float2(0.f, 0.f);
+    for (int i = 0; i < PER; ++i) {
+        const int e = lane + 64 * i, row = e / UP, u = e % UP;
+        const int g = row * U + u;
+        v[i] = src[g < last ? g : last];
+    }
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int e = lane + 64 * i, row = e / UP, u = e % UP;
+        const bool in = row < nr && u < U;
+        rowsL[row * UP + upos<UP>(u)] = in ? v[i] : make_float2(0.f, 0.f);
     }
 }
 

@@ -10,7 +10,8 @@
 // row groups, NS = UP / R slots), in FP64.
 //
 //   Gram      G_c = H_c^H H_c in FP64 on the VALU, straight into the register
-//             layout: each tile is staged in LDS as complex64 with its users
+//             layout: each 32-row tile is staged in LDS as complex64 with
+//             coalesced loads of the system's contiguous rows, its users
 //             permuted so that the NS users a lane multiplies are contiguous;
 //             complex64 products are exact in FP64
 //   invert    A_c = G_c + kappa_c I (scaled by a power of two, as the FP32
@@ -126,9 +127,7 @@ __device__ __forceinline__ void f64_system(const Prob &p, const Prob *__restrict
 #pragma unroll
     for (int q = 0; q < NT; ++q) {
         if (32 * q < nrows) {
-            Tile<UP, kF32> tq;
-            load_tile<UP, kF32, false>(Hn, U, r0 + 32 * q, min(32, nrows - 32 * q), tq);
-            stage_rows<UP>(tq, nrows - 32 * q, U, rowsL);
+            stage_rows_direct<UP>(Hn, U, r0 + 32 * q, min(32, nrows - 32 * q), rowsL);
             wave_sync();
             gram_rows<UP>(rowsL, gre, gim);
             wave_sync();  // the staging area is rewritten by the next tile and the symbols

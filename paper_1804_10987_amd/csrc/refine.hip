@@ -101,9 +101,7 @@ __device__ __forceinline__ void refine_system(const Prob &p, const Prob *__restr
 #pragma unroll
     for (int q = 0; q < NS; ++q) are[q] = aim[q] = 0.0;
     for (int t = 0; t < ntile; ++t) {
-        Tile<UP, kF32> tq;
-        load_tile<UP, kF32, false>(Hn, U, r0 + 32 * t, min(32, nrows - 32 * t), tq);
-        stage_rows<UP>(tq, nrows - 32 * t, U, rowsL);
+        stage_rows_direct<UP>(Hn, U, r0 + 32 * t, min(32, nrows - 32 * t), rowsL);
         wave_sync();
         gram_rows<UP>(rowsL, are, aim);
         wave_sync();
