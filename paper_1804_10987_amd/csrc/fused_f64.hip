@@ -9,11 +9,12 @@
 // (lane / UP, lane % UP) holds column c of rows s R + r, s < NS (R = 64 / UP
 // row groups, NS = UP / R slots), in FP64.
 //
-//   Gram      G_c = H_c^H H_c in FP64 on the VALU, straight into the register
-//             layout: each 32-row tile is staged in LDS as complex64 with
-//             coalesced loads of the system's contiguous rows, its users
-//             permuted so that the NS users a lane multiplies are contiguous;
-//             complex64 products are exact in FP64
+//   Gram      G_c = H_c^H H_c in FP64, straight into the register layout:
+//             at 16 users on FP64 MFMA from coalesced loads (gram_mfma16);
+//             at 32 on the VALU from each 32-row tile staged in LDS as
+//             complex64 (coalesced loads of the system's contiguous rows, its
+//             users permuted so that the NS users a lane multiplies are
+//             contiguous); complex64 products are exact in FP64
 //   invert    A_c = G_c + kappa_c I (scaled by a power of two, as the FP32
 //             inversion) inverted by Gauss-Jordan without pivoting (Hermitian
 //             positive definite).  Before step k the matrix is
@@ -40,6 +41,48 @@ namespace pc {
 namespace {
 
 constexpr int kF64Waves = 4;
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// G = H_c^H H_c of a system with at most 16 users and 32 NT rows on FP64
+// MFMA (v_mfma_f64_16x16x4f64, four rows per step).  A[i][k] and B[k][j] both
+// come from lane j + 16 k (i, j: users; k: row), so every lane feeds its own
+// entry h = H[row0 + 4 s + lane / 16][lane % 16] to both operands:
+//   Re G += Re h^T Re h + Im h^T Im h,   Im G += Re h^T Im h - Im h^T Re h
+// (conj(h_i) h_j).  D[i][j] lands in lane (i % 4, j), register i / 4: the
+// inversion's register layout (slot q = i / 4 of row group r = i % 4).  Each
+// lane converts two floats per four rows; the loads (consecutive addresses
+// for U = 16) are all issued first, from clamped in-range addresses.
+template <int NT>
+__device__ __forceinline__ void gram_mfma16(const float2 *__restrict__ Hn, int U, int row0, int nrows,
+                                            double (&gre)[4], double (&gim)[4]) {
+    constexpr int STEPS = 8 * NT;
+    const int lane = lane_id();
+    const int kr = lane >> 4, u = lane & 15;
+    const float2 *src = Hn + (size_t)row0 * U;
+    float2 h[STEPS];
+#pragma unroll
+    for (int st = 0; st < STEPS; ++st) {
+        const int row = 4 * st + kr;
+        h[st] = src[row < nrows && u < U ? row * U + u : 0];
+    }
+    f64x4 are = {0.0, 0.0, 0.0, 0.0}, aim = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int st = 0; st < STEPS; ++st) {
+        // masked at the use, so that no select waits on a load in flight
+        const bool in = 4 * st + kr < nrows && u < U;
+        const double hr = in ? h[st].x : 0.0, hi = in ? h[st].y : 0.0;
+        are = __builtin_amdgcn_mfma_f64_16x16x4f64(hr, hr, are, 0, 0, 0);
+        are = __builtin_amdgcn_mfma_f64_16x16x4f64(hi, hi, are, 0, 0, 0);
+        aim = __builtin_amdgcn_mfma_f64_16x16x4f64(hr, hi, aim, 0, 0, 0);
+        aim = __builtin_amdgcn_mfma_f64_16x16x4f64(-hi, hr, aim, 0, 0, 0);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        gre[q] = are[q];
+        gim[q] = aim[q];
+    }
+}
 
 // Gauss-Jordan inversion in FP64 of the system in registers (rows / columns
 // >= m hold the identity).  Step k: the lanes of row k's group write row k to
@@ -122,15 +165,19 @@ __device__ __forceinline__ void f64_system(const Prob &p, const Prob *__restrict
     // Gram in FP64, tile by tile through the staged rows (no tile is held in
     // registers across the inversion: the precode loads the rows again)
     double gre[NS], gim[NS];
+    if constexpr (UP == 16) {
+        gram_mfma16<NT>(Hn, U, r0, nrows, gre, gim);
+    } else {
 #pragma unroll
-    for (int q = 0; q < NS; ++q) gre[q] = gim[q] = 0.0;
+        for (int q = 0; q < NS; ++q) gre[q] = gim[q] = 0.0;
 #pragma unroll
-    for (int q = 0; q < NT; ++q) {
-        if (32 * q < nrows) {
-            stage_rows_direct<UP>(Hn, U, r0 + 32 * q, min(32, nrows - 32 * q), rowsL);
-            wave_sync();
-            gram_rows<UP>(rowsL, gre, gim);
-            wave_sync();  // the staging area is rewritten by the next tile and the symbols
+        for (int q = 0; q < NT; ++q) {
+            if (32 * q < nrows) {
+                stage_rows_direct<UP>(Hn, U, r0 + 32 * q, min(32, nrows - 32 * q), rowsL);
+                wave_sync();
+                gram_rows<UP>(rowsL, gre, gim);
+                wave_sync();  // the staging area is rewritten by the next tile and the symbols
+            }
         }
     }
     // the first symbol chunk, in flight during the inversion
