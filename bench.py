@@ -61,6 +61,13 @@ def measured_traffic():
     return int(fields["traffic_bytes_per_launch"]), fields.get("traffic_kernel", "").strip()
 
 
+def variant_params(pc, name):
+    """Call parameters of a precision variant name: "<precision>" or
+    "<precision>+refine1" (one fused FP64-residual refinement step)."""
+    prec, _, ref = name.partition("+refine")
+    return pc.params(precision=prec, impl="fused", refine_steps=int(ref) if ref else 0)
+
+
 def algorithmic_bytes(B, U, K, n_sc):
     """HBM bytes the method must move per frame: the channel once, the symbols
     and the precoded vectors once (complex64)."""
@@ -192,7 +199,7 @@ def main():
         return t0.elapsed_time(t1) / steps, steps
 
     def pd_fused(f, prec=HEAD_PREC):
-        ctx.pd(Hs[f], Ss[f], cell.kappa, sizes, "wf", pc.params(precision=prec, impl="fused"),
+        ctx.pd(Hs[f], Ss[f], cell.kappa, sizes, "wf", variant_params(pc, prec),
                x=Xs[f], beta=betas[f], status=stats[f], stream=torch.cuda.current_stream())
 
     def pd_plain(f):
@@ -260,7 +267,7 @@ def main():
                     "note": "one host call per frame; includes host enqueue time"},
     }
     variants = {}
-    for prec in (() if args.quick else ("fp32", "split_bf16")):
+    for prec in (() if args.quick else ("fp32", "split_bf16", "split_fp16+refine1", "split_bf16+refine1")):
         ms_v, _ = time_graph(lambda f, prec=prec: pd_fused(f, prec), args.steps, args.warmup)
         variants[prec] = {"ms_per_step": ms_v, "value": n_sc * K / (ms_v * 1e-3),
                           "achieved_gbs": frame_bytes / (ms_v * 1e-3) / 1e9, "waves_per_workgroup": ctx.last_waves}
@@ -309,7 +316,8 @@ def main():
         out["serving"] = serving_leg(ctx, pc, Hs, Ss, cell, dev, args)
     if not args.no_cpu:
         out["cpu_baseline"], out["rel_err"] = cpu_baseline(cell, Hs[0], Ss[0], Xs[0], betas[0], ctx, pc, stream,
-                                                           (HEAD_PREC, "fp32", "split_bf16"))
+                                                           (HEAD_PREC, "fp32", "split_bf16", "split_fp16+refine1",
+                                                            "split_bf16+refine1"))
     print(json.dumps(out), flush=True)
 
 
@@ -490,8 +498,7 @@ def cpu_baseline(cell, Hd, sd, xd, bd, ctx, pc, stream, precs):
     H, s = synth.make_cell(cell, seed=0, frame=0)
     gpu = {}
     for prec in precs:
-        ctx.pd(Hd, sd, cell.kappa, list(cell.sizes), "wf", pc.params(precision=prec, impl="fused"), x=xd, beta=bd,
-               stream=stream)
+        ctx.pd(Hd, sd, cell.kappa, list(cell.sizes), "wf", variant_params(pc, prec), x=xd, beta=bd, stream=stream)
         torch.cuda.synchronize()
         gpu[prec] = (xd.cpu().numpy(), bd.cpu().numpy())
     threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()

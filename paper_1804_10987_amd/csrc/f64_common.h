@@ -111,6 +111,49 @@ __device__ __forceinline__ void stage_rows_direct(const float2 *__restrict__ Hn,
     }
 }
 
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// G += H^H H over rows [row0, row0 + nrows) (nrows <= 32 NT) of a system
+// with at most 16 users, on FP64 MFMA (v_mfma_f64_16x16x4f64, four rows per
+// step).  A[i][k] and B[k][j] both
+// come from lane j + 16 k (i, j: users; k: row), so every lane feeds its own
+// entry h = H[row0 + 4 s + lane / 16][lane % 16] to both operands:
+//   Re G += Re h^T Re h + Im h^T Im h,   Im G += Re h^T Im h - Im h^T Re h
+// (conj(h_i) h_j).  D[i][j] lands in lane (i % 4, j), register i / 4: the
+// inversion's register layout (slot q = i / 4 of row group r = i % 4).  Each
+// lane converts two floats per four rows; the loads (consecutive addresses
+// for U = 16) are all issued first, from clamped in-range addresses.
+template <int NT>
+__device__ __forceinline__ void gram_mfma16(const float2 *__restrict__ Hn, int U, int row0, int nrows,
+                                            double (&gre)[4], double (&gim)[4]) {
+    constexpr int STEPS = 8 * NT;
+    const int lane = lane_id();
+    const int kr = lane >> 4, u = lane & 15;
+    const float2 *src = Hn + (size_t)row0 * U;
+    float2 h[STEPS];
+#pragma unroll
+    for (int st = 0; st < STEPS; ++st) {
+        const int row = 4 * st + kr;
+        h[st] = src[row < nrows && u < U ? row * U + u : 0];
+    }
+    f64x4 are = {gre[0], gre[1], gre[2], gre[3]}, aim = {gim[0], gim[1], gim[2], gim[3]};
+#pragma unroll
+    for (int st = 0; st < STEPS; ++st) {
+        // masked at the use, so that no select waits on a load in flight
+        const bool in = 4 * st + kr < nrows && u < U;
+        const double hr = in ? h[st].x : 0.0, hi = in ? h[st].y : 0.0;
+        are = __builtin_amdgcn_mfma_f64_16x16x4f64(hr, hr, are, 0, 0, 0);
+        are = __builtin_amdgcn_mfma_f64_16x16x4f64(hi, hi, are, 0, 0, 0);
+        aim = __builtin_amdgcn_mfma_f64_16x16x4f64(hr, hi, aim, 0, 0, 0);
+        aim = __builtin_amdgcn_mfma_f64_16x16x4f64(-hi, hr, aim, 0, 0, 0);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        gre[q] = are[q];
+        gim[q] = aim[q];
+    }
+}
+
 // G[s R + r][c] += sum over the staged tile's 32 rows of conj(h_{s R + r}) h_c.
 template <int UP>
 __device__ __forceinline__ void gram_rows(const float2 *rowsL, double (&gre)[F64L<UP>::NS],

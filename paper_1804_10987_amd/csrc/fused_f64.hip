@@ -42,48 +42,6 @@ namespace {
 
 constexpr int kF64Waves = 4;
 
-typedef double f64x4 __attribute__((ext_vector_type(4)));
-
-// G = H_c^H H_c of a system with at most 16 users and 32 NT rows on FP64
-// MFMA (v_mfma_f64_16x16x4f64, four rows per step).  A[i][k] and B[k][j] both
-// come from lane j + 16 k (i, j: users; k: row), so every lane feeds its own
-// entry h = H[row0 + 4 s + lane / 16][lane % 16] to both operands:
-//   Re G += Re h^T Re h + Im h^T Im h,   Im G += Re h^T Im h - Im h^T Re h
-// (conj(h_i) h_j).  D[i][j] lands in lane (i % 4, j), register i / 4: the
-// inversion's register layout (slot q = i / 4 of row group r = i % 4).  Each
-// lane converts two floats per four rows; the loads (consecutive addresses
-// for U = 16) are all issued first, from clamped in-range addresses.
-template <int NT>
-__device__ __forceinline__ void gram_mfma16(const float2 *__restrict__ Hn, int U, int row0, int nrows,
-                                            double (&gre)[4], double (&gim)[4]) {
-    constexpr int STEPS = 8 * NT;
-    const int lane = lane_id();
-    const int kr = lane >> 4, u = lane & 15;
-    const float2 *src = Hn + (size_t)row0 * U;
-    float2 h[STEPS];
-#pragma unroll
-    for (int st = 0; st < STEPS; ++st) {
-        const int row = 4 * st + kr;
-        h[st] = src[row < nrows && u < U ? row * U + u : 0];
-    }
-    f64x4 are = {0.0, 0.0, 0.0, 0.0}, aim = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int st = 0; st < STEPS; ++st) {
-        // masked at the use, so that no select waits on a load in flight
-        const bool in = 4 * st + kr < nrows && u < U;
-        const double hr = in ? h[st].x : 0.0, hi = in ? h[st].y : 0.0;
-        are = __builtin_amdgcn_mfma_f64_16x16x4f64(hr, hr, are, 0, 0, 0);
-        are = __builtin_amdgcn_mfma_f64_16x16x4f64(hi, hi, are, 0, 0, 0);
-        aim = __builtin_amdgcn_mfma_f64_16x16x4f64(hr, hi, aim, 0, 0, 0);
-        aim = __builtin_amdgcn_mfma_f64_16x16x4f64(-hi, hr, aim, 0, 0, 0);
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        gre[q] = are[q];
-        gim[q] = aim[q];
-    }
-}
-
 // Gauss-Jordan inversion in FP64 of the system in registers (rows / columns
 // >= m hold the identity).  Step k: the lanes of row k's group write row k to
 // LDS (as [upos(c)] complex FP64), every lane reads its column's entry (the
@@ -165,11 +123,11 @@ __device__ __forceinline__ void f64_system(const Prob &p, const Prob *__restrict
     // Gram in FP64, tile by tile through the staged rows (no tile is held in
     // registers across the inversion: the precode loads the rows again)
     double gre[NS], gim[NS];
+#pragma unroll
+    for (int q = 0; q < NS; ++q) gre[q] = gim[q] = 0.0;
     if constexpr (UP == 16) {
         gram_mfma16<NT>(Hn, U, r0, nrows, gre, gim);
     } else {
-#pragma unroll
-        for (int q = 0; q < NS; ++q) gre[q] = gim[q] = 0.0;
 #pragma unroll
         for (int q = 0; q < NT; ++q) {
             if (32 * q < nrows) {

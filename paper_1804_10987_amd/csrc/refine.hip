@@ -101,10 +101,14 @@ __device__ __forceinline__ void refine_system(const Prob &p, const Prob *__restr
 #pragma unroll
     for (int q = 0; q < NS; ++q) are[q] = aim[q] = 0.0;
     for (int t = 0; t < ntile; ++t) {
-        stage_rows_direct<UP>(Hn, U, r0 + 32 * t, min(32, nrows - 32 * t), rowsL);
-        wave_sync();
-        gram_rows<UP>(rowsL, are, aim);
-        wave_sync();
+        if constexpr (UP == 16) {
+            gram_mfma16<1>(Hn, U, r0 + 32 * t, min(32, nrows - 32 * t), are, aim);  // FP64 MFMA
+        } else {
+            stage_rows_direct<UP>(Hn, U, r0 + 32 * t, min(32, nrows - 32 * t), rowsL);
+            wave_sync();
+            gram_rows<UP>(rowsL, are, aim);
+            wave_sync();
+        }
     }
 #pragma unroll
     for (int q = 0; q < NS; ++q)
