@@ -82,6 +82,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--quick", action="store_true", help="headline launches only (for profiling)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-batch", action="store_true", help="skip the heterogeneous batch leg")
     ap.add_argument("--cell", type=int, default=2, choices=(2, 3),
                     help="2: the headline cell (B=256 as 8x32, U=16, 1200 subcarriers); 3: B=512 as 16x32, U=32, "
                          "3300 subcarriers, correlated channel (for profiling; the headline line is cell 2)")
@@ -312,6 +313,8 @@ def main():
         }
     if not args.quick:
         out["comparison"] = comparison_leg(ctx, pc, Hs, Ss, Xs, cell, dev, time_graph, args)
+    if not args.quick and not args.no_batch:
+        out["batch_mix"] = batch_mix_leg(ctx, pc, dev, args)
     if not args.quick and not args.no_serving:
         out["serving"] = serving_leg(ctx, pc, Hs, Ss, cell, dev, args)
     if not args.no_cpu:
@@ -454,6 +457,72 @@ def serving_leg(ctx, pc, Hs, Ss, cell, dev, args):
     p = run(mjobs, arr, "plain", slab_gib=64)
     res["mix"] = {"cells": len(cells), "rate": "2000/s", "slab_gib": 64, "pd_fd": "alternating", "fused": f, "plain": p,
                   "p99_plain_over_fused": p["p99_us"] / f["p99_us"]}
+    return res
+
+
+def batch_mix_leg(ctx, pc, dev, args):
+    """The heterogeneous batch: 64 cells of the mix (B in 64..512, clusters of
+    16/32/64 antennas or uneven, U in 4..64, 300/1200/3300 subcarriers, 14
+    symbols, PD and FD alternating), channels and symbols drawn on the device,
+    as one batch plan (a HIP graph: register-tile classes, one-wave FP64 and
+    wide FP64 launches) replayed, against the plain kernels (one call per
+    cell, recorded into one graph)."""
+    import torch
+
+    import synth
+
+    res = {}
+    for uneven in (False, True):
+        cells = synth.mix(64, seed=0, uneven=uneven)
+        jobs = []
+        for i, c in enumerate(cells):
+            H, s = synth.device_cell(c, dev, seed=21, cell_id=i)
+            jobs.append(dict(arch="pd" if i % 2 == 0 else "fd", mode="wf", H=H, s=s, rho=c.kappa, sizes=c.sizes))
+        units = sum(c.n_sc * c.K for c in cells)
+        plan = ctx.batch_plan(jobs)
+        plan.launch()
+        torch.cuda.synchronize()
+        reps = 5
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for _ in range(reps):
+            plan.launch()
+        t1.record()
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1) / reps
+        fused_jobs, launches = plan.fused_jobs, plan.launches
+        xs = [o[0] for o in plan.outputs]
+
+        def plain_call(i):
+            j = jobs[i]
+            fn = ctx.pd if j["arch"] == "pd" else ctx.fd
+            fn(j["H"], j["s"], j["rho"], j["sizes"], "wf", pc.params(impl="plain"), x=xs[i])
+
+        for i in range(len(jobs)):  # grows the plain workspace outside the capture
+            plain_call(i)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        cs = torch.cuda.Stream()
+        with torch.cuda.graph(g, stream=cs):
+            for i in range(len(jobs)):
+                plain_call(i)
+        g.replay()
+        torch.cuda.synchronize()
+        t0.record()
+        g.replay()
+        t1.record()
+        torch.cuda.synchronize()
+        ms_plain = t0.elapsed_time(t1)
+        res["uneven" if uneven else "even"] = {
+            "cells": len(cells), "subcarrier_symbols": units, "fused_jobs": fused_jobs, "launches": launches,
+            "ms_per_batch": ms, "value": units / (ms * 1e-3),
+            "plain_ms_per_batch": ms_plain, "speedup_vs_plain": ms_plain / ms,
+            "hbm_gb": sum(8 * c.n_sc * (c.B * c.U + c.K * (c.U + c.B)) for c in cells) / 1e9}
+        plan.destroy()
+        del plan, jobs, xs, g
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    res["precision"] = "fp32 (register tiles); FP64 on the one-wave and wide FP64 kernels"
     return res
 
 

@@ -78,6 +78,13 @@ enum precode_prec {
 };
 enum precode_impl {
     PRECODE_IMPL_AUTO = 0,  /* fused single-launch kernel where supported, else plain */
+                            /* (with K >= 1 every shape has one: the register-tile   */
+                            /* kernels for U <= 32 on the FP32 route, the one-wave   */
+                            /* FP64 kernel for FP64-route systems with U <= 32 and   */
+                            /* U <= B_eff <= 64, else a wide FP64 kernel, one        */
+                            /* workgroup per local system of order <= 64, that takes */
+                            /* U in 33..64, FD clusters with B_c < U, mixed routes   */
+                            /* and precision FP64, its systems flagged FP64)         */
     PRECODE_IMPL_FUSED = 1, /* fused kernel; PRECODE_EUNSUPPORTED if the shape is not */
     PRECODE_IMPL_PLAIN = 2  /* separate plain FP32/FP64 kernels (no MFMA, no fusion)  */
 };
@@ -310,17 +317,24 @@ int precode_frame_release(precode_ctx *ctx, precode_frame *frame);
  * subcarrier independence across cells).  Every job is described by one
  * precode_job; pointers are device pointers with the layouts above and the
  * outputs are those of precode_pd / precode_fd for the same job.
- *   - jobs the fused kernel takes (U <= 32, no FP64 route, FD clusters with
- *     B_c >= U) run as ONE launch per kernel shape class (tile width U <= 16
- *     or U <= 32, times the channel tiles a wave keeps in registers: 1, 2,
- *     4, 8 or streamed, times the load width), PD and FD jobs together: at
- *     most 18 launches however many jobs there are;
- *   - the remaining jobs run on the plain kernels after them, on `stream`.
+ *   - jobs the register-tile kernels take (U <= 32, no FP64 route, FD
+ *     clusters with B_c >= U) run as ONE launch per kernel shape class (tile
+ *     width U <= 16 or U <= 32, times the channel tiles a wave keeps in
+ *     registers: 1, 2, 4 or streamed, times the load width), PD and FD jobs
+ *     together;
+ *   - jobs whose every local system takes the FP64 route with U <= 32 and
+ *     U <= B_eff <= 64 run on the one-wave FP64 kernel, one launch per job;
+ *   - every other job with K >= 1 (U in 33..64, FD clusters with B_c < U,
+ *     mixed routes, larger FP64-route systems, precision FP64) runs on the
+ *     wide FP64 kernel: one launch per system-order class (<= 32, <= 64)
+ *     for all such jobs, every local system flagged PRECODE_ST_FP64;
+ *   - the remaining jobs (K = 0) run on the plain kernels after them, on
+ *     `stream`.
  * The whole batch is validated before anything is enqueued (first error
- * returned).  With SPLIT precision every job must be fused-capable
- * (PRECODE_EUNSUPPORTED otherwise).  The slice table is staged through a
- * pinned host buffer of the context; a call may wait on the host for the
- * previous call's table copy.
+ * returned).  With SPLIT precision every job must take one of the fused
+ * kernels (PRECODE_EUNSUPPORTED otherwise); jobs on the FP64 kernels compute
+ * in FP64.  The slice table is staged through a pinned host buffer of the
+ * context; a call may wait on the host for the previous call's table copy.
  * ------------------------------------------------------------------------- */
 typedef struct precode_job {
     int arch;                 /* enum precode_arch                         */
@@ -346,13 +360,15 @@ int precode_batch(precode_ctx *ctx, const precode_job *jobs, int n_jobs,
  * the context's budget) and instantiates the graph; every pointer in `jobs`
  * is baked in and must stay valid, with the same shapes, until destroy.
  * launch enqueues one replay on `stream` (asynchronous, no allocation, no
- * host copy).  launches returns the kernel launches one replay holds.
- * destroy synchronizes the device and frees the plan. */
+ * host copy).  launches returns the kernel launches one replay holds;
+ * fused_jobs the jobs (with n_sc > 0) it runs on the fused kernels rather
+ * than the plain ones.  destroy synchronizes the device and frees the plan. */
 typedef struct precode_batch_plan precode_batch_plan;
 int precode_batch_plan_create(precode_ctx *ctx, const precode_job *jobs, int n_jobs,
                               int precision, precode_batch_plan **out);
 int precode_batch_plan_launch(precode_batch_plan *plan, void *stream);
 int precode_batch_plan_launches(const precode_batch_plan *plan);
+int precode_batch_plan_fused_jobs(const precode_batch_plan *plan);
 int precode_batch_plan_destroy(precode_batch_plan *plan);
 
 /* ---------------------------------------------------------------------------

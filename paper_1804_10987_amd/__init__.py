@@ -342,6 +342,11 @@ class BatchPlan:
     def launches(self):
         return _lib.load().precode_batch_plan_launches(self.handle)
 
+    @property
+    def fused_jobs(self):
+        """Jobs with n_sc > 0 the plan runs on the fused kernels."""
+        return _lib.load().precode_batch_plan_fused_jobs(self.handle)
+
     def launch(self, stream=None):
         _lib.check(_lib.load().precode_batch_plan_launch(self.handle, _stream(stream)), "precode_batch_plan_launch")
 

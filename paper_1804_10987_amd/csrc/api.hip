@@ -67,6 +67,7 @@ struct precode_batch_plan {
     hipGraph_t graph;
     hipGraphExec_t exec;
     int launches;
+    int fused_jobs;  // jobs with n_sc > 0 on the fused kernels
 };
 
 namespace {
@@ -243,10 +244,14 @@ int classify(const precode_job *jobs, int n_jobs, int precision, std::vector<Bat
         if (j.n_sc == 0) continue;
         if (!j.H || (j.K > 0 && (!j.s || !j.x))) return PRECODE_EINVAL;
         if (!aligned8(j.H) || !aligned8(j.s) || !aligned8(j.x)) return PRECODE_EINVAL;
-        const bool fuse = j.K > 0 && fused_supported(p, precision);
-        if (!fuse && (precision == PRECODE_PREC_SPLIT_FP16 || precision == PRECODE_PREC_SPLIT_BF16))
+        // register tiles, else the one-wave FP64 kernel, else the wide FP64 kernel
+        int kind = -1;
+        if (j.K > 0 && fused_supported(p, precision)) kind = kBatchTile;
+        else if (fused_f64_supported(p, precision, j.K)) kind = kBatchF64;
+        else if (wide_supported(p, j.K)) kind = kBatchWide;
+        if (kind < 0 && (precision == PRECODE_PREC_SPLIT_FP16 || precision == PRECODE_PREC_SPLIT_BF16))
             return PRECODE_EUNSUPPORTED;
-        if (fuse) {
+        if (kind >= 0) {
             BatchProblem b;
             b.p = p;
             b.H = (const float2 *)j.H;
@@ -254,6 +259,7 @@ int classify(const precode_job *jobs, int n_jobs, int precision, std::vector<Bat
             b.x = (float2 *)j.x;
             b.scale_out = j.scale;
             b.status = j.status;
+            b.kind = kind;
             fused->push_back(b);
         } else {
             plain->push_back(std::make_pair(i, p));
@@ -296,9 +302,13 @@ int run(precode_ctx *ctx, int arch, const void *H, const void *s, float rho, con
     // the FP64 route fused (its Gram, inversion and solve in FP64) when every
     // local system takes it and fits; its FP64 solve needs no refinement step
     const bool can_f64 = !can_fuse && !can_refine && fused_f64_supported(p, q.precision, K);
-    if (q.impl == PRECODE_IMPL_FUSED && !can_fuse && !can_f64 && !can_refine) return PRECODE_EUNSUPPORTED;
+    // everything else with U <= 64 on the wide FP64 kernel (its FP64 solve
+    // needs no refinement step either)
+    const bool can_wide = !can_fuse && !can_refine && !can_f64 && wide_supported(p, K);
+    const bool any_fused = can_fuse || can_refine || can_f64 || can_wide;
+    if (q.impl == PRECODE_IMPL_FUSED && !any_fused) return PRECODE_EUNSUPPORTED;
     if (q.precision == PRECODE_PREC_SPLIT_FP16 || q.precision == PRECODE_PREC_SPLIT_BF16) {
-        if (!can_fuse && !can_f64 && !can_refine) return PRECODE_EUNSUPPORTED;
+        if (!any_fused) return PRECODE_EUNSUPPORTED;
     }
     const bool fixed = fixed_ws != nullptr;
     // no launch-shape timing on a fixed workspace (it would create events)
@@ -333,6 +343,14 @@ int run(precode_ctx *ctx, int arch, const void *H, const void *s, float rho, con
     }
     if (q.impl != PRECODE_IMPL_PLAIN && can_f64) {
         rc = dev_err(fused_f64_run(p, (const float2 *)H, (const float2 *)s, (float2 *)x, scale, status, st));
+        if (rc == PRECODE_OK) {
+            ctx->last_impl = PRECODE_IMPL_FUSED;
+            ctx->last_waves = 4;
+        }
+        return rc;
+    }
+    if (q.impl != PRECODE_IMPL_PLAIN && can_wide) {
+        rc = dev_err(wide_run(p, (const float2 *)H, (const float2 *)s, (float2 *)x, scale, status, st));
         if (rc == PRECODE_OK) {
             ctx->last_impl = PRECODE_IMPL_FUSED;
             ctx->last_waves = 4;
@@ -681,6 +699,15 @@ int precode_batch(precode_ctx *ctx, const precode_job *jobs, int n_jobs, int pre
     if (rc) return rc;
     hipStream_t st = (hipStream_t)stream;
     const size_t bytes = fused.empty() ? 0 : fused_batch_table_bytes(fused.data(), (int)fused.size());
+    if (!fused.empty() && bytes == 0) {
+        // one-wave FP64 problems only: no table
+        if (hipSetDevice(ctx->device) != hipSuccess) return PRECODE_EDEVICE;
+        int nl = 0;
+        if (fused_batch_launch(fused.data(), (int)fused.size(), precision, nullptr, st, &nl) != hipSuccess)
+            return PRECODE_EDEVICE;
+        ctx->last_impl = PRECODE_IMPL_FUSED;
+        ctx->last_waves = fused_default_waves();
+    }
     if (bytes > 0) {
         if (hipSetDevice(ctx->device) != hipSuccess) return PRECODE_EDEVICE;
         if (!ctx->tabCopied) {
@@ -779,7 +806,7 @@ int precode_batch_plan_create(precode_ctx *ctx, const precode_job *jobs, int n_j
     if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return fail(PRECODE_EDEVICE);
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     int nl = 0;
-    if (e == hipSuccess && pl->tabBytes > 0)
+    if (e == hipSuccess && !fused.empty())
         e = fused_batch_launch(fused.data(), (int)fused.size(), precision, pl->tab, cs, &nl);
     for (size_t i = 0; e == hipSuccess && i < plain.size(); ++i) {
         if (run_plain(plain[i].second, jobs[plain[i].first], pl->wsA, pl->wsAinv, pl->wsScale, pl->wsZ, cs))
@@ -798,6 +825,8 @@ int precode_batch_plan_create(precode_ctx *ctx, const precode_job *jobs, int n_j
         return fail(PRECODE_EDEVICE);
     }
     pl->launches = nl;
+    for (const auto &b : fused)
+        if (b.p.n_sc > 0) ++pl->fused_jobs;
     *out = pl;
     return PRECODE_OK;
 }
@@ -809,6 +838,8 @@ int precode_batch_plan_launch(precode_batch_plan *plan, void *stream) {
 }
 
 int precode_batch_plan_launches(const precode_batch_plan *plan) { return plan ? plan->launches : 0; }
+
+int precode_batch_plan_fused_jobs(const precode_batch_plan *plan) { return plan ? plan->fused_jobs : 0; }
 
 int precode_batch_plan_destroy(precode_batch_plan *plan) {
     if (!plan) return PRECODE_EINVAL;

@@ -1,15 +1,16 @@
 // batch.hip -- heterogeneous batches of fused PD / FD problems (cells of
 // different B, cluster sizes, U and subcarrier counts) in as few launches as
-// the kernel's shape classes allow.
+// the kernels' shape classes allow.
 //
-// Problems are grouped by tile width UP (16 for U <= 16, 32 for U <= 32) and
-// channel tiles per wave held in registers (1, 2, 4 or streamed) and load
-// width (U == UP with an aligned channel, or not); each
-// group -- PD and FD problems alike -- is one launch whose grid is the sum of
-// its problems' workgroups (one wave per local system, NW systems per
-// workgroup).  The problem table sits in device memory; a workgroup finds its
-// problem by binary search over the problems' first block index and then runs
-// the same body as the single-problem kernel.
+// Register-tile problems are grouped by tile width UP (16 for U <= 16, 32
+// for U <= 32), channel tiles per wave held in registers (1, 2, 4 or
+// streamed) and load width (U == UP with an aligned channel, or not); wide
+// problems (wide.hip: U <= 64, B_c < U, FP64 route) by system order (32 or
+// 64).  Each group -- PD and FD problems alike -- is one launch whose grid is
+// the sum of its problems' workgroups.  The problem table sits in device
+// memory; a workgroup finds its problem by binary search over the problems'
+// first block index and then runs the same body as the single-problem kernel.
+// Problems of the one-wave FP64 kernel launch one by one.
 #include <string.h>
 
 #include <algorithm>
@@ -22,26 +23,25 @@ namespace {
 
 constexpr int NW = 4;  // waves per workgroup of the batch launches
 
-struct Entry {
-    Prob p;
-    const float2 *H, *s;
-    float2 *x;
-    float *scale_out;
-    int *status;
-    int K;       // symbols
-    int block0;  // first block of this problem within its class launch
-};
+using Entry = BatchEntry;
 
-// Launch class of a problem: tile width and register tiles per wave.
+// Launch class of a problem: wide or not, tile width (system order for
+// wide problems), register tiles per wave and load width.
 struct Class {
-    int up, maxt, vec;
-    bool operator==(const Class &o) const { return up == o.up && maxt == o.maxt && vec == o.vec; }
+    int wide, up, maxt, vec;
+    bool operator==(const Class &o) const { return wide == o.wide && up == o.up && maxt == o.maxt && vec == o.vec; }
     bool operator<(const Class &o) const {
+        if (wide != o.wide) return wide < o.wide;
         return up != o.up ? up < o.up : (maxt != o.maxt ? maxt < o.maxt : vec < o.vec);
     }
 };
 
-Class class_of(const BatchProblem &q) { return Class{pick_up(q.p.U), pick_maxt(q.p), pick_vec(q.p, q.H) ? 1 : 0}; }
+Class class_of(const BatchProblem &q) {
+    if (q.kind == kBatchWide) return Class{1, wide_order(q.p), 0, 0};
+    return Class{0, pick_up(q.p.U), pick_maxt(q.p), pick_vec(q.p, q.H) ? 1 : 0};
+}
+
+bool in_table(const BatchProblem &q) { return q.kind != kBatchF64; }
 
 // Problems in launch order (by class, then problem order).
 struct Plan {
@@ -52,12 +52,13 @@ struct Plan {
 };
 
 Plan make_plan(const BatchProblem *bp, int n) {
-    std::vector<int> order(n);
-    for (int i = 0; i < n; ++i) order[i] = i;
+    std::vector<int> order;
+    for (int i = 0; i < n; ++i)
+        if (in_table(bp[i])) order.push_back(i);
     std::stable_sort(order.begin(), order.end(),
                      [&](int a, int b) { return class_of(bp[a]) < class_of(bp[b]); });
     Plan pl;
-    for (int oi = 0; oi < n; ++oi) {
+    for (size_t oi = 0; oi < order.size(); ++oi) {
         const BatchProblem &q = bp[order[oi]];
         const Class c = class_of(q);
         if (pl.cls.empty() || !(pl.cls.back() == c)) {
@@ -75,7 +76,7 @@ Plan make_plan(const BatchProblem *bp, int n) {
         en.status = q.status;
         en.K = q.p.K;
         en.block0 = pl.blocks.back();
-        pl.blocks.back() += blocks_for(q.p, NW);
+        pl.blocks.back() += c.wide ? n_inst(q.p) : blocks_for(q.p, NW);
         pl.e.push_back(en);
     }
     pl.first.push_back((int)pl.e.size());
@@ -137,7 +138,7 @@ hipError_t launch_prec(int prec, int maxt, int vec, const Entry *tab, int n, int
 size_t fused_batch_table_bytes(const BatchProblem *bp, int n) {
     size_t cnt = 0;
     for (int i = 0; i < n; ++i)
-        if (bp[i].p.n_sc > 0) ++cnt;
+        if (in_table(bp[i]) && bp[i].p.n_sc > 0) ++cnt;
     return cnt * sizeof(Entry);
 }
 
@@ -156,8 +157,17 @@ hipError_t fused_batch_launch(const BatchProblem *bp, int n, int precision, cons
         const int f = pl.first[r], cnt = pl.first[r + 1] - f;
         if (cnt == 0) continue;
         const Class c = pl.cls[r];
-        const hipError_t e = c.up == 16 ? launch_prec<16>(prec, c.maxt, c.vec, tab + f, cnt, pl.blocks[r], st)
-                                        : launch_prec<32>(prec, c.maxt, c.vec, tab + f, cnt, pl.blocks[r], st);
+        hipError_t e;
+        if (c.wide) e = wide_batch_launch(c.up, tab + f, cnt, pl.blocks[r], st);
+        else if (c.up == 16) e = launch_prec<16>(prec, c.maxt, c.vec, tab + f, cnt, pl.blocks[r], st);
+        else e = launch_prec<32>(prec, c.maxt, c.vec, tab + f, cnt, pl.blocks[r], st);
+        if (e != hipSuccess) return e;
+        ++nl;
+    }
+    for (int i = 0; i < n; ++i) {
+        const BatchProblem &q = bp[i];
+        if (q.kind != kBatchF64 || q.p.n_sc == 0) continue;
+        const hipError_t e = fused_f64_run(q.p, q.H, q.s, q.x, q.scale_out, q.status, st);
         if (e != hipSuccess) return e;
         ++nl;
     }

@@ -164,17 +164,35 @@ size_t fused_refine_ws_bytes(const Prob &p);
 hipError_t fused_refine_run(const Prob &p, int precision, const float2 *H, const float2 *s, float2 *x,
                             float *scale_out, int *status, void *ws, hipStream_t st);
 
-// Heterogeneous batch of fused problems (batch.hip): every problem must be
-// fused_supported at `precision` with K >= 1.  The problems are grouped by
-// tile width (U <= 16 or U <= 32) and each group -- PD and FD alike -- runs as
-// one launch over all its local systems; a block finds its problem by binary
+// Heterogeneous batch of fused problems (batch.hip), each with K >= 1 and of
+// its kind: kBatchTile problems fused_supported at `precision`, kBatchWide
+// problems wide_supported, kBatchF64 problems fused_f64_supported.  Tile
+// problems are grouped by tile width (U <= 16 or U <= 32) and register tiles,
+// wide problems by system order; each group -- PD and FD alike -- runs as one
+// launch over all its local systems, a block finding its problem by binary
 // search in a table in device memory.
+// kind: kBatchTile (the register-tile classes), kBatchWide (the wide FP64
+// kernel, one launch per system order) or kBatchF64 (the one-wave FP64
+// kernel, one launch per problem, no table entry).
+enum BatchKind { kBatchTile = 0, kBatchWide = 1, kBatchF64 = 2 };
 struct BatchProblem {
     Prob p;
     const float2 *H, *s;
     float2 *x;
     float *scale_out;
     int *status;
+    int kind;
+};
+// One problem of a launch's device table: its systems are the launch's
+// blocks block0 .. (blocks of the next entry) - 1.
+struct BatchEntry {
+    Prob p;
+    const float2 *H, *s;
+    float2 *x;
+    float *scale_out;
+    int *status;
+    int K;       // symbols
+    int block0;  // first block of this problem within its launch
 };
 // Bytes of the device table fused_batch_launch reads.
 size_t fused_batch_table_bytes(const BatchProblem *bp, int n);
@@ -184,6 +202,16 @@ void fused_batch_fill(const BatchProblem *bp, int n, void *host);
 // what fused_batch_fill wrote); *launches receives the number of launches.
 hipError_t fused_batch_launch(const BatchProblem *bp, int n, int precision, const void *dev, hipStream_t st,
                               int *launches);
+
+// Local systems of order up to 64 in one FP64 launch (wide.hip): one
+// workgroup per system, U x U form (PD; FD with B_c >= U) or B_c x B_c form
+// (FD with B_c < U); every system flagged PRECODE_ST_FP64.  Needs K >= 1 and
+// U <= 64.  wide_order: the launch's system order bound (32 or 64).
+bool wide_supported(const Prob &p, int K);
+int wide_order(const Prob &p);
+hipError_t wide_run(const Prob &p, const float2 *H, const float2 *s, float2 *x, float *scale_out, int *status,
+                    hipStream_t st);
+hipError_t wide_batch_launch(int order, const BatchEntry *tab, int n, int blocks, hipStream_t st);
 
 // Comparison precoders (compare.hip).  Centralized WF in the B x B form of
 // Theorem 1: FP32, one workgroup per subcarrier, ws holds ws_bytes of

@@ -2,7 +2,8 @@
 regularization and the power-allocation footnote of Sec. III-C) through the
 C ABI, against the FP64 oracle, on every route an FD call can take: the
 fused FP32 / split kernels, the fused FP64 route, the fused refinement, the
-plain kernels (both Q_c forms), the frame API and MRT.
+wide FP64 kernel (both Q_c forms), the plain kernels (both Q_c forms), the
+frame API and MRT.
 """
 import numpy as np
 import pytest
@@ -69,9 +70,12 @@ ROUTES = [
     ("fused_fp64_route", synth.Cell(B=256, sizes=(32,) * 8, U=16, n_sc=12, K=14, snr_db=10.0), dict(), "fused"),
     ("fused_refine", synth.Cell(B=128, sizes=(32, 32, 64), U=8, n_sc=16, K=14, snr_db=8.0),
      dict(refine_steps=1, precision="split_bf16"), "fused"),
-    ("plain_small_clusters", synth.Cell(B=44, sizes=(4, 12, 8, 20), U=8, n_sc=9, K=6, snr_db=5.0), dict(), "plain"),
+    ("wide_small_clusters", synth.Cell(B=44, sizes=(4, 12, 8, 20), U=8, n_sc=9, K=6, snr_db=5.0), dict(), "fused"),
+    ("plain_small_clusters", synth.Cell(B=44, sizes=(4, 12, 8, 20), U=8, n_sc=9, K=6, snr_db=5.0),
+     dict(impl="plain"), "plain"),
     ("plain_forced", synth.Cell(B=96, sizes=(40, 56), U=12, n_sc=7, K=5, snr_db=5.0), dict(impl="plain"), "plain"),
-    ("plain_u40", synth.Cell(B=160, sizes=(80, 80), U=40, n_sc=5, K=3, snr_db=10.0), dict(), "plain"),
+    ("wide_u40", synth.Cell(B=160, sizes=(80, 80), U=40, n_sc=5, K=3, snr_db=10.0), dict(), "fused"),
+    ("plain_u40", synth.Cell(B=160, sizes=(80, 80), U=40, n_sc=5, K=3, snr_db=10.0), dict(impl="plain"), "plain"),
 ]
 
 

@@ -124,17 +124,24 @@ def test_power_and_params(torch, ctx, pc, arch):
         _check(xg, scg, stg, xo, sco, sto)
 
 
-def test_fd_small_clusters_auto(torch, ctx, pc):
+@pytest.mark.parametrize("impl", ["auto", "plain"])
+def test_fd_small_clusters_auto(torch, ctx, pc, impl):
     """FD with clusters smaller than U (B_c x B_c branch) and square clusters
-    (FP64 route by the default ratio 0.5)."""
+    (FP64 route by the default ratio 0.5): on the plain kernels each cluster
+    takes its own route; by default the whole cell runs on the wide FP64
+    kernel (every cluster flagged FP64)."""
     cell = synth.Cell(B=44, sizes=(4, 12, 8, 20), U=8, n_sc=9, K=6)
     H, s = synth.make_cell(cell, seed=5)
     for mode in ("wf", "zf"):
-        xg, scg, stg = _run(torch, ctx, pc, "fd", H, s, cell.kappa, cell.sizes, mode)
+        xg, scg, stg = _run(torch, ctx, pc, "fd", H, s, cell.kappa, cell.sizes, mode, impl=impl)
+        assert ctx.last_impl == ("plain" if impl == "plain" else "fused")
         xo, sco, sto = _oracle("fd", H, s, cell.kappa, cell.sizes, mode)
         _check(xg, scg, stg, xo, sco, sto)
-        # clusters with U / B_c >= 0.5 ran on the FP64 route
-        assert ((stg[:, [0, 1, 2]] & 2) == 2).all() and ((stg[:, 3] & 2) == 0).all()
+        if impl == "plain":
+            # clusters with U / B_c >= 0.5 ran on the FP64 route
+            assert ((stg[:, [0, 1, 2]] & 2) == 2).all() and ((stg[:, 3] & 2) == 0).all()
+        else:
+            assert ((stg & 2) == 2).all()
 
 
 def test_fp64_route_square(torch, ctx, pc):
@@ -187,7 +194,8 @@ def test_fd_fp64_route_fused(torch, ctx, pc, cell, mode):
 def test_pd_fp64_route_fused(torch, ctx, pc, cell, mode):
     """PD with U / B = 0.5 and B <= 64 (every subcarrier on the FP64 route)
     runs on the fused FP64 kernel, 17 symbols (two chunks): against the oracle
-    and the plain FP64 kernels; precision FP64 keeps the plain kernels."""
+    and the plain FP64 kernels; precision FP64 (precode in FP64 as well) runs
+    on the wide FP64 kernel."""
     H, s = synth.make_cell(cell, seed=13)
     xg, scg, stg = _run(torch, ctx, pc, "pd", H, s, cell.kappa, cell.sizes, mode)
     assert ctx.last_impl == "fused" and (stg == 2).all()
@@ -195,8 +203,9 @@ def test_pd_fp64_route_fused(torch, ctx, pc, cell, mode):
     _check(xg, scg, stg, xo, sco, sto)
     xp, scp, stp = _run(torch, ctx, pc, "pd", H, s, cell.kappa, cell.sizes, mode, impl="plain")
     assert (stp == stg).all() and _vec_err(xg, xp).max() <= TOL
-    _run(torch, ctx, pc, "pd", H, s, cell.kappa, cell.sizes, mode, precision="fp64")
-    assert ctx.last_impl == "plain"
+    xw, scw, stw = _run(torch, ctx, pc, "pd", H, s, cell.kappa, cell.sizes, mode, precision="fp64")
+    assert ctx.last_impl == "fused" and (stw == 2).all()
+    _check(xw, scw, stw, xo, sco, sto, tol=1e-6)
 
 
 def test_fd_fp64_route_fused_singular(torch, ctx, pc):
@@ -405,9 +414,10 @@ def test_untuned_default_shape(torch, ctx, pc, monkeypatch, u, expect):
     _check(xg, scg, stg, xo, sco, sto)
 
 
-# Mixed batch spanning every launch class and the plain fallback: tile widths
-# 16 / 32, PD / FD, 1..8 channel tiles per wave, symbol slicing (K > 64),
-# FD clusters smaller than U and U > 32 (plain kernels), an empty job.
+# Mixed batch spanning every launch class: tile widths 16 / 32, PD / FD,
+# 1..8 channel tiles per wave, symbol slicing (K > 64), FD clusters smaller
+# than U and U > 32 (wide FP64 kernel), FP64-route clusters (one-wave FP64
+# kernel), an empty job.
 MIX = [
     ("pd", synth.Cell(B=64, sizes=(32, 32), U=8, n_sc=10, K=14)),
     ("fd", synth.Cell(B=128, sizes=(64, 64), U=16, n_sc=7, K=9, snr_db=3.0)),
@@ -457,18 +467,23 @@ def test_batch_mixed_classes(torch, ctx, pc, monkeypatch):
 
 @pytest.mark.parametrize("prec,tol", [("split_fp16", 1e-5), ("split_bf16", 1e-3)])
 def test_batch_split_precision(torch, ctx, pc, prec, tol):
-    # fused-capable jobs only: U <= 32, no FP64 route (U / B_eff < 0.5), FD clusters with B_c >= U
-    cells = [mc for mc in MIX if mc[1].U <= 32 and mc[1].n_sc > 0 and
-             2 * mc[1].U < (mc[1].B if mc[0] == "pd" else min(mc[1].sizes))]
+    # every job with symbols runs on a fused kernel: the register tiles at the
+    # split precision, the FP64 kernels (FP64 route, U > 32, B_c < U) in FP64
+    cells = [mc for mc in MIX if mc[1].n_sc > 0]
     jobs, host = _mix_jobs(torch, cells, seed=60)
     outs = ctx.batch(jobs, precision=prec)
     torch.cuda.synchronize()
     for (x, sc, st), (arch, c, H, s) in zip(outs, host):
         xo, sco, sto = _oracle(arch, H, s, c.kappa, c.sizes, "wf")
-        _check(x.cpu().numpy(), sc.cpu().numpy().reshape(sco.shape), st.cpu().numpy().reshape(sto.shape),
-               xo, sco, sto, tol=tol)
-    with pytest.raises(pc.PrecodeError):  # a job only the plain kernels take
-        ctx.batch(_mix_jobs(torch, [MIX[7]])[0], precision=prec)
+        stg = st.cpu().numpy().reshape(sto.shape)
+        _check(x.cpu().numpy(), sc.cpu().numpy().reshape(sco.shape), stg, xo, sco, sto,
+               tol=1e-5 if (stg & 2).all() else tol)
+    # a job without symbols (factors only) needs the plain kernels
+    arch, c = MIX[0]
+    H, s = synth.make_cell(c, seed=61)
+    j0 = dict(arch=arch, mode="wf", H=_dev(torch, H), s=_dev(torch, s[:0]), rho=c.kappa, sizes=c.sizes)
+    with pytest.raises(pc.PrecodeError):
+        ctx.batch([j0], precision=prec)
 
 
 def test_batch_plan_graph_replays(torch, ctx, pc):

@@ -1,7 +1,7 @@
 """GPU: precode_pd_noalloc (no device allocation by the call) against
 precode_pd on the same inputs, through the C ABI: the fused refinement
-(its factors in the library's fixed array) and the plain kernels (U > 32,
-their workspace in that array), two calls in a row with the second smaller
+(its factors in the library's fixed array), the plain kernels (their
+workspace in that array) and the fused kernels without workspace, two calls in a row with the second smaller
 (the array keeps the first call's contents), and a call too large for the
 array rejected before anything runs."""
 import numpy as np
@@ -42,10 +42,12 @@ def _dev(torch, a):
 
 
 CASES = [
-    # (cell, params): fused refinement, plain kernels (U > 32), fused without workspace
+    # (cell, params): fused refinement, plain kernels (forced, U > 32), fused
+    # without workspace (register tiles; the wide FP64 kernel at U > 32)
     (synth.Cell(B=256, sizes=(32,) * 8, U=16, n_sc=300, K=14, snr_db=10.0), dict(precision="split_fp16", refine_steps=1)),
-    (synth.Cell(B=128, sizes=(64, 64), U=40, n_sc=50, K=9, snr_db=15.0), dict()),
+    (synth.Cell(B=128, sizes=(64, 64), U=40, n_sc=50, K=9, snr_db=15.0), dict(impl="plain")),
     (synth.Cell(B=64, sizes=(32, 32), U=8, n_sc=64, K=14, snr_db=10.0), dict()),
+    (synth.Cell(B=128, sizes=(64, 64), U=40, n_sc=50, K=9, snr_db=15.0), dict()),
 ]
 
 
@@ -78,15 +80,17 @@ def test_noalloc_matches_precode_pd(torch, pc, case):
 
 
 def test_noalloc_rejects_oversize(torch, pc):
-    """The plain kernels' workspace of 3300 subcarriers with 40 users is
-    larger than the fixed array: PRECODE_ENOMEM, nothing written."""
+    """The plain kernels' workspace of 3300 subcarriers with 40 users (the
+    plain kernels forced: by default this shape runs on the wide FP64 kernel,
+    which needs none) is larger than the fixed array: PRECODE_ENOMEM, nothing
+    written."""
     ctx = pc.Context(0)
     c = synth.Cell(B=128, sizes=(64, 64), U=40, n_sc=3300, K=2, snr_db=10.0)
     H = torch.zeros((c.n_sc, c.B, c.U), dtype=torch.complex64, device="cuda")
     s = torch.zeros((c.K, c.n_sc, c.U), dtype=torch.complex64, device="cuda")
     x = torch.full((c.K, c.n_sc, c.B), 7.0, dtype=torch.complex64, device="cuda")
     with pytest.raises(pc.PrecodeError) as ei:
-        ctx.pd_noalloc(H, s, c.kappa, c.sizes, "wf", x=x)
+        ctx.pd_noalloc(H, s, c.kappa, c.sizes, "wf", pc.params(impl="plain"), x=x)
     assert ei.value.code == -3
     torch.cuda.synchronize()
     assert bool((x == 7.0).all())
