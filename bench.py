@@ -83,6 +83,7 @@ def parse():
     ap.add_argument("--quick", action="store_true", help="headline launches only (for profiling)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the heterogeneous batch leg")
+    ap.add_argument("--only-batch", action="store_true", help="run only the heterogeneous batch leg (for profiling)")
     ap.add_argument("--cell", type=int, default=2, choices=(2, 3),
                     help="2: the headline cell (B=256 as 8x32, U=16, 1200 subcarriers); 3: B=512 as 16x32, U=32, "
                          "3300 subcarriers, correlated channel (for profiling; the headline line is cell 2)")
@@ -114,6 +115,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_kernel": "torch.mul(a, 1.0, out=b), float32", "read_bytes": a.numel() * 4,
                           "write_bytes": b.numel() * 4, "launches": 10}), flush=True)
+        return
+    if args.only_batch:
+        print(json.dumps({"batch_mix": batch_mix_leg(pc.Context(0), pc, dev, args)}), flush=True)
         return
     cell = synth.config(args.cell)
     B, U, K, n_sc, sizes = cell.B, cell.U, cell.K, cell.n_sc, list(cell.sizes)

@@ -326,8 +326,9 @@ int precode_frame_release(precode_ctx *ctx, precode_frame *frame);
  *     U <= B_eff <= 64 run on the one-wave FP64 kernel, one launch per job;
  *   - every other job with K >= 1 (U in 33..64, FD clusters with B_c < U,
  *     mixed routes, larger FP64-route systems, precision FP64) runs on the
- *     wide FP64 kernel: one launch per system-order class (<= 32, <= 64)
- *     for all such jobs, every local system flagged PRECODE_ST_FP64;
+ *     wide FP64 kernel: one launch per system-order class (16, 32, 48, 64;
+ *     an FD job's clusters each in their own class) for all such jobs,
+ *     every local system flagged PRECODE_ST_FP64;
  *   - the remaining jobs (K = 0) run on the plain kernels after them, on
  *     `stream`.
  * The whole batch is validated before anything is enqueued (first error

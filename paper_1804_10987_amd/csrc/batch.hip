@@ -5,8 +5,8 @@
 // Register-tile problems are grouped by tile width UP (16 for U <= 16, 32
 // for U <= 32), channel tiles per wave held in registers (1, 2, 4 or
 // streamed) and load width (U == UP with an aligned channel, or not); wide
-// problems (wide.hip: U <= 64, B_c < U, FP64 route) by system order (32 or
-// 64).  Each group -- PD and FD problems alike -- is one launch whose grid is
+// problems (wide.hip: U <= 64, B_c < U, FP64 route) by system order (16, 32,
+// 48 or 64; an FD problem's clusters each in their own class).  Each group -- PD and FD problems alike -- is one launch whose grid is
 // the sum of its problems' workgroups.  The problem table sits in device
 // memory; a workgroup finds its problem by binary search over the problems'
 // first block index and then runs the same body as the single-problem kernel.
@@ -43,7 +43,9 @@ Class class_of(const BatchProblem &q) {
 
 bool in_table(const BatchProblem &q) { return q.kind != kBatchF64; }
 
-// Problems in launch order (by class, then problem order).
+// Table entries in launch order (by class, then problem order).  A wide FD
+// problem whose clusters fall into different order classes gets one entry
+// per cluster (cl >= 0), each in its own cluster's class.
 struct Plan {
     std::vector<Entry> e;
     std::vector<Class> cls;   // class of each run
@@ -51,22 +53,35 @@ struct Plan {
     std::vector<int> blocks;  // grid of each run
 };
 
+struct Unit {
+    int prob, cl;
+    Class c;
+};
+
 Plan make_plan(const BatchProblem *bp, int n) {
-    std::vector<int> order;
-    for (int i = 0; i < n; ++i)
-        if (in_table(bp[i])) order.push_back(i);
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int a, int b) { return class_of(bp[a]) < class_of(bp[b]); });
-    Plan pl;
-    for (size_t oi = 0; oi < order.size(); ++oi) {
-        const BatchProblem &q = bp[order[oi]];
+    std::vector<Unit> units;
+    for (int i = 0; i < n; ++i) {
+        const BatchProblem &q = bp[i];
+        if (!in_table(q) || q.p.n_sc == 0) continue;
         const Class c = class_of(q);
-        if (pl.cls.empty() || !(pl.cls.back() == c)) {
-            pl.cls.push_back(c);
+        bool split = false;
+        if (q.kind == kBatchWide && q.p.arch == kFD)
+            for (int cl = 0; cl < q.p.C; ++cl) split = split || wide_cluster_order(q.p, cl) != c.up;
+        if (!split) {
+            units.push_back(Unit{i, -1, c});
+        } else {
+            for (int cl = 0; cl < q.p.C; ++cl) units.push_back(Unit{i, cl, Class{1, wide_cluster_order(q.p, cl), 0, 0}});
+        }
+    }
+    std::stable_sort(units.begin(), units.end(), [](const Unit &a, const Unit &b) { return a.c < b.c; });
+    Plan pl;
+    for (const Unit &u : units) {
+        const BatchProblem &q = bp[u.prob];
+        if (pl.cls.empty() || !(pl.cls.back() == u.c)) {
+            pl.cls.push_back(u.c);
             pl.first.push_back((int)pl.e.size());
             pl.blocks.push_back(0);
         }
-        if (q.p.n_sc == 0) continue;
         Entry en;
         en.p = q.p;
         en.H = q.H;
@@ -76,7 +91,8 @@ Plan make_plan(const BatchProblem *bp, int n) {
         en.status = q.status;
         en.K = q.p.K;
         en.block0 = pl.blocks.back();
-        pl.blocks.back() += c.wide ? n_inst(q.p) : blocks_for(q.p, NW);
+        en.cl = u.cl;
+        pl.blocks.back() += u.cl >= 0 ? q.p.n_sc : (u.c.wide ? n_inst(q.p) : blocks_for(q.p, NW));
         pl.e.push_back(en);
     }
     pl.first.push_back((int)pl.e.size());
@@ -136,10 +152,7 @@ hipError_t launch_prec(int prec, int maxt, int vec, const Entry *tab, int n, int
 }  // namespace
 
 size_t fused_batch_table_bytes(const BatchProblem *bp, int n) {
-    size_t cnt = 0;
-    for (int i = 0; i < n; ++i)
-        if (in_table(bp[i]) && bp[i].p.n_sc > 0) ++cnt;
-    return cnt * sizeof(Entry);
+    return make_plan(bp, n).e.size() * sizeof(Entry);
 }
 
 void fused_batch_fill(const BatchProblem *bp, int n, void *host) {

@@ -193,6 +193,7 @@ struct BatchEntry {
     int *status;
     int K;       // symbols
     int block0;  // first block of this problem within its launch
+    int cl;      // -1: every local system; >= 0: FD cluster cl of each subcarrier (wide kernel)
 };
 // Bytes of the device table fused_batch_launch reads.
 size_t fused_batch_table_bytes(const BatchProblem *bp, int n);
@@ -206,8 +207,11 @@ hipError_t fused_batch_launch(const BatchProblem *bp, int n, int precision, cons
 // Local systems of order up to 64 in one FP64 launch (wide.hip): one
 // workgroup per system, U x U form (PD; FD with B_c >= U) or B_c x B_c form
 // (FD with B_c < U); every system flagged PRECODE_ST_FP64.  Needs K >= 1 and
-// U <= 64.  wide_order: the launch's system order bound (32 or 64).
+// U <= 64.  Launches come in classes of system order (16, 32, 48, 64):
+// wide_cluster_order is the class of FD cluster c's systems (of every
+// system for PD), wide_order the largest over the problem.
 bool wide_supported(const Prob &p, int K);
+int wide_cluster_order(const Prob &p, int c);
 int wide_order(const Prob &p);
 hipError_t wide_run(const Prob &p, const float2 *H, const float2 *s, float2 *x, float *scale_out, int *status,
                     hipStream_t st);

@@ -5,7 +5,7 @@
 //
 // One workgroup of 256 threads per local system (a PD subcarrier, or an FD
 // (subcarrier, cluster) pair), everything in FP64 (complex64 inputs widened
-// exactly).  A system of order N <= NP (NP = 32 or 64) is held as an NP x NP
+// exactly).  A system of order N <= NP (NP = 16, 32, 48 or 64) is held as an NP x NP
 // matrix that is the identity past N; thread t = 16 bi + bj owns the E x E
 // block (E = NP / 16) at rows E bi .. E bi + E - 1, columns E bj .. .
 //
@@ -16,8 +16,10 @@
 //               H_c^H, which are staged once (conjugated, transposed)
 //   Gram      the contraction rows staged 64 at a time in LDS (coalesced
 //             loads of the system's contiguous rows, the next chunk in flight
-//             while the current one is multiplied), each thread accumulating
-//             its block; complex64 products are exact in FP64
+//             while the current one is multiplied); the 16 x 16 blocks on and
+//             above the block diagonal on FP64 MFMA, each wave over a quarter
+//             of the rows, the partial sums added in LDS in wave order;
+//             complex64 products are exact in FP64
 //   invert    Gauss-Jordan without pivoting (Hermitian positive definite) on
 //             2^-e A, the largest diagonal entry in [0.5, 1), one barrier per
 //             step: the owners of row k write it to LDS.  Before step k the
@@ -48,13 +50,14 @@ constexpr int kWSR = 64;  // rows staged per chunk
 template <int NP>
 struct WideL {
     static constexpr int E = NP / 16;   // edge of a thread's block
-    static constexpr int G = kWT / NP;  // symbol groups of the solve
+    static constexpr int G = kWT / NP;  // symbol groups of the solve (threads past G NP idle there)
     static constexpr int PER = kWSR * NP / kWT;  // staged elements per thread
     // staged rows: [64][NP] complex64 (Gram), [NP][65] (transposed precode rows)
     static constexpr size_t stage_b = (size_t)NP * (kWSR + 1) * 8;
     static constexpr size_t ainv_b = (size_t)NP * NP * 16;   // A^-1 [NP][NP] (row buffers while inverting)
     static constexpr size_t vb_b = (size_t)kWKC * NP * 16;   // right-hand sides [KC][NP]
-    static constexpr size_t zb_b = (size_t)kWKC * 64 * 16;   // Z chunk [KC][NP] or symbols [KC][64] complex64
+    // Z chunk [KC][NP] (complex FP64) or symbols [KC][64] (complex64)
+    static constexpr size_t zb_b = (size_t)kWKC * (NP * 16 > 64 * 8 ? NP * 16 : 64 * 8);
     static constexpr size_t o_ainv = stage_b, o_vb = o_ainv + ainv_b, o_zb = o_vb + vb_b, o_dg = o_zb + zb_b;
     static constexpr size_t bytes = o_dg + (size_t)(NP + 8) * 8;  // + diagonal, reduction slots
 };
@@ -65,25 +68,14 @@ __device__ __forceinline__ double rcp_nr(double v) {
     return fma(inv, fma(-v, inv, 1.0), inv);
 }
 
-// E consecutive complex64 entries at p (16-byte aligned) as doubles.
-template <int E>
-__device__ __forceinline__ void ld_row(const float2 *p, double (&re)[E], double (&im)[E]) {
-#pragma unroll
-    for (int h = 0; h < E / 2; ++h) {
-        const float4 v = ((const float4 *)p)[h];
-        re[2 * h] = v.x;
-        im[2 * h] = v.y;
-        re[2 * h + 1] = v.z;
-        im[2 * h + 1] = v.w;
-    }
-}
+typedef double wf64x4 __attribute__((ext_vector_type(4)));
 
 template <int NP>
 __device__ __forceinline__ void wide_system(const Prob *__restrict__ pk, int sys, int K, const float2 *__restrict__ H,
                             const float2 *__restrict__ s, float2 *__restrict__ x, float *__restrict__ scale_out,
                             int *__restrict__ status, char *lds) {
     constexpr int E = WideL<NP>::E, G = WideL<NP>::G, PER = WideL<NP>::PER, KC = kWKC, SR = kWSR;
-    constexpr int MS = KC / G;  // symbols per thread in the solve
+    constexpr int MS = (KC + G - 1) / G;  // symbols per thread in the solve: sg + G m < KC
     const int tid = threadIdx.x, bi = tid >> 4, bj = tid & 15;
     const bool pd = pk->arch == kPD;
     const int B = pk->B, U = pk->U, C = pk->C, n_sc = pk->n_sc;
@@ -102,17 +94,25 @@ __device__ __forceinline__ void wide_system(const Prob *__restrict__ pk, int sys
     double *dg = (double *)(lds + WideL<NP>::o_dg);
     double *red = dg + NP;
 
-    // ---- Gram: G[i][j] = sum_r conj(X[r][i]) X[r][j] over the staged rows X
-    double gr[E][E], gi[E][E];
+    // ---- Gram: G[i][j] = sum_r conj(X[r][i]) X[r][j] over the staged rows X,
+    // its 16 x 16 blocks (I, J), I <= J, on FP64 MFMA (v_mfma_f64_16x16x4f64):
+    // lane l feeds X[r0 + l / 16][16 I + l % 16] as A[i][k] and
+    // X[r0 + l / 16][16 J + l % 16] as B[k][j] (k: the row of the step);
+    // D[i][j] lands in lane (i % 4) 16 + j, register i / 4.  Wave w takes
+    // rows 16 w .. 16 w + 15 of each staged chunk.
+    constexpr int NB = NP / 16, NBLK = NB * (NB + 1) / 2;
+    const int lane = tid & 63, wave = tid >> 6;
+    wf64x4 are[NBLK], aim[NBLK];
 #pragma unroll
-    for (int a = 0; a < E; ++a)
-#pragma unroll
-        for (int b = 0; b < E; ++b) gr[a][b] = gi[a][b] = 0.0;
+    for (int t = 0; t < NBLK; ++t) are[t] = aim[t] = (wf64x4){0.0, 0.0, 0.0, 0.0};
     {
-        // staged columns past the system's order stay zero
+        // staged columns past the system's order stay zero, and so do the
+        // B_c x B_c form's rows past U
         const int c0 = bform ? nrows : U, nz = NP - c0;
         if (nz > 0)
             for (int e = tid; e < SR * nz; e += kWT) st[(e / nz) * NP + c0 + e % nz] = make_float2(0.f, 0.f);
+        if (bform && nrows > 0)
+            for (int e = tid; e < (SR - U) * nrows; e += kWT) st[(U + e / nrows) * NP + e % nrows] = make_float2(0.f, 0.f);
     }
     if (bform) {
         // X[u][i] = conj(H_c[i][u]): the whole cluster (nrows x U <= 64 x 64)
@@ -159,21 +159,73 @@ __device__ __forceinline__ void wide_system(const Prob *__restrict__ pk, int sys
                 pre[m] = e < ne ? src[e] : make_float2(0.f, 0.f);
             }
         }
-#pragma unroll 2
-        for (int rr = 0; rr < nr; ++rr) {
-            double ar[E], ai[E], br[E], bim[E];
-            ld_row<E>(st + rr * NP + E * bi, ar, ai);
-            ld_row<E>(st + rr * NP + E * bj, br, bim);
+        // rows past nr in a step are zero
 #pragma unroll
-            for (int a = 0; a < E; ++a)
+        for (int qd = 0; qd < 4; ++qd) {
+            const int rb4 = 16 * wave + 4 * qd;
+            if (rb4 >= nr) break;  // wave-uniform: every lane stays active for the MFMA
+            const float2 *row = st + (rb4 + (lane >> 4)) * NP + (lane & 15);
+            double hr[NB], hi[NB];
 #pragma unroll
-                for (int b = 0; b < E; ++b) {
-                    gr[a][b] = fma(ar[a], br[b], fma(ai[a], bim[b], gr[a][b]));
-                    gi[a][b] = fma(ar[a], bim[b], fma(-ai[a], br[b], gi[a][b]));
+            for (int b = 0; b < NB; ++b) {
+                const float2 v = row[16 * b];
+                hr[b] = v.x;
+                hi[b] = v.y;
+            }
+            int t = 0;
+#pragma unroll
+            for (int I = 0; I < NB; ++I)
+#pragma unroll
+                for (int J = I; J < NB; ++J, ++t) {
+                    are[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(hr[I], hr[J], are[t], 0, 0, 0);
+                    are[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(hi[I], hi[J], are[t], 0, 0, 0);
+                    aim[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(hr[I], hi[J], aim[t], 0, 0, 0);
+                    aim[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(-hi[I], hr[J], aim[t], 0, 0, 0);
                 }
         }
         __syncthreads();  // the staging area is rewritten by the next chunk
     }
+    // the four waves' partial blocks summed in wave order into G (the A^-1
+    // area), then each thread takes its E x E block (below the block
+    // diagonal from the conjugate of the block above it)
+    cx<double> *Gm = ainv;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        if (wave == w) {
+            int t = 0;
+#pragma unroll
+            for (int I = 0; I < NB; ++I)
+#pragma unroll
+                for (int J = I; J < NB; ++J, ++t)
+#pragma unroll
+                    for (int rg = 0; rg < 4; ++rg) {
+                        cx<double> &g = Gm[(16 * I + 4 * rg + (lane >> 4)) * NP + 16 * J + (lane & 15)];
+                        if (w == 0) {
+                            g = {are[t][rg], aim[t][rg]};
+                        } else {
+                            g.re += are[t][rg];
+                            g.im += aim[t][rg];
+                        }
+                    }
+        }
+        __syncthreads();
+    }
+    double gr[E][E], gi[E][E];
+#pragma unroll
+    for (int a = 0; a < E; ++a)
+#pragma unroll
+        for (int b = 0; b < E; ++b) {
+            const int i = E * bi + a, j = E * bj + b;
+            if ((i >> 4) <= (j >> 4)) {
+                const cx<double> g = Gm[i * NP + j];
+                gr[a][b] = g.re;
+                gi[a][b] = g.im;
+            } else {
+                const cx<double> g = Gm[j * NP + i];
+                gr[a][b] = g.re;
+                gi[a][b] = -g.im;
+            }
+        }
 
     // ---- A = G + kappa I, identity past N; 2^-e scaling
 #pragma unroll
@@ -303,7 +355,16 @@ __device__ __forceinline__ void wide_system(const Prob *__restrict__ pk, int sys
         for (int b = 0; b < E; ++b) ainv[(E * bi + a) * NP + E * bj + b] = {gr[a][b], gi[a][b]};
 
     // ---- symbols, KC at a time
-    const int si = tid % NP, sg = tid / NP;  // solve: system row, symbol group
+    // solve: system row si, symbol group sg (symbols sg + G m < KC; threads
+    // past G NP take none)
+    const int si = tid % NP, sg = tid / NP;
+    bool kv[MS];
+    int kr[MS];
+#pragma unroll
+    for (int m = 0; m < MS; ++m) {
+        kv[m] = sg < G && sg + G * m < KC;
+        kr[m] = kv[m] ? sg + G * m : 0;
+    }
     for (int k0 = 0; k0 < K; k0 += KC) {
         const int kc = min(KC, K - k0);
         if (!bform) {
@@ -327,13 +388,14 @@ __device__ __forceinline__ void wide_system(const Prob *__restrict__ pk, int sys
                 const double hr = h.x, hm = -h.y;
 #pragma unroll
                 for (int m = 0; m < MS; ++m) {
-                    const float2 sv = sy[(sg + G * m) * 64 + u];
+                    const float2 sv = sy[kr[m] * 64 + u];
                     vr[m] = fma(hr, (double)sv.x, fma(-hm, (double)sv.y, vr[m]));
                     vi[m] = fma(hr, (double)sv.y, fma(hm, (double)sv.x, vi[m]));
                 }
             }
 #pragma unroll
-            for (int m = 0; m < MS; ++m) vb[(sg + G * m) * NP + si] = {vr[m], vi[m]};
+            for (int m = 0; m < MS; ++m)
+                if (kv[m]) vb[kr[m] * NP + si] = {vr[m], vi[m]};
         }
         __syncthreads();
         // z[k][i] = scale sum_j conj(A^-1[j][i]) v[k][j]  (A^-1 Hermitian)
@@ -345,14 +407,15 @@ __device__ __forceinline__ void wide_system(const Prob *__restrict__ pk, int sys
                 const cx<double> a = ainv[j * NP + si];
 #pragma unroll
                 for (int m = 0; m < MS; ++m) {
-                    const cx<double> v = vb[(sg + G * m) * NP + j];
+                    const cx<double> v = vb[kr[m] * NP + j];
                     zr[m] = fma(a.re, v.re, fma(a.im, v.im, zr[m]));
                     zi[m] = fma(a.re, v.im, fma(-a.im, v.re, zi[m]));
                 }
             }
 #pragma unroll
             for (int m = 0; m < MS; ++m) {
-                const int k = sg + G * m;
+                if (!kv[m]) continue;
+                const int k = kr[m];
                 const bool live = ok && si < N && k < kc;
                 const double a = live ? scale * zr[m] : 0.0, b = live ? scale * zi[m] : 0.0;
                 if (!bform)
@@ -422,7 +485,7 @@ __device__ __forceinline__ void wide_system(const Prob *__restrict__ pk, int sys
 }
 
 template <int NP>
-constexpr int wide_min_waves() { return NP == 64 ? 1 : 2; }
+constexpr int wide_min_waves() { return NP == 16 ? 4 : (NP == 32 ? 2 : 1); }
 
 template <int NP>
 __global__ void __launch_bounds__(kWT, (wide_min_waves<NP>()))
@@ -446,7 +509,10 @@ __global__ void __launch_bounds__(kWT, (wide_min_waves<NP>()))
         else hi = mid - 1;
     }
     const BatchEntry &en = tab[lo];
-    wide_system<NP>(&en.p, b - en.block0, en.K, en.H, en.s, en.x, en.scale_out, en.status, (char *)smem_wide);
+    // an entry holds every system of its problem, or (cl >= 0) cluster cl of every subcarrier
+    const int lb = b - en.block0;
+    const int sys = en.cl < 0 ? lb : lb * en.p.C + en.cl;
+    wide_system<NP>(&en.p, sys, en.K, en.H, en.s, en.x, en.scale_out, en.status, (char *)smem_wide);
 }
 
 template <typename F>
@@ -479,28 +545,39 @@ hipError_t launch_wide_batch(const BatchEntry *tab, int n, int blocks, hipStream
 
 bool wide_supported(const Prob &p, int K) { return K >= 1 && p.U >= 1 && p.U <= 64 && n_inst(p) > 0; }
 
+int wide_class(int n) { return n <= 16 ? 16 : (n <= 32 ? 32 : (n <= 48 ? 48 : 64)); }
+
+int wide_cluster_order(const Prob &p, int c) {
+    if (p.arch == kPD) return wide_class(p.U);
+    const int bc = p.off[c + 1] - p.off[c];
+    return wide_class(bc < p.U ? bc : p.U);
+}
+
 int wide_order(const Prob &p) {
-    int m = p.U;
-    if (p.arch == kFD) {
-        m = 0;
-        for (int c = 0; c < p.C; ++c) {
-            const int bc = p.off[c + 1] - p.off[c];
-            m = std::max(m, bc < p.U ? bc : p.U);
-        }
-    }
-    return m <= 32 ? 32 : 64;
+    int m = 0;
+    for (int c = 0; c < (p.arch == kPD ? 1 : p.C); ++c) m = std::max(m, wide_cluster_order(p, c));
+    return m;
 }
 
 hipError_t wide_run(const Prob &p, const float2 *H, const float2 *s, float2 *x, float *scale_out, int *status,
                     hipStream_t st) {
     if (n_inst(p) == 0) return hipSuccess;
-    return wide_order(p) == 32 ? launch_wide<32>(p, H, s, x, scale_out, status, st)
-                               : launch_wide<64>(p, H, s, x, scale_out, status, st);
+    switch (wide_order(p)) {
+        case 16: return launch_wide<16>(p, H, s, x, scale_out, status, st);
+        case 32: return launch_wide<32>(p, H, s, x, scale_out, status, st);
+        case 48: return launch_wide<48>(p, H, s, x, scale_out, status, st);
+        default: return launch_wide<64>(p, H, s, x, scale_out, status, st);
+    }
 }
 
 hipError_t wide_batch_launch(int order, const BatchEntry *tab, int n, int blocks, hipStream_t st) {
     if (n == 0 || blocks == 0) return hipSuccess;
-    return order == 32 ? launch_wide_batch<32>(tab, n, blocks, st) : launch_wide_batch<64>(tab, n, blocks, st);
+    switch (order) {
+        case 16: return launch_wide_batch<16>(tab, n, blocks, st);
+        case 32: return launch_wide_batch<32>(tab, n, blocks, st);
+        case 48: return launch_wide_batch<48>(tab, n, blocks, st);
+        default: return launch_wide_batch<64>(tab, n, blocks, st);
+    }
 }
 
 }  // namespace pc

@@ -1,5 +1,6 @@
-"""GPU: the wide FP64 kernel (one workgroup per local system of order <= 64)
-through the C ABI against the FP64 oracle: PD and FD with U in 33..64, FD
+"""GPU: the wide FP64 kernel (one workgroup per local system of order <= 64,
+in classes of order 32, 48 and 64) through the C ABI against the FP64
+oracle: PD and FD with U in 33..64, FD
 clusters smaller than U (the B_c x B_c form of Sec. III-C's case split),
 mixed forms and routes in one cell, ragged row counts past one 64-row chunk,
 several symbol chunks, ZF and its singular cases; and the heterogeneous
@@ -77,6 +78,7 @@ CELLS = [
     ("fd_bform_small", "fd", synth.Cell(B=44, sizes=(4, 12, 8, 20), U=24, n_sc=5, K=9, snr_db=5.0)),
     ("fd_bform_u64", "fd", synth.Cell(B=128, sizes=(1, 31, 33, 63), U=64, n_sc=3, K=17, snr_db=20.0)),
     ("fd_uform_u40", "fd", synth.Cell(B=210, sizes=(80, 130), U=40, n_sc=4, K=3, snr_db=10.0)),
+    ("fd_bform_u56", "fd", synth.Cell(B=80, sizes=(40, 40), U=56, n_sc=5, K=14, snr_db=15.0)),  # order 40 < U
     ("fd_mixed_u12", "fd", synth.Cell(B=40, sizes=(8, 32), U=12, n_sc=8, K=14, snr_db=10.0)),  # one B_c < U, one FP32 route
     ("fd_u2_bc1", "fd", synth.Cell(B=7, sizes=(1, 6), U=2, n_sc=5, K=1, snr_db=0.0)),  # a 1-antenna cluster
 ]
