@@ -156,19 +156,30 @@ size_t precode_ctx_bytes(const precode_ctx *ctx);
 int precode_ctx_last_impl(const precode_ctx *ctx);
 
 /* Waves per workgroup (1, 2 or 4) of the most recent fused precode_pd /
- * precode_fd / precode_batch call on this context, or 0 if none.  The fused
- * kernel's launch shape is chosen by an autotuner that times every feasible
- * shape on the first call of each problem shape in the process (the call's
- * own launch, repeated on its stream, before the call returns) and reuses
- * the fastest; PRECODE_FUSED_WAVES=1|2|4 in the environment forces a shape,
+ * precode_fd / precode_batch call on this context, or 0 if none.  The
+ * register-tile kernels' launch shape (waves per workgroup, and register
+ * tiles or channel rows streamed twice) is chosen by an autotuner that times
+ * every feasible shape on the first call of each problem shape (the call's
+ * own launch, repeated on its stream, before the call returns; streamed
+ * shapes only when the channel exceeds the 256 MB last-level cache or no
+ * tiles fit) and reuses the fastest.  Tuned shapes are kept for the process
+ * and appended to a cache file keyed by device (architecture, name, compute
+ * units) and HIP runtime version, which later processes read instead of
+ * timing again: PRECODE_TUNE_CACHE=path names it ("off": no file; unset:
+ * $XDG_CACHE_HOME/precode/tune.txt, else $HOME/.cache/precode/tune.txt;
+ * lines "<device> <problem shape> <waves> <streamed>").
+ * PRECODE_FUSED_WAVES=1|2|4 in the environment forces the waves,
  * PRECODE_AUTOTUNE=0 keeps the default shape (the fewest waves per
  * workgroup that keep the rows in registers; at 17 to 32 users the fewest
  * that stream them, for PD systems whose rows need a whole workgroup);
- * PRECODE_FUSED_STREAM=1 makes
- * every wave stream its channel rows twice instead of keeping them in
- * registers.  Calls made under stream capture
+ * PRECODE_FUSED_STREAM=1 makes every wave stream its channel rows twice
+ * instead of keeping them in registers.  Calls made under stream capture
  * never tune.  Shapes differ only in the order of the cluster-sum rounding. */
 int precode_ctx_last_waves(const precode_ctx *ctx);
+
+/* Forgets every launch shape the process has tuned or read; the next call
+ * of each problem shape reads the cache file again (then tunes if absent). */
+void precode_autotune_reset(void);
 
 /* ---------------------------------------------------------------------------
  * PD precoding of a frame (Sec. III-B; Theorem 1; Lemma 1).  Per subcarrier

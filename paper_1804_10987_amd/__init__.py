@@ -362,6 +362,12 @@ class BatchPlan:
             pass
 
 
+def autotune_reset():
+    """precode_autotune_reset: forget the process's tuned launch shapes; the
+    next call of each problem shape reads the tuning cache file again."""
+    _lib.load().precode_autotune_reset()
+
+
 _default = {}
 
 

@@ -105,6 +105,7 @@ SIGNATURES = {
     "precode_batch_plan_launch": (I, [VP, VP]),
     "precode_batch_plan_launches": (I, [VP]),
     "precode_batch_plan_fused_jobs": (I, [VP]),
+    "precode_autotune_reset": (None, []),
     "precode_batch_plan_destroy": (I, [VP]),
     "precode_serve": (I, [VP, ctypes.POINTER(ServeJob), I, ctypes.POINTER(ServeConfig),
                           ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ServeStats)]),

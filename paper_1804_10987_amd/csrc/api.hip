@@ -841,6 +841,8 @@ int precode_batch_plan_launches(const precode_batch_plan *plan) { return plan ? 
 
 int precode_batch_plan_fused_jobs(const precode_batch_plan *plan) { return plan ? plan->fused_jobs : 0; }
 
+void precode_autotune_reset(void) { fused_autotune_reset(); }
+
 int precode_batch_plan_destroy(precode_batch_plan *plan) {
     if (!plan) return PRECODE_EINVAL;
     precode_ctx *ctx = plan->ctx;

@@ -143,6 +143,9 @@ int fused_default_waves();
 // absorb; calls then use a shape the process has already tuned, else the
 // default shape.
 void fused_set_autotune(bool on);
+// Forgets every tuned shape of the process; the next untuned call reads the
+// cache file again.
+void fused_autotune_reset();
 // Frame split of the fused kernel: prepare writes scale * A^-1 per instance
 // (n_inst x U x U complex64, scale = 1/beta for PD, w_c for FD; zero for an
 // instance on the FP64 route or failed) with beta / weights and status;

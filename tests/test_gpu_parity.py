@@ -399,6 +399,39 @@ def test_autotuned_shape_is_cached_and_deterministic(torch, ctx, pc, monkeypatch
     assert torch.equal(x1, x2)
 
 
+def test_tune_cache_file(torch, ctx, pc, monkeypatch, tmp_path):
+    """A tuned launch shape is appended to the cache file, keyed by device and
+    HIP runtime; after a reset the process takes the shape from the file
+    without timing again (here an entry edited to another feasible shape)."""
+    path = tmp_path / "tune.txt"
+    monkeypatch.delenv("PRECODE_FUSED_WAVES", raising=False)
+    monkeypatch.setenv("PRECODE_AUTOTUNE", "1")
+    monkeypatch.setenv("PRECODE_TUNE_CACHE", str(path))
+    pc.autotune_reset()
+    try:
+        cell = synth.Cell(B=256, sizes=(32,) * 8, U=16, n_sc=301, K=14)
+        H, s = synth.make_cell(cell, seed=14)
+        Hd, sd = _dev(torch, H), _dev(torch, s)
+        ctx.pd(Hd, sd, cell.kappa, cell.sizes)
+        torch.cuda.synchronize()
+        w1 = ctx.last_waves
+        lines = [ln for ln in path.read_text().split("\n") if ln]
+        assert len(lines) == 1
+        dev, key, nw, stream = lines[0].split()
+        assert int(nw) == w1 and stream == "0" and dev.startswith("gfx950") and "|hip" in dev
+        other = 4 if w1 == 2 else 2
+        path.write_text("%s %s %d 0\n" % (dev, key, other))
+        pc.autotune_reset()
+        x2, sc2, st2 = ctx.pd(Hd, sd, cell.kappa, cell.sizes)
+        torch.cuda.synchronize()
+        assert ctx.last_waves == other
+        assert len([ln for ln in path.read_text().split("\n") if ln]) == 1  # read, not tuned again
+        xo, sco, sto = _oracle("pd", H, s, cell.kappa, cell.sizes, "wf")
+        _check(x2.cpu().numpy(), sc2.cpu().numpy(), st2.cpu().numpy(), xo, sco, sto)
+    finally:
+        pc.autotune_reset()
+
+
 @pytest.mark.parametrize("u,expect", [(16, 2), (32, 1)])
 def test_untuned_default_shape(torch, ctx, pc, monkeypatch, u, expect):
     """With tuning off (as under stream capture and in serving) PD takes the
