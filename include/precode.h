@@ -308,7 +308,11 @@ int precode_fd(precode_ctx *ctx, const void *H, const void *s, float rho,
  * frame_symbols precodes nk symbols s[nk][n_sc][U] -> x[nk][n_sc][B] with it.
  * H must stay valid and unchanged until frame_release (it is read by
  * frame_symbols).  arch: enum precode_arch.  The frame handle is owned by
- * the context and freed by frame_release or ctx_destroy.
+ * the context and freed by frame_release or ctx_destroy.  Routing as for
+ * precode_pd / precode_fd: the register-tile kernels keep scale * A^-1 in
+ * complex64, the wide FP64 kernel (every other shape with U <= 64, unless
+ * impl is PLAIN) in complex FP64 (up to 64 x 64 x 16 bytes per local
+ * system), the plain kernels their A^-1 slots.
  * ------------------------------------------------------------------------- */
 int precode_frame_prepare(precode_ctx *ctx, int arch, const void *H, float rho,
                           const int *cluster_sizes, int C, int mode, int B, int U,
@@ -391,15 +395,17 @@ int precode_batch_plan_destroy(precode_batch_plan *plan);
  * precode_serve replays the arrival trace in real time and returns when every
  * job has completed:
  *   - an arrived job is admitted (FIFO) when fewer than max_active jobs are in
- *     flight and its resident state (factors, beta / weights, status; plus
- *     the plain kernels' workspace for shapes the fused kernel does not take)
+ *     flight and its resident state (factors, beta / weights, status: scale
+ *     A^-1 in complex64 for the register-tile kernels, in complex FP64 for
+ *     the wide FP64 kernel, which takes every other job with symbols; the
+ *     plain kernels' workspace for jobs without symbols or with impl PLAIN)
  *     fits the slab of slab_bytes of device memory (the HBM budget);
  *   - admission enqueues the per-frame part (Gram, factors, beta / weights,
  *     Sec. IV-B) on one of n_streams streams; released symbols are precoded
  *     from the resident factors as they are released, jobs overlapping on
- *     the device across streams; a job with symbol_period_s == 0 whose shape
- *     the fused kernel takes is instead precoded in one launch from Gram to
- *     precode (its channel read once);
+ *     the device across streams; a job with symbol_period_s == 0 on the
+ *     fused kernels is instead precoded in one launch from Gram to precode
+ *     (its channel read once);
  *   - a job's state returns to the slab after its last symbol completes.
  * The call allocates the slab and streams once; the loop itself never
  * allocates, and runs no launch-shape timing (see precode_ctx_last_waves): a

@@ -19,9 +19,11 @@ struct precode_frame {
     Prob prob;
     const float2 *H;
     int fused;      // state from the fused prepare pass (else from the plain kernels)
+    int wide;       // state from the wide FP64 kernel's prepare pass
     int precision;
     int refine;     // refinement steps per symbol (plain kernels)
-    void *ainv;     // fused: scale * A^-1 (n_inst x U x U complex64); plain: A^-1 slots (complex<T>)
+    void *ainv;     // fused: scale * A^-1 (n_inst x U x U complex64); wide: scale * A^-1 (complex FP64,
+                    // wide_factor_bytes); plain: A^-1 slots (complex<T>)
     void *scale;    // plain-layout scale (T); unused when fused
     float *scale_out;
     int *status;
@@ -593,14 +595,18 @@ int precode_frame_prepare(precode_ctx *ctx, int arch, const void *H, float rho, 
     if (rc) return rc;
     if (n_sc > 0 && (!H || !aligned8(H))) return PRECODE_EINVAL;
     const bool fuse = q.impl != PRECODE_IMPL_PLAIN && q.refine_steps == 0 && fused_supported(p, q.precision);
-    if (q.impl == PRECODE_IMPL_FUSED && !fuse) return PRECODE_EUNSUPPORTED;
-    if ((q.precision == PRECODE_PREC_SPLIT_FP16 || q.precision == PRECODE_PREC_SPLIT_BF16) && !fuse)
+    // the shapes the register-tile kernels do not take (and refinement on
+    // them: the FP64 solve needs none) on the wide FP64 kernel
+    const bool wide = !fuse && q.impl != PRECODE_IMPL_PLAIN && !(q.refine_steps > 0 && fused_supported(p, q.precision)) &&
+                      wide_supported(p, 1);
+    if (q.impl == PRECODE_IMPL_FUSED && !fuse && !wide) return PRECODE_EUNSUPPORTED;
+    if ((q.precision == PRECODE_PREC_SPLIT_FP16 || q.precision == PRECODE_PREC_SPLIT_BF16) && !fuse && !wide)
         return PRECODE_EUNSUPPORTED;
-    // resident state: factors (fused: scale * A^-1; plain: A^-1 slots and
-    // scale), beta / weights and status
+    // resident state: factors (fused / wide: scale * A^-1; plain: A^-1 slots
+    // and scale), beta / weights and status
     const size_t ni = (size_t)n_inst(p);
-    const size_t bA = fuse ? ni * p.U * p.U * sizeof(float2) : plain_ws_bytes_A(p);
-    const size_t bS = fuse ? 0 : plain_ws_bytes_scale(p);
+    const size_t bA = fuse ? ni * p.U * p.U * sizeof(float2) : (wide ? wide_factor_bytes(p) : plain_ws_bytes_A(p));
+    const size_t bS = fuse || wide ? 0 : plain_ws_bytes_scale(p);
     const size_t bytes = bA + bS + ni * sizeof(float) + ni * sizeof(int) + 64;
     precode_frame *f = new (std::nothrow) precode_frame;
     if (!f) return PRECODE_ENOMEM;
@@ -614,6 +620,7 @@ int precode_frame_prepare(precode_ctx *ctx, int arch, const void *H, float rho, 
     f->prob = p;
     f->H = (const float2 *)H;
     f->fused = fuse;
+    f->wide = wide;
     f->precision = q.precision;
     f->refine = q.refine_steps;
     f->scale = (char *)f->ainv + bA;
@@ -623,6 +630,8 @@ int precode_frame_prepare(precode_ctx *ctx, int arch, const void *H, float rho, 
         if (fuse) {
             rc = dev_err(fused_prepare(p, q.precision, (const float2 *)H, (float2 *)f->ainv, f->scale_out, f->status,
                                        (hipStream_t)stream));
+        } else if (wide) {
+            rc = dev_err(wide_prepare(p, (const float2 *)H, f->ainv, f->scale_out, f->status, (hipStream_t)stream));
         } else {
             rc = grow(ctx, &ctx->wsA, &ctx->capA, bA, (hipStream_t)stream);
             if (!rc) rc = ws_acquire(ctx, (hipStream_t)stream);
@@ -639,7 +648,7 @@ int precode_frame_prepare(precode_ctx *ctx, int arch, const void *H, float rho, 
         delete f;
         return rc;
     }
-    if (rc == PRECODE_OK) ctx->last_impl = fuse ? PRECODE_IMPL_FUSED : PRECODE_IMPL_PLAIN;
+    if (rc == PRECODE_OK) ctx->last_impl = fuse || wide ? PRECODE_IMPL_FUSED : PRECODE_IMPL_PLAIN;
     f->next = ctx->frames;
     ctx->frames = f;
     *out = f;
@@ -657,6 +666,9 @@ int precode_frame_symbols(precode_ctx *ctx, precode_frame *f, const void *s, int
     if (f->fused)
         return dev_err(fused_symbols(p, f->precision, nk, f->H, (const float2 *)f->ainv, f->status,
                                      (const float2 *)s, (float2 *)x, (hipStream_t)stream));
+    if (f->wide)
+        return dev_err(wide_symbols(p, nk, f->H, f->ainv, f->status, (const float2 *)s, (float2 *)x,
+                                    (hipStream_t)stream));
     hipStream_t st = (hipStream_t)stream;
     int rc = grow(ctx, &ctx->wsZ, &ctx->capZ, plain_ws_bytes_z(p, nk), st);
     if (!rc) rc = ws_acquire(ctx, st);

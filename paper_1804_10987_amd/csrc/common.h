@@ -219,6 +219,14 @@ int wide_order(const Prob &p);
 hipError_t wide_run(const Prob &p, const float2 *H, const float2 *s, float2 *x, float *scale_out, int *status,
                     hipStream_t st);
 hipError_t wide_batch_launch(int order, const BatchEntry *tab, int n, int blocks, hipStream_t st);
+// Frame split of the wide kernel: prepare stores scale * A^-1 per system
+// (wide_factor_bytes: n_inst slots of order^2 complex doubles, scale = 1/beta
+// for PD, w_c for FD; zero for a failed system) with beta / weights and
+// status; symbols precodes nk symbols from it, reading prepare's status.
+size_t wide_factor_bytes(const Prob &p);
+hipError_t wide_prepare(const Prob &p, const float2 *H, void *fac, float *scale_out, int *status, hipStream_t st);
+hipError_t wide_symbols(const Prob &p, int nk, const float2 *H, const void *fac, const int *status, const float2 *s,
+                        float2 *x, hipStream_t st);
 
 // Comparison precoders (compare.hip).  Centralized WF in the B x B form of
 // Theorem 1: FP32, one workgroup per subcarrier, ws holds ws_bytes of

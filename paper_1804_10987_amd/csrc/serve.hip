@@ -16,7 +16,9 @@
 //              launch; jobs on different streams overlap on the device.  A
 //              job with a zero symbol period (every symbol released at
 //              arrival) on the fused kernels takes one launch from Gram to
-//              precode instead of prepare + symbols
+//              precode instead of prepare + symbols.  Jobs the register-tile
+//              kernels do not take run on the wide FP64 kernel (its factors
+//              scale A^-1 in FP64), jobs without symbols on the plain ones
 //   retire     when a job's last symbol completes its state returns to the slab
 //              and waiting jobs can be admitted
 //
@@ -101,13 +103,14 @@ struct Launch {
 struct JobState {
     const precode_serve_job *src;
     Prob p;
-    bool fused;
+    bool fused;  // register-tile kernels
+    bool wide;   // the wide FP64 kernel (factors scale A^-1 in FP64)
     int precision;
     size_t n_inst;
     // device state from the slab
     void *mem = nullptr;
     size_t bytes = 0;
-    float2 *ainv = nullptr;  // fused factors, or plain A^-1 slots
+    float2 *ainv = nullptr;  // fused or wide factors, or plain A^-1 slots
     void *wsA = nullptr, *wsScale = nullptr, *wsZ = nullptr;
     float *scale_out = nullptr;
     int *status = nullptr;
@@ -168,8 +171,11 @@ extern "C" int precode_serve(precode_ctx *ctx, const precode_serve_job *jobs, in
         if (rc) return rc;
         if (j.n_sc > 0 && (!j.H || (j.K > 0 && (!j.s || !j.x)))) return PRECODE_EINVAL;
         s.fused = cfg->impl != PRECODE_IMPL_PLAIN && fused_supported(s.p, cfg->precision);
-        if (!s.fused && (cfg->impl == PRECODE_IMPL_FUSED || cfg->precision == PRECODE_PREC_SPLIT_FP16 ||
-                         cfg->precision == PRECODE_PREC_SPLIT_BF16))
+        // every other job with symbols on the wide FP64 kernel
+        s.wide = !s.fused && cfg->impl != PRECODE_IMPL_PLAIN && wide_supported(s.p, j.K);
+        if (!s.fused && !s.wide &&
+            (cfg->impl == PRECODE_IMPL_FUSED || cfg->precision == PRECODE_PREC_SPLIT_FP16 ||
+             cfg->precision == PRECODE_PREC_SPLIT_BF16))
             return PRECODE_EUNSUPPORTED;
         s.precision = cfg->precision;
         s.n_inst = (size_t)n_inst(s.p);
@@ -177,6 +183,8 @@ extern "C" int precode_serve(precode_ctx *ctx, const precode_serve_job *jobs, in
         const size_t aux = ni * sizeof(float) + ni * sizeof(int) + 512;
         if (s.fused)
             s.bytes = ni * j.U * j.U * sizeof(float2) + aux;
+        else if (s.wide)
+            s.bytes = wide_factor_bytes(s.p) + aux;
         else
             s.bytes = 2 * plain_ws_bytes_A(s.p) + plain_ws_bytes_scale(s.p) + plain_ws_bytes_z(s.p, j.K) + aux + 1024;
         if (s.bytes > cfg->slab_bytes) return PRECODE_ENOMEM;  // could never be admitted
@@ -248,6 +256,9 @@ extern "C" int precode_serve(precode_ctx *ctx, const precode_serve_job *jobs, in
             if (s.fused) {
                 s.ainv = (float2 *)m;
                 m += (ni * j.U * j.U * sizeof(float2) + 255) & ~(size_t)255;
+            } else if (s.wide) {
+                s.ainv = (float2 *)m;
+                m += (wide_factor_bytes(s.p) + 255) & ~(size_t)255;
             } else {
                 const size_t bA = plain_ws_bytes_A(s.p);
                 s.wsA = m;
@@ -266,13 +277,18 @@ extern "C" int precode_serve(precode_ctx *ctx, const precode_serve_job *jobs, in
             // period) is precoded in one launch that keeps the channel in
             // registers from the Gram to the precode, so the channel is read
             // once instead of once for the factors and again for the symbols
-            const bool one_launch = s.fused && j.n_sc > 0 && j.K > 0 && s.src->symbol_period_s <= 0;
+            const bool one_launch = (s.fused || s.wide) && j.n_sc > 0 && j.K > 0 && s.src->symbol_period_s <= 0;
             if (j.n_sc > 0) {
-                if (one_launch)
+                if (one_launch && s.fused)
                     e = fused_run(s.p, s.precision, (const float2 *)j.H, (const float2 *)j.s, (float2 *)j.x,
                                   s.scale_out, s.status, stream);
+                else if (one_launch)
+                    e = wide_run(s.p, (const float2 *)j.H, (const float2 *)j.s, (float2 *)j.x, s.scale_out,
+                                 s.status, stream);
                 else if (s.fused)
                     e = fused_prepare(s.p, s.precision, (const float2 *)j.H, s.ainv, s.scale_out, s.status, stream);
+                else if (s.wide)
+                    e = wide_prepare(s.p, (const float2 *)j.H, s.ainv, s.scale_out, s.status, stream);
                 else
                     e = plain_prepare(s.p, (const float2 *)j.H, s.scale_out, s.status, s.wsA, s.ainv, s.wsScale,
                                       stream);
@@ -325,6 +341,8 @@ extern "C" int precode_serve(precode_ctx *ctx, const precode_serve_job *jobs, in
                 pk.K = nk;
                 if (s.fused)
                     e = fused_symbols(pk, s.precision, nk, (const float2 *)j.H, s.ainv, s.status, sk, xk, stream);
+                else if (s.wide)
+                    e = wide_symbols(pk, nk, (const float2 *)j.H, s.ainv, s.status, sk, xk, stream);
                 else
                     e = plain_symbols(pk, nk, (const float2 *)j.H, sk, xk, s.ainv, s.wsScale, s.wsZ, stream);
             }

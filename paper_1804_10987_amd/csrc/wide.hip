@@ -36,6 +36,12 @@
 // Status of every system: PRECODE_ST_FP64, plus PRECODE_ST_FAIL when a pivot
 // is not above kRelPivot64 times its original diagonal entry or t is not
 // positive (then x = 0 and the scale output is 0).
+//
+// Modes: the whole chain in one launch; or a prepare launch that stores
+// scale A^-1 (FP64, an NP x NP slot per system) with beta / weights and
+// status, and symbol launches that precode released symbols from it (the
+// B_c x B_c form stages H_c^H again, the U x U form its rows) -- the frame
+// API and serving.
 #include "common.h"
 
 #include <algorithm>
@@ -46,6 +52,9 @@ namespace {
 constexpr int kWT = 256;  // threads per workgroup
 constexpr int kWKC = 16;  // symbols per chunk
 constexpr int kWSR = 64;  // rows staged per chunk
+// modes: Gram to precode; Gram to the factors scale A^-1 (FP64, an NP x NP
+// slot per system) with beta / weights and status; precode from the factors
+enum { kWFull = 0, kWPrep = 1, kWSym = 2 };
 
 template <int NP>
 struct WideL {
@@ -71,9 +80,10 @@ __device__ __forceinline__ double rcp_nr(double v) {
 typedef double wf64x4 __attribute__((ext_vector_type(4)));
 
 template <int NP>
-__device__ __forceinline__ void wide_system(const Prob *__restrict__ pk, int sys, int K, const float2 *__restrict__ H,
-                            const float2 *__restrict__ s, float2 *__restrict__ x, float *__restrict__ scale_out,
-                            int *__restrict__ status, char *lds) {
+__device__ __forceinline__ void wide_system(const Prob *__restrict__ pk, int sys, int K, int mode,
+                                            const float2 *__restrict__ H, const float2 *__restrict__ s,
+                                            float2 *__restrict__ x, float *__restrict__ scale_out,
+                                            int *__restrict__ status, cx<double> *__restrict__ fac, char *lds) {
     constexpr int E = WideL<NP>::E, G = WideL<NP>::G, PER = WideL<NP>::PER, KC = kWKC, SR = kWSR;
     constexpr int MS = (KC + G - 1) / G;  // symbols per thread in the solve: sg + G m < KC
     const int tid = threadIdx.x, bi = tid >> 4, bj = tid & 15;
@@ -129,8 +139,11 @@ __device__ __forceinline__ void wide_system(const Prob *__restrict__ pk, int sys
             if (e < ne) st[(e % U) * NP + e / U] = make_float2(v[m].x, -v[m].y);
         }
     }
-    const int nch = bform ? 1 : (nrows + SR - 1) / SR;
+    bool ok = true;
+    double scale = 1.0;
     float2 pre[PER];
+    if (mode != kWSym) {
+    const int nch = bform ? 1 : (nrows + SR - 1) / SR;
     if (!bform) {
         const int ne = min(SR, nrows) * U;
 #pragma unroll
@@ -260,7 +273,6 @@ __device__ __forceinline__ void wide_system(const Prob *__restrict__ pk, int sys
             }
 
     // ---- Gauss-Jordan, steps k < N (the identity past N is its own inverse)
-    bool ok = true;
     cx<double> *rb = ainv;  // two row buffers [2][NP]
     for (int k = 0; k < N; ++k) {
         cx<double> *buf = rb + (k & 1) * NP;
@@ -335,7 +347,8 @@ __device__ __forceinline__ void wide_system(const Prob *__restrict__ pk, int sys
     fro = red[4] + red[5] + red[6] + red[7];
     const double t = tr - kap * fro;
     ok = ok && t > 0.0 && t < (double)INFINITY;
-    double out = 0.0, scale = 0.0;
+    double out = 0.0;
+    scale = 0.0;
     if (ok) {
         if (pd) {
             out = sqrt((double)pk->Es / (double)pk->power * t);  // beta
@@ -349,10 +362,27 @@ __device__ __forceinline__ void wide_system(const Prob *__restrict__ pk, int sys
         if (scale_out) scale_out[sys] = (float)out;
         if (status) status[sys] = (ok ? PRECODE_ST_OK : PRECODE_ST_FAIL) | PRECODE_ST_FP64;
     }
+    if (mode == kWPrep) {
+        // scale A^-1 to the system's slot for the symbol passes
+        cx<double> *f = fac + (size_t)sys * NP * NP;
+#pragma unroll
+        for (int a = 0; a < E; ++a)
+#pragma unroll
+            for (int b = 0; b < E; ++b)
+                f[(E * bi + a) * NP + E * bj + b] = {ok ? scale * gr[a][b] : 0.0, ok ? scale * gi[a][b] : 0.0};
+        return;
+    }
 #pragma unroll
     for (int a = 0; a < E; ++a)
 #pragma unroll
         for (int b = 0; b < E; ++b) ainv[(E * bi + a) * NP + E * bj + b] = {gr[a][b], gi[a][b]};
+    } else {
+        // a symbol pass: scale A^-1 and the status from the prepare pass
+        const cx<double> *f = fac + (size_t)sys * NP * NP;
+        for (int e = tid; e < NP * NP; e += kWT) ainv[e] = f[e];
+        ok = !status || !(status[sys] & PRECODE_ST_FAIL);
+        scale = 1.0;
+    }
 
     // ---- symbols, KC at a time
     // solve: system row si, symbol group sg (symbols sg + G m < KC; threads
@@ -489,12 +519,13 @@ constexpr int wide_min_waves() { return NP == 16 ? 4 : (NP == 32 ? 2 : 1); }
 
 template <int NP>
 __global__ void __launch_bounds__(kWT, (wide_min_waves<NP>()))
-    wide_k(Prob p, int K, const float2 *__restrict__ H, const float2 *__restrict__ s, float2 *__restrict__ x,
-           float *__restrict__ scale_out, int *__restrict__ status) {
+    wide_k(Prob p, int K, int mode, const float2 *__restrict__ H, const float2 *__restrict__ s,
+           float2 *__restrict__ x, float *__restrict__ scale_out, int *__restrict__ status,
+           cx<double> *__restrict__ fac) {
     extern __shared__ float4 smem_wide[];
     const Prob *pk = (const Prob *)__builtin_amdgcn_kernarg_segment_ptr();  // p: the first argument
     (void)p;
-    wide_system<NP>(pk, blockIdx.x, K, H, s, x, scale_out, status, (char *)smem_wide);
+    wide_system<NP>(pk, blockIdx.x, K, mode, H, s, x, scale_out, status, fac, (char *)smem_wide);
 }
 
 template <int NP>
@@ -512,7 +543,7 @@ __global__ void __launch_bounds__(kWT, (wide_min_waves<NP>()))
     // an entry holds every system of its problem, or (cl >= 0) cluster cl of every subcarrier
     const int lb = b - en.block0;
     const int sys = en.cl < 0 ? lb : lb * en.p.C + en.cl;
-    wide_system<NP>(&en.p, sys, en.K, en.H, en.s, en.x, en.scale_out, en.status, (char *)smem_wide);
+    wide_system<NP>(&en.p, sys, en.K, kWFull, en.H, en.s, en.x, en.scale_out, en.status, nullptr, (char *)smem_wide);
 }
 
 template <typename F>
@@ -522,14 +553,25 @@ hipError_t set_lds(F fn, size_t lds) {
 }
 
 template <int NP>
-hipError_t launch_wide(const Prob &p, const float2 *H, const float2 *s, float2 *x, float *scale_out, int *status,
-                       hipStream_t st) {
+hipError_t launch_wide(const Prob &p, int K, int mode, const float2 *H, const float2 *s, float2 *x, float *scale_out,
+                       int *status, cx<double> *fac, hipStream_t st) {
     const size_t lds = WideL<NP>::bytes;
     hipError_t e = set_lds(wide_k<NP>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((wide_k<NP>), dim3((unsigned)n_inst(p)), dim3(kWT), lds, st, p, p.K, H, s, x, scale_out,
-                       status);
+    hipLaunchKernelGGL((wide_k<NP>), dim3((unsigned)n_inst(p)), dim3(kWT), lds, st, p, K, mode, H, s, x, scale_out,
+                       status, fac);
     return hipGetLastError();
+}
+
+hipError_t wide_dispatch(const Prob &p, int K, int mode, const float2 *H, const float2 *s, float2 *x,
+                         float *scale_out, int *status, cx<double> *fac, hipStream_t st) {
+    if (n_inst(p) == 0) return hipSuccess;
+    switch (wide_order(p)) {
+        case 16: return launch_wide<16>(p, K, mode, H, s, x, scale_out, status, fac, st);
+        case 32: return launch_wide<32>(p, K, mode, H, s, x, scale_out, status, fac, st);
+        case 48: return launch_wide<48>(p, K, mode, H, s, x, scale_out, status, fac, st);
+        default: return launch_wide<64>(p, K, mode, H, s, x, scale_out, status, fac, st);
+    }
 }
 
 template <int NP>
@@ -561,13 +603,22 @@ int wide_order(const Prob &p) {
 
 hipError_t wide_run(const Prob &p, const float2 *H, const float2 *s, float2 *x, float *scale_out, int *status,
                     hipStream_t st) {
-    if (n_inst(p) == 0) return hipSuccess;
-    switch (wide_order(p)) {
-        case 16: return launch_wide<16>(p, H, s, x, scale_out, status, st);
-        case 32: return launch_wide<32>(p, H, s, x, scale_out, status, st);
-        case 48: return launch_wide<48>(p, H, s, x, scale_out, status, st);
-        default: return launch_wide<64>(p, H, s, x, scale_out, status, st);
-    }
+    return wide_dispatch(p, p.K, kWFull, H, s, x, scale_out, status, nullptr, st);
+}
+
+size_t wide_factor_bytes(const Prob &p) {
+    const size_t np = (size_t)wide_order(p);
+    return (size_t)n_inst(p) * np * np * sizeof(cx<double>);
+}
+
+hipError_t wide_prepare(const Prob &p, const float2 *H, void *fac, float *scale_out, int *status, hipStream_t st) {
+    return wide_dispatch(p, 0, kWPrep, H, nullptr, nullptr, scale_out, status, (cx<double> *)fac, st);
+}
+
+hipError_t wide_symbols(const Prob &p, int nk, const float2 *H, const void *fac, const int *status, const float2 *s,
+                        float2 *x, hipStream_t st) {
+    if (nk == 0) return hipSuccess;
+    return wide_dispatch(p, nk, kWSym, H, s, x, nullptr, (int *)status, (cx<double> *)fac, st);
 }
 
 hipError_t wide_batch_launch(int order, const BatchEntry *tab, int n, int blocks, hipStream_t st) {

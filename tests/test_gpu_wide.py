@@ -209,3 +209,62 @@ def test_batch_cell_mix_fused(torch, ctx, pc, uneven):
         # FP32 tiles on the FP32 route: 1e-5; the FP64 kernels: tighter
         _check(x, sc, st, xo, sco, sto, tol=1e-5)
     plan.destroy()
+
+
+FRAME_CELLS = [
+    ("pd_u40", "pd", synth.Cell(B=128, sizes=(64, 64), U=40, n_sc=7, K=17, snr_db=10.0)),
+    ("fd_bform_u40", "fd", synth.Cell(B=96, sizes=(16, 32, 48), U=40, n_sc=6, K=17, snr_db=10.0)),
+    ("fd_small_u24", "fd", synth.Cell(B=44, sizes=(4, 12, 8, 20), U=24, n_sc=5, K=17, snr_db=5.0)),
+]
+
+
+@pytest.mark.parametrize("name,arch,cell", FRAME_CELLS, ids=[c[0] for c in FRAME_CELLS])
+def test_wide_frame_api(torch, ctx, pc, name, arch, cell):
+    """The frame split on the wide FP64 kernel: prepare stores scale A^-1 in
+    FP64, symbols are precoded from it in two passes (across a 16-symbol
+    chunk boundary); the same result as the one-launch call to within FP64
+    rounding, and the oracle's."""
+    H, s = synth.make_cell(cell, seed=76)
+    Hd, sd = _dev(torch, H), _dev(torch, s)
+    fr = ctx.frame(arch, Hd, cell.kappa, cell.sizes, "wf", pc.params())
+    assert ctx.last_impl == "fused"
+    xs = [fr.symbols(sd[0:5].contiguous()), fr.symbols(sd[5:17].contiguous())]
+    w, st = fr.factors()
+    torch.cuda.synchronize()
+    x = torch.cat(xs, 0)
+    fr.release()
+    fn = ctx.pd if arch == "pd" else ctx.fd
+    x1, w1, st1 = fn(Hd, sd, cell.kappa, cell.sizes, "wf", pc.params())
+    torch.cuda.synchronize()
+    assert torch.equal(st.flatten(), st1.flatten()) and torch.equal(w.flatten(), w1.flatten())
+    assert _vec_err(x.cpu().numpy(), x1.cpu().numpy()).max() <= 1e-7
+    xo, sco, sto = _oracle(arch, H, s, cell.kappa, cell.sizes, "wf")
+    _check(x, w, st, xo, sco, sto)
+
+
+@pytest.mark.parametrize("period", [5e-5, 0.0], ids=["released", "all_at_arrival"])
+def test_wide_serving(torch, ctx, pc, period):
+    """Serving jobs the register-tile kernels do not take (U = 64, clusters
+    smaller than U, FP64-route cells) on the wide kernel: prepare and symbol
+    passes, or one launch when every symbol is released at arrival; each job
+    bitwise the same alone and in the mix, and the oracle's."""
+    cells = [("pd", synth.Cell(B=128, sizes=(128,), U=64, n_sc=6, K=14, snr_db=10.0)),
+             ("fd", synth.Cell(B=96, sizes=(16, 32, 48), U=40, n_sc=5, K=14, snr_db=10.0)),
+             ("fd", synth.Cell(B=256, sizes=(32,) * 8, U=16, n_sc=9, K=14, snr_db=10.0)),
+             ("pd", synth.Cell(B=64, sizes=(32, 32), U=8, n_sc=10, K=14))]
+    jobs, host = [], []
+    for i, (arch, c) in enumerate(cells):
+        H, s = synth.make_cell(c, seed=77, cell_id=i)
+        jobs.append(dict(arch=arch, mode="wf", H=_dev(torch, H), s=_dev(torch, s), rho=c.kappa, sizes=c.sizes))
+        host.append((arch, c, H, s))
+    outs, lat, stt = ctx.serve(jobs, [0.0, 0.0001, 0.0002, 0.0002], symbol_period_s=period, max_active=3,
+                               n_streams=2)
+    torch.cuda.synchronize()
+    assert stt["jobs_done"] == len(jobs) and stt["symbols_done"] == 14 * len(jobs)
+    for i, ((arch, c, H, s), (x, sc, st)) in enumerate(zip(host, outs)):
+        print("wide serving job %d %s U=%d" % (i, arch, c.U), flush=True)
+        (xa, sca, sta), = ctx.serve([jobs[i]], [0.0], symbol_period_s=period, max_active=1, n_streams=1)[0]
+        torch.cuda.synchronize()
+        assert torch.equal(x, xa) and torch.equal(sc, sca)
+        xo, sco, sto = _oracle(arch, H, s, c.kappa, c.sizes, "wf")
+        _check(x, sc, st, xo, sco, sto, tol=1e-5)
