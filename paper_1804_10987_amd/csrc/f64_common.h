@@ -22,7 +22,14 @@ struct F64L {
     static constexpr size_t s_bytes = (size_t)KC * UP * 8;
     static constexpr size_t z64_bytes = (size_t)KC * UP * 16;
     static constexpr size_t rowbuf_bytes = (size_t)UP * 16;
-    static constexpr size_t per_wave(bool p64) { return rows_bytes + (p64 ? z64_bytes : 0) + rowbuf_bytes; }
+    // at 32 users the Gram passes through LDS as a full 32 x 32 complex FP64
+    // matrix (gram32_to_regs), overlaying the rows and the FP64 Z chunk
+    static constexpr size_t gram_bytes = UP == 32 ? (size_t)UP * UP * 16 : 0;
+    static constexpr size_t base_bytes(bool p64) {
+        return rows_bytes + (p64 ? z64_bytes : 0) > gram_bytes ? rows_bytes + (p64 ? z64_bytes : 0) : gram_bytes;
+    }
+    // the inversion's row buffer follows
+    static constexpr size_t per_wave(bool p64) { return base_bytes(p64) + rowbuf_bytes; }
     static_assert(2 * s_bytes <= rows_bytes, "symbol and FP32 Z chunks overlay the rows");
     // symbols a lane loads per chunk
     static constexpr int SPL = UP * KC / 64;
@@ -152,6 +159,75 @@ __device__ __forceinline__ void gram_mfma16(const float2 *__restrict__ Hn, int U
         gre[q] = are[q];
         gim[q] = aim[q];
     }
+}
+
+// G += H^H H over the 32-row tile at row0 (rows past nrows zero) of a system
+// with 17..32 users, on FP64 MFMA: the blocks (0,0), (0,1), (1,1) of users
+// 0..15 / 16..31, with the operand layout of gram_mfma16 (lane l feeds
+// row row0 + 4 s + l / 16, user l % 16 of its block), into acc[2 t] (real
+// part) and acc[2 t + 1] (imaginary part) of block t.  The tile's loads are
+// all issued first, from clamped in-range addresses.
+__device__ __forceinline__ void gram_mfma32_tile(const float2 *__restrict__ Hn, int U, int row0, int nrows,
+                                                 f64x4 (&acc)[6]) {
+    const int lane = lane_id();
+    const int kr = lane >> 4, u = lane & 15;
+    const float2 *src = Hn + (size_t)row0 * U;
+    float2 h0[8], h1[8];
+#pragma unroll
+    for (int st = 0; st < 8; ++st) {
+        const int row = 4 * st + kr;
+        h0[st] = src[row < nrows && u < U ? row * U + u : 0];
+        h1[st] = src[row < nrows && 16 + u < U ? row * U + 16 + u : 0];
+    }
+#pragma unroll
+    for (int st = 0; st < 8; ++st) {
+        // masked at the use, so that no select waits on a load in flight
+        const bool rin = 4 * st + kr < nrows;
+        const bool in0 = rin && u < U, in1 = rin && 16 + u < U;
+        const double a = in0 ? h0[st].x : 0.0, b = in0 ? h0[st].y : 0.0;
+        const double c = in1 ? h1[st].x : 0.0, d = in1 ? h1[st].y : 0.0;
+        // conj(h_i) h_j: Re = a_i a'_j + b_i b'_j, Im = a_i b'_j - b_i a'_j
+        acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, a, acc[0], 0, 0, 0);
+        acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b, b, acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[1], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(-b, a, acc[1], 0, 0, 0);
+        acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, c, acc[2], 0, 0, 0);
+        acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(b, d, acc[2], 0, 0, 0);
+        acc[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, d, acc[3], 0, 0, 0);
+        acc[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(-b, c, acc[3], 0, 0, 0);
+        acc[4] = __builtin_amdgcn_mfma_f64_16x16x4f64(c, c, acc[4], 0, 0, 0);
+        acc[4] = __builtin_amdgcn_mfma_f64_16x16x4f64(d, d, acc[4], 0, 0, 0);
+        acc[5] = __builtin_amdgcn_mfma_f64_16x16x4f64(c, d, acc[5], 0, 0, 0);
+        acc[5] = __builtin_amdgcn_mfma_f64_16x16x4f64(-d, c, acc[5], 0, 0, 0);
+    }
+}
+
+// The 32 x 32 Hermitian Gram of gram_mfma32_tile's blocks in the register
+// layout of UP = 32 (lane (r, c) holds G[2 s + r][c], s < 16), through this
+// wave's LDS (gbuf: 32 x 32 complex FP64; block D[i][j] sits in lane
+// (i % 4) 16 + j, register i / 4; block (1,0) is block (0,1) conjugated and
+// transposed).
+__device__ __forceinline__ void gram32_to_regs(const f64x4 (&acc)[6], cx<double> *gbuf, double (&gre)[16],
+                                               double (&gim)[16]) {
+    const int lane = lane_id();
+    const int kr = lane >> 4, u = lane & 15;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int i = 4 * q + kr;
+        gbuf[i * 32 + u] = {acc[0][q], acc[1][q]};
+        gbuf[i * 32 + 16 + u] = {acc[2][q], acc[3][q]};
+        gbuf[(16 + u) * 32 + i] = {acc[2][q], -acc[3][q]};
+        gbuf[(16 + i) * 32 + 16 + u] = {acc[4][q], acc[5][q]};
+    }
+    wave_sync();
+    const int r = lane >> 5, c = lane & 31;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        const cx<double> g = gbuf[(2 * s + r) * 32 + c];
+        gre[s] = g.re;
+        gim[s] = g.im;
+    }
+    wave_sync();  // the area is rewritten by the staged symbols and rows
 }
 
 // G[s R + r][c] += sum over the staged tile's 32 rows of conj(h_{s R + r}) h_c.

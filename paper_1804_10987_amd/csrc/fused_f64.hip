@@ -9,12 +9,11 @@
 // (lane / UP, lane % UP) holds column c of rows s R + r, s < NS (R = 64 / UP
 // row groups, NS = UP / R slots), in FP64.
 //
-//   Gram      G_c = H_c^H H_c in FP64, straight into the register layout:
-//             at 16 users on FP64 MFMA from coalesced loads (gram_mfma16);
-//             at 32 on the VALU from each 32-row tile staged in LDS as
-//             complex64 (coalesced loads of the system's contiguous rows, its
-//             users permuted so that the NS users a lane multiplies are
-//             contiguous); complex64 products are exact in FP64
+//   Gram      G_c = H_c^H H_c in FP64 on FP64 MFMA from coalesced loads:
+//             at 16 users straight into the register layout (gram_mfma16);
+//             at 32 its blocks (0,0), (0,1), (1,1) per 32-row tile
+//             (gram_mfma32_tile), then through LDS into the register layout;
+//             complex64 products are exact in FP64
 //   invert    A_c = G_c + kappa_c I (scaled by a power of two, as the FP32
 //             inversion) inverted by Gauss-Jordan without pivoting (Hermitian
 //             positive definite).  Before step k the matrix is
@@ -117,7 +116,7 @@ __device__ __forceinline__ void f64_system(const Prob &p, const Prob *__restrict
     cx<float> *sb = (cx<float> *)wb;                                     // [KC][UP] symbols (upos order)
     cx<float> *zb32 = (cx<float> *)(wb + F64L<UP>::s_bytes);             // [UP][KC] Z chunk (FP32 precode)
     cx<double> *zb = (cx<double> *)(wb + F64L<UP>::rows_bytes);          // [KC][UP] Z chunk (FP64 precode)
-    cx<double> *rowbuf = (cx<double> *)(wb + F64L<UP>::rows_bytes + (P64 ? F64L<UP>::z64_bytes : 0));
+    cx<double> *rowbuf = (cx<double> *)(wb + F64L<UP>::base_bytes(P64));
     const double kap = pd ? (double)pd_kappa(p) : (double)fd_kappa_c(pk, cl);
 
     // Gram in FP64, tile by tile through the staged rows (no tile is held in
@@ -128,15 +127,14 @@ __device__ __forceinline__ void f64_system(const Prob &p, const Prob *__restrict
     if constexpr (UP == 16) {
         gram_mfma16<NT>(Hn, U, r0, nrows, gre, gim);
     } else {
+        f64x4 acc[6];
 #pragma unroll
-        for (int q = 0; q < NT; ++q) {
-            if (32 * q < nrows) {
-                stage_rows_direct<UP>(Hn, U, r0 + 32 * q, min(32, nrows - 32 * q), rowsL);
-                wave_sync();
-                gram_rows<UP>(rowsL, gre, gim);
-                wave_sync();  // the staging area is rewritten by the next tile and the symbols
-            }
-        }
+        for (int t = 0; t < 6; ++t) acc[t] = (f64x4){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int q = 0; q < NT; ++q)
+            if (32 * q < nrows) gram_mfma32_tile(Hn, U, r0 + 32 * q, min(32, nrows - 32 * q), acc);
+        gram32_to_regs(acc, (cx<double> *)wb, gre, gim);
+        (void)rowsL;
     }
     // the first symbol chunk, in flight during the inversion
     float2 sym[F64L<UP>::SPL];

@@ -6,10 +6,10 @@
 // and status) into a workspace of factors F = scale A^-1 (scale 1/beta for
 // PD, w_c for FD), then this kernel, one wave per local system:
 //
-//   Gram      G = H^H H accumulated in FP64 over all the system's rows (32-row
-//             tiles staged in LDS, f64_common.h); complex64 products are
-//             exact in FP64, so A = G + kappa I is the exact regularized
-//             system the factorization rounded
+//   Gram      G = H^H H accumulated in FP64 over all the system's rows on
+//             FP64 MFMA, 32-row tiles loaded coalesced (f64_common.h);
+//             complex64 products are exact in FP64, so A = G + kappa I is the
+//             exact regularized system the factorization rounded
 //   solve     Z = F S per chunk of 16 symbols, in FP64 from the FP32 factor
 //   residual  r = S - A Z / scale in FP64: with y = Z / scale the solution of
 //             A y = S as solved, r = s - (kappa y + H^H (H y)) up to FP64
@@ -26,14 +26,16 @@
 namespace pc {
 namespace {
 
-// Waves per workgroup and LDS per wave: the rows area (staged rows, then the
-// symbol chunk [KC][UP] and the complex64 Z chunk [UP][KC]) and two FP64
-// chunks [KC][UP] (Z, then the residual).
+// Waves per workgroup and LDS per wave: the rows area (the symbol chunk
+// [KC][UP] and the complex64 Z chunk [UP][KC]) and two FP64 chunks [KC][UP]
+// (Z, then the residual); at 32 users the Gram passes through the first
+// 16 KiB first.
 template <int UP>
 struct RefL {
     static constexpr int waves = UP == 16 ? 4 : 2;
     static constexpr size_t per_wave = F64L<UP>::rows_bytes + 2 * F64L<UP>::z64_bytes;
     static_assert(per_wave >= f64r::lds_bytes(UP), "FP64 retry area");
+    static_assert(per_wave >= F64L<UP>::gram_bytes, "Gram area at 32 users");
 };
 
 // v = M w over one chunk: lane (r, c) holds M[c][q R + r] (mre / mim, q < NS);
@@ -86,7 +88,6 @@ __device__ __forceinline__ void refine_system(const Prob &p, const Prob *__restr
         return;
     }
     const float2 *Hn = H + (size_t)n * B * U;
-    float2 *rowsL = (float2 *)wb;                                              // [32][UP] staged rows
     cx<float> *sb = (cx<float> *)wb;                                          // [KC][UP] symbols (upos order)
     cx<float> *zb32 = (cx<float> *)(wb + F64L<UP>::s_bytes);                  // [UP][KC] refined Z (complex64)
     cx<double> *zb = (cx<double> *)(wb + F64L<UP>::rows_bytes);               // [KC][UP] Z (upos order)
@@ -100,15 +101,16 @@ __device__ __forceinline__ void refine_system(const Prob &p, const Prob *__restr
     double are[NS], aim[NS];
 #pragma unroll
     for (int q = 0; q < NS; ++q) are[q] = aim[q] = 0.0;
-    for (int t = 0; t < ntile; ++t) {
-        if constexpr (UP == 16) {
+    if constexpr (UP == 16) {
+        for (int t = 0; t < ntile; ++t)
             gram_mfma16<1>(Hn, U, r0 + 32 * t, min(32, nrows - 32 * t), are, aim);  // FP64 MFMA
-        } else {
-            stage_rows_direct<UP>(Hn, U, r0 + 32 * t, min(32, nrows - 32 * t), rowsL);
-            wave_sync();
-            gram_rows<UP>(rowsL, are, aim);
-            wave_sync();
-        }
+    } else {
+        // FP64 MFMA blocks per tile, then through LDS into the column layout
+        f64x4 acc[6];
+#pragma unroll
+        for (int t = 0; t < 6; ++t) acc[t] = (f64x4){0.0, 0.0, 0.0, 0.0};
+        for (int t = 0; t < ntile; ++t) gram_mfma32_tile(Hn, U, r0 + 32 * t, min(32, nrows - 32 * t), acc);
+        gram32_to_regs(acc, (cx<double> *)wb, are, aim);
     }
 #pragma unroll
     for (int q = 0; q < NS; ++q)
