@@ -23,9 +23,11 @@
 //             its column-k entries
 //   factor    t = tr A^-1 - kappa ||A^-1||_F^2 (Lemma 1) in FP64; PD beta,
 //             FD w_c = sqrt(rho_c^2 / (t Es)) (Sec. III-C)
-//   solve     Z = scale A^-1 S in FP64 per chunk of 16 symbols: A^-1 is
-//             Hermitian, so lane (r, c) forms the part of Z[c][k] over its own
-//             rows from its column and the row groups add their parts
+//   solve     Z = scale A^-1 S in FP64 per chunk of 16 symbols: at 16 users
+//             on FP64 MFMA (Z^T = S^T conj(A^-1), the inverse's register
+//             layout is the B operand); at 32, A^-1 being Hermitian, lane
+//             (r, c) forms the part of Z[c][k] over its own rows from its
+//             column and the row groups add their parts
 //   precode   X_c = H_c Z (Sec. III-B/C) from register tiles loaded again
 //             after the inversion: accumulated in FP64 for ZF and for local
 //             systems with U / B_eff > 3/4 (precode_in_fp64), otherwise on
@@ -211,10 +213,36 @@ __device__ __forceinline__ void f64_system(const Prob &p, const Prob *__restrict
         if (k0 > 0) load_syms<UP>(s, k0, kc, n, n_sc, U, sym);
         stage_syms<UP>(sym, kc, U, sb);
         wave_sync();
-        // Z[c][k] = scale sum_i conj(A^-1[i][c]) S[i][k] (A^-1 Hermitian): this
-        // lane's rows i = q R + r, then the row groups' parts added; KU
+        // Z[c][k] = scale sum_i conj(A^-1[i][c]) S[i][k] (A^-1 Hermitian)
+        if constexpr (UP == 16) {
+            // Z^T = S^T conj(A^-1) on FP64 MFMA, K step q over users 4 q ..
+            // 4 q + 3: lane (r, c) feeds S[4 q + r][c] (user 4 q + r, symbol
+            // c) as A[c][r] and its slot q, conj(A^-1[4 q + r][c]), as B[r][c];
+            // D[k][c] = Z[c][k] lands in lane (k % 4, c), register k / 4
+            f64x4 dre = {0.0, 0.0, 0.0, 0.0}, dim = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int q = 0; q < NS; ++q) {
+                const cx<float> sv = sb[c * UP + upos<UP>(q * R + r)];
+                const double sr = sv.re, si = sv.im;
+                dre = __builtin_amdgcn_mfma_f64_16x16x4f64(sr, gre[q], dre, 0, 0, 0);
+                dre = __builtin_amdgcn_mfma_f64_16x16x4f64(si, gim[q], dre, 0, 0, 0);
+                dim = __builtin_amdgcn_mfma_f64_16x16x4f64(si, gre[q], dim, 0, 0, 0);
+                dim = __builtin_amdgcn_mfma_f64_16x16x4f64(-sr, gim[q], dim, 0, 0, 0);
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int k = 4 * t + r;
+                const bool live = ok && c < U && k < kc;
+                const double a = live ? scale * dre[t] : 0.0, b = live ? scale * dim[t] : 0.0;
+                if constexpr (P64)
+                    zb[k * UP + c] = {a, b};
+                else
+                    zb32[c * KC + k] = {(float)a, (float)b};
+            }
+        }
+        // this lane's rows i = q R + r, then the row groups' parts added; KU
         // symbols per pass (independent accumulation chains)
-        for (int k4 = 0; k4 < KC; k4 += KU) {
+        for (int k4 = 0; k4 < (UP == 16 ? 0 : KC); k4 += KU) {
             double zr[KU], zi[KU];
 #pragma unroll
             for (int u = 0; u < KU; ++u) zr[u] = zi[u] = 0.0;
