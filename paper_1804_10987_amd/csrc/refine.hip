@@ -68,6 +68,42 @@ __device__ __forceinline__ void apply_rows(const double (&mre)[F64L<UP>::NS], co
     vi = group_sum_d<UP>(vi);
 }
 
+// apply_rows for all 16 symbols of a chunk at 16 users, on FP64 MFMA:
+// V^T = W^T M^T, K step q over indices 4 q .. 4 q + 3; lane (r, c) feeds
+// W[4 q + r][c] (index 4 q + r, symbol c) as A[c][r] and its slot q,
+// M[c][4 q + r], as B[r][c]; V[c][k] lands in lane (k % 4, c), register
+// k / 4 (vr[t], vi[t] for symbol 4 t + r).
+template <bool W32>
+__device__ __forceinline__ void apply_mfma16(const double (&mre)[4], const double (&mim)[4], const void *w,
+                                             double (&vr)[4], double (&vi)[4]) {
+    const int lane = lane_id();
+    const int r = lane >> 4, c = lane & 15;
+    f64x4 dre = {0.0, 0.0, 0.0, 0.0}, dim = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        double wr, wi;
+        const int e = c * 16 + upos<16>(4 * q + r);
+        if constexpr (W32) {
+            const cx<float> v = ((const cx<float> *)w)[e];
+            wr = v.re;
+            wi = v.im;
+        } else {
+            const cx<double> v = ((const cx<double> *)w)[e];
+            wr = v.re;
+            wi = v.im;
+        }
+        dre = __builtin_amdgcn_mfma_f64_16x16x4f64(wr, mre[q], dre, 0, 0, 0);
+        dre = __builtin_amdgcn_mfma_f64_16x16x4f64(-wi, mim[q], dre, 0, 0, 0);
+        dim = __builtin_amdgcn_mfma_f64_16x16x4f64(wi, mre[q], dim, 0, 0, 0);
+        dim = __builtin_amdgcn_mfma_f64_16x16x4f64(wr, mim[q], dim, 0, 0, 0);
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        vr[t] = dre[t];
+        vi[t] = dim[t];
+    }
+}
+
 template <int UP>
 __device__ __forceinline__ void refine_system(const Prob &p, const Prob *__restrict__ pk, int sys, int K,
                                               const float2 *__restrict__ H, const float2 *__restrict__ s,
@@ -136,6 +172,36 @@ __device__ __forceinline__ void refine_system(const Prob &p, const Prob *__restr
         load_syms<UP>(s, k0, kc, n, n_sc, U, sym);
         stage_syms<UP>(sym, kc, U, sb);
         wave_sync();
+        if constexpr (UP == 16) {
+            // the three products on FP64 MFMA, every lane writing its 4 symbols
+            double vr[4], vi[4];
+            // Z = F S
+            apply_mfma16<true>(fre, fim, sb, vr, vi);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) zb[(4 * t + r) * UP + upos<UP>(c)] = {vr[t], vi[t]};
+            wave_sync();
+            // r = S - A Z / scale
+            apply_mfma16<false>(are, aim, zb, vr, vi);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int k = 4 * t + r;
+                const cx<float> sk = sb[k * UP + upos<UP>(c)];
+                const bool live = ok && c < U && k < kc;
+                rb[k * UP + upos<UP>(c)] = {live ? (double)sk.re - vr[t] * inv_scale : 0.0,
+                                            live ? (double)sk.im - vi[t] * inv_scale : 0.0};
+            }
+            wave_sync();
+            // Z += F r, rounded to complex64 for the precode
+            apply_mfma16<false>(fre, fim, rb, vr, vi);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int k = 4 * t + r;
+                const cx<double> z = zb[k * UP + upos<UP>(c)];
+                const bool live = ok && c < U && k < kc;
+                zb32[c * KC + k] = {live ? (float)(z.re + vr[t]) : 0.f, live ? (float)(z.im + vi[t]) : 0.f};
+            }
+            wave_sync();
+        } else {
         // Z = F S
         for (int k = 0; k < KC; ++k) {
             double vr, vi;
@@ -166,6 +232,7 @@ __device__ __forceinline__ void refine_system(const Prob &p, const Prob *__restr
             }
         }
         wave_sync();
+        }
         ZOp<UP, kF32> z;
         make_zop<UP, kF32>(zb32, KC, 1, kc, z);
         for (int t = 0; t < ntile; ++t) {
