@@ -104,15 +104,133 @@ __device__ __forceinline__ void apply_mfma16(const double (&mre)[4], const doubl
     }
 }
 
+// A = G + kappa I in the column layout with its imaginary part negated
+// ((A Z)[c] = sum_i conj(A[i][c]) Z[i]), and F = scale A^-1 of system sys in
+// the row layout (lane (r, c) holds F[c][q R + r]).
+template <int UP>
+__device__ __forceinline__ void ref_setup(double (&are)[F64L<UP>::NS], double (&aim)[F64L<UP>::NS],
+                                          double (&fre)[F64L<UP>::NS], double (&fim)[F64L<UP>::NS], double kap,
+                                          int U, int sys, const cx<float> *__restrict__ fac) {
+    constexpr int R = F64L<UP>::R, NS = F64L<UP>::NS;
+    const int lane = lane_id();
+    const int r = lane / UP, c = lane % UP;
+#pragma unroll
+    for (int q = 0; q < NS; ++q)
+        if (q * R + r == c) are[q] += kap;
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        const int i = q * R + r;
+        const bool in = c < U && i < U;
+        const cx<float> v = fac[(size_t)sys * U * U + (in ? c * U + i : 0)];
+        fre[q] = in ? v.re : 0.0;
+        fim[q] = in ? v.im : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < NS; ++q) aim[q] = -aim[q];
+}
+
+// One chunk of kc symbols from k0: Z = F S, r = S - A Z / scale, Z += F r
+// (FP64), the refined Z rounded to complex64 into zb32 ([UP][KC]).  Ends
+// with zb32 complete in this wave.
+template <int UP>
+__device__ __forceinline__ void ref_products(const double (&are)[F64L<UP>::NS], const double (&aim)[F64L<UP>::NS],
+                                             const double (&fre)[F64L<UP>::NS], const double (&fim)[F64L<UP>::NS],
+                                             bool ok, double inv_scale, const float2 *__restrict__ s, int k0,
+                                             int kc, int n, int n_sc, int U, cx<float> *sb, cx<double> *zb,
+                                             cx<double> *rb, cx<float> *zb32) {
+    const int lane = lane_id();
+    const int r = lane / UP, c = lane % UP;
+    float2 sym[F64L<UP>::SPL];
+    load_syms<UP>(s, k0, kc, n, n_sc, U, sym);
+    stage_syms<UP>(sym, kc, U, sb);
+    wave_sync();
+    if constexpr (UP == 16) {
+        // the three products on FP64 MFMA, every lane writing its 4 symbols
+        double vr[4], vi[4];
+        // Z = F S
+        apply_mfma16<true>(fre, fim, sb, vr, vi);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) zb[(4 * t + r) * UP + upos<UP>(c)] = {vr[t], vi[t]};
+        wave_sync();
+        // r = S - A Z / scale
+        apply_mfma16<false>(are, aim, zb, vr, vi);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int k = 4 * t + r;
+            const cx<float> sk = sb[k * UP + upos<UP>(c)];
+            const bool live = ok && c < U && k < kc;
+            rb[k * UP + upos<UP>(c)] = {live ? (double)sk.re - vr[t] * inv_scale : 0.0,
+                                        live ? (double)sk.im - vi[t] * inv_scale : 0.0};
+        }
+        wave_sync();
+        // Z += F r, rounded to complex64 for the precode
+        apply_mfma16<false>(fre, fim, rb, vr, vi);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int k = 4 * t + r;
+            const cx<double> z = zb[k * UP + upos<UP>(c)];
+            const bool live = ok && c < U && k < kc;
+            zb32[c * KC + k] = {live ? (float)(z.re + vr[t]) : 0.f, live ? (float)(z.im + vi[t]) : 0.f};
+        }
+        wave_sync();
+    } else {
+        // Z = F S
+        for (int k = 0; k < KC; ++k) {
+            double vr, vi;
+            apply_rows<UP, true>(fre, fim, sb, k, vr, vi);
+            if (r == 0) zb[k * UP + upos<UP>(c)] = {vr, vi};
+        }
+        wave_sync();
+        // r = S - A Z / scale
+        for (int k = 0; k < KC; ++k) {
+            double vr, vi;
+            apply_rows<UP, false>(are, aim, zb, k, vr, vi);
+            if (r == 0) {
+                const cx<float> sk = sb[k * UP + upos<UP>(c)];
+                const bool live = ok && c < U && k < kc;
+                rb[k * UP + upos<UP>(c)] = {live ? (double)sk.re - vr * inv_scale : 0.0,
+                                            live ? (double)sk.im - vi * inv_scale : 0.0};
+            }
+        }
+        wave_sync();
+        // Z += F r, rounded to complex64 for the precode
+        for (int k = 0; k < KC; ++k) {
+            double vr, vi;
+            apply_rows<UP, false>(fre, fim, rb, k, vr, vi);
+            if (r == 0) {
+                const cx<double> z = zb[k * UP + upos<UP>(c)];
+                const bool live = ok && c < U && k < kc;
+                zb32[c * KC + k] = {live ? (float)(z.re + vr) : 0.f, live ? (float)(z.im + vi) : 0.f};
+            }
+        }
+        wave_sync();
+    }
+}
+
+// X = H Z for the row tiles t0, t0 + dt, ... of a system on FP32 MFMA from
+// the refined Z chunk zb32, the tiles loaded again.
+template <int UP>
+__device__ __forceinline__ void ref_precode(const float2 *__restrict__ Hn, int U, int r0, int nrows, int t0, int dt,
+                                            const cx<float> *zb32, int k0, int kc, int n, int n_sc, int B,
+                                            float2 *__restrict__ x) {
+    const int ntile = (nrows + 31) >> 5;
+    ZOp<UP, kF32> z;
+    make_zop<UP, kF32>(zb32, KC, 1, kc, z);
+    for (int t = t0; t < ntile; t += dt) {
+        Tile<UP, kF32> tq;
+        const int nt = min(32, nrows - 32 * t);
+        load_tile<UP, kF32, false>(Hn, U, r0 + 32 * t, nt, tq);
+        store_x(mfma_apply_packed<UP, kF32>(tq, z), r0 + 32 * t, nt, k0, kc, n, n_sc, B, x);
+    }
+}
+
 template <int UP>
 __device__ __forceinline__ void refine_system(const Prob &p, const Prob *__restrict__ pk, int sys, int K,
                                               const float2 *__restrict__ H, const float2 *__restrict__ s,
                                               float2 *__restrict__ x, const cx<float> *__restrict__ fac,
                                               const float *__restrict__ scale_in, const int *__restrict__ status,
                                               char *wb) {
-    constexpr int R = F64L<UP>::R, NS = F64L<UP>::NS;
-    const int lane = lane_id();
-    const int r = lane / UP, c = lane % UP;
+    constexpr int NS = F64L<UP>::NS;
     const bool pd = p.arch == kPD;
     const int B = p.B, U = p.U, C = p.C, n_sc = p.n_sc;
     const int n = pd ? sys : sys / C;
@@ -148,100 +266,121 @@ __device__ __forceinline__ void refine_system(const Prob &p, const Prob *__restr
         for (int t = 0; t < ntile; ++t) gram_mfma32_tile(Hn, U, r0 + 32 * t, min(32, nrows - 32 * t), acc);
         gram32_to_regs(acc, (cx<double> *)wb, are, aim);
     }
-#pragma unroll
-    for (int q = 0; q < NS; ++q)
-        if (q * R + r == c) are[q] += kap;
-    // F in row layout: lane (r, c) holds F[c][q R + r]
     double fre[NS], fim[NS];
-#pragma unroll
-    for (int q = 0; q < NS; ++q) {
-        const int i = q * R + r;
-        const bool in = c < U && i < U;
-        const cx<float> v = fac[(size_t)sys * U * U + (in ? c * U + i : 0)];
-        fre[q] = in ? v.re : 0.0;
-        fim[q] = in ? v.im : 0.0;
-    }
-    // (A Z)[c] = sum_i conj(A[i][c]) Z[i]: the column layout of A, conjugated
-#pragma unroll
-    for (int q = 0; q < NS; ++q) aim[q] = -aim[q];
+    ref_setup<UP>(are, aim, fre, fim, kap, U, sys, fac);
     const bool ok = scale > 0.0;
     const double inv_scale = ok ? 1.0 / scale : 0.0;
-    float2 sym[F64L<UP>::SPL];
     for (int k0 = 0; k0 < K; k0 += KC) {
         const int kc = min(KC, K - k0);
-        load_syms<UP>(s, k0, kc, n, n_sc, U, sym);
-        stage_syms<UP>(sym, kc, U, sb);
-        wave_sync();
-        if constexpr (UP == 16) {
-            // the three products on FP64 MFMA, every lane writing its 4 symbols
-            double vr[4], vi[4];
-            // Z = F S
-            apply_mfma16<true>(fre, fim, sb, vr, vi);
-#pragma unroll
-            for (int t = 0; t < 4; ++t) zb[(4 * t + r) * UP + upos<UP>(c)] = {vr[t], vi[t]};
-            wave_sync();
-            // r = S - A Z / scale
-            apply_mfma16<false>(are, aim, zb, vr, vi);
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int k = 4 * t + r;
-                const cx<float> sk = sb[k * UP + upos<UP>(c)];
-                const bool live = ok && c < U && k < kc;
-                rb[k * UP + upos<UP>(c)] = {live ? (double)sk.re - vr[t] * inv_scale : 0.0,
-                                            live ? (double)sk.im - vi[t] * inv_scale : 0.0};
-            }
-            wave_sync();
-            // Z += F r, rounded to complex64 for the precode
-            apply_mfma16<false>(fre, fim, rb, vr, vi);
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int k = 4 * t + r;
-                const cx<double> z = zb[k * UP + upos<UP>(c)];
-                const bool live = ok && c < U && k < kc;
-                zb32[c * KC + k] = {live ? (float)(z.re + vr[t]) : 0.f, live ? (float)(z.im + vi[t]) : 0.f};
-            }
-            wave_sync();
-        } else {
-        // Z = F S
-        for (int k = 0; k < KC; ++k) {
-            double vr, vi;
-            apply_rows<UP, true>(fre, fim, sb, k, vr, vi);
-            if (r == 0) zb[k * UP + upos<UP>(c)] = {vr, vi};
-        }
-        wave_sync();
-        // r = S - A Z / scale
-        for (int k = 0; k < KC; ++k) {
-            double vr, vi;
-            apply_rows<UP, false>(are, aim, zb, k, vr, vi);
-            if (r == 0) {
-                const cx<float> sk = sb[k * UP + upos<UP>(c)];
-                const bool live = ok && c < U && k < kc;
-                rb[k * UP + upos<UP>(c)] = {live ? (double)sk.re - vr * inv_scale : 0.0,
-                                            live ? (double)sk.im - vi * inv_scale : 0.0};
-            }
-        }
-        wave_sync();
-        // Z += F r, rounded to complex64 for the precode
-        for (int k = 0; k < KC; ++k) {
-            double vr, vi;
-            apply_rows<UP, false>(fre, fim, rb, k, vr, vi);
-            if (r == 0) {
-                const cx<double> z = zb[k * UP + upos<UP>(c)];
-                const bool live = ok && c < U && k < kc;
-                zb32[c * KC + k] = {live ? (float)(z.re + vr) : 0.f, live ? (float)(z.im + vi) : 0.f};
-            }
-        }
-        wave_sync();
-        }
-        ZOp<UP, kF32> z;
-        make_zop<UP, kF32>(zb32, KC, 1, kc, z);
-        for (int t = 0; t < ntile; ++t) {
-            Tile<UP, kF32> tq;
-            const int nt = min(32, nrows - 32 * t);
-            load_tile<UP, kF32, false>(Hn, U, r0 + 32 * t, nt, tq);
-            store_x(mfma_apply_packed<UP, kF32>(tq, z), r0 + 32 * t, nt, k0, kc, n, n_sc, B, x);
-        }
+        ref_products<UP>(are, aim, fre, fim, ok, inv_scale, s, k0, kc, n, n_sc, U, sb, zb, rb, zb32);
+        ref_precode<UP>(Hn, U, r0, nrows, 0, 1, zb32, k0, kc, n, n_sc, B, x);
         wave_sync();  // the chunks are rewritten by the next one
+    }
+}
+
+// One PD subcarrier per workgroup of kSplitW waves: wave w forms the FP64
+// partial Gram of the row tiles w, w + kSplitW, ... (the partials are added in
+// LDS in fixed wave order), the master (wave 0) runs the three products of
+// each symbol chunk, and every wave precodes its own tiles from the master's
+// refined Z.  An instance on the FP64 route is solved there by the master.
+constexpr int kSplitW = 4;
+
+template <int UP>
+struct SplitL {
+    // per wave: its partial Gram (UP = 16: NS = 4 real and 4 imaginary parts
+    // per lane; 32: the six 16 x 16 MFMA accumulators, 24 doubles per lane)
+    static constexpr size_t part = (size_t)64 * (UP == 16 ? 8 : 24) * 8;
+    static constexpr size_t bytes = RefL<UP>::per_wave + kSplitW * part;
+};
+
+template <int UP>
+__global__ void __launch_bounds__(64 * kSplitW, 1)
+    refine_split_k(Prob p, int K, const float2 *__restrict__ H, const float2 *__restrict__ s, float2 *__restrict__ x,
+                   const cx<float> *__restrict__ fac, const float *__restrict__ scale_in,
+                   const int *__restrict__ status) {
+    extern __shared__ float4 smem_split[];
+    constexpr int NS = F64L<UP>::NS;
+    const Prob *pk = (const Prob *)__builtin_amdgcn_kernarg_segment_ptr();  // p: the first argument
+    char *wb = (char *)smem_split;                                           // the master's buffers
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = lane_id();
+    const int n = blockIdx.x, B = p.B, U = p.U, n_sc = p.n_sc;
+    const int ntile = (B + 31) >> 5;
+    if (on_f64_route(status, n)) {
+        if (wave == 0) f64r::instance(f64r::shape_of(p), pk, n, K, false, H, s, x, nullptr, nullptr, wb);
+        return;
+    }
+    const float2 *Hn = H + (size_t)n * B * U;
+    double *part = (double *)(wb + RefL<UP>::per_wave);
+    double are[NS], aim[NS];
+#pragma unroll
+    for (int q = 0; q < NS; ++q) are[q] = aim[q] = 0.0;
+    if constexpr (UP == 16) {
+        for (int t = wave; t < ntile; t += kSplitW)
+            gram_mfma16<1>(Hn, U, 32 * t, min(32, B - 32 * t), are, aim);
+        double *pw = part + (size_t)wave * 64 * 8;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            pw[(2 * q) * 64 + lane] = are[q];
+            pw[(2 * q + 1) * 64 + lane] = aim[q];
+        }
+        __syncthreads();
+        if (wave == 0)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                double a = 0.0, b = 0.0;
+#pragma unroll
+                for (int w = 0; w < kSplitW; ++w) {
+                    a += part[(size_t)w * 64 * 8 + (2 * q) * 64 + lane];
+                    b += part[(size_t)w * 64 * 8 + (2 * q + 1) * 64 + lane];
+                }
+                are[q] = a;
+                aim[q] = b;
+            }
+    } else {
+        f64x4 acc[6];
+#pragma unroll
+        for (int t = 0; t < 6; ++t) acc[t] = (f64x4){0.0, 0.0, 0.0, 0.0};
+        for (int t = wave; t < ntile; t += kSplitW) gram_mfma32_tile(Hn, U, 32 * t, min(32, B - 32 * t), acc);
+        double *pw = part + (size_t)wave * 64 * 24;
+#pragma unroll
+        for (int t = 0; t < 6; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) pw[(4 * t + i) * 64 + lane] = acc[t][i];
+        __syncthreads();
+        if (wave == 0) {
+#pragma unroll
+            for (int t = 0; t < 6; ++t)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    double a = 0.0;
+#pragma unroll
+                    for (int w = 0; w < kSplitW; ++w) a += part[(size_t)w * 64 * 24 + (4 * t + i) * 64 + lane];
+                    acc[t][i] = a;
+                }
+            gram32_to_regs(acc, (cx<double> *)wb, are, aim);
+        }
+    }
+    cx<float> *sb = (cx<float> *)wb;
+    cx<float> *zb32 = (cx<float> *)(wb + F64L<UP>::s_bytes);
+    cx<double> *zb = (cx<double> *)(wb + F64L<UP>::rows_bytes);
+    cx<double> *rb = (cx<double> *)(wb + F64L<UP>::rows_bytes + F64L<UP>::z64_bytes);
+    double fre[NS], fim[NS];
+    bool ok = false;
+    double inv_scale = 0.0;
+    if (wave == 0) {
+        const float sv = scale_in[n];
+        const double scale = sv > 0.f ? 1.0 / (double)sv : 0.0;
+        ref_setup<UP>(are, aim, fre, fim, (double)pd_kappa(p), U, n, fac);
+        ok = scale > 0.0;
+        inv_scale = ok ? 1.0 / scale : 0.0;
+    }
+    for (int k0 = 0; k0 < K; k0 += KC) {
+        const int kc = min(KC, K - k0);
+        if (wave == 0) ref_products<UP>(are, aim, fre, fim, ok, inv_scale, s, k0, kc, n, n_sc, U, sb, zb, rb, zb32);
+        __syncthreads();  // the refined Z chunk is complete
+        ref_precode<UP>(Hn, U, 0, B, wave, kSplitW, zb32, k0, kc, n, n_sc, B, x);
+        __syncthreads();  // the chunk buffers are rewritten by the next one
     }
 }
 
@@ -261,6 +400,18 @@ __global__ void __launch_bounds__(64 * RefL<UP>::waves, 2)
 template <int UP>
 hipError_t launch_refine(const Prob &p, const float2 *H, const float2 *s, float2 *x, const void *fac,
                          const float *scale_in, const int *status, hipStream_t st) {
+    if (p.arch == kPD && p.B >= 32 * kSplitW) {
+        // PD over at least kSplitW row tiles: the subcarrier split over a workgroup
+        const size_t lds = SplitL<UP>::bytes;
+        if (lds > 64 * 1024) {
+            const hipError_t e = hipFuncSetAttribute((const void *)refine_split_k<UP>,
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL((refine_split_k<UP>), dim3((unsigned)p.n_sc), dim3(64 * kSplitW), lds, st, p, p.K, H, s,
+                           x, (const cx<float> *)fac, scale_in, status);
+        return hipGetLastError();
+    }
     constexpr int W = RefL<UP>::waves;
     const unsigned blocks = (unsigned)((n_inst(p) + W - 1) / W);
     const size_t lds = RefL<UP>::per_wave * W;
