@@ -180,3 +180,23 @@ def test_batch_retries_fused_jobs(torch, pc, ctx):
         expect = np.zeros(H.shape[0], np.int32)
         expect[bad] = ST_FP64
         _check(x.cpu().numpy(), sc.cpu().numpy(), st.cpu().numpy(), xo, bo, so, expect)
+
+
+@pytest.mark.parametrize("B,sizes", [(256, (32,) * 8), (64, (32, 32))], ids=["b256_split", "b64_one_wave"])
+def test_refinement_retry(torch, ctx, pc, B, sizes):
+    """One refinement step over a frame with nearly collinear (FP32 fails, FP64
+    solves) and exactly singular subcarriers, 40 symbols (three chunks): the
+    refinement kernel hands the FP64-route instances to the FP64 solve (at 256
+    antennas the split workgroup's master wave), the others are refined; all
+    against the oracle."""
+    bad, singular = (3, 10), (7,)
+    H, s = collinear_cell(B, 4, 12, 40, bad, 120 if B > 64 else 400, seed=31, singular=singular)
+    x, sc, st = ctx.pd(_dev(torch, H), _dev(torch, s), 0.0, sizes, "zf",
+                       pc.params(precision="split_fp16", refine_steps=1, fp64_ratio=2.0))
+    torch.cuda.synchronize()
+    assert ctx.last_impl == "fused"
+    xo, sco, sto = oracle.pd(H, s, 0.0, sizes, zf=True)
+    expect = np.zeros(12, dtype=np.int32)
+    expect[list(bad)] = ST_FP64
+    expect[list(singular)] = ST_FAIL | ST_FP64
+    _check(x.cpu().numpy(), sc.cpu().numpy(), st.cpu().numpy(), xo, sco, sto, expect)
