@@ -1,6 +1,7 @@
 // api.hip -- the C ABI declared in include/precode.h: argument validation,
-// context workspace under an HBM budget, dispatch between the fused and the
-// plain kernels, the frame/symbol split and the heterogeneous batch call.
+// context workspace under an HBM budget, dispatch between the fused kernels
+// (register tiles, refinement, one-wave FP64, wide FP64) and the plain
+// kernels, the frame/symbol split and the heterogeneous batch call.
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -229,8 +230,8 @@ int make_prob(int arch, float rho, const int *sizes, int C, int mode, int B, int
 }
 
 // Validates every job of a batch and splits it into problems for the fused
-// batch launch and jobs for the plain kernels.  Nothing is launched unless the
-// whole batch is valid.
+// batch launches (each with its kind) and jobs for the plain kernels (those
+// without symbols).  Nothing is launched unless the whole batch is valid.
 int classify(const precode_job *jobs, int n_jobs, int precision, std::vector<BatchProblem> *fused,
              std::vector<std::pair<int, Prob>> *plain) {
     for (int i = 0; i < n_jobs; ++i) {

@@ -129,9 +129,10 @@ bool fused_supported(const Prob &p, int precision);
 // *nw_used (may be NULL) receives the waves per workgroup the launch used.
 hipError_t fused_run(const Prob &p, int precision, const float2 *H, const float2 *s, float2 *x,
                      float *scale_out, int *status, hipStream_t st, int *nw_used = nullptr);
-// The FP64 route in one fused launch (fused_f64.hip): every local system of
-// the problem on the FP64 route, U <= 16 and U <= B_eff <= 32, K >= 1, not
-// precision FP64 (which keeps the precode in FP64 on the plain kernels).
+// The FP64 route in one fused launch (fused_f64.hip), one wave per local
+// system: every local system of the problem on the FP64 route, U <= 32 and
+// U <= B_eff <= 64, K >= 1, not precision FP64 (which the wide FP64 kernel
+// takes, its precode in FP64 throughout).
 bool fused_f64_supported(const Prob &p, int precision, int K);
 hipError_t fused_f64_run(const Prob &p, const float2 *H, const float2 *s, float2 *x, float *scale_out, int *status,
                          hipStream_t st);

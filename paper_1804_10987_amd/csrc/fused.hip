@@ -312,9 +312,11 @@ int choose_shape(const Prob &p, int prec, int mode, int K, const float2 *H, cons
         }
         // every candidate once untimed (a kernel's first launch also loads
         // it), then kRounds rounds over the candidates in turn, each timing
-        // two back-to-back calls; a candidate's time is its best round, so a
-        // one-off stall in one round does not decide the shape
-        constexpr int kRounds = 3;
+        // kCalls back-to-back calls (so that the dispatch gaps between calls,
+        // larger under a tracing profiler, do not decide the shape); a
+        // candidate's time is its best round, so a one-off stall in one round
+        // does not decide the shape either
+        constexpr int kRounds = 3, kCalls = 8;
         float best_of[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         bool ok = true;
         for (int i = 0; i < nc && ok; ++i)
@@ -322,7 +324,7 @@ int choose_shape(const Prob &p, int prec, int mode, int K, const float2 *H, cons
         for (int round = 0; round < kRounds && ok; ++round)
             for (int i = 0; i < nc && ok; ++i) {
                 ok = hipEventRecord(e0, st) == hipSuccess;
-                for (int r = 0; r < 2 && ok; ++r)
+                for (int r = 0; r < kCalls && ok; ++r)
                     ok = run_once(cands[i], p, prec, mode, K, H, s, x, ainv, scale_out, status, st) == hipSuccess;
                 float ms = 0.f;
                 ok = ok && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&

@@ -1,7 +1,7 @@
 // fused_f64.hip -- the FP64 route in one fused launch: local systems whose
-// conditioning calls for FP64 (U / B_eff >= fp64_ratio; precision FP64 keeps
-// the precode in FP64 on the plain kernels) with U <= 32 users and
-// U <= B_eff <= 64 rows.
+// conditioning calls for FP64 (U / B_eff >= fp64_ratio; precision FP64, with
+// its precode in FP64 throughout, runs on the wide FP64 kernel) with U <= 32
+// users and U <= B_eff <= 64 rows.
 //
 // One wave per local system (FD cluster c of subcarrier n, or a PD subcarrier
 // of at most 64 antennas), four systems per workgroup, no workgroup barrier.
