@@ -371,6 +371,8 @@ __global__ void __launch_bounds__(kCenThreads) central_k(Cen c, const float2 *__
 // otherwise each chunk is staged again for the second pass.
 constexpr size_t kMrtChunkLds = 48 * 1024;
 constexpr int kMrtSyms = 16;
+// The precoded symbols are written once and never read back: non-temporal stores.
+typedef float mfloat2 __attribute__((ext_vector_type(2)));
 
 __host__ __device__ inline int mrt_chunk_rows(int B, int U) {
     const int r = (int)(kMrtChunkLds / ((size_t)(U + 1) * sizeof(float2)));
@@ -453,7 +455,8 @@ __global__ void __launch_bounds__(256) mrt_k(Prob p, const float2 *__restrict__ 
                 float2 acc = make_float2(0.f, 0.f);
                 for (int u = 0; u < U; ++u) acc = mac(acc, hb[u], sk[u]);
                 const float w = rn[b0 + b];
-                x[((size_t)(k0 + kk) * p.n_sc + n) * B + b0 + b] = make_float2(acc.x * w, acc.y * w);
+                __builtin_nontemporal_store((mfloat2){acc.x * w, acc.y * w},
+                                            (mfloat2 *)(x + ((size_t)(k0 + kk) * p.n_sc + n) * B + b0 + b));
             }
         }
     }

@@ -308,7 +308,7 @@ __device__ __forceinline__ void f64_system(const Prob &p, const Prob *__restrict
                         const int k = k4 + u;
                         const double a = xr[u] + swap32_d(xr[u], g == 0), b = xi[u] + swap32_d(xi[u], g == 0);
                         if ((k & 1) == g && k < kc && j < nq)
-                            xq[(size_t)k * n_sc * B] = make_float2((float)a, (float)b);
+                            __builtin_nontemporal_store((floatx2){(float)a, (float)b}, (floatx2 *)(xq + (size_t)k * n_sc * B));
                     }
                 }
             }

@@ -78,6 +78,8 @@ __device__ __forceinline__ double rcp_nr(double v) {
 }
 
 typedef double wf64x4 __attribute__((ext_vector_type(4)));
+// x is written once and never read back by the launch: non-temporal stores.
+typedef float wfloat2 __attribute__((ext_vector_type(2)));
 
 template <int NP>
 __device__ __forceinline__ void wide_system(const Prob *__restrict__ pk, int sys, int K, int mode,
@@ -451,7 +453,8 @@ __device__ __forceinline__ void wide_system(const Prob *__restrict__ pk, int sys
                 if (!bform)
                     zb[k * NP + si] = {a, b};
                 else if (si < N && k < kc)
-                    x[((size_t)(k0 + k) * n_sc + n) * B + r0 + si] = make_float2((float)a, (float)b);
+                    __builtin_nontemporal_store((wfloat2){(float)a, (float)b},
+                                                (wfloat2 *)(x + ((size_t)(k0 + k) * n_sc + n) * B + r0 + si));
             }
         }
         if (!bform) {
@@ -504,8 +507,9 @@ __device__ __forceinline__ void wide_system(const Prob *__restrict__ pk, int sys
                     for (int m = 0; m < XS; ++m) {
                         const int k = g + 4 * m;
                         if (k < kc)
-                            x[((size_t)(k0 + k) * n_sc + n) * B + r0 + 64 * c + r] =
-                                make_float2((float)xr[m], (float)xi[m]);
+                            __builtin_nontemporal_store(
+                                (wfloat2){(float)xr[m], (float)xi[m]},
+                                (wfloat2 *)(x + ((size_t)(k0 + k) * n_sc + n) * B + r0 + 64 * c + r));
                     }
                 __syncthreads();  // the staging area is rewritten by the next chunk
             }
