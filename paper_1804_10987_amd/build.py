@@ -17,7 +17,7 @@ LIB = os.path.join(PKG, "libprecode.so")
 ARCH = "gfx950"
 
 SOURCES = ["api.hip", "plain.hip", "fused.hip", "fused_nw1.hip", "fused_nw2.hip", "fused_nw4.hip", "fused_f64.hip",
-           "refine.hip", "batch.hip", "serve.hip", "noalloc.hip", "compare.hip", "ue.hip", "wide.hip"]
+           "refine.hip", "batch.hip", "serve.hip", "noalloc.hip", "compare.hip", "mrt.hip", "ue.hip", "wide.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=" + ARCH,

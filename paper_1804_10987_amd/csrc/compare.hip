@@ -19,10 +19,7 @@
 // below by that inverse (the triangular solve as a product) while one wave
 // advances the forward substitution by one tile row.
 //
-// MRT: x_c = sqrt(rho_c^2 / (||H_c||_F^2 Es)) H_c s with rho_c^2 = rho^2 / C
-// or the call's per-cluster budgets: the matched filter with the per-cluster
-// power normalization of Sec. III-C (C = 1: centralized MRT).  One workgroup
-// per subcarrier.
+// MRT is in mrt.hip.
 #include <algorithm>
 
 #include "common.h"
@@ -361,107 +358,6 @@ __global__ void __launch_bounds__(kCenThreads) central_k(Cen c, const float2 *__
     }
 }
 
-// MRT, one workgroup per subcarrier, in two passes over chunks of antenna
-// rows staged in LDS with coalesced loads (rows padded to U + 1 entries
-// against bank conflicts): row norms, then per-cluster weights (and each
-// row's weight), then the outputs x_k[b] = w_c sum_u H[b][u] s_k[u] with
-// consecutive threads on consecutive rows of one symbol (coalesced stores),
-// the symbols staged in LDS kMrtSyms at a time.  ONE: the subcarrier's
-// channel fits one chunk, staged once for both passes (HBM sees it once);
-// otherwise each chunk is staged again for the second pass.
-constexpr size_t kMrtChunkLds = 48 * 1024;
-constexpr int kMrtSyms = 16;
-// The precoded symbols are written once and never read back: non-temporal stores.
-typedef float mfloat2 __attribute__((ext_vector_type(2)));
-
-__host__ __device__ inline int mrt_chunk_rows(int B, int U) {
-    const int r = (int)(kMrtChunkLds / ((size_t)(U + 1) * sizeof(float2)));
-    return r < B ? r : B;
-}
-// row norms, then row weights [B]; cluster weights [C]; symbols [kMrtSyms][U]
-__host__ __device__ inline size_t mrt_head(int B, int C, int U) {
-    return (((size_t)(B + C) * sizeof(float) + 15) & ~(size_t)15) + (size_t)kMrtSyms * U * sizeof(float2);
-}
-
-template <bool ONE>
-__global__ void __launch_bounds__(256) mrt_k(Prob p, const float2 *__restrict__ H, const float2 *__restrict__ s,
-                                            float2 *__restrict__ x, float *__restrict__ wgt,
-                                            int *__restrict__ status) {
-    extern __shared__ float4 smem_mrt[];
-    const Prob *pk = (const Prob *)__builtin_amdgcn_kernarg_segment_ptr();  // p: the first argument
-    const int n = blockIdx.x, tid = threadIdx.x;
-    const int B = p.B, U = p.U, C = p.C, K = p.K, ru = U + 1;
-    const int R = mrt_chunk_rows(B, U);
-    float *rn = (float *)smem_mrt;  // [B] row norms, then row weights
-    float *cw = rn + B;             // [C] cluster weights
-    float2 *sl = (float2 *)((char *)smem_mrt + (((size_t)(B + C) * sizeof(float) + 15) & ~(size_t)15));  // [kMrtSyms][U]
-    float2 *Hl = (float2 *)((char *)smem_mrt + mrt_head(B, C, U));  // [R][U + 1]
-    const float2 *Hn = H + (size_t)n * B * U;
-    auto stage = [&](int b0, int nb) {
-        __syncthreads();  // the previous chunk is consumed
-        for (int e = tid; e < nb * U; e += 256) {
-            const int b = e / U;
-            Hl[b * ru + (e - b * U)] = Hn[(size_t)b0 * U + e];
-        }
-        __syncthreads();
-    };
-    for (int b0 = 0; b0 < B; b0 += R) {
-        const int nb = min(R, B - b0);
-        if (!ONE || b0 == 0) stage(b0, nb);
-        for (int b = tid; b < nb; b += 256) {
-            float f = 0.f;
-            for (int u = 0; u < U; ++u) {
-                const float2 h = Hl[b * ru + u];
-                f = fmaf(h.x, h.x, fmaf(h.y, h.y, f));
-            }
-            rn[b0 + b] = f;
-        }
-    }
-    __syncthreads();
-    for (int cl = tid; cl < C; cl += 256) {
-        float f = 0.f;
-        for (int b = pk->off[cl]; b < pk->off[cl + 1]; ++b) f += rn[b];
-        const bool bad = !(f > 0.f) || !(f - f == 0.f);
-        const float w = bad ? 0.f : sqrtf(fd_power_c(pk, cl) / (f * p.Es));
-        cw[cl] = w;
-        if (wgt) wgt[(size_t)n * C + cl] = w;
-        if (status) status[(size_t)n * C + cl] = bad ? PRECODE_ST_FAIL : PRECODE_ST_OK;
-    }
-    __syncthreads();
-    // each row's weight, over the row norms (no longer needed)
-    for (int b = tid; b < B; b += 256) {
-        int lo = 0, hi = C - 1;  // cluster of row b: off[lo] <= b < off[lo + 1]
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (pk->off[mid] <= b) lo = mid; else hi = mid - 1;
-        }
-        rn[b] = cw[lo];
-    }
-    for (int b0 = 0; b0 < B; b0 += R) {
-        const int nb = min(R, B - b0);
-        if (!ONE) stage(b0, nb);
-        for (int k0 = 0; k0 < K; k0 += kMrtSyms) {
-            const int ks = min(kMrtSyms, K - k0);
-            __syncthreads();  // the previous symbols are consumed (and the row weights written)
-            for (int e = tid; e < ks * U; e += 256) {
-                const int kk = e / U;
-                sl[e] = s[((size_t)(k0 + kk) * p.n_sc + n) * U + (e - kk * U)];
-            }
-            __syncthreads();
-            for (int o = tid; o < nb * ks; o += 256) {
-                const int kk = o / nb, b = o - kk * nb;
-                const float2 *sk = sl + kk * U;
-                const float2 *hb = Hl + b * ru;
-                float2 acc = make_float2(0.f, 0.f);
-                for (int u = 0; u < U; ++u) acc = mac(acc, hb[u], sk[u]);
-                const float w = rn[b0 + b];
-                __builtin_nontemporal_store((mfloat2){acc.x * w, acc.y * w},
-                                            (mfloat2 *)(x + ((size_t)(k0 + kk) * p.n_sc + n) * B + b0 + b));
-            }
-        }
-    }
-}
-
 }  // namespace
 
 size_t central_lds_bytes(int B, int U) { return CenLds((B + TE - 1) / TE, U).bytes; }
@@ -497,23 +393,6 @@ hipError_t central_run(int B, int U, int n_sc, int K, float kappa, float Es, flo
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
-}
-
-hipError_t mrt_run(const Prob &p, const float2 *H, const float2 *s, float2 *x, float *wgt, int *status,
-                   hipStream_t st) {
-    if (p.n_sc == 0) return hipSuccess;
-    const int R = mrt_chunk_rows(p.B, p.U);
-    const size_t lds = mrt_head(p.B, p.C, p.U) + (size_t)R * (p.U + 1) * sizeof(float2);
-    if (lds > 64 * 1024) {
-        const void *fn = R == p.B ? (const void *)mrt_k<true> : (const void *)mrt_k<false>;
-        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-    }
-    if (R == p.B)
-        hipLaunchKernelGGL(mrt_k<true>, dim3(p.n_sc), dim3(256), lds, st, p, H, s, x, wgt, status);
-    else
-        hipLaunchKernelGGL(mrt_k<false>, dim3(p.n_sc), dim3(256), lds, st, p, H, s, x, wgt, status);
-    return hipGetLastError();
 }
 
 }  // namespace pc

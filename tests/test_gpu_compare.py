@@ -163,6 +163,14 @@ MRT = [
     ("central", synth.Cell(B=256, sizes=(256,), U=16, n_sc=7, K=3)),
     ("u64", synth.Cell(B=128, sizes=(64, 64), U=64, n_sc=5, K=2)),
     ("b300u40_chunks", synth.Cell(B=300, sizes=(100, 200), U=40, n_sc=4, K=3)),  # 3 row chunks, ragged tail
+    # the matrix-core kernel (U = 16 or 32, B <= 512), each launch shape:
+    # 4 waves x 1 tile, ragged last tile, clusters across tiles, 2 symbol chunks
+    ("mfma_b100u16", synth.Cell(B=100, sizes=(37, 63), U=16, n_sc=9, K=19)),
+    ("mfma_b20u32_k1", synth.Cell(B=20, sizes=(20,), U=32, n_sc=3, K=1)),
+    ("mfma_b256u32", synth.Cell(B=256, sizes=(64,) * 4, U=32, n_sc=6, K=17)),  # 8 waves x 1 tile
+    ("mfma_b480u16", synth.Cell(B=480, sizes=(96,) * 5, U=16, n_sc=5, K=3)),  # 8 x 2, waves with 1 tile
+    ("mfma_b512u32", synth.Cell(B=512, sizes=(32,) * 16, U=32, n_sc=5, K=14)),  # 8 x 2
+    ("generic_b544u16", synth.Cell(B=544, sizes=(272, 272), U=16, n_sc=3, K=2)),  # past 512 rows
 ]
 
 
@@ -189,6 +197,48 @@ def test_mrt_zero_cluster(torch, ctx, pc):
     xg = x.cpu().numpy()
     assert (xg[:, 2, 32:] == 0).all()
     assert _vec_err(xg, xo).max() <= TOL
+
+
+def test_mrt_zero_cluster_mfma(torch, ctx, pc):
+    # a silent cluster on the matrix-core kernel: weight 0, status FAIL, x 0
+    cell = synth.Cell(B=96, sizes=(40, 56), U=16, n_sc=4, K=5)
+    H, s = synth.make_cell(cell, seed=36)
+    H[1, :40] = 0
+    x, w, st = ctx.mrt(_dev(torch, H), _dev(torch, s), cell.sizes)
+    torch.cuda.synchronize()
+    xo, wo, so = oracle.mrt(H, s, cell.sizes)
+    assert (st.cpu().numpy() == so).all() and so[1, 0] == 1
+    xg = x.cpu().numpy()
+    assert (xg[:, 1, :40] == 0).all()
+    assert _vec_err(xg, xo).max() <= TOL
+    assert (np.abs(w.cpu().numpy() - wo) <= TOL * wo).all()
+
+
+def test_mrt_misaligned_channel(torch, ctx, pc):
+    # a channel that is not 16-byte aligned takes the general kernel
+    cell = synth.Cell(B=64, sizes=(32, 32), U=16, n_sc=3, K=4)
+    H, s = synth.make_cell(cell, seed=37)
+    flat = torch.empty(H.size + 1, dtype=torch.complex64, device="cuda")
+    Hd = flat[1:].view(H.shape)
+    Hd.copy_(_dev(torch, H))
+    assert Hd.data_ptr() % 16 == 8
+    x, w, st = ctx.mrt(Hd, _dev(torch, s), cell.sizes)
+    torch.cuda.synchronize()
+    xo, wo, so = oracle.mrt(H, s, cell.sizes)
+    assert (st.cpu().numpy() == so).all()
+    assert _vec_err(x.cpu().numpy(), xo).max() <= TOL
+
+
+def test_mrt_full_frame(torch, ctx, pc):
+    # every subcarrier of the 256-antenna / 16-user frame (8 clusters of 32)
+    cell = synth.config(2)
+    H, s = synth.make_cell(cell, seed=38)
+    x, w, st = ctx.mrt(_dev(torch, H), _dev(torch, s), cell.sizes)
+    torch.cuda.synchronize()
+    xo, wo, so = oracle.mrt(H, s, cell.sizes)
+    assert (st.cpu().numpy() == so).all()
+    assert _vec_err(x.cpu().numpy(), xo).max() <= TOL
+    assert (np.abs(w.cpu().numpy() - wo) <= TOL * wo).all()
 
 
 # ---------------------------------------------------------------------------
