@@ -18,8 +18,6 @@
 namespace pc {
 namespace {
 
-constexpr int kUeRows = 32;  // antenna rows staged per step of the receive kernel
-
 __device__ __forceinline__ int gray_to_index(int g) {
     int i = g;
     for (int sh = 1; sh < 16; sh <<= 1) i ^= i >> sh;
@@ -36,46 +34,119 @@ __global__ void __launch_bounds__(256) qam_map_k(const int *__restrict__ labels,
     s[e] = make_float2((float)(2 * ir - (m - 1)) * d, (float)(2 * ii - (m - 1)) * d);
 }
 
-// One workgroup per subcarrier; thread t owns outputs (u, k) = (o % U, o / U)
-// for o = t, t + 256, ...; antenna rows are staged 32 at a time in LDS
-// (H rows [32][U], x [K][32]).
+// One workgroup (256 threads) per subcarrier.  The outputs come in blocks of
+// 4 users x 4 symbols (nbu = ceil(U / 4) by nbk = ceil(K / 4) blocks, at most
+// 256); thread t takes block t % nblk for the antenna rows t / nblk, + G, ..
+// of each staged chunk (G = 256 / nblk row groups), so each row's 4 channel
+// entries and 4 precoded entries (8 LDS reads) feed 16 complex
+// multiply-adds.  Rows are staged RC at a time: H rows [RC][U + 1] and x
+// [K][XS] (XS = 1 mod 4), padded so that a wave's row groups and symbol
+// blocks fall in different banks.  The row groups' partial sums are added
+// within each wave by shuffles when nblk divides 64 (then per wave through
+// LDS), otherwise through LDS per row group.
+__host__ __device__ inline int ue_xs(int rc) { return rc + ((1 - rc) & 3); }
+
 __global__ void __launch_bounds__(256) ue_receive_k(const float2 *__restrict__ H, const float2 *__restrict__ x,
                                                    const float2 *__restrict__ noise, float sq_n0,
                                                    const float *__restrict__ scale, int B, int U, int n_sc, int K,
-                                                   float2 *__restrict__ y) {
+                                                   int RC, float2 *__restrict__ y) {
     extern __shared__ float2 smem_ue[];
-    float2 *Hs = smem_ue;                 // [32][U]
-    float2 *Xs = smem_ue + kUeRows * U;  // [K][32]
+    const int HS = U + 1, XS = ue_xs(RC);
+    float2 *Hs = smem_ue;            // [RC][HS]
+    float2 *Xs = smem_ue + RC * HS;  // [K][XS]
     const int n = blockIdx.x, tid = threadIdx.x;
     const float2 *Hn = H + (size_t)n * B * U;
-    const float sc = scale ? scale[n] : 1.f;
-    for (int o0 = 0; o0 < U * K; o0 += 256) {
-        const int o = o0 + tid;
-        const int u = o % U, k = o / U;
-        float2 acc = make_float2(0.f, 0.f);
-        for (int b0 = 0; b0 < B; b0 += kUeRows) {
-            const int nb = min(kUeRows, B - b0);
-            __syncthreads();
-            for (int e = tid; e < nb * U; e += 256) Hs[e] = Hn[(size_t)b0 * U + e];
-            for (int e = tid; e < K * kUeRows; e += 256) {
-                const int kk = e / kUeRows, bb = e % kUeRows;
-                Xs[e] = bb < nb ? x[((size_t)kk * n_sc + n) * B + b0 + bb] : make_float2(0.f, 0.f);
+    const int nbu = (U + 3) >> 2, nbk = (K + 3) >> 2, nblk = nbu * nbk, G = 256 / nblk;
+    const int blk = tid % nblk, grp = tid / nblk;
+    const int u0 = 4 * (blk % nbu), k0 = 4 * (blk / nbu);
+    const int hq = 256 / U, hr = 256 - hq * U;
+    float2 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[a][c] = make_float2(0.f, 0.f);
+    for (int b0 = 0; b0 < B; b0 += RC) {
+        const int nb = min(RC, B - b0);
+        __syncthreads();  // the previous chunk is consumed
+        // element e = tid + 256 i of the chunk: (row, user) and (symbol, row)
+        // stepped without a division per element
+        for (int e = tid, r = tid / U, c = tid - (tid / U) * U; e < nb * U; e += 256) {
+            Hs[r * HS + c] = Hn[(size_t)b0 * U + e];
+            r += hq;
+            c += hr;
+            if (c >= U) {
+                c -= U;
+                ++r;
             }
-            __syncthreads();
-            if (o < U * K)
-                for (int bb = 0; bb < nb; ++bb) {
-                    const float2 h = Hs[bb * U + u], v = Xs[k * kUeRows + bb];
-                    acc = make_float2(fmaf(h.x, v.x, fmaf(h.y, v.y, acc.x)), fmaf(h.x, v.y, fmaf(-h.y, v.x, acc.y)));
+        }
+        {
+            const int q = 256 / nb, qr = 256 - q * nb;
+            for (int e = tid, kk = tid / nb, bb = tid - (tid / nb) * nb; e < K * nb; e += 256) {
+                Xs[kk * XS + bb] = x[((size_t)kk * n_sc + n) * B + b0 + bb];
+                kk += q;
+                bb += qr;
+                if (bb >= nb) {
+                    bb -= nb;
+                    ++kk;
                 }
-        }
-        if (o < U * K) {
-            const size_t e = ((size_t)k * n_sc + n) * U + u;
-            if (noise) {
-                const float2 w = noise[e];
-                acc = make_float2(fmaf(sq_n0, w.x, acc.x), fmaf(sq_n0, w.y, acc.y));
             }
-            y[e] = make_float2(acc.x * sc, acc.y * sc);
         }
+        __syncthreads();
+        if (grp < G)
+            for (int r = grp; r < nb; r += G) {
+                float2 h[4], v[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    h[i] = u0 + i < U ? Hs[r * HS + u0 + i] : make_float2(0.f, 0.f);
+                    v[i] = k0 + i < K ? Xs[(k0 + i) * XS + r] : make_float2(0.f, 0.f);
+                }
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c)  // acc += conj(h) v
+                        acc[a][c] = make_float2(fmaf(h[a].x, v[c].x, fmaf(h[a].y, v[c].y, acc[a][c].x)),
+                                                fmaf(h[a].x, v[c].y, fmaf(-h[a].y, v[c].x, acc[a][c].y)));
+            }
+    }
+    // partial sums [ng][nblk][16] in the staging area
+    const bool in_wave = (64 % nblk) == 0;  // then every thread is in a row group
+    int ng = G, slot = grp;
+    if (in_wave) {
+        // lanes l and l ^ nblk ^ 2 nblk .. of a wave hold the same block
+        for (int off = nblk; off < 64; off <<= 1)
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    acc[a][c].x += __shfl_xor(acc[a][c].x, off);
+                    acc[a][c].y += __shfl_xor(acc[a][c].y, off);
+                }
+        ng = 4;
+        slot = (tid & 63) < nblk ? tid >> 6 : ng;  // one lane per block and wave writes
+    }
+    __syncthreads();  // the staging area becomes the partial sums
+    float2 *part = smem_ue;
+    if (slot < ng)
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) part[(slot * nblk + blk) * 16 + 4 * a + c] = acc[a][c];
+    __syncthreads();
+    const float sc = scale ? scale[n] : 1.f;
+    for (int o = tid; o < U * K; o += 256) {
+        const int u = o % U, k = o / U;
+        const int ob = (u >> 2) + (k >> 2) * nbu, oi = 4 * (u & 3) + (k & 3);
+        float2 t = make_float2(0.f, 0.f);
+        for (int g = 0; g < ng; ++g) {
+            const float2 v = part[(g * nblk + ob) * 16 + oi];
+            t = make_float2(t.x + v.x, t.y + v.y);
+        }
+        const size_t e = ((size_t)k * n_sc + n) * U + u;
+        if (noise) {
+            const float2 w = noise[e];
+            t = make_float2(fmaf(sq_n0, w.x, t.x), fmaf(sq_n0, w.y, t.y));
+        }
+        y[e] = make_float2(t.x * sc, t.y * sc);
     }
 }
 
@@ -135,19 +206,33 @@ hipError_t qam_map_run(const int *labels, long long n, int half_bits, float2 *s,
     return hipGetLastError();
 }
 
-// Symbols per receive launch: a launch stages [32][U] channel rows and
-// [kUeSyms][32] precoded entries in LDS (at most 48 KiB for U <= 64).
+// Symbols per receive launch (at most 16 x 16 output blocks of 4 x 4).
 constexpr int kUeSyms = 64;
+
+// Rows per staged chunk: the chunk takes at most 16 KiB, so that at 16 users
+// and 14 symbols nine workgroups share a CU (a frame's 1200 subcarriers are
+// resident together); a multiple of 16 rows, so that each symbol's part of a
+// chunk starts on a 128-byte line (66 rows at 256 antennas took 35.8 us per
+// frame, 64 rows 33.5 us; 512 antennas / 32 users: 204 and 194 us).
+int ue_rows(int B, int U, int K) {
+    int rc = 2048 / (U + 1 + K);  // at least 15 (U, K <= 64)
+    rc = rc > 128 ? 128 : rc >= 16 ? rc / 16 * 16 : rc;
+    return rc < B ? rc : B;
+}
 
 hipError_t ue_receive_run(const float2 *H, const float2 *x, const float2 *noise, float N0, const float *scale, int B,
                           int U, int n_sc, int K, float2 *y, hipStream_t st) {
     if (n_sc == 0 || K == 0) return hipSuccess;
     for (int k0 = 0; k0 < K; k0 += kUeSyms) {
         const int kc = K - k0 < kUeSyms ? K - k0 : kUeSyms;
-        const size_t lds = (size_t)(kUeRows * U + kc * kUeRows) * sizeof(float2);
+        const int rc = ue_rows(B, U, kc);
+        const size_t nblk = (size_t)((U + 3) / 4) * ((kc + 3) / 4);
+        const size_t stage = (size_t)rc * (U + 1) + (size_t)kc * ue_xs(rc);
+        const size_t part = (64 % nblk == 0 ? 4 : 256 / nblk) * nblk * 16;
+        const size_t lds = (stage > part ? stage : part) * sizeof(float2);
         const size_t xo = (size_t)k0 * n_sc * B, yo = (size_t)k0 * n_sc * U;
         hipLaunchKernelGGL(ue_receive_k, dim3(n_sc), dim3(256), lds, st, H, x + xo, noise ? noise + yo : nullptr,
-                           sqrtf(N0), scale, B, U, n_sc, kc, y + yo);
+                           sqrtf(N0), scale, B, U, n_sc, kc, rc, y + yo);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

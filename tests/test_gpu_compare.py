@@ -252,9 +252,18 @@ def test_qam_map(torch, pc, order):
     assert np.abs(s.cpu().numpy() - ober.qam_map(lab, order)).max() <= 1e-6
 
 
-def test_ue_receive(torch, pc):
+UE_SHAPES = [
+    (7, 100, 13, 70),  # K beyond one launch's 64 symbols
+    (5, 256, 16, 14),  # two row chunks, 16 row groups of 4 x 4 blocks
+    (3, 300, 64, 64),  # 256 blocks, one row group, rows in chunks of 32
+    (4, 1, 1, 1),
+    (3, 37, 5, 3),
+]
+
+
+@pytest.mark.parametrize("n_sc,B,U,K", UE_SHAPES)
+def test_ue_receive(torch, pc, n_sc, B, U, K):
     rng = np.random.default_rng(36)
-    n_sc, B, U, K = 7, 100, 13, 70  # K beyond one launch's 64 symbols
     H = synth.cn_noise((n_sc, B, U), rng)
     x = synth.cn_noise((K, n_sc, B), rng)
     w = synth.cn_noise((K, n_sc, U), rng)
