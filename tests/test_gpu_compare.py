@@ -214,6 +214,20 @@ def test_mrt_zero_cluster_mfma(torch, ctx, pc):
     assert (np.abs(w.cpu().numpy() - wo) <= TOL * wo).all()
 
 
+@pytest.mark.parametrize("U", [16, 13])  # the matrix-core kernel and the general one
+def test_mrt_no_symbols(torch, ctx, pc, U):
+    # K = 0: weights and status only
+    cell = synth.Cell(B=96, sizes=(40, 56), U=U, n_sc=5, K=1)
+    H, s = synth.make_cell(cell, seed=39)
+    s0 = np.zeros((0, cell.n_sc, U), np.complex64)
+    x, w, st = ctx.mrt(_dev(torch, H), _dev(torch, s0), cell.sizes)
+    torch.cuda.synchronize()
+    assert tuple(x.shape) == (0, cell.n_sc, cell.B)
+    _, wo, so = oracle.mrt(H, s, cell.sizes)
+    assert (st.cpu().numpy() == so).all()
+    assert (np.abs(w.cpu().numpy() - wo) <= TOL * wo).all()
+
+
 def test_mrt_misaligned_channel(torch, ctx, pc):
     # a channel that is not 16-byte aligned takes the general kernel
     cell = synth.Cell(B=64, sizes=(32, 32), U=16, n_sc=3, K=4)
