@@ -50,7 +50,6 @@ namespace pc {
 namespace {
 
 constexpr int kWT = 256;  // threads per workgroup
-constexpr int kWKC = 16;  // symbols per chunk
 constexpr int kWSR = 64;  // rows staged per chunk
 // modes: Gram to precode; Gram to the factors scale A^-1 (FP64, an NP x NP
 // slot per system) with beta / weights and status; precode from the factors
@@ -58,15 +57,18 @@ enum { kWFull = 0, kWPrep = 1, kWSym = 2 };
 
 template <int NP>
 struct WideL {
+    // symbols per chunk: 8 at order 48, so that its LDS (72.8 KiB) lets two
+    // workgroups share a CU; 16 otherwise
+    static constexpr int KC = NP == 48 ? 8 : 16;
     static constexpr int E = NP / 16;   // edge of a thread's block
     static constexpr int G = kWT / NP;  // symbol groups of the solve (threads past G NP idle there)
     static constexpr int PER = kWSR * NP / kWT;  // staged elements per thread
     // staged rows: [64][NP] complex64 (Gram), [NP][65] (transposed precode rows)
     static constexpr size_t stage_b = (size_t)NP * (kWSR + 1) * 8;
     static constexpr size_t ainv_b = (size_t)NP * NP * 16;   // A^-1 [NP][NP] (row buffers while inverting)
-    static constexpr size_t vb_b = (size_t)kWKC * NP * 16;   // right-hand sides [KC][NP]
+    static constexpr size_t vb_b = (size_t)KC * NP * 16;   // right-hand sides [KC][NP]
     // Z chunk [KC][NP] (complex FP64) or symbols [KC][64] (complex64)
-    static constexpr size_t zb_b = (size_t)kWKC * (NP * 16 > 64 * 8 ? NP * 16 : 64 * 8);
+    static constexpr size_t zb_b = (size_t)KC * (NP * 16 > 64 * 8 ? NP * 16 : 64 * 8);
     static constexpr size_t o_ainv = stage_b, o_vb = o_ainv + ainv_b, o_zb = o_vb + vb_b, o_dg = o_zb + zb_b;
     static constexpr size_t bytes = o_dg + (size_t)(NP + 8) * 8;  // + diagonal, reduction slots
 };
@@ -86,7 +88,7 @@ __device__ __forceinline__ void wide_system(const Prob *__restrict__ pk, int sys
                                             const float2 *__restrict__ H, const float2 *__restrict__ s,
                                             float2 *__restrict__ x, float *__restrict__ scale_out,
                                             int *__restrict__ status, cx<double> *__restrict__ fac, char *lds) {
-    constexpr int E = WideL<NP>::E, G = WideL<NP>::G, PER = WideL<NP>::PER, KC = kWKC, SR = kWSR;
+    constexpr int E = WideL<NP>::E, G = WideL<NP>::G, PER = WideL<NP>::PER, KC = WideL<NP>::KC, SR = kWSR;
     constexpr int MS = (KC + G - 1) / G;  // symbols per thread in the solve: sg + G m < KC
     const int tid = threadIdx.x, bi = tid >> 4, bj = tid & 15;
     const bool pd = pk->arch == kPD;
@@ -519,7 +521,7 @@ __device__ __forceinline__ void wide_system(const Prob *__restrict__ pk, int sys
 }
 
 template <int NP>
-constexpr int wide_min_waves() { return NP == 16 ? 4 : (NP == 32 ? 2 : 1); }
+constexpr int wide_min_waves() { return NP == 16 ? 4 : (NP == 32 || NP == 48 ? 2 : 1); }
 
 template <int NP>
 __global__ void __launch_bounds__(kWT, (wide_min_waves<NP>()))
